@@ -1,0 +1,248 @@
+"""ctypes wrapper of the CPU FP64 oracle (libsidm_oracle.so).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, by the smoke check and by the
+CPU-baseline leg of the benchmark.  The product path never imports it.
+
+All arrays are numpy, halo-local, structure of arrays.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(HERE, "libsidm_oracle.so")
+_lib = None
+
+EVENT_DTYPE = np.dtype([("a", np.uint32), ("b", np.uint32), ("ia", np.int64),
+                        ("ib", np.int64), ("u", np.float64), ("P", np.float64)],
+                       align=True)
+
+
+class OrcParams(C.Structure):
+    _fields_ = [("G", C.c_double), ("eps", C.c_double), ("sigma_m", C.c_double),
+                ("dt", C.c_double), ("k", C.c_int32), ("seed", C.c_uint64),
+                ("host_kind", C.c_int32), ("host_rho_s", C.c_double),
+                ("host_r_s", C.c_double), ("host_c", C.c_double * 3)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from oracle import build as _b
+            _b.build()
+        _lib = C.CDLL(_LIB_PATH)
+        _declare(_lib)
+    return _lib
+
+
+_dp = C.POINTER(C.c_double)
+_u32p = C.POINTER(C.c_uint32)
+_i64p = C.POINTER(C.c_int64)
+_u8p = C.POINTER(C.c_uint8)
+
+
+def _declare(L):
+    L.orc_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
+    L.orc_u53.argtypes = [C.c_uint32, C.c_uint32]
+    L.orc_u53.restype = C.c_double
+    L.orc_accept_u.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32]
+    L.orc_accept_u.restype = C.c_double
+    L.orc_kernel_W.argtypes = [C.c_double, C.c_double]
+    L.orc_kernel_W.restype = C.c_double
+    L.orc_lambda.argtypes = [C.c_double, C.c_double, C.c_double]
+    L.orc_lambda.restype = C.c_double
+    L.orc_gravity.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, C.c_double, C.c_double,
+                              C.c_int64, _i64p, _dp, _dp, _dp, _dp, _dp]
+    L.orc_host_nfw.argtypes = [C.c_int64, _dp, _dp, _dp, C.c_double, C.c_double,
+                               C.c_double, _dp, _dp, _dp, _dp, _dp]
+    L.orc_knn.argtypes = [C.c_int64, _dp, _dp, _dp, _u32p, C.c_int32, C.c_int64,
+                          _i64p, _dp, _u32p]
+    L.orc_find_events.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _u32p,
+                                  _dp, C.c_double, C.c_double, C.c_uint64, C.c_uint32,
+                                  _u8p, C.c_void_p, C.c_int64, _i64p, _i64p]
+    L.orc_find_events.restype = C.c_int64
+    L.orc_kick_pair.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
+                                C.c_double, C.c_double, _dp, _dp]
+    L.orc_apply_events.argtypes = [C.c_int64, C.c_void_p, _dp, _dp, _dp, _dp,
+                                   C.c_uint64, C.c_uint32]
+    L.orc_diag.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+    L.orc_kdk_step.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _u32p,
+                               _dp, _dp, _dp, _dp, _dp, C.POINTER(OrcParams),
+                               C.c_uint32, C.c_void_p, C.c_int64]
+    L.orc_kdk_step.restype = C.c_int64
+    L.orc_num_threads.restype = C.c_int
+
+
+def _d(a):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_dp)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def num_threads():
+    return int(lib().orc_num_threads())
+
+
+# ---------------------------------------------------------------- random
+def philox(ctr, key):
+    c = (C.c_uint32 * 4)(*[int(v) & 0xffffffff for v in ctr])
+    k = (C.c_uint32 * 2)(*[int(v) & 0xffffffff for v in key])
+    o = (C.c_uint32 * 4)()
+    lib().orc_philox4x32_10(c, k, o)
+    return [int(v) for v in o]
+
+
+def u53(hi, lo):
+    return lib().orc_u53(int(hi), int(lo))
+
+
+def accept_u(seed, step, a, b):
+    return lib().orc_accept_u(int(seed), int(step), int(a), int(b))
+
+
+# ---------------------------------------------------------------- kernel
+def kernel_W(r, h):
+    return lib().orc_kernel_W(float(r), float(h))
+
+
+def lam(d, hi, hj):
+    return lib().orc_lambda(float(d), float(hi), float(hj))
+
+
+# ---------------------------------------------------------------- gravity
+def gravity(x, y, z, m, G, eps, query=None, want_norm=False):
+    """Self-gravity (a, phi) for all particles or a query subset."""
+    x, y, z, m = _f64(x), _f64(y), _f64(z), _f64(m)
+    n = x.size
+    if query is None:
+        nq, qp = n, None
+    else:
+        query = np.ascontiguousarray(query, dtype=np.int64)
+        nq, qp = query.size, query.ctypes.data_as(_i64p)
+    ax, ay, az, pot = (np.zeros(nq) for _ in range(4))
+    an = np.zeros(nq) if want_norm else None
+    lib().orc_gravity(n, _d(x), _d(y), _d(z), _d(m), float(G), float(eps), nq, qp,
+                      _d(ax), _d(ay), _d(az), _d(pot), _d(an) if want_norm else None)
+    if want_norm:
+        return ax, ay, az, pot, an
+    return ax, ay, az, pot
+
+
+def host_nfw(x, y, z, G, rho_s, r_s, c):
+    x, y, z = _f64(x), _f64(y), _f64(z)
+    n = x.size
+    ax, ay, az, pot = (np.zeros(n) for _ in range(4))
+    cc = (C.c_double * 3)(*[float(v) for v in c])
+    lib().orc_host_nfw(n, _d(x), _d(y), _d(z), float(G), float(rho_s), float(r_s),
+                       cc, _d(ax), _d(ay), _d(az), _d(pot))
+    return ax, ay, az, pot
+
+
+# ---------------------------------------------------------------- kNN
+def knn(x, y, z, ids, k, query=None, want_list=False):
+    x, y, z = _f64(x), _f64(y), _f64(z)
+    ids = np.ascontiguousarray(ids, dtype=np.uint32)
+    n = x.size
+    if query is None:
+        nq, qp = n, None
+    else:
+        query = np.ascontiguousarray(query, dtype=np.int64)
+        nq, qp = query.size, query.ctypes.data_as(_i64p)
+    h = np.zeros(nq)
+    nbr = np.zeros((nq, k), dtype=np.uint32) if want_list else None
+    lib().orc_knn(n, _d(x), _d(y), _d(z), ids.ctypes.data_as(_u32p), int(k), nq, qp,
+                  _d(h), nbr.ctypes.data_as(_u32p) if want_list else None)
+    return (h, nbr) if want_list else h
+
+
+# ---------------------------------------------------------------- scatter
+def find_events(x, y, z, vx, vy, vz, m, ids, h, sigma_m, dt, seed, step, qmask=None):
+    """Events (structured array in (a, b) order), pair count, count of P > 1."""
+    arrs = [_f64(a) for a in (x, y, z, vx, vy, vz, m)]
+    ids = np.ascontiguousarray(ids, dtype=np.uint32)
+    h = _f64(h)
+    n = arrs[0].size
+    qm = None
+    if qmask is not None:
+        qmask = np.ascontiguousarray(qmask, dtype=np.uint8)
+        qm = qmask.ctypes.data_as(_u8p)
+    npairs, npgt1 = C.c_int64(0), C.c_int64(0)
+    args = [n] + [_d(a) for a in arrs] + [ids.ctypes.data_as(_u32p), _d(h), float(sigma_m),
+                                          float(dt), int(seed), int(step), qm]
+    found = lib().orc_find_events(*args, None, 0, C.byref(npairs), C.byref(npgt1))
+    ev = np.zeros(max(found, 1), dtype=EVENT_DTYPE)
+    found2 = lib().orc_find_events(*args, ev.ctypes.data, found, None, None)
+    assert found2 == found
+    return ev[:found], int(npairs.value), int(npgt1.value)
+
+
+def kick_pair(seed, step, a, b, ma, mb, va, vb):
+    va = (C.c_double * 3)(*[float(v) for v in va])
+    vb = (C.c_double * 3)(*[float(v) for v in vb])
+    lib().orc_kick_pair(int(seed), int(step), int(a), int(b), float(ma), float(mb), va, vb)
+    return np.array(list(va)), np.array(list(vb))
+
+
+def apply_events(ev, m, vx, vy, vz, seed, step):
+    """Applies events (in (a, b) order) in place to vx, vy, vz."""
+    ev = np.ascontiguousarray(ev, dtype=EVENT_DTYPE)
+    for a in (vx, vy, vz):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    lib().orc_apply_events(ev.size, ev.ctypes.data, _d(_f64(m)), _d(vx), _d(vy), _d(vz),
+                           int(seed), int(step))
+
+
+def diag(vx, vy, vz, m, pot, pext=None):
+    out = np.zeros(6)
+    vx, vy, vz, m, pot = (_f64(a) for a in (vx, vy, vz, m, pot))
+    pe = _d(_f64(pext)) if pext is not None else None
+    lib().orc_diag(vx.size, _d(vx), _d(vy), _d(vz), _d(m), _d(pot), pe, _d(out))
+    return dict(K=out[0], W=out[1], Eext=out[2], px=out[3], py=out[4], pz=out[5])
+
+
+# ---------------------------------------------------------------- step
+def make_params(G=1.0, eps=0.01, sigma_m=1.0, dt=1e-3, k=32, seed=0, host=None):
+    p = OrcParams()
+    p.G, p.eps, p.sigma_m, p.dt, p.k, p.seed = G, eps, sigma_m, dt, k, seed
+    if host is None:
+        p.host_kind = 0
+        p.host_rho_s, p.host_r_s = 0.0, 1.0
+        p.host_c = (C.c_double * 3)(0.0, 0.0, 0.0)
+    else:
+        p.host_kind = 1
+        p.host_rho_s, p.host_r_s = float(host["rho_s"]), float(host["r_s"])
+        p.host_c = (C.c_double * 3)(*[float(v) for v in host["center"]])
+    return p
+
+
+def total_accel(s, p):
+    """a and pot (self + host) at the state's positions, written into s."""
+    ax, ay, az, pot = gravity(s["x"], s["y"], s["z"], s["m"], p.G, p.eps)
+    if p.host_kind == 1:
+        hx, hy, hz, hp = host_nfw(s["x"], s["y"], s["z"], p.G, p.host_rho_s, p.host_r_s,
+                                  list(p.host_c))
+        ax, ay, az, pot = ax + hx, ay + hy, az + hz, pot + hp
+    s["ax"], s["ay"], s["az"], s["pot"] = ax, ay, az, pot
+    return s
+
+
+def kdk_step(s, p, step, ev_cap=1 << 20):
+    """One full step on the dict-of-arrays state s (modified in place)."""
+    n = s["x"].size
+    for key in ("x", "y", "z", "vx", "vy", "vz", "ax", "ay", "az", "pot", "m"):
+        s[key] = _f64(s[key]).copy() if not s[key].flags.writeable else _f64(s[key])
+    s.setdefault("h", np.zeros(n))
+    ids = np.ascontiguousarray(s["id"], dtype=np.uint32)
+    ev = np.zeros(max(ev_cap, 1), dtype=EVENT_DTYPE)
+    found = lib().orc_kdk_step(n, *[_d(s[k]) for k in ("x", "y", "z", "vx", "vy", "vz", "m")],
+                               ids.ctypes.data_as(_u32p),
+                               *[_d(s[k]) for k in ("ax", "ay", "az", "pot", "h")],
+                               C.byref(p), int(step), ev.ctypes.data, ev_cap)
+    if found < 0:
+        raise RuntimeError("event capacity exceeded in oracle step")
+    return ev[:found]

@@ -1,0 +1,554 @@
+/*
+ * sidm_oracle.c -- plain FP64 CPU reference for the SIDM N-body step.
+ *
+ * TEST INFRASTRUCTURE ONLY: used by the tests, the smoke check and the CPU
+ * baseline leg of the benchmark.  The product library never links or calls it.
+ *
+ * Written from the paper (Fischer, Yu & Dolag, arXiv 2506.06269) and the
+ * published definitions it relies on.  Build with -ffp-contract=off so that
+ * every expression is evaluated exactly as written (no fused multiply-add).
+ * Readings where the paper is silent are marked "reading:".
+ */
+#include "sidm_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11).  Each round multiplies
+ * words 0 and 2 by the two Philox multipliers, and the new block is
+ * (hi(M1*c2) ^ c1 ^ k0, lo(M1*c2), hi(M0*c0) ^ c3 ^ k1, lo(M0*c0)).  Between
+ * rounds the key is advanced by the two Weyl constants (golden ratio and
+ * sqrt(3) - 1, scaled to 32 bits). */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    const uint32_t mult0 = 0xD2511F53u, mult1 = 0xCD9E8D57u;
+    const uint32_t weyl0 = 0x9E3779B9u, weyl1 = 0xBB67AE85u;
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += weyl0;
+            k1 += weyl1;
+        }
+        uint64_t p0 = (uint64_t)mult0 * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)mult1 * (uint64_t)c2;
+        uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        uint32_t n1 = (uint32_t)p1;
+        uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        uint32_t n3 = (uint32_t)p0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+double orc_u53(uint32_t hi, uint32_t lo)
+{
+    uint64_t bits = (((uint64_t)hi << 32) | (uint64_t)lo) >> 11;
+    return (double)bits * (1.0 / 9007199254740992.0); /* 2^-53 */
+}
+
+static void philox_pair(uint64_t seed, uint32_t step, uint32_t a, uint32_t b,
+                        uint32_t stream, uint32_t w[4])
+{
+    uint32_t ctr[4] = {a, b, step, stream};
+    uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+    orc_philox4x32_10(ctr, key, w);
+}
+
+double orc_accept_u(uint64_t seed, uint32_t step, uint32_t a, uint32_t b)
+{
+    uint32_t w[4];
+    philox_pair(seed, step, a, b, 0u, w);
+    return orc_u53(w[0], w[1]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Spline kernel (Monaghan 1985) in the compact-support-h form:
+ * W = 8/(pi h^3) (1 - 6q^2 + 6q^3) for q <= 1/2, 8/(pi h^3) 2(1-q)^3 for
+ * 1/2 < q <= 1, zero beyond; q = r/h.  Reading: h is the radius that holds the
+ * N_ngb neighbours, which is what the h/l relation of Sec. 3.5 implies. */
+double orc_kernel_W(double r, double h)
+{
+    double q = r / h;
+    double norm = 8.0 / (M_PI * h * h * h);
+    if (q <= 0.5) return norm * (1.0 - 6.0 * q * q + 6.0 * q * q * q);
+    if (q <= 1.0) {
+        double t = 1.0 - q;
+        return norm * 2.0 * t * t * t;
+    }
+    return 0.0;
+}
+
+/* Gauss-Legendre nodes and weights on [-1, 1] from their closed forms. */
+static void gauss_legendre5(double xk[5], double wk[5])
+{
+    double s = 2.0 * sqrt(10.0 / 7.0);
+    double x1 = sqrt(5.0 - s) / 3.0, x2 = sqrt(5.0 + s) / 3.0;
+    double w1 = (322.0 + 13.0 * sqrt(70.0)) / 900.0;
+    double w2 = (322.0 - 13.0 * sqrt(70.0)) / 900.0;
+    xk[0] = -x2; xk[1] = -x1; xk[2] = 0.0; xk[3] = x1; xk[4] = x2;
+    wk[0] = w2;  wk[1] = w1;  wk[2] = 128.0 / 225.0; wk[3] = w1; wk[4] = w2;
+}
+
+static void gauss_legendre3(double xk[3], double wk[3])
+{
+    double x = sqrt(3.0 / 5.0);
+    xk[0] = -x; xk[1] = 0.0; xk[2] = x;
+    wk[0] = 5.0 / 9.0; wk[1] = 8.0 / 9.0; wk[2] = 5.0 / 9.0;
+}
+
+/* integral of s W(s, h) over [s0, s0 + w]; 3-point Gauss-Legendre is exact
+ * because s W(s) is a polynomial of degree 4 on the segment (which must not
+ * straddle h/2 or h). */
+static double seg_sW(double s0, double w, double h)
+{
+    double xk[3], wk[3], sum = 0.0;
+    gauss_legendre3(xk, wk);
+    for (int k = 0; k < 3; ++k) {
+        double s = s0 + 0.5 * w * (1.0 + xk[k]);
+        sum += wk[k] * s * orc_kernel_W(s, h);
+    }
+    return 0.5 * w * sum;
+}
+
+/* G(r, d) = integral of s W(s, hj) ds over s in [|d - r|, min(d + r, hj)]:
+ * the part of the spherical shell of radius r about particle i that lies inside
+ * the support of particle j, reduced to one dimension (bipolar coordinates). */
+static double shell_overlap(double r, double d, double hj)
+{
+    double lo = fabs(d - r);
+    double up, width;
+    if (d + r <= hj) {
+        up = d + r;
+        width = 2.0 * (d < r ? d : r); /* (d + r) - |d - r| without cancellation */
+    } else {
+        up = hj;
+        width = hj - lo;
+    }
+    if (!(width > 0.0)) return 0.0;
+    double half = 0.5 * hj;
+    if (up <= half || lo >= half) return seg_sW(lo, width, hj);
+    return seg_sW(lo, half - lo, hj) + seg_sW(half, up - half, hj);
+}
+
+static int cmp_double(const void *pa, const void *pb)
+{
+    double a = *(const double *)pa, b = *(const double *)pb;
+    return (a > b) - (a < b);
+}
+
+/* Lambda(d; hi, hj) = integral of W(|x - xi|, hi) W(|x - xj|, hj) d^3x.
+ * With r = |x - xi| and s = |x - xj| the volume element of a shell of radius r
+ * about xi at distance s from xj is (2 pi r s / d) ds dr, so
+ *   Lambda = (2 pi / d) int_0^hi r W(r, hi) G(r, d) dr,
+ * and at d = 0 simply 4 pi int r^2 W(r, hi) W(r, hj) dr.  On each interval
+ * between the breakpoints {hi/2, d, |d -+ hj/2|, d + hj/2, |d - hj|, d + hj}
+ * the integrand is a polynomial of degree <= 9, so 5-point Gauss-Legendre per
+ * interval is exact up to rounding.  Reading: the paper cites the geometric
+ * factor of its SIDM scheme without printing it; it is taken here as the
+ * overlap integral of the two particles' kernels. */
+double orc_lambda(double d, double hi, double hj)
+{
+    double xk[5], wk[5];
+    gauss_legendre5(xk, wk);
+    if (!(d < hi + hj)) return 0.0;
+    if (d == 0.0) {
+        double hmin = hi < hj ? hi : hj;
+        double bp[4] = {0.0, 0.5 * hi, 0.5 * hj, hmin};
+        qsort(bp, 4, sizeof(double), cmp_double);
+        double total = 0.0;
+        for (int p = 0; p < 3; ++p) {
+            double r0 = bp[p], r1 = bp[p + 1];
+            if (r1 > hmin) r1 = hmin;
+            if (!(r1 > r0)) continue;
+            double w = r1 - r0, sum = 0.0;
+            for (int k = 0; k < 5; ++k) {
+                double r = r0 + 0.5 * w * (1.0 + xk[k]);
+                sum += wk[k] * r * r * orc_kernel_W(r, hi) * orc_kernel_W(r, hj);
+            }
+            total += 0.5 * w * sum;
+        }
+        return 4.0 * M_PI * total;
+    }
+    double cand[8] = {0.5 * hi, d, fabs(d - 0.5 * hj), d + 0.5 * hj,
+                      fabs(d - hj), d + hj, 0.0, hi};
+    double bp[8];
+    int nb = 0;
+    bp[nb++] = 0.0;
+    bp[nb++] = hi;
+    for (int c = 0; c < 6; ++c)
+        if (cand[c] > 0.0 && cand[c] < hi) bp[nb++] = cand[c];
+    qsort(bp, (size_t)nb, sizeof(double), cmp_double);
+    double total = 0.0;
+    for (int p = 0; p + 1 < nb; ++p) {
+        double r0 = bp[p], r1 = bp[p + 1];
+        if (!(r1 > r0)) continue;
+        double w = r1 - r0, sum = 0.0;
+        for (int k = 0; k < 5; ++k) {
+            double r = r0 + 0.5 * w * (1.0 + xk[k]);
+            sum += wk[k] * r * orc_kernel_W(r, hi) * shell_overlap(r, d, hj);
+        }
+        total += 0.5 * w * sum;
+    }
+    return 2.0 * M_PI / d * total;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Neumaier's compensated summation. */
+typedef struct { double s, c; } neum;
+
+static void neum_add(neum *acc, double v)
+{
+    double t = acc->s + v;
+    if (fabs(acc->s) >= fabs(v)) acc->c += (acc->s - t) + v;
+    else acc->c += (v - t) + acc->s;
+    acc->s = t;
+}
+
+static double neum_get(const neum *acc) { return acc->s + acc->c; }
+
+/* Softened self-gravity (Sec. 2: softening length eps; reading: Plummer form,
+ * self term excluded from both a and phi). */
+void orc_gravity(int64_t n, const double *x, const double *y, const double *z,
+                 const double *m, double G, double eps,
+                 int64_t nq, const int64_t *q,
+                 double *ax, double *ay, double *az, double *pot, double *anorm)
+{
+    if (q == NULL) nq = n;
+    double eps2 = eps * eps;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < nq; ++k) {
+        int64_t i = q ? q[k] : k;
+        neum sx = {0, 0}, sy = {0, 0}, sz = {0, 0}, sp = {0, 0}, sa = {0, 0};
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double dx = x[j] - x[i], dy = y[j] - y[i], dz = z[j] - z[i];
+            double d2 = dx * dx + dy * dy + dz * dz;
+            double r2 = d2 + eps2;
+            double rinv = 1.0 / sqrt(r2);
+            double rinv3 = rinv * rinv * rinv;
+            double w = m[j] * rinv3;
+            neum_add(&sx, w * dx);
+            neum_add(&sy, w * dy);
+            neum_add(&sz, w * dz);
+            neum_add(&sp, -m[j] * rinv);
+            if (anorm) neum_add(&sa, w * sqrt(d2));
+        }
+        ax[k] = G * neum_get(&sx);
+        ay[k] = G * neum_get(&sy);
+        az[k] = G * neum_get(&sz);
+        pot[k] = G * neum_get(&sp);
+        if (anorm) anorm[k] = G * neum_get(&sa);
+    }
+}
+
+/* NFW host (Sec. 4.1, Eq. nfw_potential).  With s = r/r_s and
+ * K = 4 pi G rho_s r_s^3:  Phi = -K ln(1+s)/r, and the enclosed mass gives
+ * a = -K [ln(1+s) - s/(1+s)] (x - c)/r^3.  For s < 1e-4 the bracket uses its
+ * series s^2/2 - 2s^3/3 + 3s^4/4 - 4s^5/5 to avoid cancellation. */
+void orc_host_nfw(int64_t n, const double *x, const double *y, const double *z,
+                  double G, double rho_s, double r_s, const double c[3],
+                  double *ax, double *ay, double *az, double *pot)
+{
+    double K = 4.0 * M_PI * G * rho_s * r_s * r_s * r_s;
+    for (int64_t i = 0; i < n; ++i) {
+        double dx = x[i] - c[0], dy = y[i] - c[1], dz = z[i] - c[2];
+        double r = sqrt(dx * dx + dy * dy + dz * dz);
+        if (r == 0.0) {
+            ax[i] = ay[i] = az[i] = 0.0;
+            pot[i] = -K / r_s;
+            continue;
+        }
+        double s = r / r_s;
+        double mu;
+        if (s < 1e-4) mu = s * s * (0.5 - s * (2.0 / 3.0 - s * (0.75 - s * 0.8)));
+        else mu = log1p(s) - s / (1.0 + s);
+        double f = -K * mu / (r * r * r);
+        ax[i] = f * dx;
+        ay[i] = f * dy;
+        az[i] = f * dz;
+        pot[i] = -K * log1p(s) / r;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* k nearest neighbours by brute force (Sec. 2: kernel size set by the next
+ * N_ngb neighbours).  Reading: h_i is the exact distance of the k-th nearest
+ * other particle, ties broken by id. */
+static int key_less(double d2a, uint32_t ida, double d2b, uint32_t idb)
+{
+    return d2a < d2b || (d2a == d2b && ida < idb);
+}
+
+void orc_knn(int64_t n, const double *x, const double *y, const double *z,
+             const uint32_t *id, int32_t k, int64_t nq, const int64_t *q,
+             double *h, uint32_t *nbr)
+{
+    if (q == NULL) nq = n;
+#pragma omp parallel
+    {
+        double *bd = (double *)malloc(sizeof(double) * (size_t)k);
+        uint32_t *bi = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)k);
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t t = 0; t < nq; ++t) {
+            int64_t i = q ? q[t] : t;
+            int32_t cnt = 0;
+            for (int64_t j = 0; j < n; ++j) {
+                if (j == i) continue;
+                double dx = x[j] - x[i], dy = y[j] - y[i], dz = z[j] - z[i];
+                double d2 = (dx * dx + dy * dy) + dz * dz;
+                if (cnt == k && !key_less(d2, id[j], bd[k - 1], bi[k - 1])) continue;
+                /* insertion into the sorted list of the best k */
+                int32_t pos = cnt < k ? cnt : k - 1;
+                while (pos > 0 && key_less(d2, id[j], bd[pos - 1], bi[pos - 1])) {
+                    bd[pos] = bd[pos - 1];
+                    bi[pos] = bi[pos - 1];
+                    --pos;
+                }
+                bd[pos] = d2;
+                bi[pos] = id[j];
+                if (cnt < k) ++cnt;
+            }
+            h[t] = sqrt(bd[k - 1]);
+            if (nbr) memcpy(nbr + (size_t)t * (size_t)k, bi, sizeof(uint32_t) * (size_t)k);
+        }
+        free(bd);
+        free(bi);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Scattering decisions (Sec. 2: pairwise interactions through the spline
+ * kernel; Sec. 3.5: the geometric factor Lambda).  Readings: every unordered
+ * pair whose supports overlap is tested once; the probability uses the
+ * velocities at the start of the pass, so the event set does not depend on the
+ * order of evaluation. */
+static int cmp_event(const void *pa, const void *pb)
+{
+    const orc_event *a = (const orc_event *)pa, *b = (const orc_event *)pb;
+    if (a->a != b->a) return a->a < b->a ? -1 : 1;
+    if (a->b != b->b) return a->b < b->b ? -1 : 1;
+    return 0;
+}
+
+int64_t orc_find_events(int64_t n, const double *x, const double *y, const double *z,
+                        const double *vx, const double *vy, const double *vz,
+                        const double *m, const uint32_t *id, const double *h,
+                        double sigma_m, double dt, uint64_t seed, uint32_t step,
+                        const uint8_t *qmask, orc_event *ev, int64_t cap,
+                        int64_t *n_pairs, int64_t *n_p_gt1)
+{
+    int64_t found = 0, pairs = 0, pgt1 = 0;
+    int64_t stored = 0;
+    orc_event *all = NULL;
+    int64_t all_cap = 0;
+#pragma omp parallel
+    {
+        int64_t my_pairs = 0, my_pgt1 = 0, my_n = 0, my_cap = 64;
+        orc_event *mine = (orc_event *)malloc(sizeof(orc_event) * (size_t)my_cap);
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t i = 0; i < n; ++i) {
+            if (qmask && !qmask[i]) continue;
+            for (int64_t j = 0; j < n; ++j) {
+                if (j == i) continue;
+                if (qmask) {
+                    if (qmask[j] && j < i) continue; /* pair already seen from j */
+                } else if (j < i) {
+                    continue;
+                }
+                double dx = x[j] - x[i], dy = y[j] - y[i], dz = z[j] - z[i];
+                double d2 = (dx * dx + dy * dy) + dz * dz;
+                double hs = h[i] + h[j];
+                if (!(d2 < hs * hs)) continue;
+                ++my_pairs;
+                int64_t ia = id[i] < id[j] ? i : j;
+                int64_t ib = id[i] < id[j] ? j : i;
+                uint32_t a = id[ia], b = id[ib];
+                double u = orc_accept_u(seed, step, a, b);
+                double gx = vx[ia] - vx[ib], gy = vy[ia] - vy[ib], gz = vz[ia] - vz[ib];
+                double g = sqrt((gx * gx + gy * gy) + gz * gz);
+                double lam = orc_lambda(sqrt(d2), h[ia], h[ib]);
+                double P = sigma_m * m[ib] * g * lam * dt;
+                if (P > 1.0) ++my_pgt1;
+                if (u < P) {
+                    if (my_n == my_cap) {
+                        my_cap *= 2;
+                        mine = (orc_event *)realloc(mine, sizeof(orc_event) * (size_t)my_cap);
+                    }
+                    orc_event e = {a, b, ia, ib, u, P};
+                    mine[my_n++] = e;
+                }
+            }
+        }
+#pragma omp critical
+        {
+            if (found + my_n > all_cap) {
+                all_cap = 2 * (found + my_n) + 64;
+                all = (orc_event *)realloc(all, sizeof(orc_event) * (size_t)all_cap);
+            }
+            memcpy(all + found, mine, sizeof(orc_event) * (size_t)my_n);
+            found += my_n;
+            pairs += my_pairs;
+            pgt1 += my_pgt1;
+        }
+        free(mine);
+    }
+    if (found > 0) qsort(all, (size_t)found, sizeof(orc_event), cmp_event);
+    stored = found < cap ? found : cap;
+    if (stored > 0 && ev) memcpy(ev, all, sizeof(orc_event) * (size_t)stored);
+    free(all);
+    if (n_pairs) *n_pairs = pairs;
+    if (n_p_gt1) *n_p_gt1 = pgt1;
+    return found;
+}
+
+/* Elastic isotropic scattering in the pair's centre-of-mass frame (Sec. 2:
+ * explicit conservation of energy and linear momentum).  The relative speed g
+ * is kept, the direction of the relative velocity is redrawn uniformly on the
+ * sphere: cos(theta) = 1 - 2 u_c, phi = 2 pi u_phi, from the direction draw at
+ * counter (a, b, step, 1). */
+void orc_kick_pair(uint64_t seed, uint32_t step, uint32_t a, uint32_t b,
+                   double ma, double mb, double va[3], double vb[3])
+{
+    uint32_t w[4];
+    philox_pair(seed, step, a, b, 1u, w);
+    double uc = orc_u53(w[0], w[1]);
+    double uphi = orc_u53(w[2], w[3]);
+    double M = ma + mb;
+    double dvx = va[0] - vb[0], dvy = va[1] - vb[1], dvz = va[2] - vb[2];
+    double g = sqrt((dvx * dvx + dvy * dvy) + dvz * dvz);
+    double cth = 1.0 - 2.0 * uc;
+    double s2 = 1.0 - cth * cth;
+    double sth = sqrt(s2 > 0.0 ? s2 : 0.0);
+    double ph = 2.0 * M_PI * uphi;
+    double nvec[3] = {sth * cos(ph), sth * sin(ph), cth};
+    double fa = mb / M * g, fb = ma / M * g;
+    for (int c = 0; c < 3; ++c) {
+        double vcm = (ma * va[c] + mb * vb[c]) / M;
+        va[c] = vcm + fa * nvec[c];
+        vb[c] = vcm - fb * nvec[c];
+    }
+}
+
+void orc_apply_events(int64_t n_ev, const orc_event *ev, const double *m,
+                      double *vx, double *vy, double *vz, uint64_t seed, uint32_t step)
+{
+    for (int64_t e = 0; e < n_ev; ++e) {
+        int64_t ia = ev[e].ia, ib = ev[e].ib;
+        double va[3] = {vx[ia], vy[ia], vz[ia]};
+        double vb[3] = {vx[ib], vy[ib], vz[ib]};
+        orc_kick_pair(seed, step, ev[e].a, ev[e].b, m[ia], m[ib], va, vb);
+        vx[ia] = va[0]; vy[ia] = va[1]; vz[ia] = va[2];
+        vx[ib] = vb[0]; vy[ib] = vb[1]; vz[ib] = vb[2];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+void orc_diag(int64_t n, const double *vx, const double *vy, const double *vz,
+              const double *m, const double *pot, const double *pext, double out[6])
+{
+    neum K = {0, 0}, W = {0, 0}, E = {0, 0}, px = {0, 0}, py = {0, 0}, pz = {0, 0};
+    for (int64_t i = 0; i < n; ++i) {
+        double v2 = (vx[i] * vx[i] + vy[i] * vy[i]) + vz[i] * vz[i];
+        double pe = pext ? pext[i] : 0.0;
+        neum_add(&K, 0.5 * m[i] * v2);
+        neum_add(&W, 0.5 * m[i] * (pot[i] - pe));
+        neum_add(&E, m[i] * pe);
+        neum_add(&px, m[i] * vx[i]);
+        neum_add(&py, m[i] * vy[i]);
+        neum_add(&pz, m[i] * vz[i]);
+    }
+    out[0] = neum_get(&K);
+    out[1] = neum_get(&W);
+    out[2] = neum_get(&E);
+    out[3] = neum_get(&px);
+    out[4] = neum_get(&py);
+    out[5] = neum_get(&pz);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Total acceleration and potential at the current positions: self-gravity plus
+ * the static host. */
+static void accel_total(int64_t n, const double *x, const double *y, const double *z,
+                        const double *m, const orc_params *p,
+                        double *ax, double *ay, double *az, double *pot)
+{
+    orc_gravity(n, x, y, z, m, p->G, p->eps, n, NULL, ax, ay, az, pot, NULL);
+    if (p->host_kind == 1) {
+        double *hx = (double *)malloc(sizeof(double) * (size_t)n * 4);
+        double *hy = hx + n, *hz = hy + n, *hp = hz + n;
+        orc_host_nfw(n, x, y, z, p->G, p->host_rho_s, p->host_r_s, p->host_c, hx, hy, hz, hp);
+        for (int64_t i = 0; i < n; ++i) {
+            ax[i] += hx[i];
+            ay[i] += hy[i];
+            az[i] += hz[i];
+            pot[i] += hp[i];
+        }
+        free(hx);
+    }
+}
+
+/* One step: K(dt/2) D(dt) [forces] K(dt/2), then the SIDM pass at the
+ * synchronised point (reading: the paper does not state where scattering sits
+ * inside the step; placing it after the closing kick keeps x fixed during the
+ * pass, so the pass conserves energy exactly and sigma = 0 is plain KDK). */
+int64_t orc_kdk_step(int64_t n, double *x, double *y, double *z,
+                     double *vx, double *vy, double *vz, const double *m,
+                     const uint32_t *id, double *ax, double *ay, double *az,
+                     double *pot, double *h, const orc_params *p, uint32_t step,
+                     orc_event *ev, int64_t ev_cap)
+{
+    double hdt = 0.5 * p->dt;
+    for (int64_t i = 0; i < n; ++i) {
+        vx[i] += ax[i] * hdt;
+        vy[i] += ay[i] * hdt;
+        vz[i] += az[i] * hdt;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        x[i] += vx[i] * p->dt;
+        y[i] += vy[i] * p->dt;
+        z[i] += vz[i] * p->dt;
+    }
+    accel_total(n, x, y, z, m, p, ax, ay, az, pot);
+    for (int64_t i = 0; i < n; ++i) {
+        vx[i] += ax[i] * hdt;
+        vy[i] += ay[i] * hdt;
+        vz[i] += az[i] * hdt;
+    }
+    orc_knn(n, x, y, z, id, p->k, n, NULL, h, NULL);
+    if (p->sigma_m == 0.0) return 0;
+    int64_t cap = ev_cap > 0 ? ev_cap : 0;
+    orc_event *buf = ev;
+    int64_t found = orc_find_events(n, x, y, z, vx, vy, vz, m, id, h, p->sigma_m, p->dt,
+                                    p->seed, step, NULL, buf, cap, NULL, NULL);
+    if (found > cap) {
+        /* not enough room to hold the ordered list: collect it privately */
+        buf = (orc_event *)malloc(sizeof(orc_event) * (size_t)found);
+        orc_find_events(n, x, y, z, vx, vy, vz, m, id, h, p->sigma_m, p->dt,
+                        p->seed, step, NULL, buf, found, NULL, NULL);
+    }
+    orc_apply_events(found, buf, m, vx, vy, vz, p->seed, step);
+    if (buf != ev) {
+        free(buf);
+        return -1;
+    }
+    return found;
+}

@@ -1,0 +1,144 @@
+/*
+ * sidm_oracle.h -- plain, slow, FP64 CPU reference for the SIDM N-body step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing on the product path links, loads or calls
+ * this library: it exists so that tests, the smoke check and the CPU baseline
+ * leg of the benchmark can compare the GPU library against a reading of the
+ * paper (Fischer, Yu & Dolag, "Accurately simulating core-collapse
+ * self-interacting dark matter halos") that a reader can check by eye.  It
+ * shares no code, header, table or constant with the HIP library.
+ *
+ * Every array is host memory, halo-local (indices 0..n-1), structure of arrays,
+ * double precision unless stated.  Particle identities `id` are unsigned 32-bit
+ * and unique within a halo.
+ */
+#ifndef SIDM_ORACLE_H
+#define SIDM_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- counter-based random numbers (Philox4x32-10, Salmon et al. 2011) ---- */
+
+/* One Philox4x32-10 block: 10 rounds of the 4x32 bijection keyed by `key`,
+ * with the Weyl key schedule between rounds. */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* Uniform double in [0,1) from two 32-bit words: the top 53 bits of (hi:lo). */
+double orc_u53(uint32_t hi, uint32_t lo);
+
+/* The accept draw u for pair (a, b) with a < b at step `step`:
+ * counter (a, b, step, 0), key (lo32(seed), hi32(seed)), u = u53(w0, w1). */
+double orc_accept_u(uint64_t seed, uint32_t step, uint32_t a, uint32_t b);
+
+/* ---- SIDM kernel and overlap (paper Sec. 2: spline kernel of Monaghan 1985;
+ *      Sec. 3.5: geometric factor Lambda of the interaction probability) ---- */
+
+/* Cubic spline with compact support h (Gadget convention), normalised to 1. */
+double orc_kernel_W(double r, double h);
+
+/* Kernel overlap Lambda(d; hi, hj) = integral of W(|x - xi|, hi) W(|x - xj|, hj) d^3x
+ * for two particles at distance d. */
+double orc_lambda(double d, double hi, double hj);
+
+/* ---- gravity (paper Sec. 2: softened self-gravity, softening length eps) ---- */
+
+/* Plummer-softened direct sum, self term excluded, j ascending, Neumaier
+ * compensated.  For the `nq` particles listed in `q` (or all n when q == NULL,
+ * in which case nq is ignored) writes
+ *   a_i   =  G sum_{j != i} m_j (x_j - x_i) / (r_ij^2 + eps^2)^{3/2}
+ *   phi_i = -G sum_{j != i} m_j / (r_ij^2 + eps^2)^{1/2}
+ * into ax/ay/az/pot at position k of the query list (or i).  Also writes the
+ * normwise scale A_i = G sum_j m_j r_ij / (r^2+eps^2)^{3/2} into `anorm`
+ * (nullable).  Uses OpenMP over the query particles. */
+void orc_gravity(int64_t n, const double *x, const double *y, const double *z,
+                 const double *m, double G, double eps,
+                 int64_t nq, const int64_t *q,
+                 double *ax, double *ay, double *az, double *pot, double *anorm);
+
+/* Static NFW host (paper Sec. 4.1, Eq. nfw_potential) centred at c:
+ * Phi(r) = -4 pi G rho_s r_s^3 ln(1 + r/r_s) / r and a = -grad Phi.
+ * Writes (not adds) the host acceleration and potential for n particles. */
+void orc_host_nfw(int64_t n, const double *x, const double *y, const double *z,
+                  double G, double rho_s, double r_s, const double c[3],
+                  double *ax, double *ay, double *az, double *pot);
+
+/* ---- kernel size from the N_ngb nearest neighbours (paper Sec. 2) ---- */
+
+/* Brute force: for each queried i, order j != i by (d2_ij, id_j) with
+ * d2 = (dx*dx + dy*dy) + dz*dz, dx = x_j - x_i; h_i = sqrt of the k-th d2.
+ * Writes h for the query list; nbr (nullable) receives the k ids in order,
+ * row-major [nq][k]. */
+void orc_knn(int64_t n, const double *x, const double *y, const double *z,
+             const uint32_t *id, int32_t k, int64_t nq, const int64_t *q,
+             double *h, uint32_t *nbr);
+
+/* ---- pairwise scattering (paper Sec. 2 and Sec. 3.5) ---- */
+
+typedef struct {
+    uint32_t a, b;     /* ids, a < b                                 */
+    int64_t ia, ib;    /* halo-local indices of the particles a, b  */
+    double u, P;       /* accept draw and probability                */
+} orc_event;
+
+/* Tests every unordered pair {i, j} with d2_ij < (h_i + h_j)^2 once, with
+ * a = min id, b = max id, P_ab = (sigma/m) m_b |v_a - v_b| Lambda_ab dt and the
+ * accept draw u of orc_accept_u; an event is u < P.  When `q` is non-NULL only
+ * pairs with at least one endpoint in the query set (flag array `qmask` of
+ * length n) are tested.  Writes up to `cap` events in (a, b) order and returns
+ * the number found.  n_pairs / n_p_gt1 (nullable) receive the pair count and
+ * the number of pairs with P > 1. */
+int64_t orc_find_events(int64_t n, const double *x, const double *y, const double *z,
+                        const double *vx, const double *vy, const double *vz,
+                        const double *m, const uint32_t *id, const double *h,
+                        double sigma_m, double dt, uint64_t seed, uint32_t step,
+                        const uint8_t *qmask, orc_event *ev, int64_t cap,
+                        int64_t *n_pairs, int64_t *n_p_gt1);
+
+/* Elastic isotropic scattering of one pair in its centre-of-mass frame, using
+ * the direction draw at counter (a, b, step, 1).  Updates the two velocities. */
+void orc_kick_pair(uint64_t seed, uint32_t step, uint32_t a, uint32_t b,
+                   double ma, double mb, double va[3], double vb[3]);
+
+/* Applies events (already in (a, b) order) one after the other. */
+void orc_apply_events(int64_t n_ev, const orc_event *ev, const double *m,
+                      double *vx, double *vy, double *vz, uint64_t seed, uint32_t step);
+
+/* ---- diagnostics ---- */
+
+/* K = 1/2 sum m v^2, W = 1/2 sum m phi_self, Eext = sum m Phi_ext, p = sum m v.
+ * pot holds phi_self + Phi_ext and pext holds Phi_ext (nullable: zero). */
+void orc_diag(int64_t n, const double *vx, const double *vy, const double *vz,
+              const double *m, const double *pot, const double *pext, double out[6]);
+
+/* ---- one kick-drift-kick step with SIDM at the synchronised point ---- */
+
+typedef struct {
+    double G, eps, sigma_m, dt;
+    int32_t k;
+    uint64_t seed;
+    int32_t host_kind;          /* 0 none, 1 NFW                             */
+    double host_rho_s, host_r_s, host_c[3];
+} orc_params;
+
+/* Full-N brute-force step for one halo.  On entry a/pot hold the acceleration
+ * and potential at x (self + host).  Performs K(dt/2), D(dt), gravity + host,
+ * K(dt/2), h from kNN, events, ordered kicks.  Writes h; returns the number of
+ * events (or -1 if more than `ev_cap` events were found; ev may be NULL when
+ * ev_cap is 0).  `ev` receives the applied events in (a, b) order. */
+int64_t orc_kdk_step(int64_t n, double *x, double *y, double *z,
+                     double *vx, double *vy, double *vz, const double *m,
+                     const uint32_t *id, double *ax, double *ay, double *az,
+                     double *pot, double *h, const orc_params *p, uint32_t step,
+                     orc_event *ev, int64_t ev_cap);
+
+/* Number of OpenMP threads the oracle uses. */
+int orc_num_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
