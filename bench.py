@@ -1,0 +1,208 @@
+#!/usr/bin/env python3
+"""Benchmark of the SIDM N-body step on one MI355X.
+
+Workload: the N = 2^20 NFW halo (r_s = rho_s = G = 1, truncated at 10 r_s,
+Eddington velocities) on a circular orbit at 20 host scale radii in a static
+NFW host, Plummer softening 0.01, k = 64 neighbours, sigma/m = 10, dt = 1e-3,
+mixed precision (FP32 gravity tiles with compensated accumulation, FP64
+everything else).  A step is one full kick-drift-kick step with the kNN kernel
+sizes and the scattering pass.  Inputs are synthetic and resident in HBM.
+
+Prints one JSON line: gravity interactions per second of whole steps (value),
+SIDM particle updates per second, |dE/E| over the run, the same for the
+all-FP64 form, per-pass times from HIP events, the roofline of the dominant
+kernel (the gravity tiles) and the CPU oracle on a bounded sample.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP32_PEAK_TFLOPS = 157.3      # MI355X vector FP32 (datasheet)
+FP64_PEAK_TFLOPS = 78.6       # MI355X vector FP64 (datasheet)
+FLOPS_PER_INTERACTION = 20    # 3 sub, 3 fma (r^2+eps^2), rsqrt, 4 mul/add, 3 fma
+
+
+def _args():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--fp64-steps", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def _energy(d):
+    return d["K"] + d["W"] + d["Eext"]
+
+
+def _run(S, torch, cfg, s, prec, steps, warmup, timing):
+    n = cfg["n"]
+    halo = dict(n=n, eps=cfg["eps"], G=1.0, sigma_m=cfg["sigma_m"], dt=cfg["dt"], k=cfg["k"],
+                seed=cfg["seed"], host=cfg["host"])
+    dev = S.state_to_device(s)
+    ctx = S.sidm_create(0, n, 1)
+    diag = S.diag_buffer(1)
+    S.sidm_gravity(ctx, [halo], dev, prec)
+    S.sidm_diagnostics(ctx, [halo], dev, diag)
+    e0 = _energy(S.read_diag(diag)[0])
+    step = 0
+    for _ in range(warmup):
+        S.sidm_kdk_step(ctx, [halo], dev, step, prec, diag=diag)
+        step += 1
+    if timing:
+        S.sidm_enable_timing(ctx, True)
+    passes = {}
+    events = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        S.sidm_kdk_step(ctx, [halo], dev, step, prec, diag=diag)
+        step += 1
+        if timing:
+            for k, v in S.sidm_pass_times(ctx).items():
+                passes[k] = passes.get(k, 0.0) + v
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    d = S.read_diag(diag)[0]
+    events = d["n_events"]
+    rel_e = abs(_energy(d) - e0) / abs(e0)
+    for k in passes:
+        passes[k] /= steps
+    S.sidm_destroy(ctx)
+    return (t1 - t0) / steps, rel_e, passes, d, events
+
+
+def _cpu_baseline(cfg, s, budget_s):
+    """The oracle as it stands, on a bounded sample of the same workload: the
+    full per-particle work (gravity against all N, brute-force kNN, pair tests
+    with probabilities) for a random subset of particles, extrapolated to N."""
+    import numpy as np
+    from oracle import oracle as O
+    n = cfg["n"]
+    rng = np.random.default_rng(0)
+
+    def per_particle_seconds(m):
+        q = np.sort(rng.choice(n, m, replace=False))
+        t = time.perf_counter()
+        O.gravity(s["x"], s["y"], s["z"], s["m"], 1.0, cfg["eps"], query=q)
+        tg = time.perf_counter() - t
+        t = time.perf_counter()
+        h = O.knn(s["x"], s["y"], s["z"], s["id"], cfg["k"], query=q)
+        tk = time.perf_counter() - t
+        hh = np.full(n, float(np.median(h)))
+        hh[q] = h
+        qm = np.zeros(n, np.uint8)
+        qm[q] = 1
+        t = time.perf_counter()
+        O.find_events(s["x"], s["y"], s["z"], s["vx"], s["vy"], s["vz"], s["m"], s["id"], hh,
+                      cfg["sigma_m"], cfg["dt"], 0, 0, qmask=qm)
+        ts = time.perf_counter() - t
+        return (tg + tk + ts) / m, (tg, tk, ts)
+
+    probe, _ = per_particle_seconds(16)
+    m = int(max(16, min(4096, budget_s / max(probe, 1e-9))))
+    per, parts = per_particle_seconds(m)
+    step_s = per * n
+    return {
+        "value": n * (n - 1) / step_s,
+        "unit": "gravity interactions/s",
+        "cores": O.num_threads(),
+        "kind": "oracle",
+        "sample": (f"{m} random particles of the N=2^20 halo: gravity against all N, brute-force "
+                   f"kNN and pair tests with probabilities ({parts[0]:.1f} s, {parts[1]:.1f} s, "
+                   f"{parts[2]:.1f} s), extrapolated to a full step of N particles"),
+        "step_seconds_extrapolated": step_s,
+    }
+
+
+def _traffic(per_launch_flops):
+    """HBM bytes per launch of the gravity tiles from committed rocprofv3
+    counter runs, if taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic_grav_mixed_c2.json")
+    src = os.path.join(ROOT, "paper_2506_06269_amd", "csrc", "k_gravity.hip")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+        with open(src, "rb") as f:
+            h = hashlib.sha256(f.read()).hexdigest()
+        if rec.get("kernel_source_sha256") != h:
+            return None
+        return rec.get("bytes_per_launch")
+    except (OSError, ValueError):
+        return None
+
+
+def main():
+    a = _args()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for "
+              f"--gpus {a.gpus}); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2506_06269_amd as S
+    import workloads as W
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+
+    cfg = W.config("C2")
+    n = cfg["n"]
+    s = W.make_state(cfg)
+    inter = n * (n - 1)
+
+    ms_mixed, de_mixed, passes, dlast, events = _run(S, torch, cfg, s, S.SIDM_PREC_MIXED,
+                                                     a.steps, a.warmup, True)
+    fp64 = None
+    if a.fp64_steps > 0:
+        ms64, de64, p64, _, _ = _run(S, torch, cfg, s, S.SIDM_PREC_FP64, a.fp64_steps, 1, True)
+        fp64 = {"interactions_per_s": inter / ms64, "ms_per_step": ms64 * 1e3, "dE_over_E": de64,
+                "gravity_tiles_ms": p64.get("gravity_tiles"),
+                "gravity_tiles_frac_fp64_peak":
+                    FLOPS_PER_INTERACTION * inter / (p64["gravity_tiles"] * 1e-3) / 1e12
+                    / FP64_PEAK_TFLOPS if p64.get("gravity_tiles") else None}
+
+    tiles_s = passes["gravity_tiles"] * 1e-3
+    achieved = FLOPS_PER_INTERACTION * inter / tiles_s / 1e12
+    roof = {"bound": "alu", "kernel": "k_grav_mixed<4>", "achieved": achieved,
+            "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
+            "traffic": _traffic(FLOPS_PER_INTERACTION * inter)}
+
+    out = {
+        "metric": "gravity interactions/s + SIDM particle-updates/s, mixed vs FP64 at |dE/E|",
+        "value": inter / ms_mixed,
+        "unit": "gravity interactions/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_mixed * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 gravity tiles (compensated), f64 elsewhere",
+        "data": "synthetic NFW halo (Eddington ICs), resident in HBM",
+        "config": {"workload": "NFW N=2^20 satellite on a circular orbit in a static NFW host, "
+                               "eps=0.01, k=64, sigma/m=10, dt=1e-3, mixed precision",
+                   "n": n, "k": cfg["k"], "sigma_m": cfg["sigma_m"], "dt": cfg["dt"],
+                   "eps": cfg["eps"], "parallelism": "single GPU"},
+        "sidm_particle_updates_per_s": n / ms_mixed,
+        "dE_over_E": de_mixed,
+        "events_last_step": events,
+        "pass_ms": passes,
+        "fp64": fp64,
+        "roofline": roof,
+        "cpu_baseline": None,
+    }
+    if not a.no_cpu:
+        out["cpu_baseline"] = _cpu_baseline(cfg, s, a.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

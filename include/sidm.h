@@ -1,0 +1,221 @@
+/*
+ * sidm.h -- C ABI of libsidm, an MI355X (gfx950) implementation of the
+ * data-parallel hot path of a self-interacting dark matter (SIDM) N-body step
+ * as studied by Fischer, Yu & Dolag (arXiv 2506.06269):
+ *
+ *   - softened self-gravity for every particle plus a static analytic NFW host
+ *     (Sec. 2 "softening length"; Sec. 4.1 Eq. nfw_potential),
+ *   - the SIDM kernel size h_i from the N_ngb nearest neighbours (Sec. 2),
+ *   - rare pairwise scattering through the spline-kernel overlap Lambda_ij
+ *     (Sec. 2; Sec. 3.5 geometric factor), with explicit energy and momentum
+ *     conservation (Sec. 2),
+ *   - all inside a fixed-step kick-drift-kick leapfrog (Sec. 3.1: constant
+ *     time steps remove the integrator's energy error).
+ *
+ * Conventions shared by every entry point
+ *   - Every particle array is DEVICE memory owned by the caller, structure of
+ *     arrays, length n_total (the largest offset + n over the halos passed).
+ *     The library owns only the scratch memory inside its context.
+ *   - Work is enqueued on `stream` (a hipStream_t passed as void*, NULL = the
+ *     null stream) and the call returns without waiting, unless a host
+ *     out-parameter is requested (documented per call).
+ *   - Argument errors are detected on the host before anything is enqueued and
+ *     return SIDM_ERR_INVALID (or SIDM_ERR_UNSUPPORTED) with a message in
+ *     sidm_last_error().  HIP launch errors return SIDM_ERR_HIP.  Conditions the
+ *     device detects (event buffer overflow, kNN search overflow, non-finite
+ *     state) are reported in sidm_diag.status and, for synchronous calls, as
+ *     SIDM_ERR_CAPACITY.
+ *   - Halos are independent systems: particles of different halos neither
+ *     attract nor scatter.  Halo ranges must not overlap.
+ *   - A context is thread-compatible (one thread at a time), not thread-safe.
+ *     Calls on one context must be issued to one stream or be ordered by the
+ *     caller: they share the context's scratch memory.
+ *   - Units are whatever the caller uses consistently (the tests use
+ *     G = r_s = rho_s = 1).
+ */
+#ifndef SIDM_H
+#define SIDM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SIDM_ABI_VERSION 1
+#define SIDM_MAX_K 128          /* largest supported neighbour number N_ngb */
+
+typedef struct sidm_ctx sidm_ctx;
+
+typedef enum {
+    SIDM_OK = 0,
+    SIDM_ERR_INVALID = -1,      /* bad argument, see sidm_last_error()              */
+    SIDM_ERR_NOMEM = -2,        /* device allocation failed                         */
+    SIDM_ERR_HIP = -3,          /* a HIP runtime call or launch failed              */
+    SIDM_ERR_CAPACITY = -4,     /* a device-side capacity was exceeded             */
+    SIDM_ERR_UNSUPPORTED = -5   /* valid request this version does not implement    */
+} sidm_status;
+
+typedef enum {
+    SIDM_PREC_FP64 = 0,         /* all arithmetic in FP64                           */
+    SIDM_PREC_MIXED = 1         /* gravity tiles in FP32 with compensated (Kahan)
+                                   accumulation; kicks, drift, SIDM and reductions
+                                   in FP64                                          */
+} sidm_precision;
+
+/* One halo (host memory; an array of these is a batch). */
+typedef struct {
+    int64_t offset;             /* particles [offset, offset + n) of the arrays    */
+    int64_t n;                  /* number of particles, 2 <= n <= 2^24             */
+    double G;                   /* gravitational constant                           */
+    double eps;                 /* Plummer softening length, > 0 (Sec. 2)           */
+    double sigma_m;             /* cross-section per unit mass, >= 0 (isotropic,
+                                   velocity independent: Sec. 2)                    */
+    double dt;                  /* fixed time step, > 0                             */
+    int32_t k;                  /* N_ngb, 1 <= k <= min(n - 1, SIDM_MAX_K)          */
+    int32_t host_kind;          /* 0: isolated; 1: static NFW host (Sec. 4.1)       */
+    uint64_t seed;              /* Philox key of the scattering draws               */
+    double host_rho_s;          /* host NFW density parameter                       */
+    double host_r_s;            /* host NFW scale radius, > 0 when host_kind == 1   */
+    double host_center[3];      /* host centre                                      */
+} sidm_halo;
+
+/* Particle state (device pointers, length n_total each). */
+typedef struct {
+    double *x, *y, *z;          /* positions (FP64: Sec. 2 stores them in double)  */
+    double *vx, *vy, *vz;       /* velocities                                       */
+    const double *m;            /* masses; equal within a halo when sigma_m > 0    */
+    const uint32_t *id;         /* identities, unique within a halo: they key the
+                                   random draws and fix the order of the kicks     */
+    double *ax, *ay, *az;       /* total acceleration (self + host) at x            */
+    double *pot;                /* total potential (self + host) at x               */
+    double *h;                  /* SIDM kernel size                                 */
+} sidm_state;
+
+/* One scattering event: ids a < b, the halo index in the call's halo array and
+ * the conflict-free round in which it was applied (1-based). */
+typedef struct {
+    uint32_t a, b;
+    int32_t halo;
+    uint32_t round;
+} sidm_event;
+
+/* Per-halo diagnostics after a step (device memory, one per halo). */
+typedef struct {
+    double K;                   /* 1/2 sum m v^2                                    */
+    double W;                   /* 1/2 sum m phi_self                               */
+    double Eext;                /* sum m Phi_host                                   */
+    double px, py, pz;          /* sum m v                                          */
+    int64_t n_events;           /* scatterings applied this step                    */
+    int64_t n_rounds;           /* conflict-free rounds used                        */
+    int64_t n_pairs;            /* pairs with overlapping kernels that were tested  */
+    int64_t n_p_gt1;            /* pairs with P > 1 (accepted with certainty)       */
+    int32_t status;             /* SIDM_DEV_* bits                                  */
+    int32_t reserved;
+} sidm_diag;
+
+#define SIDM_DEV_EVENT_OVERFLOW 1   /* more events than the context can hold: no
+                                       kicks were applied this step              */
+#define SIDM_DEV_KNN_OVERFLOW   2   /* a neighbour search needed more refinement
+                                       levels than supported (h is NaN there)   */
+#define SIDM_DEV_NONFINITE      4   /* a position or velocity is not finite     */
+
+/* ---- context ---------------------------------------------------------------
+ * Creates a context on HIP device `device` with scratch memory for up to
+ * `max_particles` particles in total and `max_halos` halos per call, and room
+ * for max(4096, max_particles / 8) scattering events per call.  Allocates
+ * device memory (SIDM_ERR_NOMEM on failure).  *out is NULL on error. */
+sidm_status sidm_create(sidm_ctx **out, int device, int64_t max_particles, int32_t max_halos);
+
+/* Sets the per-call event capacity (reallocates; call outside graph capture). */
+sidm_status sidm_set_event_capacity(sidm_ctx *ctx, int64_t max_events);
+
+/* Releases the context and its scratch memory (waits for the device). */
+void sidm_destroy(sidm_ctx *ctx);
+
+/* Static text for a status code. */
+const char *sidm_status_string(sidm_status s);
+
+/* Detail text of the last error on this context ("" if none).  The pointer is
+ * valid until the next call on the context. */
+const char *sidm_last_error(const sidm_ctx *ctx);
+
+/* ---- gravity -----------------------------------------------------------------
+ * a_i   = G sum_{j != i} m_j (x_j - x_i) / (|x_j - x_i|^2 + eps^2)^{3/2} + a_host(x_i)
+ * pot_i = -G sum_{j != i} m_j / (|x_j - x_i|^2 + eps^2)^{1/2} + Phi_host(x_i)
+ * over the particles of the same halo (Sec. 2: softened gravity, here in the
+ * Plummer form; Sec. 4.1 Eq. nfw_potential for the host, a = -grad Phi).
+ * Writes state->ax/ay/az/pot; reads x, y, z, m.  SIDM_PREC_MIXED evaluates the
+ * pair terms in FP32 on positions re-centred in FP64 on the halo's mean
+ * position, accumulated with compensation, and returns FP64. */
+sidm_status sidm_gravity(sidm_ctx *ctx, const sidm_halo *halos, int32_t n_halos,
+                         const sidm_state *state, sidm_precision prec, void *stream);
+
+/* ---- kernel size -----------------------------------------------------------
+ * h_i = distance to the k-th nearest other particle of the same halo (Sec. 2:
+ * the kernel size is set by the next N_ngb neighbours), with distances
+ * d2 = (dx*dx + dy*dy) + dz*dz evaluated in FP64 without fused multiply-add,
+ * ties ordered by id, h = correctly rounded sqrt(d2).  Writes state->h.
+ * nbr (nullable, device) receives the k neighbour ids of each particle in
+ * (d2, id) order, row-major [n_total][k_max] where k_max is the largest k
+ * of the halos (rows of halos with smaller k are filled up to their k). */
+sidm_status sidm_knn_h(sidm_ctx *ctx, const sidm_halo *halos, int32_t n_halos,
+                       const sidm_state *state, uint32_t *nbr, void *stream);
+
+/* ---- scattering ----------------------------------------------------------------
+ * Tests every unordered pair {i, j} of a halo with d2_ij < (h_i + h_j)^2 once:
+ * a = min id, b = max id,
+ *   P_ab = (sigma/m) m_b |v_a - v_b| Lambda(|x_a - x_b|; h_a, h_b) dt,
+ * Lambda = integral of W(|x - x_a|, h_a) W(|x - x_b|, h_b) d^3x with W the
+ * cubic spline of compact support h (Sec. 2, Monaghan 1985; Sec. 3.5).  The
+ * accept draw is u = top 53 bits of Philox4x32-10 words (w0, w1) at counter
+ * (a, b, step, 0) and key (lo32(seed), hi32(seed)); the pair scatters iff
+ * u < P.  Probabilities use the velocities at the start of the call.  The
+ * events are then applied as elastic isotropic kicks in the pair's
+ * centre-of-mass frame (direction cos(theta) = 1 - 2 u_c, phi = 2 pi u_phi from
+ * words (w0,w1), (w2,w3) at counter (a, b, step, 1)), in (a, b) order: events
+ * sharing no particle are applied concurrently in conflict-free rounds, which
+ * gives the same result as applying them one after the other.  Reads x, v, m,
+ * id, h; updates vx, vy, vz.
+ * events (nullable, device, capacity `cap`) receives the applied events in
+ * unspecified order (sort by (halo, a, b) for the application order).
+ * n_events_host (nullable): if given, the call waits for the device and stores
+ * the number of events; it returns SIDM_ERR_CAPACITY if the context's event
+ * capacity or `cap` was exceeded (then no kick was applied; the decisions are a
+ * pure function of the state, so a retry with more capacity reproduces them). */
+sidm_status sidm_scatter(sidm_ctx *ctx, const sidm_halo *halos, int32_t n_halos,
+                         const sidm_state *state, uint32_t step, sidm_event *events,
+                         int64_t cap, int64_t *n_events_host, void *stream);
+
+/* ---- one step ------------------------------------------------------------------
+ * Pre-condition: state a/pot hold the values at the current x (call
+ * sidm_gravity once after loading the initial conditions).
+ * K(dt/2) D(dt) gravity+host K(dt/2), then h from the k nearest neighbours,
+ * then the scattering pass of sidm_scatter with this `step`.  diag (nullable,
+ * device, n_halos entries) receives the energy and momentum after the step. */
+sidm_status sidm_kdk_step(sidm_ctx *ctx, const sidm_halo *halos, int32_t n_halos,
+                          const sidm_state *state, uint32_t step, sidm_precision prec,
+                          sidm_diag *diag, void *stream);
+
+/* Energies and momentum of the current state (diag: device, n_halos entries).
+ * pot must hold the total potential at x.  The event, pair and status fields
+ * are those of the last kNN / scattering pass run on this context with the
+ * same halos. */
+sidm_status sidm_diagnostics(sidm_ctx *ctx, const sidm_halo *halos, int32_t n_halos,
+                             const sidm_state *state, sidm_diag *diag, void *stream);
+
+/* ---- pass timing ---------------------------------------------------------
+ * When enabled, sidm_kdk_step records HIP events on its stream around each
+ * pass (not usable while the stream is being captured into a graph).
+ * sidm_pass_times waits for the last timed step and writes SIDM_N_PASSES
+ * durations in milliseconds: kick+drift, gravity (all kernels), gravity tiles
+ * (the pair-sum kernel alone), cell list, kNN, pair search, ordered kicks,
+ * diagnostics. */
+#define SIDM_N_PASSES 8
+sidm_status sidm_enable_timing(sidm_ctx *ctx, int on);
+sidm_status sidm_pass_times(sidm_ctx *ctx, double ms[SIDM_N_PASSES]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

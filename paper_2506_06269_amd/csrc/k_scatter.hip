@@ -1,0 +1,373 @@
+// k_scatter.hip -- SIDM scattering pass (Sec. 2: rare pairwise scatterings
+// through the spline kernel, explicitly conserving energy and momentum;
+// Sec. 3.5: the geometric factor Lambda of the interaction probability).
+//
+// k_pairs: one wavefront per bucket, one i per lane.  Candidate buckets come
+// from the search tree with the criterion box distance < hmax(b) + hmax(c).
+// A pair {i, j} is owned by the lane with the smaller id and tested when
+// d2 < (h_i + h_j)^2; accepted pairs are compacted through an LDS queue
+// (ballot + prefix count) so that the expensive per-pair work -- Philox4x32-10,
+// |dv|, and Lambda when the draw falls below a cheap upper bound of P -- runs
+// on full wavefronts.  Events (u < P) are appended to a global buffer.
+//
+// k_rounds: the events of a step are applied in (a, b) order as elastic,
+// isotropic kicks in the pair's centre-of-mass frame.  Events that share no
+// particle commute, so the order is realised by rounds: in each round every
+// particle elects the smallest pending event key it belongs to (atomicMin),
+// and an event fires when it is the elected one for both of its particles.
+// This is exactly the dependency order of one-after-the-other application.
+#include "sidm_math.hpp"
+#include "sidm_plan.hpp"
+
+namespace sidm {
+
+__device__ inline double dist2_pair(double ax, double ay, double az, double bx, double by,
+                                    double bz)
+{
+#pragma clang fp contract(off)
+    const double dx = bx - ax, dy = by - ay, dz = bz - az;
+    return (dx * dx + dy * dy) + dz * dz;
+}
+
+__device__ inline double norm3(double x, double y, double z)
+{
+#pragma clang fp contract(off)
+    return sqrt((x * x + y * y) + z * z);
+}
+
+__device__ inline double box_dist2_s(const double* q, const double* __restrict__ b)
+{
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double g = fmax(fmax(b[c] - q[3 + c], q[c] - b[3 + c]), 0.0);
+        s += g * g;
+    }
+    return s;
+}
+
+__global__ void k_scatter_reset(DevCounters* __restrict__ counters,
+                                unsigned long long* __restrict__ ev_counts, int* __restrict__ status,
+                                int n_halos)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0) {
+        counters->n_events_total = 0ull;
+        counters->ticket = 0ull;
+    }
+    if (t < 4 * n_halos) ev_counts[t] = 0ull;
+    if (t < n_halos) status[t] = 0;
+}
+
+struct PairSide {
+    double x[kBucket], y[kBucket], z[kBucket];
+    double vx[kBucket], vy[kBucket], vz[kBucket];
+    double h[kBucket], m[kBucket];
+    uint32_t id[kBucket], orig[kBucket];
+};
+
+template <class Test, class F>
+__device__ inline void tree_visit_s(const HaloDev& H, const NodeChild* __restrict__ nodes,
+                                    int64_t n_buckets, int64_t* stack, Test test, F f)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t root = H.level_off[H.n_levels - 1];
+    if (H.n_levels == 1) {
+        f(root);
+        return;
+    }
+    __syncthreads();
+    if (lane == 0) stack[0] = root;
+    int sp = 1;
+    __syncthreads();
+    while (sp > 0) {
+        const int64_t node = stack[sp - 1];
+        --sp;
+        const NodeChild N = nodes[node];
+        const bool pass = lane < N.nchild && test(N.child0 + lane);
+        unsigned long long mask = __ballot(pass);
+        __syncthreads();
+        if (N.child0 < n_buckets) {
+            while (mask) {
+                const int l = __ffsll((long long)mask) - 1;
+                mask &= mask - 1ull;
+                f(N.child0 + l);
+            }
+        } else {
+            const int cnt = __popcll(mask);
+            if (pass) {
+                const int below = __popcll(mask & ((1ull << lane) - 1ull));
+                stack[sp + cnt - 1 - below] = N.child0 + lane;
+            }
+            sp += cnt;
+            __syncthreads();
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBucket) void k_pairs(
+    const HaloDev* __restrict__ halos, const BucketInfo* __restrict__ buckets,
+    const NodeChild* __restrict__ nodes, const double* __restrict__ box,
+    const double* __restrict__ hmax, int64_t n_buckets, const double* __restrict__ sx,
+    const double* __restrict__ sy, const double* __restrict__ sz, const double* __restrict__ svx,
+    const double* __restrict__ svy, const double* __restrict__ svz, const double* __restrict__ sh,
+    const double* __restrict__ sm, const uint32_t* __restrict__ sid,
+    const uint32_t* __restrict__ perm, uint32_t step, DevCounters* __restrict__ counters,
+    EventRec* __restrict__ events, int64_t max_events, unsigned long long* __restrict__ ev_counts)
+{
+    __shared__ PairSide I, J;
+    __shared__ uint16_t queue[2 * kBucket];
+    __shared__ int64_t stack[96];
+    const int64_t b = blockIdx.x;
+    const int lane = threadIdx.x;
+    const BucketInfo B = buckets[b];
+    const HaloDev& H = halos[B.halo];
+    if (!(H.sigma_m > 0.0)) return;   // uniform over the block
+    const bool act = lane < B.count;
+    auto load = [&](PairSide& S, int64_t p) {
+        S.x[lane] = sx[p]; S.y[lane] = sy[p]; S.z[lane] = sz[p];
+        S.vx[lane] = svx[p]; S.vy[lane] = svy[p]; S.vz[lane] = svz[p];
+        S.h[lane] = sh[p]; S.m[lane] = sm[p];
+        S.id[lane] = sid[p]; S.orig[lane] = perm[p];
+    };
+    if (act) load(I, B.start + lane);
+    double qb[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) qb[c] = box[6 * b + c];
+    const double hb = hmax[b];
+    const uint32_t k0 = (uint32_t)(H.seed & 0xffffffffull), k1 = (uint32_t)(H.seed >> 32);
+    const double kInvPi8 = 8.0 / 3.14159265358979323846;
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    long long my_pairs = 0;
+    int qn = 0;
+
+    // per-pair work for queue entries [0, cnt): lane l takes entry l
+    auto process = [&](int cnt) {
+        __syncthreads();
+        if (lane < cnt) {
+            const int e = queue[lane];
+            const int il = e & 63, jl = e >> 8;
+            const uint32_t a = I.id[il], bb = J.id[jl];
+            const Philox4 w = philox4x32_10(a, bb, step, 0u, k0, k1);
+            const double u = unit53(w.w[0], w.w[1]);
+            const double g = norm3(I.vx[il] - J.vx[jl], I.vy[il] - J.vy[jl], I.vz[il] - J.vz[jl]);
+            const double ha = I.h[il], hbb = J.h[jl];
+            const double hm = fmax(ha, hbb);
+            const double mb = J.m[jl];
+            // Lambda <= min(W_a(0), W_b(0)) = 8 / (pi max(h)^3)
+            const double pub = H.sigma_m * mb * g * (kInvPi8 / (hm * hm * hm)) * H.dt;
+            if (u < pub) {
+                const double d =
+                    sqrt(dist2_pair(I.x[il], I.y[il], I.z[il], J.x[jl], J.y[jl], J.z[jl]));
+                const double lam = kernel_overlap(d, ha, hbb);
+                const double P = H.sigma_m * mb * g * lam * H.dt;
+                if (P > 1.0) atomicAdd(&ev_counts[4 * B.halo + 3], 1ull);
+                if (u < P) {
+                    const unsigned long long slot = atomicAdd(&counters->n_events_total, 1ull);
+                    if ((int64_t)slot < max_events) {
+                        EventRec r;
+                        r.key = ((unsigned long long)a << 32) | bb;
+                        r.ia = I.orig[il];
+                        r.ib = J.orig[jl];
+                        r.halo = B.halo;
+                        r.round = 0u;
+                        events[slot] = r;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    };
+
+    auto near = [&](int64_t c) {
+        const double r = hb + hmax[c];
+        return box_dist2_s(qb, box + 6 * c) <= r * r * (1.0 + 1e-9);
+    };
+    tree_visit_s(H, nodes, n_buckets, stack, near, [&](int64_t c) {
+        const BucketInfo C = buckets[c];
+        __syncthreads();
+        if (lane < C.count) load(J, C.start + lane);
+        __syncthreads();
+        const double xi = I.x[act ? lane : 0], yi = I.y[act ? lane : 0], zi = I.z[act ? lane : 0];
+        const double hi = I.h[act ? lane : 0];
+        const uint32_t idi = I.id[act ? lane : 0];
+        for (int jj = 0; jj < C.count; ++jj) {
+            bool pair = false;
+            if (act && idi < J.id[jj]) {
+                const double d2 = dist2_pair(xi, yi, zi, J.x[jj], J.y[jj], J.z[jj]);
+                const double hs = hi + J.h[jj];
+                pair = d2 < hs * hs;
+            }
+            const unsigned long long mask = __ballot(pair);
+            if (pair) queue[qn + __popcll(mask & lt)] = (uint16_t)(lane | (jj << 8));
+            qn += __popcll(mask);
+            my_pairs += pair ? 1 : 0;
+            if (qn >= kBucket) {
+                process(kBucket);
+                const int rest = qn - kBucket;
+                const uint16_t moved = lane < rest ? queue[kBucket + lane] : 0;
+                __syncthreads();
+                if (lane < rest) queue[lane] = moved;
+                qn = rest;
+                __syncthreads();
+            }
+        }
+        if (qn > 0) {
+            process(qn);   // entries refer to this candidate bucket: flush now
+            qn = 0;
+        }
+    });
+    // pairs tested by this bucket
+    long long v = my_pairs;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (lane == 0 && v > 0) atomicAdd(&ev_counts[4 * B.halo + 2], (unsigned long long)v);
+}
+
+// Elastic isotropic scattering in the centre-of-mass frame: the relative speed
+// is kept and its direction redrawn uniformly on the sphere from the draw at
+// counter (a, b, step, 1).
+__device__ inline void kick_pair(uint64_t seed, uint32_t step, uint32_t a, uint32_t b, double ma,
+                                 double mb, double* va, double* vb)
+{
+#pragma clang fp contract(off)
+    const Philox4 w = philox4x32_10(a, b, step, 1u, (uint32_t)(seed & 0xffffffffull),
+                                    (uint32_t)(seed >> 32));
+    const double uc = unit53(w.w[0], w.w[1]);
+    const double uphi = unit53(w.w[2], w.w[3]);
+    const double M = ma + mb;
+    const double dvx = va[0] - vb[0], dvy = va[1] - vb[1], dvz = va[2] - vb[2];
+    const double g = sqrt((dvx * dvx + dvy * dvy) + dvz * dvz);
+    const double cth = 1.0 - 2.0 * uc;
+    const double s2 = 1.0 - cth * cth;
+    const double sth = sqrt(s2 > 0.0 ? s2 : 0.0);
+    const double ph = 2.0 * 3.14159265358979323846 * uphi;
+    double sp, cp;
+    sincos(ph, &sp, &cp);
+    const double n[3] = {sth * cp, sth * sp, cth};
+    const double fa = mb / M * g, fb = ma / M * g;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double vcm = (ma * va[c] + mb * vb[c]) / M;
+        va[c] = vcm + fa * n[c];
+        vb[c] = vcm - fb * n[c];
+    }
+}
+
+__device__ inline unsigned long long owner_load(unsigned long long* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline void owner_free(unsigned long long* p)
+{
+    __hip_atomic_store(p, ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+constexpr int kRoundThreads = 1024;
+
+// One workgroup applies all events of the step; every wave leaves the loop in
+// the same round (the pending count is reduced through LDS).
+__global__ __launch_bounds__(kRoundThreads) void k_rounds(
+    const HaloDev* __restrict__ halos, int n_halos, const DevCounters* __restrict__ counters,
+    EventRec* __restrict__ ev, int64_t max_events, unsigned long long* __restrict__ owner,
+    double* __restrict__ vx, double* __restrict__ vy, double* __restrict__ vz,
+    const double* __restrict__ m, unsigned long long* __restrict__ ev_counts,
+    int* __restrict__ status, uint32_t step, int64_t out_cap, sidm_event* __restrict__ out)
+{
+    __shared__ int pending;
+    const int t = threadIdx.x;
+    const unsigned long long total = counters->n_events_total;
+    if ((int64_t)total > max_events) {
+        for (int h = t; h < n_halos; h += kRoundThreads) atomicOr(&status[h], SIDM_DEV_EVENT_OVERFLOW);
+        return;
+    }
+    const int64_t n = (int64_t)total;
+    for (int64_t e = t; e < n; e += kRoundThreads) {
+        ev[e].round = 0u;
+        owner_free(&owner[ev[e].ia]);
+        owner_free(&owner[ev[e].ib]);
+    }
+    __syncthreads();
+    for (uint32_t r = 1; n > 0; ++r) {
+        for (int64_t e = t; e < n; e += kRoundThreads)
+            if (ev[e].round == 0u) {
+                atomicMin(&owner[ev[e].ia], ev[e].key);
+                atomicMin(&owner[ev[e].ib], ev[e].key);
+            }
+        __syncthreads();
+        for (int64_t e = t; e < n; e += kRoundThreads)
+            if (ev[e].round == 0u) {
+                const unsigned long long key = ev[e].key;
+                if (owner_load(&owner[ev[e].ia]) == key && owner_load(&owner[ev[e].ib]) == key)
+                    ev[e].round = r;
+            }
+        __syncthreads();
+        if (t == 0) pending = 0;
+        for (int64_t e = t; e < n; e += kRoundThreads) {
+            const uint32_t er = ev[e].round;
+            if (er == 0u || er == r) {
+                owner_free(&owner[ev[e].ia]);
+                owner_free(&owner[ev[e].ib]);
+            }
+        }
+        __syncthreads();
+        int mine = 0;
+        for (int64_t e = t; e < n; e += kRoundThreads) {
+            const EventRec E = ev[e];
+            if (E.round == r) {
+                const HaloDev& H = halos[E.halo];
+                double va[3] = {vx[E.ia], vy[E.ia], vz[E.ia]};
+                double vb[3] = {vx[E.ib], vy[E.ib], vz[E.ib]};
+                kick_pair(H.seed, step, (uint32_t)(E.key >> 32), (uint32_t)E.key, m[E.ia], m[E.ib],
+                          va, vb);
+                vx[E.ia] = va[0]; vy[E.ia] = va[1]; vz[E.ia] = va[2];
+                vx[E.ib] = vb[0]; vy[E.ib] = vb[1]; vz[E.ib] = vb[2];
+                atomicAdd(&ev_counts[4 * E.halo + 0], 1ull);
+                atomicMax(&ev_counts[4 * E.halo + 1], (unsigned long long)r);
+            } else if (E.round == 0u) {
+                ++mine;
+            }
+        }
+        if (mine) atomicAdd(&pending, mine);
+        __syncthreads();
+        const int left = pending;
+        __syncthreads();
+        if (left == 0) break;
+    }
+    if (out) {
+        const int64_t nout = n < out_cap ? n : out_cap;
+        for (int64_t e = t; e < nout; e += kRoundThreads) {
+            sidm_event o;
+            o.a = (uint32_t)(ev[e].key >> 32);
+            o.b = (uint32_t)ev[e].key;
+            o.halo = ev[e].halo;
+            o.round = ev[e].round;
+            out[e] = o;
+        }
+    }
+}
+
+hipError_t launch_reset(const Plan& P, Scratch& w, hipStream_t st)
+{
+    const int nt = 4 * P.n_halos + 1;
+    hipLaunchKernelGGL(k_scatter_reset, dim3((nt + 255) / 256), dim3(256), 0, st, w.counters,
+                       (unsigned long long*)w.ev_counts, w.status, P.n_halos);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(const Plan& P, const sidm_state* s, Scratch& w, uint32_t step,
+                          sidm_event* out_events, int64_t out_cap, hipStream_t st,
+                          hipEvent_t after_pairs)
+{
+    hipLaunchKernelGGL(k_pairs, dim3((unsigned)P.n_buckets), dim3(kBucket), 0, st, w.halos,
+                       w.buckets, w.nodes, w.box, w.hmax, P.n_buckets, w.sx, w.sy, w.sz, w.svx,
+                       w.svy, w.svz, w.sh, w.sm, w.sid, w.perm, step, w.counters, w.events,
+                       w.max_events, (unsigned long long*)w.ev_counts);
+    if (after_pairs) (void)hipEventRecord(after_pairs, st);
+    hipLaunchKernelGGL(k_rounds, dim3(1), dim3(kRoundThreads), 0, st, w.halos, P.n_halos,
+                       w.counters, w.events, w.max_events, w.owner, s->vx, s->vy, s->vz, s->m,
+                       (unsigned long long*)w.ev_counts, w.status, step, out_cap, out_events);
+    return hipGetLastError();
+}
+
+}  // namespace sidm

@@ -1,0 +1,134 @@
+// k_stream.hip -- streaming FP64 passes of the leapfrog and the energy and
+// momentum reductions (kick-drift-kick with a fixed step; the paper's energy
+// error is measured relative to the absolute initial energy, App. B).
+#include "sidm_internal.hpp"
+
+namespace sidm {
+
+// v += a dt/2 ; x += v dt   (opening half kick fused with the drift)
+__global__ __launch_bounds__(kStreamBlock) void k_kick_drift(
+    const StreamBlock* __restrict__ blocks, const HaloDev* __restrict__ halos,
+    double* __restrict__ x, double* __restrict__ y, double* __restrict__ z,
+    double* __restrict__ vx, double* __restrict__ vy, double* __restrict__ vz,
+    const double* __restrict__ ax, const double* __restrict__ ay, const double* __restrict__ az)
+{
+    const StreamBlock B = blocks[blockIdx.x];
+    const int t = threadIdx.x;
+    if (t >= B.count) return;
+    const HaloDev& H = halos[B.halo];
+    const int64_t i = B.start + t;
+    const double hdt = 0.5 * H.dt;
+    const double ux = vx[i] + ax[i] * hdt;
+    const double uy = vy[i] + ay[i] * hdt;
+    const double uz = vz[i] + az[i] * hdt;
+    vx[i] = ux; vy[i] = uy; vz[i] = uz;
+    x[i] += ux * H.dt;
+    y[i] += uy * H.dt;
+    z[i] += uz * H.dt;
+}
+
+__device__ inline void host_pot_only(const HaloDev& H, double px, double py, double pz,
+                                     double& phi)
+{
+    const double dx = px - H.host_c[0], dy = py - H.host_c[1], dz = pz - H.host_c[2];
+    const double r = sqrt(dx * dx + dy * dy + dz * dz);
+    if (r == 0.0) {
+        phi = -H.host_K / H.host_r_s;
+        return;
+    }
+    phi = -H.host_K * log1p(r / H.host_r_s) / r;
+}
+
+// Per-block partial sums of K, W, Eext, px, py, pz and a non-finite flag.
+__global__ __launch_bounds__(kStreamBlock) void k_diag_block(
+    const StreamBlock* __restrict__ blocks, const HaloDev* __restrict__ halos,
+    const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
+    const double* __restrict__ vx, const double* __restrict__ vy, const double* __restrict__ vz,
+    const double* __restrict__ m, const double* __restrict__ pot, double* __restrict__ bsum)
+{
+    __shared__ double red[7][kStreamBlock];
+    const StreamBlock B = blocks[blockIdx.x];
+    const HaloDev& H = halos[B.halo];
+    const int t = threadIdx.x;
+    double v[7] = {0, 0, 0, 0, 0, 0, 0};
+    if (t < B.count) {
+        const int64_t i = B.start + t;
+        const double mi = m[i];
+        const double ux = vx[i], uy = vy[i], uz = vz[i];
+        double pe = 0.0;
+        if (H.host_kind == 1) host_pot_only(H, x[i], y[i], z[i], pe);
+        v[0] = 0.5 * mi * ((ux * ux + uy * uy) + uz * uz);
+        v[1] = 0.5 * mi * (pot[i] - pe);
+        v[2] = mi * pe;
+        v[3] = mi * ux; v[4] = mi * uy; v[5] = mi * uz;
+        const double chk = x[i] + y[i] + z[i] + ux + uy + uz;
+        v[6] = isfinite(chk) ? 0.0 : 1.0;
+    }
+    for (int c = 0; c < 7; ++c) red[c][t] = v[c];
+    __syncthreads();
+    for (int s = kStreamBlock / 2; s > 0; s >>= 1) {
+        if (t < s)
+            for (int c = 0; c < 7; ++c) red[c][t] += red[c][t + s];
+        __syncthreads();
+    }
+    if (t < 7) bsum[7 * (int64_t)blockIdx.x + t] = red[t][0];
+}
+
+// One block per halo: fixed-order sum of the block partials into sidm_diag.
+__global__ __launch_bounds__(kStreamBlock) void k_diag_halo(
+    const HaloDev* __restrict__ halos, const double* __restrict__ bsum,
+    const long long* __restrict__ ev_counts, const int* __restrict__ status,
+    sidm_diag* __restrict__ diag)
+{
+    __shared__ double red[7][kStreamBlock];
+    const HaloDev& H = halos[blockIdx.x];
+    const int t = threadIdx.x;
+    const int64_t nb = (H.n + kStreamBlock - 1) / kStreamBlock;
+    double s[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int64_t b = t; b < nb; b += kStreamBlock)
+        for (int c = 0; c < 7; ++c) s[c] += bsum[7 * (H.stream_block0 + b) + c];
+    for (int c = 0; c < 7; ++c) red[c][t] = s[c];
+    __syncthreads();
+    for (int st = kStreamBlock / 2; st > 0; st >>= 1) {
+        if (t < st)
+            for (int c = 0; c < 7; ++c) red[c][t] += red[c][t + st];
+        __syncthreads();
+    }
+    if (t == 0) {
+        sidm_diag d;
+        d.K = red[0][0]; d.W = red[1][0]; d.Eext = red[2][0];
+        d.px = red[3][0]; d.py = red[4][0]; d.pz = red[5][0];
+        const int h = blockIdx.x;
+        d.n_events = ev_counts ? ev_counts[4 * h + 0] : 0;
+        d.n_rounds = ev_counts ? ev_counts[4 * h + 1] : 0;
+        d.n_pairs = ev_counts ? ev_counts[4 * h + 2] : 0;
+        d.n_p_gt1 = ev_counts ? ev_counts[4 * h + 3] : 0;
+        d.status = (status ? status[h] : 0) | (red[6][0] > 0.0 ? SIDM_DEV_NONFINITE : 0);
+        d.reserved = 0;
+        diag[h] = d;
+    }
+}
+
+hipError_t launch_kick_drift(const StreamBlock* d_blocks, int64_t n_blocks, const HaloDev* d_halos,
+                             double* x, double* y, double* z, double* vx, double* vy, double* vz,
+                             const double* ax, const double* ay, const double* az, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_kick_drift, dim3((unsigned)n_blocks), dim3(kStreamBlock), 0, st, d_blocks,
+                       d_halos, x, y, z, vx, vy, vz, ax, ay, az);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag(const StreamBlock* d_blocks, int64_t n_blocks, const HaloDev* d_halos,
+                       int n_halos, const double* x, const double* y, const double* z,
+                       const double* vx, const double* vy, const double* vz, const double* m,
+                       const double* pot, double* bsum, const long long* ev_counts,
+                       const int* status, sidm_diag* diag, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_diag_block, dim3((unsigned)n_blocks), dim3(kStreamBlock), 0, st, d_blocks,
+                       d_halos, x, y, z, vx, vy, vz, m, pot, bsum);
+    hipLaunchKernelGGL(k_diag_halo, dim3(n_halos), dim3(kStreamBlock), 0, st, d_halos, bsum,
+                       ev_counts, status, diag);
+    return hipGetLastError();
+}
+
+}  // namespace sidm

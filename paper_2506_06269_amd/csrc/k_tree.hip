@@ -1,0 +1,351 @@
+// k_tree.hip -- cell list for the neighbour and pair searches: particles of
+// each halo are ordered along a Morton curve (48-bit keys over the halo's
+// bounding box, halo rank in the high bits) by a stable LSD radix sort, cut
+// into buckets of kBucket consecutive particles, and the bucket bounding boxes
+// are merged kFanout at a time into a search tree per halo.
+#include "sidm_plan.hpp"
+
+namespace sidm {
+
+// ---------------------------------------------------------------- bounding boxes
+__global__ __launch_bounds__(kStreamBlock) void k_block_bbox(
+    const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
+    const StreamBlock* __restrict__ blocks, double* __restrict__ bout)
+{
+    __shared__ double lo[3][kStreamBlock], hi[3][kStreamBlock];
+    const StreamBlock B = blocks[blockIdx.x];
+    const int t = threadIdx.x;
+    const int64_t i = B.start + (t < B.count ? t : 0);
+    const double p[3] = {x[i], y[i], z[i]};
+    for (int c = 0; c < 3; ++c) { lo[c][t] = p[c]; hi[c][t] = p[c]; }
+    __syncthreads();
+    for (int s = kStreamBlock / 2; s > 0; s >>= 1) {
+        if (t < s)
+            for (int c = 0; c < 3; ++c) {
+                lo[c][t] = fmin(lo[c][t], lo[c][t + s]);
+                hi[c][t] = fmax(hi[c][t], hi[c][t + s]);
+            }
+        __syncthreads();
+    }
+    if (t < 3) {
+        bout[7 * (int64_t)blockIdx.x + t] = lo[t][0];
+        bout[7 * (int64_t)blockIdx.x + 3 + t] = hi[t][0];
+    }
+}
+
+__global__ __launch_bounds__(kStreamBlock) void k_halo_bbox(
+    const HaloDev* __restrict__ halos, const double* __restrict__ bin, double* __restrict__ bbox)
+{
+    __shared__ double lo[3][kStreamBlock], hi[3][kStreamBlock];
+    const HaloDev& H = halos[blockIdx.x];
+    const int t = threadIdx.x;
+    const int64_t nb = (H.n + kStreamBlock - 1) / kStreamBlock;
+    double l[3] = {INFINITY, INFINITY, INFINITY}, u[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t b = t; b < nb; b += kStreamBlock)
+        for (int c = 0; c < 3; ++c) {
+            l[c] = fmin(l[c], bin[7 * (H.stream_block0 + b) + c]);
+            u[c] = fmax(u[c], bin[7 * (H.stream_block0 + b) + 3 + c]);
+        }
+    for (int c = 0; c < 3; ++c) { lo[c][t] = l[c]; hi[c][t] = u[c]; }
+    __syncthreads();
+    for (int s = kStreamBlock / 2; s > 0; s >>= 1) {
+        if (t < s)
+            for (int c = 0; c < 3; ++c) {
+                lo[c][t] = fmin(lo[c][t], lo[c][t + s]);
+                hi[c][t] = fmax(hi[c][t], hi[c][t + s]);
+            }
+        __syncthreads();
+    }
+    if (t < 3) {
+        bbox[6 * blockIdx.x + t] = lo[t][0];
+        bbox[6 * blockIdx.x + 3 + t] = hi[t][0];
+    }
+}
+
+// ---------------------------------------------------------------- Morton keys
+__device__ inline unsigned long long spread3(unsigned v)   // bit k -> bit 3k
+{
+    unsigned long long x = v & 0xFFFFull;
+    x = (x | (x << 32)) & 0x001F00000000FFFFull;
+    x = (x | (x << 16)) & 0x001F0000FF0000FFull;
+    x = (x | (x << 8)) & 0x100F00F00F00F00Full;
+    x = (x | (x << 4)) & 0x10C30C30C30C30C3ull;
+    x = (x | (x << 2)) & 0x1249249249249249ull;
+    return x;
+}
+
+__device__ inline unsigned quant16(double v, double lo, double inv)
+{
+    double q = (v - lo) * inv;
+    q = fmin(fmax(q, 0.0), 65535.0);
+    return (unsigned)q;
+}
+
+__global__ __launch_bounds__(kStreamBlock) void k_morton_keys(
+    const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
+    const StreamBlock* __restrict__ blocks, const HaloDev* __restrict__ halos,
+    const double* __restrict__ bbox, unsigned long long* __restrict__ keys,
+    uint32_t* __restrict__ vals)
+{
+    const StreamBlock B = blocks[blockIdx.x];
+    const int t = threadIdx.x;
+    if (t >= B.count) return;
+    const HaloDev& H = halos[B.halo];
+    const int64_t i = B.start + t;
+    const double* bb = bbox + 6 * B.halo;
+    double ext = fmax(fmax(bb[3] - bb[0], bb[4] - bb[1]), bb[5] - bb[2]);
+    const double inv = ext > 0.0 ? 65535.0 / ext : 0.0;
+    const unsigned long long code = spread3(quant16(x[i], bb[0], inv)) |
+                                    (spread3(quant16(y[i], bb[1], inv)) << 1) |
+                                    (spread3(quant16(z[i], bb[2], inv)) << 2);
+    const int64_t pos = H.sbase + (i - H.offset);
+    keys[pos] = ((unsigned long long)H.rank << 48) | code;
+    vals[pos] = (uint32_t)i;
+}
+
+// ---------------------------------------------------------------- radix sort
+constexpr int kTile = kSortBlock * kSortItems;
+
+__global__ __launch_bounds__(kSortBlock) void k_sort_count(
+    const unsigned long long* __restrict__ keys, int64_t n, int shift, uint32_t* __restrict__ hist,
+    int64_t nblk)
+{
+    __shared__ uint32_t cnt[1 << kSortBits];
+    const int t = threadIdx.x;
+    cnt[t] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    for (int r = 0; r < kSortItems; ++r) {
+        const int64_t i = base + (int64_t)r * kSortBlock + t;
+        if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & 0xFF], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)t * nblk + blockIdx.x] = cnt[t];
+}
+
+// Exclusive scan of len counts, in place, by one block of 1024 threads.
+__global__ __launch_bounds__(1024) void k_scan_exclusive(uint32_t* __restrict__ a, int64_t len)
+{
+    __shared__ uint32_t part[1024];
+    const int t = threadIdx.x;
+    const int64_t chunk = (len + 1023) / 1024;
+    const int64_t b = t * chunk, e = b + chunk < len ? b + chunk : len;
+    uint32_t s = 0;
+    for (int64_t i = b; i < e; ++i) s += a[i];
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        uint32_t v = t >= off ? part[t - off] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    uint32_t run = part[t] - s;  // exclusive prefix of this chunk
+    for (int64_t i = b; i < e; ++i) {
+        const uint32_t v = a[i];
+        a[i] = run;
+        run += v;
+    }
+}
+
+// Stable scatter: items of a tile are taken 256 at a time in index order; the
+// rank of an item among equal digits is the running count of the digit plus
+// the count in earlier waves plus the count in lower lanes of its own wave.
+__global__ __launch_bounds__(kSortBlock) void k_sort_scatter(
+    const unsigned long long* __restrict__ kin, const uint32_t* __restrict__ vin,
+    unsigned long long* __restrict__ kout, uint32_t* __restrict__ vout, int64_t n, int shift,
+    const uint32_t* __restrict__ hist, int64_t nblk)
+{
+    constexpr int kWaves = kSortBlock / 64;
+    __shared__ uint32_t run[1 << kSortBits];
+    __shared__ uint32_t wcnt[kWaves][1 << kSortBits];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    run[t] = hist[(int64_t)t * nblk + blockIdx.x];
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    for (int r = 0; r < kSortItems; ++r) {
+        const int64_t i = base + (int64_t)r * kSortBlock + t;
+        const bool valid = i < n;
+        const unsigned long long key = valid ? kin[i] : 0ull;
+        const uint32_t val = valid ? vin[i] : 0u;
+        const uint32_t d = (uint32_t)(key >> shift) & 0xFFu;
+#pragma unroll
+        for (int q = 0; q < kWaves; ++q) wcnt[q][t] = 0;
+        __syncthreads();
+        unsigned long long peers = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < kSortBits; ++bit) {
+            const bool set = (d >> bit) & 1u;
+            const unsigned long long m = __ballot(set);
+            peers &= set ? m : ~m;
+        }
+        const uint32_t rank = (uint32_t)__popcll(peers & lt);
+        if (valid && rank == (uint32_t)__popcll(peers) - 1u) wcnt[w][d] = rank + 1u;
+        __syncthreads();
+        {
+            uint32_t acc = run[t];
+#pragma unroll
+            for (int q = 0; q < kWaves; ++q) {
+                const uint32_t c = wcnt[q][t];
+                wcnt[q][t] = acc;
+                acc += c;
+            }
+            run[t] = acc;
+        }
+        __syncthreads();
+        if (valid) {
+            const uint32_t pos = wcnt[w][d] + rank;
+            kout[pos] = key;
+            vout[pos] = val;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- permute
+__global__ __launch_bounds__(kStreamBlock) void k_permute(
+    int64_t n, const uint32_t* __restrict__ order, const double* __restrict__ x,
+    const double* __restrict__ y, const double* __restrict__ z, const double* __restrict__ vx,
+    const double* __restrict__ vy, const double* __restrict__ vz, const double* __restrict__ m,
+    const uint32_t* __restrict__ id, const double* __restrict__ h, double* __restrict__ sx,
+    double* __restrict__ sy, double* __restrict__ sz, double* __restrict__ svx,
+    double* __restrict__ svy, double* __restrict__ svz, double* __restrict__ sm,
+    uint32_t* __restrict__ sid, double* __restrict__ sh, uint32_t* __restrict__ perm)
+{
+    const int64_t p = (int64_t)blockIdx.x * kStreamBlock + threadIdx.x;
+    if (p >= n) return;
+    const uint32_t o = order[p];
+    sx[p] = x[o]; sy[p] = y[o]; sz[p] = z[o];
+    if (vx) { svx[p] = vx[o]; svy[p] = vy[o]; svz[p] = vz[o]; }
+    sm[p] = m[o];
+    sid[p] = id[o];
+    sh[p] = h ? h[o] : 0.0;
+    perm[p] = o;
+}
+
+// ---------------------------------------------------------------- boxes
+__device__ inline double wave_min(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ inline double wave_max(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// One wave per bucket.
+__global__ __launch_bounds__(256) void k_bucket_boxes(
+    const BucketInfo* __restrict__ buckets, int64_t nb, const double* __restrict__ sx,
+    const double* __restrict__ sy, const double* __restrict__ sz, double* __restrict__ box)
+{
+    const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (b >= nb) return;
+    const int lane = threadIdx.x & 63;
+    const BucketInfo B = buckets[b];
+    const int64_t p = B.start + (lane < B.count ? lane : 0);
+    const double px = sx[p], py = sy[p], pz = sz[p];
+    const double l0 = wave_min(px), l1 = wave_min(py), l2 = wave_min(pz);
+    const double u0 = wave_max(px), u1 = wave_max(py), u2 = wave_max(pz);
+    if (lane == 0) {
+        double* o = box + 6 * b;
+        o[0] = l0; o[1] = l1; o[2] = l2; o[3] = u0; o[4] = u1; o[5] = u2;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bucket_hmax(
+    const BucketInfo* __restrict__ buckets, int64_t nb, const double* __restrict__ sh,
+    double* __restrict__ hmax)
+{
+    const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (b >= nb) return;
+    const int lane = threadIdx.x & 63;
+    const BucketInfo B = buckets[b];
+    const double v = wave_max(sh[B.start + (lane < B.count ? lane : 0)]);
+    if (lane == 0) hmax[b] = v;
+}
+
+__global__ __launch_bounds__(256) void k_node_boxes(const NodeTask* __restrict__ tasks,
+                                                     int64_t nt, double* __restrict__ box)
+{
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= nt) return;
+    const NodeTask T = tasks[k];
+    double o[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    for (int c = 0; c < T.nchild; ++c) {
+        const double* b = box + 6 * (T.child0 + c);
+        for (int q = 0; q < 3; ++q) {
+            o[q] = fmin(o[q], b[q]);
+            o[3 + q] = fmax(o[3 + q], b[3 + q]);
+        }
+    }
+    for (int q = 0; q < 6; ++q) box[6 * T.node + q] = o[q];
+}
+
+__global__ __launch_bounds__(256) void k_node_hmax(const NodeTask* __restrict__ tasks, int64_t nt,
+                                                    double* __restrict__ hmax)
+{
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= nt) return;
+    const NodeTask T = tasks[k];
+    double v = 0.0;
+    for (int c = 0; c < T.nchild; ++c) v = fmax(v, hmax[T.child0 + c]);
+    hmax[T.node] = v;
+}
+
+// ---------------------------------------------------------------- launchers
+static unsigned grid_of(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+hipError_t launch_cell_list(const Plan& P, const sidm_state* s, Scratch& w, hipStream_t st)
+{
+    const int64_t n = P.n_sorted;
+    hipLaunchKernelGGL(k_block_bbox, dim3((unsigned)P.n_blocks), dim3(kStreamBlock), 0, st, s->x,
+                       s->y, s->z, w.blocks, w.bsum);
+    hipLaunchKernelGGL(k_halo_bbox, dim3(P.n_halos), dim3(kStreamBlock), 0, st, w.halos, w.bsum,
+                       w.bbox);
+    hipLaunchKernelGGL(k_morton_keys, dim3((unsigned)P.n_blocks), dim3(kStreamBlock), 0, st, s->x,
+                       s->y, s->z, w.blocks, w.halos, w.bbox, w.keys[0], w.vals[0]);
+    int cur = 0;
+    const int passes = (P.key_bits + kSortBits - 1) / kSortBits;
+    const int64_t nblk = P.sort_blocks;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = p * kSortBits;
+        hipLaunchKernelGGL(k_sort_count, dim3((unsigned)nblk), dim3(kSortBlock), 0, st,
+                           w.keys[cur], n, shift, w.hist, nblk);
+        hipLaunchKernelGGL(k_scan_exclusive, dim3(1), dim3(1024), 0, st, w.hist,
+                           nblk * (1 << kSortBits));
+        hipLaunchKernelGGL(k_sort_scatter, dim3((unsigned)nblk), dim3(kSortBlock), 0, st,
+                           w.keys[cur], w.vals[cur], w.keys[cur ^ 1], w.vals[cur ^ 1], n, shift,
+                           w.hist, nblk);
+        cur ^= 1;
+    }
+    hipLaunchKernelGGL(k_permute, dim3(grid_of(n, kStreamBlock)), dim3(kStreamBlock), 0, st, n,
+                       w.vals[cur], s->x, s->y, s->z, s->vx, s->vy, s->vz, s->m, s->id, s->h,
+                       w.sx, w.sy, w.sz, w.svx, w.svy, w.svz, w.sm, w.sid, w.sh, w.perm);
+    hipLaunchKernelGGL(k_bucket_boxes, dim3(grid_of(P.n_buckets, 4)), dim3(256), 0, st, w.buckets,
+                       P.n_buckets, w.sx, w.sy, w.sz, w.box);
+    for (int l = 1; l < P.n_levels; ++l) {
+        const int64_t t0 = P.level_task_off[l - 1], nt = P.level_task_off[l] - t0;
+        if (nt > 0)
+            hipLaunchKernelGGL(k_node_boxes, dim3(grid_of(nt, 256)), dim3(256), 0, st,
+                               w.node_tasks + t0, nt, w.box);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_tree_hmax(const Plan& P, Scratch& w, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_bucket_hmax, dim3(grid_of(P.n_buckets, 4)), dim3(256), 0, st, w.buckets,
+                       P.n_buckets, w.sh, w.hmax);
+    for (int l = 1; l < P.n_levels; ++l) {
+        const int64_t t0 = P.level_task_off[l - 1], nt = P.level_task_off[l] - t0;
+        if (nt > 0)
+            hipLaunchKernelGGL(k_node_hmax, dim3(grid_of(nt, 256)), dim3(256), 0, st,
+                               w.node_tasks + t0, nt, w.hmax);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace sidm

@@ -1,0 +1,459 @@
+// sidm_api.hip -- host side of the libsidm C ABI: argument validation,
+// context and scratch memory, per-configuration launch plans, and the
+// sequencing of the kernels of each entry point.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "sidm_internal.hpp"
+
+namespace sidm {
+hipError_t launch_gravity(bool mixed, const double* x, const double* y, const double* z,
+                          const double* m, const HaloDev* d_halos, int n_halos,
+                          const StreamBlock* d_blocks, int64_t n_blocks, const GravItem* d_items,
+                          int64_t n_items, double* bsum, double* cref, float4* xm32,
+                          double4* partial, double* ax, double* ay, double* az, double* pot,
+                          double* vx, double* vy, double* vz, int kick, hipStream_t st,
+                          hipEvent_t tile_begin, hipEvent_t tile_end);
+hipError_t launch_kick_drift(const StreamBlock* d_blocks, int64_t n_blocks, const HaloDev* d_halos,
+                             double* x, double* y, double* z, double* vx, double* vy, double* vz,
+                             const double* ax, const double* ay, const double* az, hipStream_t st);
+hipError_t launch_diag(const StreamBlock* d_blocks, int64_t n_blocks, const HaloDev* d_halos,
+                       int n_halos, const double* x, const double* y, const double* z,
+                       const double* vx, const double* vy, const double* vz, const double* m,
+                       const double* pot, double* bsum, const long long* ev_counts,
+                       const int* status, sidm_diag* diag, hipStream_t st);
+
+}  // namespace sidm
+
+#include "sidm_plan.hpp"
+
+namespace sidm {
+hipError_t launch_cell_list(const Plan& plan, const sidm_state* s, Scratch& w, hipStream_t st);
+hipError_t launch_knn(const Plan& plan, const sidm_state* s, Scratch& w, uint32_t* nbr, int k_max,
+                      hipStream_t st);
+hipError_t launch_tree_hmax(const Plan& plan, Scratch& w, hipStream_t st);
+hipError_t launch_reset(const Plan& plan, Scratch& w, hipStream_t st);
+hipError_t launch_scatter(const Plan& plan, const sidm_state* s, Scratch& w, uint32_t step,
+                          sidm_event* out_events, int64_t out_cap, hipStream_t st,
+                          hipEvent_t after_pairs);
+}  // namespace sidm
+
+using namespace sidm;
+
+struct sidm_ctx {
+    int device = 0;
+    int64_t max_particles = 0;
+    int32_t max_halos = 0;
+    std::string err;
+    Scratch w;
+    Plan plan;
+    std::vector<sidm_halo> plan_key;
+    bool plan_valid = false;
+    bool timing = false;
+    bool timed = false;               // the last step recorded its events
+    hipEvent_t ev[SIDM_N_PASSES + 2] = {};
+};
+
+namespace {
+
+void set_err(sidm_ctx* c, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    c->err = buf;
+}
+
+sidm_status hip_fail(sidm_ctx* c, hipError_t e, const char* where)
+{
+    set_err(c, "%s: %s", where, hipGetErrorString(e));
+    return SIDM_ERR_HIP;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+enum Need { NEED_GRAV = 1, NEED_KNN = 2, NEED_SCATTER = 4, NEED_STEP = 8 };
+
+sidm_status validate(sidm_ctx* c, const sidm_halo* halos, int32_t n_halos, const sidm_state* s,
+                     int need)
+{
+    if (!c) return SIDM_ERR_INVALID;
+    if (!halos || n_halos <= 0) {
+        set_err(c, "need at least one halo (halos=%p, n_halos=%d)", (const void*)halos, n_halos);
+        return SIDM_ERR_INVALID;
+    }
+    if (n_halos > c->max_halos) {
+        set_err(c, "n_halos=%d exceeds the context's max_halos=%d", n_halos, c->max_halos);
+        return SIDM_ERR_INVALID;
+    }
+    if (!s) {
+        set_err(c, "state is NULL");
+        return SIDM_ERR_INVALID;
+    }
+    const bool need_pos = true;
+    if (need_pos && (!s->x || !s->y || !s->z || !s->m)) {
+        set_err(c, "state x, y, z and m must be device pointers");
+        return SIDM_ERR_INVALID;
+    }
+    if ((need & (NEED_GRAV | NEED_STEP)) && (!s->ax || !s->ay || !s->az || !s->pot)) {
+        set_err(c, "state ax, ay, az and pot are required");
+        return SIDM_ERR_INVALID;
+    }
+    if ((need & (NEED_KNN | NEED_SCATTER | NEED_STEP)) && (!s->id || !s->h)) {
+        set_err(c, "state id and h are required");
+        return SIDM_ERR_INVALID;
+    }
+    if ((need & (NEED_SCATTER | NEED_STEP)) && (!s->vx || !s->vy || !s->vz)) {
+        set_err(c, "state vx, vy and vz are required");
+        return SIDM_ERR_INVALID;
+    }
+    std::vector<std::pair<int64_t, int64_t>> ranges;
+    int64_t total = 0;
+    for (int32_t h = 0; h < n_halos; ++h) {
+        const sidm_halo& H = halos[h];
+        if (H.offset < 0 || H.n < 2 || H.n > (int64_t(1) << 24)) {
+            set_err(c, "halo %d: need offset >= 0 and 2 <= n <= 2^24 (offset=%lld n=%lld)", h,
+                    (long long)H.offset, (long long)H.n);
+            return SIDM_ERR_INVALID;
+        }
+        if (!(H.eps > 0.0) || !std::isfinite(H.eps) || !std::isfinite(H.G)) {
+            set_err(c, "halo %d: softening eps must be finite and > 0 (eps=%g)", h, H.eps);
+            return SIDM_ERR_INVALID;
+        }
+        if ((need & (NEED_SCATTER | NEED_STEP)) && (!(H.dt > 0.0) || !std::isfinite(H.dt))) {
+            set_err(c, "halo %d: dt must be finite and > 0 (dt=%g)", h, H.dt);
+            return SIDM_ERR_INVALID;
+        }
+        if ((need & (NEED_SCATTER | NEED_STEP)) && (!(H.sigma_m >= 0.0) || !std::isfinite(H.sigma_m))) {
+            set_err(c, "halo %d: sigma_m must be finite and >= 0", h);
+            return SIDM_ERR_INVALID;
+        }
+        if ((need & (NEED_KNN | NEED_STEP)) &&
+            (H.k < 1 || H.k > SIDM_MAX_K || (int64_t)H.k > H.n - 1)) {
+            set_err(c, "halo %d: need 1 <= k <= min(n-1, %d) (k=%d n=%lld)", h, SIDM_MAX_K, H.k,
+                    (long long)H.n);
+            return SIDM_ERR_INVALID;
+        }
+        if (H.host_kind != 0 && H.host_kind != 1) {
+            set_err(c, "halo %d: host_kind must be 0 or 1", h);
+            return SIDM_ERR_UNSUPPORTED;
+        }
+        if (H.host_kind == 1 && (!(H.host_r_s > 0.0) || !std::isfinite(H.host_rho_s))) {
+            set_err(c, "halo %d: host needs r_s > 0 and finite rho_s", h);
+            return SIDM_ERR_INVALID;
+        }
+        ranges.push_back({H.offset, H.offset + H.n});
+        total = std::max(total, H.offset + H.n);
+    }
+    if (total > c->max_particles) {
+        set_err(c, "particles up to index %lld exceed the context's max_particles=%lld",
+                (long long)total, (long long)c->max_particles);
+        return SIDM_ERR_INVALID;
+    }
+    std::sort(ranges.begin(), ranges.end());
+    for (size_t r = 1; r < ranges.size(); ++r)
+        if (ranges[r].first < ranges[r - 1].second) {
+            set_err(c, "halo particle ranges overlap");
+            return SIDM_ERR_INVALID;
+        }
+    return SIDM_OK;
+}
+
+sidm_status ensure_plan(sidm_ctx* c, const sidm_halo* halos, int32_t n_halos, hipStream_t st)
+{
+    if (c->plan_valid && (int32_t)c->plan_key.size() == n_halos &&
+        std::memcmp(c->plan_key.data(), halos, sizeof(sidm_halo) * (size_t)n_halos) == 0)
+        return SIDM_OK;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) {
+        set_err(c, "the halo configuration changed during stream capture; call once before "
+                   "capturing so the launch plan is built");
+        return SIDM_ERR_INVALID;
+    }
+    std::string why;
+    if (!build_plan(c->plan, c->w, halos, n_halos, why)) {
+        set_err(c, "%s", why.c_str());
+        return SIDM_ERR_CAPACITY;
+    }
+    hipError_t e = upload_plan(c->plan, c->w);
+    if (e != hipSuccess) return hip_fail(c, e, "uploading the launch plan");
+    c->plan_key.assign(halos, halos + n_halos);
+    c->plan_valid = true;
+    return SIDM_OK;
+}
+
+int max_k(const sidm_halo* halos, int32_t n)
+{
+    int k = 0;
+    for (int32_t h = 0; h < n; ++h) k = std::max(k, (int)halos[h].k);
+    return k;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sidm_status_string(sidm_status s)
+{
+    switch (s) {
+    case SIDM_OK: return "ok";
+    case SIDM_ERR_INVALID: return "invalid argument";
+    case SIDM_ERR_NOMEM: return "out of device memory";
+    case SIDM_ERR_HIP: return "HIP runtime error";
+    case SIDM_ERR_CAPACITY: return "device capacity exceeded";
+    case SIDM_ERR_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char* sidm_last_error(const sidm_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+sidm_status sidm_create(sidm_ctx** out, int device, int64_t max_particles, int32_t max_halos)
+{
+    if (!out) return SIDM_ERR_INVALID;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return SIDM_ERR_INVALID;
+    if (max_particles < 2 || max_halos < 1 || max_particles > (int64_t(1) << 31))
+        return SIDM_ERR_INVALID;
+    sidm_ctx* c = new sidm_ctx();
+    c->device = device;
+    c->max_particles = max_particles;
+    c->max_halos = max_halos;
+    DeviceGuard g(device);
+    std::string why;
+    const int64_t max_events = std::max<int64_t>(4096, max_particles / 8);
+    if (!alloc_scratch(c->w, max_particles, max_halos, max_events, why)) {
+        free_scratch(c->w);
+        delete c;
+        return SIDM_ERR_NOMEM;
+    }
+    *out = c;
+    return SIDM_OK;
+}
+
+sidm_status sidm_set_event_capacity(sidm_ctx* c, int64_t max_events)
+{
+    if (!c || max_events < 1) return SIDM_ERR_INVALID;
+    DeviceGuard g(c->device);
+    std::string why;
+    if (!realloc_events(c->w, max_events, why)) {
+        set_err(c, "%s", why.c_str());
+        return SIDM_ERR_NOMEM;
+    }
+    return SIDM_OK;
+}
+
+void sidm_destroy(sidm_ctx* c)
+{
+    if (!c) return;
+    {
+        DeviceGuard g(c->device);
+        (void)hipDeviceSynchronize();
+        free_scratch(c->w);
+        for (auto& ev : c->ev)
+            if (ev) (void)hipEventDestroy(ev);
+    }
+    delete c;
+}
+
+sidm_status sidm_gravity(sidm_ctx* c, const sidm_halo* halos, int32_t n_halos,
+                         const sidm_state* s, sidm_precision prec, void* stream)
+{
+    sidm_status r = validate(c, halos, n_halos, s, NEED_GRAV);
+    if (r != SIDM_OK) return r;
+    if (prec != SIDM_PREC_FP64 && prec != SIDM_PREC_MIXED) {
+        set_err(c, "unknown precision %d", (int)prec);
+        return SIDM_ERR_INVALID;
+    }
+    DeviceGuard g(c->device);
+    hipStream_t st = (hipStream_t)stream;
+    if ((r = ensure_plan(c, halos, n_halos, st)) != SIDM_OK) return r;
+    const Plan& P = c->plan;
+    hipError_t e = launch_gravity(prec == SIDM_PREC_MIXED, s->x, s->y, s->z, s->m, c->w.halos,
+                                  n_halos, c->w.blocks, P.n_blocks, c->w.items, P.n_items,
+                                  c->w.bsum, c->w.cref, c->w.xm32, c->w.partial, s->ax, s->ay,
+                                  s->az, s->pot, nullptr, nullptr, nullptr, 0, st, nullptr,
+                                  nullptr);
+    if (e != hipSuccess) return hip_fail(c, e, "gravity launch");
+    c->err.clear();
+    return SIDM_OK;
+}
+
+sidm_status sidm_knn_h(sidm_ctx* c, const sidm_halo* halos, int32_t n_halos, const sidm_state* s,
+                       uint32_t* nbr, void* stream)
+{
+    sidm_status r = validate(c, halos, n_halos, s, NEED_KNN);
+    if (r != SIDM_OK) return r;
+    DeviceGuard g(c->device);
+    hipStream_t st = (hipStream_t)stream;
+    if ((r = ensure_plan(c, halos, n_halos, st)) != SIDM_OK) return r;
+    hipError_t e = launch_reset(c->plan, c->w, st);
+    if (e == hipSuccess) e = launch_cell_list(c->plan, s, c->w, st);
+    if (e == hipSuccess) e = launch_knn(c->plan, s, c->w, nbr, max_k(halos, n_halos), st);
+    if (e != hipSuccess) return hip_fail(c, e, "kNN launch");
+    c->err.clear();
+    return SIDM_OK;
+}
+
+sidm_status sidm_scatter(sidm_ctx* c, const sidm_halo* halos, int32_t n_halos,
+                         const sidm_state* s, uint32_t step, sidm_event* events, int64_t cap,
+                         int64_t* n_events_host, void* stream)
+{
+    sidm_status r = validate(c, halos, n_halos, s, NEED_SCATTER);
+    if (r != SIDM_OK) return r;
+    if (events && cap < 0) {
+        set_err(c, "negative event capacity");
+        return SIDM_ERR_INVALID;
+    }
+    DeviceGuard g(c->device);
+    hipStream_t st = (hipStream_t)stream;
+    if ((r = ensure_plan(c, halos, n_halos, st)) != SIDM_OK) return r;
+    hipError_t e = launch_reset(c->plan, c->w, st);
+    if (e == hipSuccess) e = launch_cell_list(c->plan, s, c->w, st);
+    if (e == hipSuccess) e = launch_tree_hmax(c->plan, c->w, st);
+    if (e == hipSuccess)
+        e = launch_scatter(c->plan, s, c->w, step, events, events ? cap : 0, st, nullptr);
+    if (e != hipSuccess) return hip_fail(c, e, "scatter launch");
+    if (n_events_host) {
+        unsigned long long cnt = 0;
+        e = hipMemcpyAsync(&cnt, &c->w.counters->n_events_total, sizeof cnt,
+                           hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(c, e, "reading the event count");
+        *n_events_host = (int64_t)cnt;
+        if ((int64_t)cnt > c->w.max_events || (events && (int64_t)cnt > cap)) {
+            set_err(c, "%llu events exceed the capacity (context %lld, caller %lld)", cnt,
+                    (long long)c->w.max_events, (long long)(events ? cap : -1));
+            return SIDM_ERR_CAPACITY;
+        }
+    }
+    c->err.clear();
+    return SIDM_OK;
+}
+
+sidm_status sidm_kdk_step(sidm_ctx* c, const sidm_halo* halos, int32_t n_halos,
+                          const sidm_state* s, uint32_t step, sidm_precision prec,
+                          sidm_diag* diag, void* stream)
+{
+    sidm_status r = validate(c, halos, n_halos, s, NEED_STEP);
+    if (r != SIDM_OK) return r;
+    if (prec != SIDM_PREC_FP64 && prec != SIDM_PREC_MIXED) {
+        set_err(c, "unknown precision %d", (int)prec);
+        return SIDM_ERR_INVALID;
+    }
+    DeviceGuard g(c->device);
+    hipStream_t st = (hipStream_t)stream;
+    if ((r = ensure_plan(c, halos, n_halos, st)) != SIDM_OK) return r;
+    const Plan& P = c->plan;
+    // events: 0 start, 1 after kick+drift, 2/3 around the gravity tiles,
+    // 4 after gravity, 5 after the cell list, 6 after kNN, 7 after the pair
+    // search, 8 after the kicks, 9 after the diagnostics
+    hipEvent_t* E = c->ev;
+    const bool tm = c->timing;
+    auto mark = [&](int i) {
+        if (tm) (void)hipEventRecord(E[i], st);
+    };
+    mark(0);
+    hipError_t e = launch_reset(P, c->w, st);
+    if (e == hipSuccess)
+        e = launch_kick_drift(c->w.blocks, P.n_blocks, c->w.halos, s->x, s->y, s->z, s->vx,
+                              s->vy, s->vz, s->ax, s->ay, s->az, st);
+    mark(1);
+    if (e == hipSuccess)
+        e = launch_gravity(prec == SIDM_PREC_MIXED, s->x, s->y, s->z, s->m, c->w.halos, n_halos,
+                           c->w.blocks, P.n_blocks, c->w.items, P.n_items, c->w.bsum, c->w.cref,
+                           c->w.xm32, c->w.partial, s->ax, s->ay, s->az, s->pot, s->vx, s->vy,
+                           s->vz, 1, st, tm ? E[2] : nullptr, tm ? E[3] : nullptr);
+    mark(4);
+    if (e == hipSuccess) e = launch_cell_list(P, s, c->w, st);
+    mark(5);
+    if (e == hipSuccess) e = launch_knn(P, s, c->w, nullptr, max_k(halos, n_halos), st);
+    if (e == hipSuccess) e = launch_tree_hmax(P, c->w, st);
+    mark(6);
+    if (e == hipSuccess) e = launch_scatter(P, s, c->w, step, nullptr, 0, st, tm ? E[7] : nullptr);
+    mark(8);
+    if (e == hipSuccess && diag)
+        e = launch_diag(c->w.blocks, P.n_blocks, c->w.halos, n_halos, s->x, s->y, s->z, s->vx,
+                        s->vy, s->vz, s->m, s->pot, c->w.bsum, c->w.ev_counts, c->w.status, diag,
+                        st);
+    mark(9);
+    c->timed = tm;
+    if (e != hipSuccess) return hip_fail(c, e, "step launch");
+    c->err.clear();
+    return SIDM_OK;
+}
+
+sidm_status sidm_diagnostics(sidm_ctx* c, const sidm_halo* halos, int32_t n_halos,
+                             const sidm_state* s, sidm_diag* diag, void* stream)
+{
+    sidm_status r = validate(c, halos, n_halos, s, 0);
+    if (r != SIDM_OK) return r;
+    if (!diag || !s->vx || !s->vy || !s->vz || !s->pot) {
+        set_err(c, "diag, vx, vy, vz and pot are required");
+        return SIDM_ERR_INVALID;
+    }
+    DeviceGuard g(c->device);
+    hipStream_t st = (hipStream_t)stream;
+    if ((r = ensure_plan(c, halos, n_halos, st)) != SIDM_OK) return r;
+    const Plan& P = c->plan;
+    hipError_t e = launch_diag(c->w.blocks, P.n_blocks, c->w.halos, n_halos, s->x, s->y, s->z,
+                               s->vx, s->vy, s->vz, s->m, s->pot, c->w.bsum, c->w.ev_counts,
+                               c->w.status, diag, st);
+    if (e != hipSuccess) return hip_fail(c, e, "diagnostics launch");
+    c->err.clear();
+    return SIDM_OK;
+}
+
+sidm_status sidm_enable_timing(sidm_ctx* c, int on)
+{
+    if (!c) return SIDM_ERR_INVALID;
+    DeviceGuard g(c->device);
+    if (on && !c->ev[0])
+        for (auto& ev : c->ev)
+            if (hipEventCreate(&ev) != hipSuccess) return hip_fail(c, hipGetLastError(), "events");
+    c->timing = on != 0;
+    return SIDM_OK;
+}
+
+sidm_status sidm_pass_times(sidm_ctx* c, double ms[SIDM_N_PASSES])
+{
+    if (!c || !ms) return SIDM_ERR_INVALID;
+    if (!c->timed) {
+        set_err(c, "no timed step recorded (enable timing, then run sidm_kdk_step)");
+        return SIDM_ERR_INVALID;
+    }
+    DeviceGuard g(c->device);
+    hipError_t e = hipEventSynchronize(c->ev[9]);
+    if (e != hipSuccess) return hip_fail(c, e, "waiting for the timed step");
+    const int from[SIDM_N_PASSES] = {0, 1, 2, 4, 5, 6, 7, 8};
+    const int to[SIDM_N_PASSES] = {1, 4, 3, 5, 6, 7, 8, 9};
+    for (int p = 0; p < SIDM_N_PASSES; ++p) {
+        float t = 0.f;
+        e = hipEventElapsedTime(&t, c->ev[from[p]], c->ev[to[p]]);
+        if (e != hipSuccess) return hip_fail(c, e, "reading pass times");
+        ms[p] = t;
+    }
+    return SIDM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,74 @@
+// sidm_internal.hpp -- data layout shared by the HIP kernels and the host
+// side of libsidm.  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+
+#include "sidm.h"
+
+namespace sidm {
+
+constexpr int kBucket = 64;          // particles per leaf bucket of the search tree
+constexpr int kFanout = 8;           // children per tree node
+constexpr int kMaxLevels = 10;       // tree levels above the buckets
+constexpr int kStreamBlock = 256;    // threads per block of the streaming kernels
+constexpr int kGravThreads = 256;    // threads per gravity block
+constexpr int kGravTileJ = 256;      // j-particles per LDS tile
+constexpr int kSortBits = 8;         // radix digit width
+constexpr int kSortItems = 16;       // keys per thread per sort block
+constexpr int kSortBlock = 256;
+
+// Per-halo parameters and derived layout, uploaded once per halo configuration.
+struct HaloDev {
+    int64_t offset, n;
+    double G, eps, eps2, sigma_m, dt;
+    int32_t k, host_kind;
+    uint64_t seed;
+    double host_K, host_r_s, host_c[3];   // host_K = 4 pi G rho_s r_s^3
+    // search tree: level 0 are the buckets, node ranges per level (global index
+    // into the box arrays)
+    int64_t level_off[kMaxLevels + 1];
+    int64_t level_n[kMaxLevels + 1];
+    int32_t n_levels;                     // number of levels (>= 1, level 0 = buckets)
+    int32_t grav_split;                   // j-splits of the gravity sum
+    int64_t part_base;                    // first partial row of this halo
+    int64_t stream_block0;                // first streaming block of this halo
+    int64_t sbase;                        // first position in the sorted (compact) order
+    int32_t rank;                         // halo rank by offset (high bits of the sort key)
+    int32_t pad0;
+    int32_t win_lo, win_hi;               // kNN bound window, in buckets around b
+    int32_t pad;
+};
+
+// A block of the streaming kernels never spans two halos.
+struct StreamBlock {
+    int64_t start;                        // first particle (global index)
+    int32_t count;                        // particles in this block (<= kStreamBlock)
+    int32_t halo;
+};
+
+// One gravity work item: i-block x j-range of one halo.
+struct GravItem {
+    int64_t i0;                           // first i (global index)
+    int64_t j0, j1;                       // j range (global indices), tile aligned
+    int32_t halo;
+    int32_t slot;                         // which partial row set
+};
+
+struct BucketInfo {
+    int64_t start;                        // first sorted position
+    int32_t count;
+    int32_t halo;
+};
+
+// Device-side error bits live in a per-halo status word.
+struct DevCounters {
+    unsigned long long n_events_total;    // events found (may exceed capacity)
+    unsigned long long ticket;            // persistent-kernel work counter
+};
+
+}  // namespace sidm

@@ -1,0 +1,344 @@
+// sidm_plan.hpp -- scratch memory of a context and the launch plan built for
+// one halo configuration (tables of streaming blocks, gravity work items,
+// search-tree buckets and nodes).  Host side only uses the std containers.
+#pragma once
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "sidm_internal.hpp"
+
+namespace sidm {
+
+// Event record kept on the device while the conflict-free rounds run.
+struct EventRec {
+    unsigned long long key;   // (a << 32) | b
+    int64_t ia, ib;           // original particle indices
+    int32_t halo;
+    uint32_t round;
+};
+
+// A tree node of level >= 1 and the range of its children (global indices).
+struct NodeTask {
+    int64_t node;
+    int64_t child0;
+    int32_t nchild;
+    int32_t pad;
+};
+
+// Children of every node of the search tree (buckets have none).
+struct NodeChild {
+    int64_t child0;
+    int32_t nchild;
+    int32_t pad;
+};
+
+struct Scratch {
+    int64_t max_particles = 0, max_events = 0;
+    int32_t max_halos = 0;
+    // plan tables
+    HaloDev* halos = nullptr;
+    StreamBlock* blocks = nullptr;
+    int64_t blocks_cap = 0;
+    GravItem* items = nullptr;
+    int64_t items_cap = 0;
+    BucketInfo* buckets = nullptr;
+    int64_t buckets_cap = 0;
+    NodeTask* node_tasks = nullptr;
+    NodeChild* nodes = nullptr;
+    int64_t nodes_cap = 0;        // bucket boxes + tree nodes
+    // gravity
+    double* bsum = nullptr;       // 7 doubles per streaming block
+    double* cref = nullptr;       // 3 per halo
+    double* bbox = nullptr;       // 6 per halo (min xyz, max xyz)
+    float4* xm32 = nullptr;
+    double4* partial = nullptr;
+    int64_t partial_rows = 0;
+    // cell list
+    unsigned long long* keys[2] = {nullptr, nullptr};
+    uint32_t* vals[2] = {nullptr, nullptr};
+    uint32_t* hist = nullptr;
+    int64_t hist_cap = 0;
+    double *sx = nullptr, *sy = nullptr, *sz = nullptr;
+    double *svx = nullptr, *svy = nullptr, *svz = nullptr;
+    double *sh = nullptr, *sm = nullptr;
+    uint32_t* sid = nullptr;
+    uint32_t* perm = nullptr;
+    double* box = nullptr;        // 6 per node (buckets first)
+    double* hmax = nullptr;       // 1 per node
+    // scattering
+    unsigned long long* owner = nullptr;
+    EventRec* events = nullptr;
+    DevCounters* counters = nullptr;
+    long long* ev_counts = nullptr;   // 4 per halo: events, rounds, pairs, P>1
+    int* status = nullptr;            // per halo
+};
+
+struct Plan {
+    int n_halos = 0;
+    int64_t n_sorted = 0;             // particles in halos
+    int64_t n_blocks = 0, n_items = 0, n_buckets = 0, n_nodes = 0;
+    int n_levels = 1;                 // max levels over halos
+    int key_bits = 48;
+    int64_t sort_blocks = 0;
+    std::vector<HaloDev> halos;
+    std::vector<StreamBlock> blocks;
+    std::vector<GravItem> items;
+    std::vector<BucketInfo> buckets;
+    std::vector<NodeTask> node_tasks;
+    std::vector<NodeChild> nodes;
+    std::vector<int64_t> level_task_off;  // tasks of level l: [off[l-1], off[l])
+    std::vector<int> rank_of;
+};
+
+template <typename T>
+inline bool dalloc(T*& p, int64_t count)
+{
+    p = nullptr;
+    if (count <= 0) count = 1;
+    return hipMalloc((void**)&p, sizeof(T) * (size_t)count) == hipSuccess;
+}
+
+template <typename T>
+inline void dfree(T*& p)
+{
+    if (p) (void)hipFree((void*)p);
+    p = nullptr;
+}
+
+inline bool realloc_events(Scratch& w, int64_t max_events, std::string& why)
+{
+    dfree(w.events);
+    w.max_events = max_events;
+    if (!dalloc(w.events, max_events)) {
+        why = "cannot allocate the event buffer";
+        w.max_events = 0;
+        return false;
+    }
+    return true;
+}
+
+inline bool alloc_scratch(Scratch& w, int64_t N, int32_t H, int64_t max_events, std::string& why)
+{
+    w.max_particles = N;
+    w.max_halos = H;
+    const int64_t nb = N / kStreamBlock + H + 1;
+    w.blocks_cap = nb;
+    w.items_cap = (N / (kGravThreads * 4) + H + 1) * 64;
+    w.partial_rows = std::max<int64_t>(4 * N, 1 << 18);
+    w.buckets_cap = N / kBucket + H + 1;
+    w.nodes_cap = w.buckets_cap * 2 + (int64_t)H * (kMaxLevels + 1);
+    const int64_t sort_blocks = N / (kSortBlock * kSortItems) + 1;
+    w.hist_cap = sort_blocks * (1 << kSortBits) + 1;
+    bool ok = dalloc(w.halos, H) && dalloc(w.blocks, nb) && dalloc(w.items, w.items_cap) &&
+              dalloc(w.buckets, w.buckets_cap) && dalloc(w.node_tasks, w.nodes_cap) && dalloc(w.nodes, w.nodes_cap) &&
+              dalloc(w.bsum, 7 * nb) && dalloc(w.cref, 3 * H) && dalloc(w.bbox, 6 * H) &&
+              dalloc(w.xm32, N) && dalloc(w.partial, w.partial_rows) && dalloc(w.keys[0], N) &&
+              dalloc(w.keys[1], N) && dalloc(w.vals[0], N) && dalloc(w.vals[1], N) &&
+              dalloc(w.hist, w.hist_cap) && dalloc(w.sx, N) && dalloc(w.sy, N) &&
+              dalloc(w.sz, N) && dalloc(w.svx, N) && dalloc(w.svy, N) && dalloc(w.svz, N) &&
+              dalloc(w.sh, N) && dalloc(w.sm, N) && dalloc(w.sid, N) && dalloc(w.perm, N) &&
+              dalloc(w.box, 6 * w.nodes_cap) && dalloc(w.hmax, w.nodes_cap) &&
+              dalloc(w.owner, N) && dalloc(w.counters, 1) && dalloc(w.ev_counts, 4 * H) &&
+              dalloc(w.status, H);
+    if (!ok) {
+        why = "device allocation failed";
+        return false;
+    }
+    if (!realloc_events(w, max_events, why)) return false;
+    // owner slots start free; the scattering pass restores them after use
+    std::vector<unsigned long long> ones((size_t)std::min<int64_t>(N, 1 << 20), ~0ull);
+    for (int64_t o = 0; o < N; o += (int64_t)ones.size()) {
+        const int64_t c = std::min<int64_t>((int64_t)ones.size(), N - o);
+        if (hipMemcpy(w.owner + o, ones.data(), sizeof(unsigned long long) * (size_t)c,
+                      hipMemcpyHostToDevice) != hipSuccess) {
+            why = "cannot initialise scratch";
+            return false;
+        }
+    }
+    return true;
+}
+
+inline void free_scratch(Scratch& w)
+{
+    dfree(w.halos); dfree(w.blocks); dfree(w.items); dfree(w.buckets); dfree(w.node_tasks); dfree(w.nodes);
+    dfree(w.bsum); dfree(w.cref); dfree(w.bbox); dfree(w.xm32); dfree(w.partial);
+    dfree(w.keys[0]); dfree(w.keys[1]); dfree(w.vals[0]); dfree(w.vals[1]); dfree(w.hist);
+    dfree(w.sx); dfree(w.sy); dfree(w.sz); dfree(w.svx); dfree(w.svy); dfree(w.svz);
+    dfree(w.sh); dfree(w.sm); dfree(w.sid); dfree(w.perm); dfree(w.box); dfree(w.hmax);
+    dfree(w.owner); dfree(w.events); dfree(w.counters); dfree(w.ev_counts); dfree(w.status);
+}
+
+// Number of j-splits for the gravity sum of each halo: enough work items to
+// fill the chip (a few blocks per CU), within the partial-row budget.
+inline void choose_splits(std::vector<HaloDev>& hd, int64_t partial_rows)
+{
+    const int64_t kIBlock = kGravThreads * 4;
+    int64_t iblocks = 0, ntot = 0;
+    for (auto& H : hd) {
+        iblocks += (H.n + kIBlock - 1) / kIBlock;
+        ntot += H.n;
+    }
+    const int64_t target = 2048;
+    int64_t split = std::max<int64_t>(1, (target + iblocks - 1) / iblocks);
+    split = std::min<int64_t>(split, std::max<int64_t>(1, partial_rows / std::max<int64_t>(ntot, 1)));
+    for (auto& H : hd) {
+        const int64_t tiles = (H.n + kGravTileJ - 1) / kGravTileJ;
+        H.grav_split = (int32_t)std::max<int64_t>(1, std::min<int64_t>(split, tiles));
+    }
+}
+
+inline bool build_plan(Plan& P, const Scratch& w, const sidm_halo* halos, int32_t n_halos,
+                       std::string& why)
+{
+    P = Plan();
+    P.n_halos = n_halos;
+    P.halos.resize(n_halos);
+    // halos ordered by offset define the sorted (compact) index space
+    std::vector<int> order(n_halos);
+    for (int h = 0; h < n_halos; ++h) order[h] = h;
+    std::sort(order.begin(), order.end(),
+              [&](int a, int b) { return halos[a].offset < halos[b].offset; });
+    std::vector<int64_t> sbase(n_halos);
+    int64_t acc = 0;
+    for (int r = 0; r < n_halos; ++r) {
+        sbase[order[r]] = acc;
+        P.rank_of.resize(n_halos);
+        P.rank_of[order[r]] = r;
+        acc += halos[order[r]].n;
+    }
+    P.n_sorted = acc;
+    int64_t node_count = 0;
+    for (int h = 0; h < n_halos; ++h) {
+        const sidm_halo& S = halos[h];
+        HaloDev& H = P.halos[h];
+        std::memset(&H, 0, sizeof H);
+        H.offset = S.offset;
+        H.n = S.n;
+        H.G = S.G;
+        H.eps = S.eps;
+        H.eps2 = S.eps * S.eps;
+        H.sigma_m = S.sigma_m;
+        H.dt = S.dt;
+        H.k = S.k;
+        H.host_kind = S.host_kind;
+        H.seed = S.seed;
+        H.host_r_s = S.host_r_s > 0 ? S.host_r_s : 1.0;
+        H.host_K = 4.0 * M_PI * S.G * S.host_rho_s * H.host_r_s * H.host_r_s * H.host_r_s;
+        for (int c = 0; c < 3; ++c) H.host_c[c] = S.host_center[c];
+        H.sbase = sbase[h];
+        H.rank = P.rank_of[h];
+        // streaming blocks
+        H.stream_block0 = (int64_t)P.blocks.size();
+        for (int64_t s0 = 0; s0 < S.n; s0 += kStreamBlock)
+            P.blocks.push_back(
+                {S.offset + s0, (int32_t)std::min<int64_t>(kStreamBlock, S.n - s0), h});
+        // buckets over the sorted range
+        const int64_t nbk = (S.n + kBucket - 1) / kBucket;
+        H.level_off[0] = (int64_t)P.buckets.size();
+        H.level_n[0] = nbk;
+        for (int64_t b = 0; b < nbk; ++b)
+            P.buckets.push_back({H.sbase + b * kBucket,
+                                 (int32_t)std::min<int64_t>(kBucket, S.n - b * kBucket), h});
+        // kNN bound window: buckets around b holding at least 2(k+1) particles
+        const int64_t want = 2 * ((int64_t)std::max(S.k, 1) + 1);
+        const int64_t wb = std::min<int64_t>(nbk, (want + kBucket - 1) / kBucket + 1);
+        H.win_lo = (int32_t)(wb / 2);
+        H.win_hi = (int32_t)(wb - 1 - wb / 2);
+    }
+    // tree levels (nodes after all buckets)
+    P.n_buckets = (int64_t)P.buckets.size();
+    node_count = P.n_buckets;
+    P.n_levels = 1;
+    std::vector<std::vector<NodeTask>> per_level(kMaxLevels + 1);
+    for (int h = 0; h < n_halos; ++h) {
+        HaloDev& H = P.halos[h];
+        int l = 0;
+        while (H.level_n[l] > 1) {
+            if (l + 1 > kMaxLevels) {
+                why = "search tree too deep";
+                return false;
+            }
+            const int64_t nn = (H.level_n[l] + kFanout - 1) / kFanout;
+            H.level_off[l + 1] = node_count;
+            H.level_n[l + 1] = nn;
+            for (int64_t j = 0; j < nn; ++j) {
+                const int64_t c0 = H.level_off[l] + j * kFanout;
+                const int32_t nc = (int32_t)std::min<int64_t>(kFanout, H.level_n[l] - j * kFanout);
+                per_level[l + 1].push_back({node_count + j, c0, nc, 0});
+            }
+            node_count += nn;
+            ++l;
+        }
+        H.n_levels = l + 1;
+        P.n_levels = std::max(P.n_levels, H.n_levels);
+    }
+    P.n_nodes = node_count;
+    P.nodes.assign((size_t)node_count, NodeChild{0, 0, 0});
+    for (int l = 1; l <= kMaxLevels; ++l)
+        for (auto& t : per_level[l]) P.nodes[(size_t)t.node] = NodeChild{t.child0, t.nchild, 0};
+    P.level_task_off.push_back(0);
+    for (int l = 1; l < P.n_levels; ++l) {
+        for (auto& t : per_level[l]) P.node_tasks.push_back(t);
+        P.level_task_off.push_back((int64_t)P.node_tasks.size());
+    }
+    // gravity work items
+    choose_splits(P.halos, w.partial_rows);
+    int64_t prow = 0;
+    const int64_t kIBlock = kGravThreads * 4;
+    for (int h = 0; h < n_halos; ++h) {
+        HaloDev& H = P.halos[h];
+        H.part_base = prow;
+        prow += H.n * H.grav_split;
+        const int64_t tiles = (H.n + kGravTileJ - 1) / kGravTileJ;
+        for (int s = 0; s < H.grav_split; ++s) {
+            const int64_t t0 = tiles * s / H.grav_split, t1 = tiles * (s + 1) / H.grav_split;
+            const int64_t j0 = H.offset + t0 * kGravTileJ;
+            const int64_t j1 = std::min<int64_t>(H.offset + H.n, H.offset + t1 * kGravTileJ);
+            for (int64_t i0 = 0; i0 < H.n; i0 += kIBlock)
+                P.items.push_back({H.offset + i0, j0, j1, h, s});
+        }
+    }
+    // largest items first so that the uneven tail is short
+    std::stable_sort(P.items.begin(), P.items.end(), [](const GravItem& a, const GravItem& b) {
+        return (a.j1 - a.j0) > (b.j1 - b.j0);
+    });
+    P.n_items = (int64_t)P.items.size();
+    P.n_blocks = (int64_t)P.blocks.size();
+    int hb = 0;
+    while ((1 << hb) < n_halos) ++hb;
+    P.key_bits = 48 + hb;
+    P.sort_blocks = (P.n_sorted + kSortBlock * kSortItems - 1) / (kSortBlock * kSortItems);
+    if (prow > w.partial_rows || P.n_items > w.items_cap || P.n_blocks > w.blocks_cap ||
+        P.n_buckets > w.buckets_cap || P.n_nodes > w.nodes_cap ||
+        (int64_t)P.node_tasks.size() > w.nodes_cap) {
+        why = "launch plan exceeds the context's table capacity";
+        return false;
+    }
+    return true;
+}
+
+inline hipError_t upload_plan(const Plan& P, const Scratch& w)
+{
+    hipError_t e = hipMemcpy(w.halos, P.halos.data(), sizeof(HaloDev) * P.halos.size(),
+                             hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(w.blocks, P.blocks.data(), sizeof(StreamBlock) * P.blocks.size(),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(w.items, P.items.data(), sizeof(GravItem) * P.items.size(),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(w.buckets, P.buckets.data(), sizeof(BucketInfo) * P.buckets.size(),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(w.nodes, P.nodes.data(), sizeof(NodeChild) * P.nodes.size(),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess && !P.node_tasks.empty())
+        e = hipMemcpy(w.node_tasks, P.node_tasks.data(), sizeof(NodeTask) * P.node_tasks.size(),
+                      hipMemcpyHostToDevice);
+    return e;
+}
+
+}  // namespace sidm

@@ -1,0 +1,114 @@
+"""GPU parity of sidm_knn_h (kernel sizes from the k nearest neighbours)
+against the oracle's brute force: h must match bit for bit (same FP64
+distance expression without fused multiply-add, correctly rounded sqrt), and
+the optional neighbour lists must equal the oracle's (d2, id)-ordered lists."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    import paper_2506_06269_amd as S
+    assert torch.cuda.is_available()
+    S.lib()
+    return S
+
+
+def _gpu_knn(S, halos, s, want_list=False, ctx=None):
+    import torch
+    dev = S.state_to_device(s)
+    n = s["x"].size
+    ctx = ctx or S.sidm_create(0, n, len(halos))
+    kmax = max(h["k"] for h in halos)
+    nbr = torch.zeros(n * kmax, dtype=torch.int32, device="cuda") if want_list else None
+    S.sidm_knn_h(ctx, halos, dev, nbr=nbr)
+    torch.cuda.synchronize()
+    h = dev["h"].cpu().numpy()
+    lists = nbr.cpu().numpy().view(np.uint32).reshape(n, kmax) if want_list else None
+    return h, lists
+
+
+@pytest.mark.parametrize("kind,n,k", [("nfw", 8192, 32), ("random", 1000, 16), ("random", 33, 32),
+                                      ("clustered", 3000, 128), ("lattice", 1000, 16),
+                                      ("lattice", 512, 1), ("nfw", 4100, 64)])
+def test_knn_bit_exact(S, orc, kind, n, k):
+    if kind == "nfw":
+        s = W.nfw_halo(n, seed=3)
+    elif kind == "random":
+        s = W.maxwell_box(n, seed=5)
+    elif kind == "clustered":
+        s = W.clustered(n, seed=8, width=0.005)
+    else:
+        s = W.lattice(round(n ** (1 / 3)), seed=4)
+        n = s["x"].size
+    print(f"knn {kind} n={n} k={k}", flush=True)
+    halo = dict(n=n, eps=0.01, k=k)
+    h, lists = _gpu_knn(S, [halo], s, want_list=n <= 8192)
+    href, lref = orc.knn(s["x"], s["y"], s["z"], s["id"], k, want_list=True)
+    bad = np.flatnonzero(h != href)
+    assert bad.size == 0, (bad[:5], h[bad[:5]], href[bad[:5]])
+    if lists is not None:
+        assert np.array_equal(lists[:, :k], lref)
+
+
+def test_knn_batched_mixed_k(S, orc):
+    """Four halos (k = 16, 32, 64, 128) in one call, offsets not in order."""
+    sizes = [4096, 5000, 6144, 4500]
+    ks = [16, 32, 64, 128]
+    offs = [11300, 0, 5100, 15500]
+    total = 20000
+    s = {f: np.zeros(total) for f in ("x", "y", "z", "vx", "vy", "vz")}
+    s["m"] = np.ones(total)
+    s["id"] = np.zeros(total, dtype=np.uint32)
+    halos, parts = [], []
+    for b, (n, k, o) in enumerate(zip(sizes, ks, offs)):
+        p = W.nfw_halo(n, seed=20 + b)
+        parts.append(p)
+        for f in ("x", "y", "z", "vx", "vy", "vz", "m", "id"):
+            s[f][o:o + n] = p[f]
+        halos.append(dict(n=n, offset=o, eps=0.01, k=k))
+    h, _ = _gpu_knn(S, halos, s)
+    for p, hh in zip(parts, halos):
+        ref = orc.knn(p["x"], p["y"], p["z"], p["id"], hh["k"])
+        got = h[hh["offset"]:hh["offset"] + hh["n"]]
+        assert np.array_equal(got, ref), hh
+
+
+def test_knn_large_sampled(S, orc):
+    """N = 2^20 halo in the host (the benchmark's workload), k = 64: h of 512
+    sampled particles against the oracle's brute force over all N."""
+    cfg = W.config("C2")
+    s = W.make_state(cfg)
+    halo = dict(n=cfg["n"], eps=cfg["eps"], k=cfg["k"])
+    h, _ = _gpu_knn(S, [halo], s)
+    q = np.random.default_rng(1).choice(cfg["n"], 512, replace=False)
+    ref = orc.knn(s["x"], s["y"], s["z"], s["id"], cfg["k"], query=q)
+    assert np.array_equal(h[q], ref)
+    assert np.all(np.isfinite(h)) and np.all(h > 0)
+
+
+def test_knn_coincident_particles(S, orc):
+    """Exact duplicates: zero distances and ties everywhere."""
+    base = W.maxwell_box(200, seed=2)
+    s = {f: np.concatenate([base[f]] * 3) for f in ("x", "y", "z", "vx", "vy", "vz", "m")}
+    s["id"] = np.random.default_rng(0).permutation(600).astype(np.uint32)
+    for k in (1, 2, 5):
+        halo = dict(n=600, eps=0.01, k=k)
+        h, lists = _gpu_knn(S, [halo], s, want_list=True)
+        href, lref = orc.knn(s["x"], s["y"], s["z"], s["id"], k, want_list=True)
+        assert np.array_equal(h, href)
+        assert np.array_equal(lists[:, :k], lref)
+
+
+def test_knn_rejects_bad_k(S):
+    s = W.maxwell_box(64, seed=0)
+    dev = S.state_to_device(s)
+    ctx = S.sidm_create(0, 64, 1)
+    for k in (0, 64, 200):
+        with pytest.raises(S.SidmError):
+            S.sidm_knn_h(ctx, [dict(n=64, eps=0.1, k=k)], dev)

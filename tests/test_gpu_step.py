@@ -1,0 +1,151 @@
+"""GPU parity of the full step (sidm_kdk_step) with the step-wise protocol:
+trajectories of an N-body system are chaotic, so at each checked step the GPU
+state S_n is copied to the oracle, the oracle makes one step, and its S_{n+1}
+is compared with the GPU's.  FP64 bars: 1e-12 (positions and velocities
+relative to their largest magnitude, accelerations normwise), kernel sizes to
+1e-12 relative, identical event counts; the mixed path: 1e-5 normwise for the
+accelerations.  Also: leapfrog reversibility and energy conservation."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    import paper_2506_06269_amd as S
+    assert torch.cuda.is_available()
+    S.lib()
+    return S
+
+
+def _orc_params(orc, halo):
+    return orc.make_params(G=halo.get("G", 1.0), eps=halo["eps"], sigma_m=halo["sigma_m"],
+                           dt=halo["dt"], k=halo["k"], seed=halo.get("seed", 0),
+                           host=halo.get("host"))
+
+
+def _c1(n=8192):
+    cfg = W.config("C1")
+    halo = dict(n=n, eps=cfg["eps"], sigma_m=cfg["sigma_m"], dt=cfg["dt"], k=cfg["k"], seed=0)
+    return W.nfw_halo(n, seed=0), halo
+
+
+def _start(S, orc, s, halo, prec):
+    import torch
+    dev = S.state_to_device(s)
+    ctx = S.sidm_create(0, s["x"].size, 1)
+    S.sidm_gravity(ctx, [halo], dev, prec)
+    torch.cuda.synchronize()
+    return ctx, dev
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_step_parity_c1(S, orc, prec):
+    """Isolated NFW halo, N = 8192, k = 32, sigma/m = 1, dt = 1e-3."""
+    import torch
+    s, halo = _c1()
+    p = _orc_params(orc, halo)
+    ctx, dev = _start(S, orc, s, halo, prec)
+    diag = S.diag_buffer(1)
+    tol_a = 1e-12 if prec == 0 else 1e-5
+    tol_xv = 1e-12 if prec == 0 else 1e-7
+    total_events = 0
+    for step in range(4):
+        before = S.state_to_host(dev)
+        ref = {k: v.copy() for k, v in before.items()}
+        ev = orc.kdk_step(ref, p, step)
+        S.sidm_kdk_step(ctx, [halo], dev, step, prec, diag=diag)
+        torch.cuda.synchronize()
+        out = S.state_to_host(dev)
+        d = S.read_diag(diag)[0]
+        print(f"step {step}: events gpu {d['n_events']} oracle {ev.size} rounds {d['n_rounds']}",
+              flush=True)
+        _, _, _, _, an = orc.gravity(ref["x"], ref["y"], ref["z"], ref["m"], 1.0, halo["eps"],
+                                     want_norm=True)
+        ea = np.sqrt((out["ax"] - ref["ax"]) ** 2 + (out["ay"] - ref["ay"]) ** 2 +
+                     (out["az"] - ref["az"]) ** 2) / an
+        assert ea.max() < tol_a, ea.max()
+        for c in ("x", "y", "z", "vx", "vy", "vz"):
+            assert np.max(np.abs(out[c] - ref[c])) <= tol_xv * np.max(np.abs(ref[c])), c
+        rel_h = np.abs(out["h"] - ref["h"]) / ref["h"]
+        assert rel_h.max() <= (1e-12 if prec == 0 else 1e-6)
+        if prec == 0:
+            assert d["n_events"] == ev.size
+        assert d["status"] == 0
+        total_events += d["n_events"]
+        od = orc.diag(out["vx"], out["vy"], out["vz"], out["m"], out["pot"])
+        assert d["K"] == pytest.approx(od["K"], rel=1e-12)
+        assert d["W"] == pytest.approx(od["W"], rel=1e-12)
+    assert total_events > 0
+
+
+def test_step_reversible_fp64(S, orc):
+    """sigma = 0: 16 steps forward, reverse the velocities, 16 steps back."""
+    import torch
+    s = W.plummer(2048, seed=8)
+    halo = dict(n=2048, eps=0.05, sigma_m=0.0, dt=0.01, k=8)
+    ctx, dev = _start(S, orc, s, halo, 0)
+    x0 = np.stack([s["x"], s["y"], s["z"]])
+    for step in range(16):
+        S.sidm_kdk_step(ctx, [halo], dev, step, 0)
+    for c in ("vx", "vy", "vz"):
+        dev[c].neg_()
+    for step in range(16):
+        S.sidm_kdk_step(ctx, [halo], dev, step, 0)
+    torch.cuda.synchronize()
+    out = S.state_to_host(dev)
+    x1 = np.stack([out["x"], out["y"], out["z"]])
+    err = np.max(np.abs(x1 - x0)) / np.max(np.abs(x0))
+    print(f"reversibility error {err:.2e}")
+    assert err < 1e-12
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_step_energy_conservation(S, orc, prec):
+    """C1 for its 32 steps: |E(t) - E(0)| / |E(0)| stays far below the 1e-3
+    target; momentum stays at roundoff."""
+    import torch
+    s, halo = _c1()
+    ctx, dev = _start(S, orc, s, halo, prec)
+    diag = S.diag_buffer(1)
+    S.sidm_diagnostics(ctx, [halo], dev, diag)
+    d0 = S.read_diag(diag)[0]
+    e0 = d0["K"] + d0["W"] + d0["Eext"]
+    worst = 0.0
+    for step in range(32):
+        S.sidm_kdk_step(ctx, [halo], dev, step, prec, diag=diag)
+        d = S.read_diag(diag)[0]
+        worst = max(worst, abs(d["K"] + d["W"] + d["Eext"] - e0) / abs(e0))
+    torch.cuda.synchronize()
+    print(f"prec {prec}: max |dE/E| over 32 steps = {worst:.3e}; last p = "
+          f"({d['px']:.2e}, {d['py']:.2e}, {d['pz']:.2e})")
+    assert worst < 1e-4
+    assert abs(d["px"]) + abs(d["py"]) + abs(d["pz"]) < 1e-9
+
+
+def test_step_satellite_in_host(S, orc):
+    """Halo on its circular orbit in the static host (mixed precision):
+    one step against the oracle, and the centre of mass follows the orbit."""
+    import torch
+    n = 4096
+    s = W.place_on_orbit(W.nfw_halo(n, seed=12))
+    halo = dict(n=n, eps=0.01, sigma_m=10.0, dt=1e-3, k=64, seed=0, host=W.host_params())
+    p = _orc_params(orc, halo)
+    ctx, dev = _start(S, orc, s, halo, 1)
+    before = S.state_to_host(dev)
+    ref = {k: v.copy() for k, v in before.items()}
+    orc.kdk_step(ref, p, 0)
+    S.sidm_kdk_step(ctx, [halo], dev, 0, 1)
+    torch.cuda.synchronize()
+    out = S.state_to_host(dev)
+    for c in ("x", "y", "z"):
+        assert np.max(np.abs(out[c] - ref[c])) <= 1e-12 * np.max(np.abs(ref[c]))
+    vs = np.max(np.abs(ref["vy"]))
+    for c in ("vx", "vy", "vz"):
+        assert np.max(np.abs(out[c] - ref[c])) <= 1e-6 * vs
+    cx = np.mean(out["x"])
+    assert abs(cx - W.ORBIT_R) < 0.05
