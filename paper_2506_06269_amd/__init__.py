@@ -180,6 +180,15 @@ def sidm_destroy(ctx):
         ctx.handle = None
 
 
+def sidm_status_string(status):
+    return lib().sidm_status_string(int(status)).decode()
+
+
+def sidm_last_error(ctx):
+    msg = lib().sidm_last_error(ctx.handle if ctx is not None else None)
+    return msg.decode() if msg else ""
+
+
 def sidm_set_event_capacity(ctx, max_events):
     _check(ctx, lib().sidm_set_event_capacity(ctx.handle, int(max_events)))
 

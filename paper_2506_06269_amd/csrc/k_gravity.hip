@@ -1,165 +1,221 @@
 // k_gravity.hip -- softened direct-sum self-gravity plus the static NFW host
 // (Sec. 2: softening length eps; Sec. 4.1 Eq. nfw_potential).
 //
+// The sums run over the Morton-sorted order of the cell list, in tiles of
+// kGravTileJ consecutive particles.  In the mixed form the frames are the
+// compact sub-ranges of the cell list's 64-particle buckets; FP32 positions
+// are stored relative to the FP64 centre of their frame, and an i-particle is
+// moved into the frame of the j-particles once per frame (x_i - c_j computed as
+// (x_i - c_i) - (c_j - c_i)),
+// so close pairs subtract small local coordinates: FP32 position rounding is
+// relative to the pair separation, not to the size of the halo.
+//
 // Work decomposition: a work item is (halo, i-block of kGravThreads * IREG
 // particles, j-range).  Each thread keeps IREG i-particles in registers; the
-// block stages kGravTileJ j-particles at a time in LDS with one coalesced load
-// per thread, and every lane of a wave reads the same j (LDS broadcast).  The
-// pair terms of one tile are summed plainly, and the tile sums are folded into
-// Kahan-compensated accumulators, so the rounding error does not grow with N.
-// The self pair j == i is skipped exactly in the few tiles that hold i.
-// Each item writes one FP64 partial row per i; a finalize pass adds the rows
-// of an i in a fixed order, scales by G, adds the host and (optionally)
-// applies the closing half kick.
-#include "sidm_internal.hpp"
+// block stages a j-tile in LDS with one coalesced load per thread, and every
+// lane of a wave reads the same j (LDS broadcast).  The pair terms of one tile
+// are summed plainly and the tile sums are folded into Kahan-compensated
+// accumulators, so the rounding error does not grow with N.  The self pair is
+// skipped exactly in the few tiles that hold i.  Each item writes one FP64
+// partial row per i; a finalize pass adds the rows of an i in a fixed order,
+// scales by G, adds the host, optionally applies the closing half kick, and
+// scatters to the caller's (unsorted) arrays.
+#include "sidm_plan.hpp"
 
 namespace sidm {
 
-// ---------------------------------------------------------------- recentre
-// Mean position of each halo (FP64), deterministic two-level reduction.
-__global__ __launch_bounds__(kStreamBlock) void k_block_sum_pos(
-    const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
-    const StreamBlock* __restrict__ blocks, double* __restrict__ bsum)
+// ---------------------------------------------------------------- masses, tiles
+// Smallest and largest mass per streaming block, then per halo: cmass[h] is
+// the common mass when all masses of the halo are equal (else 0).
+__global__ __launch_bounds__(kStreamBlock) void k_block_mass_range(
+    const double* __restrict__ m, const StreamBlock* __restrict__ blocks, double* __restrict__ bsum)
 {
-    __shared__ double red[3][kStreamBlock];
+    __shared__ double lo[kStreamBlock], hi[kStreamBlock];
     const StreamBlock B = blocks[blockIdx.x];
     const int t = threadIdx.x;
-    double sx = 0, sy = 0, sz = 0;
-    if (t < B.count) {
-        const int64_t i = B.start + t;
-        sx = x[i]; sy = y[i]; sz = z[i];
-    }
-    red[0][t] = sx; red[1][t] = sy; red[2][t] = sz;
+    const double mi = m[B.start + (t < B.count ? t : 0)];
+    lo[t] = mi;
+    hi[t] = mi;
     __syncthreads();
     for (int s = kStreamBlock / 2; s > 0; s >>= 1) {
         if (t < s) {
-            red[0][t] += red[0][t + s];
-            red[1][t] += red[1][t + s];
-            red[2][t] += red[2][t + s];
+            lo[t] = fmin(lo[t], lo[t + s]);
+            hi[t] = fmax(hi[t], hi[t + s]);
         }
         __syncthreads();
     }
     if (t == 0) {
-        bsum[3 * (int64_t)blockIdx.x + 0] = red[0][0];
-        bsum[3 * (int64_t)blockIdx.x + 1] = red[1][0];
-        bsum[3 * (int64_t)blockIdx.x + 2] = red[2][0];
+        bsum[7 * (int64_t)blockIdx.x + 0] = lo[0];
+        bsum[7 * (int64_t)blockIdx.x + 1] = hi[0];
     }
 }
 
-// One block per halo: sums its block partials in a fixed order.
-__global__ __launch_bounds__(kStreamBlock) void k_halo_mean_pos(
-    const HaloDev* __restrict__ halos, const double* __restrict__ bsum,
-    double* __restrict__ cref)
+__global__ __launch_bounds__(kStreamBlock) void k_halo_mass(
+    const HaloDev* __restrict__ halos, const double* __restrict__ bsum, double* __restrict__ cmass)
 {
-    __shared__ double red[3][kStreamBlock];
+    __shared__ double lo[kStreamBlock], hi[kStreamBlock];
     const HaloDev& H = halos[blockIdx.x];
     const int t = threadIdx.x;
     const int64_t nb = (H.n + kStreamBlock - 1) / kStreamBlock;
-    double s[3] = {0, 0, 0};
-    for (int64_t b = t; b < nb; b += kStreamBlock)
-        for (int c = 0; c < 3; ++c) s[c] += bsum[3 * (H.stream_block0 + b) + c];
-    for (int c = 0; c < 3; ++c) red[c][t] = s[c];
+    double l = INFINITY, u = -INFINITY;
+    for (int64_t b = t; b < nb; b += kStreamBlock) {
+        l = fmin(l, bsum[7 * (H.stream_block0 + b) + 0]);
+        u = fmax(u, bsum[7 * (H.stream_block0 + b) + 1]);
+    }
+    lo[t] = l;
+    hi[t] = u;
     __syncthreads();
-    for (int st = kStreamBlock / 2; st > 0; st >>= 1) {
-        if (t < st)
-            for (int c = 0; c < 3; ++c) red[c][t] += red[c][t + st];
+    for (int s = kStreamBlock / 2; s > 0; s >>= 1) {
+        if (t < s) {
+            lo[t] = fmin(lo[t], lo[t + s]);
+            hi[t] = fmax(hi[t], hi[t + s]);
+        }
         __syncthreads();
     }
-    if (t == 0)
-        for (int c = 0; c < 3; ++c) cref[3 * blockIdx.x + c] = red[c][0] / (double)H.n;
+    if (t == 0) cmass[blockIdx.x] = lo[0] == hi[0] ? lo[0] : 0.0;
 }
 
-// x32 = f32(x - c_ref), w = f32(m)
-__global__ __launch_bounds__(kStreamBlock) void k_pack32(
-    const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
-    const double* __restrict__ m, const StreamBlock* __restrict__ blocks,
-    const double* __restrict__ cref, float4* __restrict__ xm32)
+// Frame of a sorted position: the compact sub-range of its bucket that holds
+// it; its centre is the midpoint of the sub-range's box.
+__device__ inline void frame_of(const HaloDev& H, const SubRange* __restrict__ sub,
+                                const int* __restrict__ sub_n, int64_t local, double* c)
+{
+    const int64_t b = H.level_off[0] + local / kBucket;
+    const int o = (int)(local % kBucket);
+    const int ns = sub_n[b];
+    int f = 0;
+    while (f + 1 < ns && o >= sub[kSubMax * b + f + 1].off) ++f;
+    const double* bx = sub[kSubMax * b + f].box;
+    c[0] = 0.5 * (bx[0] + bx[3]);
+    c[1] = 0.5 * (bx[1] + bx[4]);
+    c[2] = 0.5 * (bx[2] + bx[5]);
+}
+
+// FP32 positions relative to the centre of their frame, and the mass.
+__global__ __launch_bounds__(kStreamBlock) void k_pack_frames(
+    const double* __restrict__ sx, const double* __restrict__ sy, const double* __restrict__ sz,
+    const double* __restrict__ sm, const StreamBlock* __restrict__ blocks,
+    const HaloDev* __restrict__ halos, const SubRange* __restrict__ sub,
+    const int* __restrict__ sub_n, float4* __restrict__ xm32)
 {
     const StreamBlock B = blocks[blockIdx.x];
     const int t = threadIdx.x;
     if (t >= B.count) return;
-    const int64_t i = B.start + t;
-    const double* c = cref + 3 * B.halo;
-    xm32[i] = make_float4((float)(x[i] - c[0]), (float)(y[i] - c[1]), (float)(z[i] - c[2]),
-                          (float)m[i]);
+    const HaloDev& H = halos[B.halo];
+    const int64_t local = (B.start - H.offset) + t;
+    const int64_t p = H.sbase + local;
+    double c[3];
+    frame_of(H, sub, sub_n, local, c);
+    xm32[p] = make_float4((float)(sx[p] - c[0]), (float)(sy[p] - c[1]), (float)(sz[p] - c[2]),
+                          (float)sm[p]);
 }
 
 // ---------------------------------------------------------------- FP32 tiles
-template <int IREG>
-__global__ __launch_bounds__(kGravThreads) void k_grav_mixed(
-    const float4* __restrict__ xm32, const GravItem* __restrict__ items,
-    const HaloDev* __restrict__ halos, double4* __restrict__ partial)
+// Sums of the pair terms of one LDS tile for IREG i-particles.  With EQM (all
+// masses of the halo equal) the mass is factored out of the sums and applied
+// once per partial row: one multiply fewer per interaction.  DIAG tiles hold
+// some of the block's own i and skip j == i exactly.
+template <int IREG, bool EQM, bool DIAG>
+__device__ inline void tile_f32(const float4* __restrict__ tile, int ja, int jb, const float* xi,
+                                const float* yi, const float* zi, float eps2, int64_t j0, int64_t i0,
+                                int t, float* px, float* py, float* pz, float* pp)
 {
-    __shared__ float4 tile[kGravTileJ];
-    const GravItem it = items[blockIdx.x];
-    const HaloDev& H = halos[it.halo];
-    const int64_t hend = H.offset + H.n;
+#pragma unroll 4
+    for (int jj = ja; jj < jb; ++jj) {
+        const float4 q = tile[jj];
+#pragma unroll
+        for (int r = 0; r < IREG; ++r) {
+            const float dx = q.x - xi[r];
+            const float dy = q.y - yi[r];
+            const float dz = q.z - zi[r];
+            const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
+            float rinv = __builtin_amdgcn_rsqf(r2);
+            if (DIAG && j0 + jj == i0 + (int64_t)r * kGravThreads + t) rinv = 0.f;
+            if (EQM) {
+                const float rinv3 = rinv * (rinv * rinv);
+                px[r] = fmaf(rinv3, dx, px[r]);
+                py[r] = fmaf(rinv3, dy, py[r]);
+                pz[r] = fmaf(rinv3, dz, pz[r]);
+                pp[r] += rinv;
+            } else {
+                const float mr = q.w * rinv;
+                const float mr3 = mr * (rinv * rinv);
+                px[r] = fmaf(mr3, dx, px[r]);
+                py[r] = fmaf(mr3, dy, py[r]);
+                pz[r] = fmaf(mr3, dz, pz[r]);
+                pp[r] += mr;
+            }
+        }
+    }
+}
+
+template <int IREG, bool EQM>
+__device__ inline void grav_mixed_body(const float4* __restrict__ xm32,
+                                       const SubRange* __restrict__ sub,
+                                       const int* __restrict__ sub_n, const GravItem& it,
+                                       const HaloDev& H, double mscale,
+                                       double4* __restrict__ partial, float4* tile)
+{
     const int t = threadIdx.x;
     const float eps2 = (float)H.eps2;
+    const int64_t il0 = it.i0 - H.offset;   // local (sorted) index of the i-block
 
     float xi[IREG], yi[IREG], zi[IREG];
+    double cix[IREG], ciy[IREG], ciz[IREG];          // centre of each i's frame
     float sx[IREG], sy[IREG], sz[IREG], sp[IREG];     // Kahan sums
     float cx[IREG], cy[IREG], cz[IREG], cp[IREG];     // Kahan compensations
 #pragma unroll
     for (int r = 0; r < IREG; ++r) {
-        const int64_t i = it.i0 + (int64_t)r * kGravThreads + t;
+        const int64_t li = il0 + (int64_t)r * kGravThreads + t;
         float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (i < hend) p = xm32[i];
+        cix[r] = ciy[r] = ciz[r] = 0.0;
+        if (li < H.n) {
+            p = xm32[H.sbase + li];
+            double c[3];
+            frame_of(H, sub, sub_n, li, c);
+            cix[r] = c[0]; ciy[r] = c[1]; ciz[r] = c[2];
+        }
         xi[r] = p.x; yi[r] = p.y; zi[r] = p.z;
         sx[r] = sy[r] = sz[r] = sp[r] = 0.f;
         cx[r] = cy[r] = cz[r] = cp[r] = 0.f;
     }
-
+    const int64_t last_bucket = H.level_off[0] + H.level_n[0] - 1;
     for (int64_t j0 = it.j0; j0 < it.j1; j0 += kGravTileJ) {
-        const int64_t j = j0 + t;
-        float4 pj = make_float4(0.f, 0.f, 0.f, 0.f);   // m = 0 pads the last tile
-        if (j < it.j1) pj = xm32[j];
+        const int64_t lj0 = j0 - H.offset;
+        float4 pj = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (j0 + t < it.j1) pj = xm32[H.sbase + lj0 + t];
         __syncthreads();
         tile[t] = pj;
         __syncthreads();
         float px[IREG], py[IREG], pz[IREG], pp[IREG];
 #pragma unroll
         for (int r = 0; r < IREG; ++r) px[r] = py[r] = pz[r] = pp[r] = 0.f;
-        // the few tiles that hold i itself skip j == i exactly; all others
-        // run the branch-free loop
         const bool diag = j0 < it.i0 + (int64_t)IREG * kGravThreads && j0 + kGravTileJ > it.i0;
-        if (diag) {
-            for (int jj = 0; jj < kGravTileJ; ++jj) {
-                const float4 q = tile[jj];
+        // the tile's buckets and their compact sub-ranges are the frames
+        const int64_t b0 = H.level_off[0] + lj0 / kBucket;
+        for (int64_t b = b0; b < b0 + kGravTileJ / kBucket && b <= last_bucket; ++b) {
+            const int ns = sub_n[b];
+            const int base = (int)((b - b0) * kBucket);
+            for (int f = 0; f < ns; ++f) {
+                const SubRange& R = sub[kSubMax * b + f];
+                const double fx = 0.5 * (R.box[0] + R.box[3]);
+                const double fy = 0.5 * (R.box[1] + R.box[4]);
+                const double fz = 0.5 * (R.box[2] + R.box[5]);
+                // i-positions in the frame of these j
+                float qx[IREG], qy[IREG], qz[IREG];
 #pragma unroll
                 for (int r = 0; r < IREG; ++r) {
-                    const float dx = q.x - xi[r];
-                    const float dy = q.y - yi[r];
-                    const float dz = q.z - zi[r];
-                    const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
-                    const float rinv = __builtin_amdgcn_rsqf(r2);
-                    const bool self = j0 + jj == it.i0 + (int64_t)r * kGravThreads + t;
-                    const float mr = self ? 0.f : q.w * rinv;
-                    const float mr3 = mr * (rinv * rinv);
-                    px[r] = fmaf(mr3, dx, px[r]);
-                    py[r] = fmaf(mr3, dy, py[r]);
-                    pz[r] = fmaf(mr3, dz, pz[r]);
-                    pp[r] += mr;
+                    qx[r] = xi[r] - (float)(fx - cix[r]);
+                    qy[r] = yi[r] - (float)(fy - ciy[r]);
+                    qz[r] = zi[r] - (float)(fz - ciz[r]);
                 }
-            }
-        } else {
-#pragma unroll 4
-            for (int jj = 0; jj < kGravTileJ; ++jj) {
-                const float4 q = tile[jj];
-#pragma unroll
-                for (int r = 0; r < IREG; ++r) {
-                    const float dx = q.x - xi[r];
-                    const float dy = q.y - yi[r];
-                    const float dz = q.z - zi[r];
-                    const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
-                    const float rinv = __builtin_amdgcn_rsqf(r2);
-                    const float mr = q.w * rinv;
-                    const float mr3 = mr * (rinv * rinv);
-                    px[r] = fmaf(mr3, dx, px[r]);
-                    py[r] = fmaf(mr3, dy, py[r]);
-                    pz[r] = fmaf(mr3, dz, pz[r]);
-                    pp[r] += mr;
-                }
+                const int ja = base + R.off, jb = base + R.off + R.cnt;
+                if (diag)
+                    tile_f32<IREG, EQM, true>(tile, ja, jb, qx, qy, qz, eps2, j0, it.i0, t, px, py,
+                                              pz, pp);
+                else
+                    tile_f32<IREG, EQM, false>(tile, ja, jb, qx, qy, qz, eps2, j0, it.i0, t, px,
+                                               py, pz, pp);
             }
         }
 #pragma unroll
@@ -173,44 +229,65 @@ __global__ __launch_bounds__(kGravThreads) void k_grav_mixed(
     }
 #pragma unroll
     for (int r = 0; r < IREG; ++r) {
-        const int64_t i = it.i0 + (int64_t)r * kGravThreads + t;
-        if (i >= hend) continue;
-        const int64_t row = H.part_base + (int64_t)it.slot * H.n + (i - H.offset);
+        const int64_t li = il0 + (int64_t)r * kGravThreads + t;
+        if (li >= H.n) continue;
+        const int64_t row = H.part_base + (int64_t)it.slot * H.n + li;
         // the compensation holds the negated lost low part
-        partial[row] = make_double4((double)sx[r] - (double)cx[r], (double)sy[r] - (double)cy[r],
-                                    (double)sz[r] - (double)cz[r], (double)sp[r] - (double)cp[r]);
+        partial[row] = make_double4(mscale * ((double)sx[r] - (double)cx[r]),
+                                    mscale * ((double)sy[r] - (double)cy[r]),
+                                    mscale * ((double)sz[r] - (double)cz[r]),
+                                    mscale * ((double)sp[r] - (double)cp[r]));
     }
 }
 
-// ---------------------------------------------------------------- FP64 tiles
 template <int IREG>
-__global__ __launch_bounds__(kGravThreads) void k_grav_fp64(
-    const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
-    const double* __restrict__ m, const GravItem* __restrict__ items,
-    const HaloDev* __restrict__ halos, double4* __restrict__ partial)
+__global__ __launch_bounds__(kGravThreads) void k_grav_mixed(
+    const float4* __restrict__ xm32, const SubRange* __restrict__ sub,
+    const int* __restrict__ sub_n, const GravItem* __restrict__ items,
+    const HaloDev* __restrict__ halos,
+    const double* __restrict__ cmass, double4* __restrict__ partial)
 {
-    __shared__ double4 tile[kGravTileJ];
+    __shared__ float4 tile[kGravTileJ];
     const GravItem it = items[blockIdx.x];
     const HaloDev& H = halos[it.halo];
-    const int64_t hend = H.offset + H.n;
+    const double meq = cmass[it.halo];
+    if (meq > 0.0)
+        grav_mixed_body<IREG, true>(xm32, sub, sub_n, it, H, (double)(float)meq, partial, tile);
+    else
+        grav_mixed_body<IREG, false>(xm32, sub, sub_n, it, H, 1.0, partial, tile);
+}
+
+// ---------------------------------------------------------------- FP64 tiles
+template <int IREG, bool EQM>
+__device__ inline void grav_fp64_body(const double* __restrict__ x, const double* __restrict__ y,
+                                      const double* __restrict__ z, const double* __restrict__ m,
+                                      const GravItem& it, const HaloDev& H, double mscale,
+                                      double4* __restrict__ partial, double4* tile)
+{
     const int t = threadIdx.x;
     const double eps2 = H.eps2;
+    const int64_t il0 = it.i0 - H.offset;
 
     double xi[IREG], yi[IREG], zi[IREG];
     double sx[IREG], sy[IREG], sz[IREG], sp[IREG];
     double cx[IREG], cy[IREG], cz[IREG], cp[IREG];
 #pragma unroll
     for (int r = 0; r < IREG; ++r) {
-        const int64_t i = it.i0 + (int64_t)r * kGravThreads + t;
+        const int64_t li = il0 + (int64_t)r * kGravThreads + t;
         xi[r] = yi[r] = zi[r] = 0.0;
-        if (i < hend) { xi[r] = x[i]; yi[r] = y[i]; zi[r] = z[i]; }
+        if (li < H.n) {
+            const int64_t p = H.sbase + li;
+            xi[r] = x[p]; yi[r] = y[p]; zi[r] = z[p];
+        }
         sx[r] = sy[r] = sz[r] = sp[r] = 0.0;
         cx[r] = cy[r] = cz[r] = cp[r] = 0.0;
     }
     for (int64_t j0 = it.j0; j0 < it.j1; j0 += kGravTileJ) {
-        const int64_t j = j0 + t;
-        double4 pj = make_double4(0.0, 0.0, 0.0, 0.0);
-        if (j < it.j1) pj = make_double4(x[j], y[j], z[j], m[j]);
+        double4 pj = make_double4(1.0e300, 1.0e300, 1.0e300, 0.0);  // padding: no contribution
+        if (j0 + t < it.j1) {
+            const int64_t p = H.sbase + (j0 - H.offset) + t;
+            pj = make_double4(x[p], y[p], z[p], m[p]);
+        }
         __syncthreads();
         tile[t] = pj;
         __syncthreads();
@@ -227,14 +304,22 @@ __global__ __launch_bounds__(kGravThreads) void k_grav_fp64(
                 const double dy = q.y - yi[r];
                 const double dz = q.z - zi[r];
                 const double r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
-                const double rinv = rsqrt(r2);
-                const bool self = diag && j0 + jj == it.i0 + (int64_t)r * kGravThreads + t;
-                const double mr = self ? 0.0 : q.w * rinv;
-                const double mr3 = mr * (rinv * rinv);
-                px[r] = fma(mr3, dx, px[r]);
-                py[r] = fma(mr3, dy, py[r]);
-                pz[r] = fma(mr3, dz, pz[r]);
-                pp[r] += mr;
+                double rinv = rsqrt(r2);
+                if (diag && j0 + jj == it.i0 + (int64_t)r * kGravThreads + t) rinv = 0.0;
+                if (EQM) {
+                    const double rinv3 = rinv * (rinv * rinv);
+                    px[r] = fma(rinv3, dx, px[r]);
+                    py[r] = fma(rinv3, dy, py[r]);
+                    pz[r] = fma(rinv3, dz, pz[r]);
+                    pp[r] += rinv;
+                } else {
+                    const double mr = q.w * rinv;
+                    const double mr3 = mr * (rinv * rinv);
+                    px[r] = fma(mr3, dx, px[r]);
+                    py[r] = fma(mr3, dy, py[r]);
+                    pz[r] = fma(mr3, dz, pz[r]);
+                    pp[r] += mr;
+                }
             }
         }
 #pragma unroll
@@ -248,11 +333,29 @@ __global__ __launch_bounds__(kGravThreads) void k_grav_fp64(
     }
 #pragma unroll
     for (int r = 0; r < IREG; ++r) {
-        const int64_t i = it.i0 + (int64_t)r * kGravThreads + t;
-        if (i >= hend) continue;
-        const int64_t row = H.part_base + (int64_t)it.slot * H.n + (i - H.offset);
-        partial[row] = make_double4(sx[r] - cx[r], sy[r] - cy[r], sz[r] - cz[r], sp[r] - cp[r]);
+        const int64_t li = il0 + (int64_t)r * kGravThreads + t;
+        if (li >= H.n) continue;
+        const int64_t row = H.part_base + (int64_t)it.slot * H.n + li;
+        partial[row] = make_double4(mscale * (sx[r] - cx[r]), mscale * (sy[r] - cy[r]),
+                                    mscale * (sz[r] - cz[r]), mscale * (sp[r] - cp[r]));
     }
+}
+
+template <int IREG>
+__global__ __launch_bounds__(kGravThreads) void k_grav_fp64(
+    const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
+    const double* __restrict__ m, const GravItem* __restrict__ items,
+    const HaloDev* __restrict__ halos, const double* __restrict__ cmass,
+    double4* __restrict__ partial)
+{
+    __shared__ double4 tile[kGravTileJ];
+    const GravItem it = items[blockIdx.x];
+    const HaloDev& H = halos[it.halo];
+    const double meq = cmass[it.halo];
+    if (meq > 0.0)
+        grav_fp64_body<IREG, true>(x, y, z, m, it, H, meq, partial, tile);
+    else
+        grav_fp64_body<IREG, false>(x, y, z, m, it, H, 1.0, partial, tile);
 }
 
 // ---------------------------------------------------------------- host + finalize
@@ -281,71 +384,71 @@ __device__ inline void host_nfw(const HaloDev& H, double px, double py, double p
 }
 
 // Sums the partial rows of each i in slot order, scales by G, adds the host,
-// optionally kicks v by a * dt/2.
+// optionally kicks v by a * dt/2 (and refreshes the sorted copy of v that the
+// scattering pass reads), and writes to the caller's particle order.
 __global__ __launch_bounds__(kStreamBlock) void k_grav_finalize(
     const StreamBlock* __restrict__ blocks, const HaloDev* __restrict__ halos,
-    const double4* __restrict__ partial, const float4* __restrict__ xm32,
+    const double4* __restrict__ partial, const uint32_t* __restrict__ perm,
     const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
-    const double* __restrict__ m, double* __restrict__ ax, double* __restrict__ ay,
-    double* __restrict__ az, double* __restrict__ pot, double* __restrict__ vx,
-    double* __restrict__ vy, double* __restrict__ vz, int kick)
+    double* __restrict__ ax, double* __restrict__ ay, double* __restrict__ az,
+    double* __restrict__ pot, double* __restrict__ vx, double* __restrict__ vy,
+    double* __restrict__ vz, double* __restrict__ svx, double* __restrict__ svy,
+    double* __restrict__ svz, int kick)
 {
     const StreamBlock B = blocks[blockIdx.x];
     const int t = threadIdx.x;
     if (t >= B.count) return;
     const HaloDev& H = halos[B.halo];
-    const int64_t i = B.start + t;
-    const int64_t li = i - H.offset;
+    const int64_t li = (B.start - H.offset) + t;
+    const int64_t p = H.sbase + li;
+    const int64_t o = perm[p];
     double sx = 0, sy = 0, sz = 0, sp = 0;
     for (int s = 0; s < H.grav_split; ++s) {
-        const double4 p = partial[H.part_base + (int64_t)s * H.n + li];
-        sx += p.x; sy += p.y; sz += p.z; sp += p.w;
+        const double4 q = partial[H.part_base + (int64_t)s * H.n + li];
+        sx += q.x; sy += q.y; sz += q.z; sp += q.w;
     }
     double gx = H.G * sx, gy = H.G * sy, gz = H.G * sz, gp = -H.G * sp;
     if (H.host_kind == 1) {
         double hx, hy, hz, hp;
-        host_nfw(H, x[i], y[i], z[i], hx, hy, hz, hp);
+        host_nfw(H, x[o], y[o], z[o], hx, hy, hz, hp);
         gx += hx; gy += hy; gz += hz; gp += hp;
     }
-    ax[i] = gx; ay[i] = gy; az[i] = gz; pot[i] = gp;
+    ax[o] = gx; ay[o] = gy; az[o] = gz; pot[o] = gp;
     if (kick) {
         const double hdt = 0.5 * H.dt;
-        vx[i] += gx * hdt; vy[i] += gy * hdt; vz[i] += gz * hdt;
+        const double ux = vx[o] + gx * hdt, uy = vy[o] + gy * hdt, uz = vz[o] + gz * hdt;
+        vx[o] = ux; vy[o] = uy; vz[o] = uz;
+        svx[p] = ux; svy[p] = uy; svz[p] = uz;
     }
 }
 
 // ---------------------------------------------------------------- launchers
-hipError_t launch_gravity(bool mixed, const double* x, const double* y, const double* z,
-                          const double* m, const HaloDev* d_halos, int n_halos,
-                          const StreamBlock* d_blocks, int64_t n_blocks, const GravItem* d_items,
-                          int64_t n_items, double* bsum, double* cref, float4* xm32,
-                          double4* partial, double* ax, double* ay, double* az, double* pot,
-                          double* vx, double* vy, double* vz, int kick, hipStream_t st,
-                          hipEvent_t tile_begin, hipEvent_t tile_end)
+// Expects the cell list of the current positions (sorted copies sx, sy, sz, sm
+// and perm) to be in place.
+hipError_t launch_gravity(bool mixed, const Plan& P, Scratch& w, const sidm_state* s, int kick,
+                          hipStream_t st, hipEvent_t tile_begin, hipEvent_t tile_end)
 {
+    const unsigned nb = (unsigned)P.n_blocks;
+    hipLaunchKernelGGL(k_block_mass_range, dim3(nb), dim3(kStreamBlock), 0, st, s->m, w.blocks,
+                       w.bsum);
+    hipLaunchKernelGGL(k_halo_mass, dim3(P.n_halos), dim3(kStreamBlock), 0, st, w.halos, w.bsum,
+                       w.cref);
     if (mixed) {
-        hipLaunchKernelGGL(k_block_sum_pos, dim3((unsigned)n_blocks), dim3(kStreamBlock), 0, st,
-                           x, y, z, d_blocks, bsum);
-        hipLaunchKernelGGL(k_halo_mean_pos, dim3(n_halos), dim3(kStreamBlock), 0, st, d_halos,
-                           bsum, cref);
-        hipLaunchKernelGGL(k_pack32, dim3((unsigned)n_blocks), dim3(kStreamBlock), 0, st, x, y, z,
-                           m, d_blocks, cref, xm32);
+        hipLaunchKernelGGL(k_pack_frames, dim3(nb), dim3(kStreamBlock), 0, st, w.sx, w.sy, w.sz,
+                           w.sm, w.blocks, w.halos, w.sub, w.sub_n, w.xm32);
         if (tile_begin) (void)hipEventRecord(tile_begin, st);
-        hipLaunchKernelGGL((k_grav_mixed<4>), dim3((unsigned)n_items), dim3(kGravThreads), 0, st,
-                           xm32, d_items, d_halos, partial);
+        hipLaunchKernelGGL((k_grav_mixed<4>), dim3((unsigned)P.n_items), dim3(kGravThreads), 0,
+                           st, w.xm32, w.sub, w.sub_n, w.items, w.halos, w.cref, w.partial);
         if (tile_end) (void)hipEventRecord(tile_end, st);
-        hipLaunchKernelGGL(k_grav_finalize, dim3((unsigned)n_blocks), dim3(kStreamBlock),
-                           0, st, d_blocks, d_halos, partial, xm32, x, y, z, m, ax, ay, az, pot,
-                           vx, vy, vz, kick);
     } else {
         if (tile_begin) (void)hipEventRecord(tile_begin, st);
-        hipLaunchKernelGGL((k_grav_fp64<4>), dim3((unsigned)n_items), dim3(kGravThreads), 0, st,
-                           x, y, z, m, d_items, d_halos, partial);
+        hipLaunchKernelGGL((k_grav_fp64<4>), dim3((unsigned)P.n_items), dim3(kGravThreads), 0, st,
+                           w.sx, w.sy, w.sz, w.sm, w.items, w.halos, w.cref, w.partial);
         if (tile_end) (void)hipEventRecord(tile_end, st);
-        hipLaunchKernelGGL(k_grav_finalize, dim3((unsigned)n_blocks), dim3(kStreamBlock),
-                           0, st, d_blocks, d_halos, partial, xm32, x, y, z, m, ax, ay, az, pot,
-                           vx, vy, vz, kick);
     }
+    hipLaunchKernelGGL(k_grav_finalize, dim3(nb), dim3(kStreamBlock), 0, st, w.blocks, w.halos,
+                       w.partial, w.perm, s->x, s->y, s->z, s->ax, s->ay, s->az, s->pot, s->vx,
+                       s->vy, s->vz, w.svx, w.svy, w.svz, kick);
     return hipGetLastError();
 }
 

@@ -3,28 +3,30 @@
 // neighbours).
 //
 // One wavefront per bucket of 64 Morton-consecutive particles, one particle
-// per lane.  Candidates are staged bucket by bucket in LDS and every lane reads
-// the same candidate (broadcast), as in the gravity tiles.  Selection works on
-// values only:
-//   1. a bound u_i^2 >= d2_(k) from a window of buckets around the bucket
-//      (histogram of its distances, smallest bin edge holding k of them);
-//   2. all buckets whose box lies within max_i u_i of the bucket's box are
-//      visited through the search tree; each lane histograms its distances in
-//      [0, u_i^2] into 32 bins (a private LDS column, no atomics) and keeps the
-//      bin that holds the k-th;
-//   3. a second visit collects that bin's members (at most 16) or, if it holds
-//      more, refines the bin by its own min..max range; equal values end the
-//      refinement at once.
+// per lane; the lanes of each compact sub-range of the bucket are resolved
+// together.  Candidates are staged sub-range by sub-range in LDS and every
+// lane reads the same candidate (broadcast), as in the gravity tiles.  A
+// candidate sub-range is visited only if it intersects the search sphere of
+// at least one lane.
+// Selection works on values only, with a private 32-bin histogram per lane
+// (an LDS column, no atomics):
+//   1. each lane starts below an estimate from its 8th-nearest bucket-mate and
+//      grows the radius by 1.5 until the sphere holds k (counts at four radii
+//      in registers pick the smallest that does); a histogram of the
+//      distances in [0, u_i^2] then names the bin of the k-th;
+//   2. a visit restricted to that bin's shell collects its members (at most
+//      16) or, if it holds more, refines the bin by its own min..max range
+//      (again visiting only the shell); equal values end the refinement.
 // Distances d2 = (dx*dx + dy*dy) + dz*dz are evaluated in FP64 without fused
 // multiply-add, the same expression the oracle uses, so h matches bit for bit.
-#include "sidm_plan.hpp"
+#include "sidm_tree.hpp"
 
 namespace sidm {
 
 constexpr int kKnnBins = 32;
 constexpr int kKnnSurv = 16;
-constexpr int kKnnLevels = 6;
-constexpr int kStackMax = 96;
+constexpr int kKnnLevels = 4;
+constexpr int kKnnGrow = 80;
 
 struct KnnLds {
     double cx[kBucket], cy[kBucket], cz[kBucket];
@@ -45,62 +47,10 @@ __device__ inline double dist2_exact(double ax, double ay, double az, double bx,
     return (dx * dx + dy * dy) + dz * dz;
 }
 
-__device__ inline double box_dist2(const double* q, const double* __restrict__ b)
+__device__ inline double box_diag2_k(const double* b)
 {
-    double s = 0.0;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const double g = fmax(fmax(b[c] - q[3 + c], q[c] - b[3 + c]), 0.0);
-        s += g * g;
-    }
-    return s;
-}
-
-__device__ inline double wave_max_d(double v)
-{
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
-// Depth-first visit of the buckets whose box passes `test`.  Wave-uniform:
-// every lane calls f(bucket) for every bucket visited.
-template <class Test, class F>
-__device__ inline void tree_visit(const HaloDev& H, const NodeChild* __restrict__ nodes,
-                                  int64_t n_buckets, int64_t* stack, Test test, F f)
-{
-    const int lane = threadIdx.x & 63;
-    const int64_t root = H.level_off[H.n_levels - 1];
-    if (H.n_levels == 1) {
-        f(root);
-        return;
-    }
-    __syncthreads();
-    if (lane == 0) stack[0] = root;
-    int sp = 1;
-    __syncthreads();
-    while (sp > 0) {
-        const int64_t node = stack[sp - 1];
-        --sp;
-        const NodeChild N = nodes[node];
-        const bool pass = lane < N.nchild && test(N.child0 + lane);
-        unsigned long long mask = __ballot(pass);
-        __syncthreads();
-        if (N.child0 < n_buckets) {
-            while (mask) {
-                const int l = __ffsll((long long)mask) - 1;
-                mask &= mask - 1ull;
-                f(N.child0 + l);
-            }
-        } else {
-            const int cnt = __popcll(mask);
-            if (pass) {
-                const int below = __popcll(mask & ((1ull << lane) - 1ull));
-                stack[sp + cnt - 1 - below] = N.child0 + lane;
-            }
-            sp += cnt;
-            __syncthreads();
-        }
-    }
+    const double ex = b[3] - b[0], ey = b[4] - b[1], ez = b[5] - b[2];
+    return ex * ex + ey * ey + ez * ez;
 }
 
 __device__ inline int bin_of(double d2, double lo, double inv)
@@ -112,7 +62,8 @@ __device__ inline int bin_of(double d2, double lo, double inv)
 
 __global__ __launch_bounds__(kBucket) void k_knn(
     const HaloDev* __restrict__ halos, const BucketInfo* __restrict__ buckets,
-    const NodeChild* __restrict__ nodes, const double* __restrict__ box, int64_t n_buckets,
+    const NodeChild* __restrict__ nodes, const double* __restrict__ box,
+    const SubRange* __restrict__ sub, const int* __restrict__ sub_n, int64_t n_buckets,
     const double* __restrict__ sx, const double* __restrict__ sy, const double* __restrict__ sz,
     const uint32_t* __restrict__ perm, double* __restrict__ sh, double* __restrict__ h_out,
     int* __restrict__ status)
@@ -123,153 +74,220 @@ __global__ __launch_bounds__(kBucket) void k_knn(
     const BucketInfo B = buckets[b];
     const HaloDev& H = halos[B.halo];
     const int k = H.k;
-    const bool act = lane < B.count;
-    const uint32_t mypos = (uint32_t)(B.start + (act ? lane : 0));
+    const bool in_bucket = lane < B.count;
+    const uint32_t mypos = (uint32_t)(B.start + (in_bucket ? lane : 0));
     const double xi = sx[mypos], yi = sy[mypos], zi = sz[mypos];
-    double qb[6];
-#pragma unroll
-    for (int c = 0; c < 6; ++c) qb[c] = box[6 * b + c];
+    auto all_nodes = [](int64_t) { return true; };
 
-    auto stage = [&](int64_t c) -> int {
-        const BucketInfo C = buckets[c];
+    // stage particles [p0, p0 + cnt) of the sorted order into LDS
+    auto stage = [&](int64_t p0, int cnt) {
         __syncthreads();
-        if (lane < C.count) {
-            const int64_t p = C.start + lane;
+        if (lane < cnt) {
+            const int64_t p = p0 + lane;
             L.cx[lane] = sx[p]; L.cy[lane] = sy[p]; L.cz[lane] = sz[p];
             L.cpos[lane] = (uint32_t)p;
         }
         __syncthreads();
-        return C.count;
+    };
+    // visit every candidate sub-range within reach of a lane's sphere
+    // (radius^2 r2 of the lane, ignored when `off` is true for the lane)
+    auto visit = [&](double r2, bool off, auto body) {
+        tree_visit(H, nodes, n_buckets, L.stack,
+                   [&](int64_t c) { return !off && point_box_dist2(xi, yi, zi, box + 6 * c) <= r2; },
+                   all_nodes, [&](int64_t c) {
+                       const int64_t c0 = buckets[c].start;
+                       const int ns = sub_n[c];
+                       for (int q = 0; q < ns; ++q) {
+                           const SubRange R = sub[kSubMax * c + q];
+                           if (!__ballot(!off && point_box_dist2(xi, yi, zi, R.box) <= r2)) continue;
+                           stage(c0 + R.off, R.cnt);
+                           if (!off) body(R.cnt);
+                       }
+                   });
     };
 
-    // ---- 1. bound from a window of buckets around b
-    const int64_t hb0 = H.level_off[0], hb1 = H.level_off[0] + H.level_n[0] - 1;
-    int64_t w0 = b - H.win_lo, w1 = b + H.win_hi;
-    if (w0 < hb0) { w1 += hb0 - w0; w0 = hb0; }
-    if (w1 > hb1) { w0 -= w1 - hb1; w1 = hb1; }
-    if (w0 < hb0) w0 = hb0;
-    double mx = 0.0;
-    for (int64_t c = w0; c <= w1; ++c) {
-        const int cnt = stage(c);
-        for (int j = 0; j < cnt; ++j)
-            if (L.cpos[j] != mypos) mx = fmax(mx, dist2_exact(xi, yi, zi, L.cx[j], L.cy[j], L.cz[j]));
-    }
-    for (int q = 0; q < kKnnBins; ++q) L.hist[q][lane] = 0;
-    const double winv = mx > 0.0 ? (double)kKnnBins / mx : 0.0;
-    for (int64_t c = w0; c <= w1; ++c) {
-        const int cnt = stage(c);
-        for (int j = 0; j < cnt; ++j)
-            if (L.cpos[j] != mypos)
-                ++L.hist[bin_of(dist2_exact(xi, yi, zi, L.cx[j], L.cy[j], L.cz[j]), 0.0, winv)][lane];
-    }
-    int wbeta = kKnnBins - 1;
-    {
-        int cum = 0;
-        for (int q = 0; q < kKnnBins; ++q) {
-            cum += L.hist[q][lane];
-            if (cum >= k) { wbeta = q; break; }
-        }
-    }
-    double u2 = 0.0;
-    for (int64_t c = w0; c <= w1; ++c) {
-        const int cnt = stage(c);
-        for (int j = 0; j < cnt; ++j)
-            if (L.cpos[j] != mypos) {
-                const double d2 = dist2_exact(xi, yi, zi, L.cx[j], L.cy[j], L.cz[j]);
-                if (bin_of(d2, 0.0, winv) <= wbeta) u2 = fmax(u2, d2);
+    // the lanes of each compact sub-range of this bucket are resolved together
+    const int ngroups = sub_n[b];
+    for (int g = 0; g < ngroups; ++g) {
+        const SubRange G = sub[kSubMax * b + g];
+        const bool act = in_bucket && lane >= G.off && lane < G.off + G.cnt;
+
+        // ---- 1. starting radius: distance to the m-th nearest member of the
+        // lane's own sub-range (m <= 8), scaled to k neighbours, started low
+        double u2;
+        {
+            constexpr int kM = 8;
+            double best[kM];
+#pragma unroll
+            for (int q = 0; q < kM; ++q) best[q] = INFINITY;
+            stage(B.start + G.off, G.cnt);
+            for (int j = 0; j < G.cnt; ++j) {
+                if (L.cpos[j] == mypos) continue;
+                double v = dist2_exact(xi, yi, zi, L.cx[j], L.cy[j], L.cz[j]);
+#pragma unroll
+                for (int q = 0; q < kM; ++q) {   // insertion into the sorted best list
+                    const double lo = fmin(best[q], v);
+                    v = fmax(best[q], v);
+                    best[q] = lo;
+                }
             }
-    }
-    if (!act) u2 = 0.0;
-    const double R2 = wave_max_d(u2) * (1.0 + 1e-9);
-    auto near = [&](int64_t c) { return box_dist2(qb, box + 6 * c) <= R2; };
-
-    // ---- 2./3. histogram refinement over the tree candidates
-    bool done = !act;
-    int level = 0, below = 0;
-    double d2k = 0.0;
-    L.lv_lo[0][lane] = 0.0;
-    L.lv_inv[0][lane] = u2 > 0.0 ? (double)kKnnBins / u2 : 0.0;
-    auto member = [&](double d2, int upto) {
-        if (!(d2 <= u2)) return false;
-        for (int l = 0; l < upto; ++l)
-            if (bin_of(d2, L.lv_lo[l][lane], L.lv_inv[l][lane]) != L.lv_beta[l][lane]) return false;
-        return true;
-    };
-    while (__ballot(!done)) {
+            const int m = min(min(kM, k), G.cnt - 1);
+            double rm2 = 0.0;
+#pragma unroll
+            for (int q = 0; q < kM; ++q)
+                if (q == m - 1) rm2 = best[q];
+            if (m >= 1 && rm2 > 0.0 && rm2 < INFINITY) {
+                // start below the estimate: a pass over a small sphere is
+                // cheap, one over a sphere far too large is not
+                u2 = 0.3 * 1.44 * rm2 * pow((double)k / (double)m, 2.0 / 3.0);
+            } else {
+                const double* rb = box + 6 * H.level_off[H.n_levels - 1];
+                u2 = box_diag2_k(rb) / cbrt((double)H.n * (double)H.n);
+            }
+        }
+        bool done = !act;      // this lane's h is known
+        // grow the radius by 1.5 until the sphere holds k others; counts at four
+        // radii inside the sphere (registers only) give the smallest that does
+        bool found = !act;
+        int grow = 0;
+        while (__ballot(!found)) {
+            int c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+            const double t0 = 0.55 * u2, t1 = 0.7 * u2, t2 = 0.85 * u2, t3 = u2;
+            visit(u2 * (1.0 + 1e-9), found, [&](int cnt) {
+                for (int j = 0; j < cnt; ++j) {
+                    const double d2 = dist2_exact(xi, yi, zi, L.cx[j], L.cy[j], L.cz[j]);
+                    const int self = L.cpos[j] == mypos;
+                    c0 += (d2 <= t0) - self;
+                    c1 += (d2 <= t1) - self;
+                    c2 += (d2 <= t2) - self;
+                    c3 += (d2 <= t3) - self;
+                }
+            });
+            if (!found) {
+                if (c3 >= k) {
+                    found = true;
+                    u2 = c0 >= k ? t0 : c1 >= k ? t1 : c2 >= k ? t2 : t3;
+                } else if (++grow > kKnnGrow) {
+                    found = done = true;
+                    atomicOr(&status[B.halo], SIDM_DEV_KNN_OVERFLOW);
+                } else if (u2 > 0.0) {
+                    u2 *= 2.25;
+                } else {
+                    u2 = box_diag2_k(box + 6 * H.level_off[H.n_levels - 1]) /
+                         cbrt((double)H.n * (double)H.n);
+                    if (!(u2 > 0.0)) u2 = 1.0;
+                }
+            }
+        }
+        // ---- 2. level-0 histogram of the distances in [0, u2]
+        const double inv0 = u2 > 0.0 ? (double)kKnnBins / u2 : 0.0;
         for (int q = 0; q < kKnnBins; ++q) L.hist[q][lane] = 0;
-        const double lo_l = L.lv_lo[level][lane], inv_l = L.lv_inv[level][lane];
-        tree_visit(H, nodes, n_buckets, L.stack, near, [&](int64_t c) {
-            const int cnt = stage(c);
-            if (done) return;
+        L.lv_lo[0][lane] = 0.0;
+        L.lv_inv[0][lane] = inv0;
+        visit(u2 * (1.0 + 1e-9), done, [&](int cnt) {
             for (int j = 0; j < cnt; ++j) {
                 if (L.cpos[j] == mypos) continue;
                 const double d2 = dist2_exact(xi, yi, zi, L.cx[j], L.cy[j], L.cz[j]);
-                if (member(d2, level)) ++L.hist[bin_of(d2, lo_l, inv_l)][lane];
+                if (d2 <= u2) atomicAdd(&L.hist[bin_of(d2, 0.0, inv0)][lane], 1u);
             }
         });
-        int sel = -1, inb = 0, cum = below;
-        if (!done) {
-            for (int q = 0; q < kKnnBins; ++q) {
-                const int hq = (int)L.hist[q][lane];
-                if (cum + hq >= k) { sel = q; inb = hq; break; }
-                cum += hq;
-            }
-            if (sel < 0) {  // cannot happen when the bound holds
-                d2k = NAN;
-                done = true;
-                atomicOr(&status[B.halo], SIDM_DEV_KNN_OVERFLOW);
-            } else {
-                L.lv_beta[level][lane] = sel;
-            }
-        }
-        double mn = INFINITY, mxv = -INFINITY;
-        int ns = 0;
-        tree_visit(H, nodes, n_buckets, L.stack, near, [&](int64_t c) {
-            const int cnt = stage(c);
-            if (done) return;
-            for (int j = 0; j < cnt; ++j) {
-                if (L.cpos[j] == mypos) continue;
-                const double d2 = dist2_exact(xi, yi, zi, L.cx[j], L.cy[j], L.cz[j]);
-                if (member(d2, level + 1)) {
-                    mn = fmin(mn, d2);
-                    mxv = fmax(mxv, d2);
-                    if (inb <= kKnnSurv && ns < kKnnSurv) L.surv[ns++][lane] = d2;
-                }
-            }
-        });
-        if (!done) {
-            if (inb <= kKnnSurv) {
-                for (int a = 1; a < ns; ++a) {   // insertion sort of the bin's members
-                    const double v = L.surv[a][lane];
-                    int q = a - 1;
-                    while (q >= 0 && L.surv[q][lane] > v) {
-                        L.surv[q + 1][lane] = L.surv[q][lane];
-                        --q;
+        __syncthreads();
+
+        // ---- 3. select the bin of the k-th, collect or refine
+        bool ready = true;
+        int level = 0, below = 0;
+        double d2k = NAN;
+        auto member = [&](double d2, int upto) {
+            if (!(d2 <= u2)) return false;
+            for (int l = 0; l < upto; ++l)
+                if (bin_of(d2, L.lv_lo[l][lane], L.lv_inv[l][lane]) != L.lv_beta[l][lane])
+                    return false;
+            return true;
+        };
+        double cull2 = u2 * (1.0 + 1e-9);   // members of the current bin lie within
+        while (__ballot(!done)) {
+            if (__ballot(!done && !ready)) {
+                const double lo_l = L.lv_lo[level][lane], inv_l = L.lv_inv[level][lane];
+                const bool skip = done || ready;
+                if (!skip)
+                    for (int q = 0; q < kKnnBins; ++q) L.hist[q][lane] = 0;
+                visit(cull2, skip, [&](int cnt) {
+                    for (int j = 0; j < cnt; ++j) {
+                        if (L.cpos[j] == mypos) continue;
+                        const double d2 = dist2_exact(xi, yi, zi, L.cx[j], L.cy[j], L.cz[j]);
+                        if (member(d2, level))
+                            atomicAdd(&L.hist[bin_of(d2, lo_l, inv_l)][lane], 1u);
                     }
-                    L.surv[q + 1][lane] = v;
+                });
+                ready = true;
+                __syncthreads();
+            }
+            int sel = -1, inb = 0, cum = below;
+            double shell2 = 0.0;   // members of the selected bin lie within this
+            if (!done) {
+                for (int q = 0; q < kKnnBins; ++q) {
+                    const int hq = (int)L.hist[q][lane];
+                    if (cum + hq >= k) { sel = q; inb = hq; break; }
+                    cum += hq;
                 }
-                const int r = k - cum - 1;
-                d2k = (r >= 0 && r < ns) ? L.surv[r][lane] : NAN;
-                done = true;
-            } else if (mn == mxv) {
-                d2k = mn;           // all members tie at the k-th distance
-                done = true;
-            } else if (level + 1 >= kKnnLevels) {
-                d2k = NAN;
-                done = true;
-                atomicOr(&status[B.halo], SIDM_DEV_KNN_OVERFLOW);
-            } else {
-                below = cum;
-                ++level;
-                L.lv_lo[level][lane] = mn;
-                L.lv_inv[level][lane] = (double)kKnnBins / (mxv - mn);
+                if (sel < 0) {   // cannot happen: the sphere holds at least k
+                    done = true;
+                    atomicOr(&status[B.halo], SIDM_DEV_KNN_OVERFLOW);
+                } else {
+                    L.lv_beta[level][lane] = sel;
+                    const double inv_l = L.lv_inv[level][lane];
+                    shell2 = inv_l > 0.0 ? L.lv_lo[level][lane] + (double)(sel + 1) / inv_l : u2;
+                    shell2 = fmin(u2, shell2) * (1.0 + 1e-9);
+                }
+            }
+            double mn = INFINITY, mxv = -INFINITY;
+            int ns = 0;
+            visit(shell2, done, [&](int cnt) {
+                for (int j = 0; j < cnt; ++j) {
+                    if (L.cpos[j] == mypos) continue;
+                    const double d2 = dist2_exact(xi, yi, zi, L.cx[j], L.cy[j], L.cz[j]);
+                    if (member(d2, level + 1)) {
+                        mn = fmin(mn, d2);
+                        mxv = fmax(mxv, d2);
+                        if (inb <= kKnnSurv && ns < kKnnSurv) L.surv[ns++][lane] = d2;
+                    }
+                }
+            });
+            if (!done) {
+                if (inb <= kKnnSurv) {
+                    for (int a = 1; a < ns; ++a) {   // insertion sort of the bin's members
+                        const double v = L.surv[a][lane];
+                        int q = a - 1;
+                        while (q >= 0 && L.surv[q][lane] > v) {
+                            L.surv[q + 1][lane] = L.surv[q][lane];
+                            --q;
+                        }
+                        L.surv[q + 1][lane] = v;
+                    }
+                    const int r = k - cum - 1;
+                    if (r >= 0 && r < ns) d2k = L.surv[r][lane];
+                    done = true;
+                } else if (mn == mxv) {
+                    d2k = mn;        // all members tie at the k-th distance
+                    done = true;
+                } else if (level + 1 >= kKnnLevels) {
+                    done = true;
+                    atomicOr(&status[B.halo], SIDM_DEV_KNN_OVERFLOW);
+                } else {
+                    below = cum;
+                    ++level;
+                    L.lv_lo[level][lane] = mn;
+                    L.lv_inv[level][lane] = (double)kKnnBins / (mxv - mn);
+                    ready = false;
+                    cull2 = shell2;
+                }
             }
         }
-    }
-    if (act) {
-        const double h = sqrt(d2k);
-        sh[mypos] = h;
-        h_out[perm[mypos]] = h;
+        if (act) {
+            const double h = sqrt(d2k);
+            sh[mypos] = h;
+            h_out[perm[mypos]] = h;
+        }
     }
 }
 
@@ -312,8 +330,8 @@ hipError_t launch_knn(const Plan& P, const sidm_state* s, Scratch& w, uint32_t* 
                       hipStream_t st)
 {
     hipLaunchKernelGGL(k_knn, dim3((unsigned)P.n_buckets), dim3(kBucket), 0, st, w.halos,
-                       w.buckets, w.nodes, w.box, P.n_buckets, w.sx, w.sy, w.sz, w.perm, w.sh,
-                       s->h, w.status);
+                       w.buckets, w.nodes, w.box, w.sub, w.sub_n, P.n_buckets, w.sx, w.sy, w.sz,
+                       w.perm, w.sh, s->h, w.status);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !nbr) return e;
     double* rowd2 = nullptr;

@@ -3,9 +3,11 @@
 // Sec. 3.5: the geometric factor Lambda of the interaction probability).
 //
 // k_pairs: one wavefront per bucket, one i per lane.  Candidate buckets come
-// from the search tree with the criterion box distance < hmax(b) + hmax(c).
-// A pair {i, j} is owned by the lane with the smaller id and tested when
-// d2 < (h_i + h_j)^2; accepted pairs are compacted through an LDS queue
+// from the search tree: bucket c is visited when, for some lane i, the
+// distance from x_i to c's box is below h_i + hmax(c).
+// A bucket visits only candidate buckets of equal or higher index (pairs
+// inside a bucket are owned by the smaller id), so each pair is tested once,
+// when d2 < (h_i + h_j)^2; accepted pairs are compacted through an LDS queue
 // (ballot + prefix count) so that the expensive per-pair work -- Philox4x32-10,
 // |dv|, and Lambda when the draw falls below a cheap upper bound of P -- runs
 // on full wavefronts.  Events (u < P) are appended to a global buffer.
@@ -17,7 +19,7 @@
 // and an event fires when it is the elected one for both of its particles.
 // This is exactly the dependency order of one-after-the-other application.
 #include "sidm_math.hpp"
-#include "sidm_plan.hpp"
+#include "sidm_tree.hpp"
 
 namespace sidm {
 
@@ -33,17 +35,6 @@ __device__ inline double norm3(double x, double y, double z)
 {
 #pragma clang fp contract(off)
     return sqrt((x * x + y * y) + z * z);
-}
-
-__device__ inline double box_dist2_s(const double* q, const double* __restrict__ b)
-{
-    double s = 0.0;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const double g = fmax(fmax(b[c] - q[3 + c], q[c] - b[3 + c]), 0.0);
-        s += g * g;
-    }
-    return s;
 }
 
 __global__ void k_scatter_reset(DevCounters* __restrict__ counters,
@@ -66,49 +57,11 @@ struct PairSide {
     uint32_t id[kBucket], orig[kBucket];
 };
 
-template <class Test, class F>
-__device__ inline void tree_visit_s(const HaloDev& H, const NodeChild* __restrict__ nodes,
-                                    int64_t n_buckets, int64_t* stack, Test test, F f)
-{
-    const int lane = threadIdx.x & 63;
-    const int64_t root = H.level_off[H.n_levels - 1];
-    if (H.n_levels == 1) {
-        f(root);
-        return;
-    }
-    __syncthreads();
-    if (lane == 0) stack[0] = root;
-    int sp = 1;
-    __syncthreads();
-    while (sp > 0) {
-        const int64_t node = stack[sp - 1];
-        --sp;
-        const NodeChild N = nodes[node];
-        const bool pass = lane < N.nchild && test(N.child0 + lane);
-        unsigned long long mask = __ballot(pass);
-        __syncthreads();
-        if (N.child0 < n_buckets) {
-            while (mask) {
-                const int l = __ffsll((long long)mask) - 1;
-                mask &= mask - 1ull;
-                f(N.child0 + l);
-            }
-        } else {
-            const int cnt = __popcll(mask);
-            if (pass) {
-                const int below = __popcll(mask & ((1ull << lane) - 1ull));
-                stack[sp + cnt - 1 - below] = N.child0 + lane;
-            }
-            sp += cnt;
-            __syncthreads();
-        }
-    }
-}
-
 __global__ __launch_bounds__(kBucket) void k_pairs(
     const HaloDev* __restrict__ halos, const BucketInfo* __restrict__ buckets,
     const NodeChild* __restrict__ nodes, const double* __restrict__ box,
-    const double* __restrict__ hmax, int64_t n_buckets, const double* __restrict__ sx,
+    const double* __restrict__ hmax, const SubRange* __restrict__ sub,
+    const int* __restrict__ sub_n, int64_t n_buckets, const double* __restrict__ sx,
     const double* __restrict__ sy, const double* __restrict__ sz, const double* __restrict__ svx,
     const double* __restrict__ svy, const double* __restrict__ svz, const double* __restrict__ sh,
     const double* __restrict__ sm, const uint32_t* __restrict__ sid,
@@ -117,7 +70,7 @@ __global__ __launch_bounds__(kBucket) void k_pairs(
 {
     __shared__ PairSide I, J;
     __shared__ uint16_t queue[2 * kBucket];
-    __shared__ int64_t stack[96];
+    __shared__ int64_t stack[kStackMax];
     const int64_t b = blockIdx.x;
     const int lane = threadIdx.x;
     const BucketInfo B = buckets[b];
@@ -131,10 +84,6 @@ __global__ __launch_bounds__(kBucket) void k_pairs(
         S.id[lane] = sid[p]; S.orig[lane] = perm[p];
     };
     if (act) load(I, B.start + lane);
-    double qb[6];
-#pragma unroll
-    for (int c = 0; c < 6; ++c) qb[c] = box[6 * b + c];
-    const double hb = hmax[b];
     const uint32_t k0 = (uint32_t)(H.seed & 0xffffffffull), k1 = (uint32_t)(H.seed >> 32);
     const double kInvPi8 = 8.0 / 3.14159265358979323846;
     const unsigned long long lt = (1ull << lane) - 1ull;
@@ -147,19 +96,21 @@ __global__ __launch_bounds__(kBucket) void k_pairs(
         if (lane < cnt) {
             const int e = queue[lane];
             const int il = e & 63, jl = e >> 8;
-            const uint32_t a = I.id[il], bb = J.id[jl];
+            // canonical order of the pair: a = smaller id, b = larger id
+            const bool iswap = I.id[il] > J.id[jl];
+            const uint32_t a = iswap ? J.id[jl] : I.id[il], bb = iswap ? I.id[il] : J.id[jl];
             const Philox4 w = philox4x32_10(a, bb, step, 0u, k0, k1);
             const double u = unit53(w.w[0], w.w[1]);
             const double g = norm3(I.vx[il] - J.vx[jl], I.vy[il] - J.vy[jl], I.vz[il] - J.vz[jl]);
             const double ha = I.h[il], hbb = J.h[jl];
             const double hm = fmax(ha, hbb);
-            const double mb = J.m[jl];
+            const double mb = iswap ? I.m[il] : J.m[jl];
             // Lambda <= min(W_a(0), W_b(0)) = 8 / (pi max(h)^3)
             const double pub = H.sigma_m * mb * g * (kInvPi8 / (hm * hm * hm)) * H.dt;
             if (u < pub) {
                 const double d =
                     sqrt(dist2_pair(I.x[il], I.y[il], I.z[il], J.x[jl], J.y[jl], J.z[jl]));
-                const double lam = kernel_overlap(d, ha, hbb);
+                const double lam = iswap ? kernel_overlap(d, hbb, ha) : kernel_overlap(d, ha, hbb);
                 const double P = H.sigma_m * mb * g * lam * H.dt;
                 if (P > 1.0) atomicAdd(&ev_counts[4 * B.halo + 3], 1ull);
                 if (u < P) {
@@ -167,8 +118,8 @@ __global__ __launch_bounds__(kBucket) void k_pairs(
                     if ((int64_t)slot < max_events) {
                         EventRec r;
                         r.key = ((unsigned long long)a << 32) | bb;
-                        r.ia = I.orig[il];
-                        r.ib = J.orig[jl];
+                        r.ia = iswap ? J.orig[jl] : I.orig[il];
+                        r.ib = iswap ? I.orig[il] : J.orig[jl];
                         r.halo = B.halo;
                         r.round = 0u;
                         events[slot] = r;
@@ -179,42 +130,57 @@ __global__ __launch_bounds__(kBucket) void k_pairs(
         __syncthreads();
     };
 
-    auto near = [&](int64_t c) {
-        const double r = hb + hmax[c];
-        return box_dist2_s(qb, box + 6 * c) <= r * r * (1.0 + 1e-9);
-    };
-    tree_visit_s(H, nodes, n_buckets, stack, near, [&](int64_t c) {
+    // bucket c can hold a partner of lane i only if its box is closer than
+    // h_i + max h over c; pairs between two buckets are handled by the lower
+    // bucket index, pairs inside a bucket by the smaller id
+    const double hi_l = act ? I.h[lane] : 0.0;
+    const double xl = I.x[act ? lane : 0], yl = I.y[act ? lane : 0], zl = I.z[act ? lane : 0];
+    tree_visit(H, nodes, n_buckets, stack,
+               [&](int64_t c) {
+                   const double r = hi_l + hmax[c];
+                   return act && point_box_dist2(xl, yl, zl, box + 6 * c) < r * r * (1.0 + 1e-9);
+               },
+               [&](int64_t c) { return nodes[c].last >= b; },
+               [&](int64_t c) {
         const BucketInfo C = buckets[c];
-        __syncthreads();
-        if (lane < C.count) load(J, C.start + lane);
-        __syncthreads();
-        const double xi = I.x[act ? lane : 0], yi = I.y[act ? lane : 0], zi = I.z[act ? lane : 0];
-        const double hi = I.h[act ? lane : 0];
-        const uint32_t idi = I.id[act ? lane : 0];
-        for (int jj = 0; jj < C.count; ++jj) {
-            bool pair = false;
-            if (act && idi < J.id[jj]) {
-                const double d2 = dist2_pair(xi, yi, zi, J.x[jj], J.y[jj], J.z[jj]);
-                const double hs = hi + J.h[jj];
-                pair = d2 < hs * hs;
+        const double hc = hmax[c];
+        const int nsub = sub_n[c];
+        for (int q = 0; q < nsub; ++q) {
+            const SubRange R = sub[kSubMax * c + q];
+            const double rr = hi_l + hc;
+            if (!__ballot(act && point_box_dist2(xl, yl, zl, R.box) < rr * rr * (1.0 + 1e-9)))
+                continue;
+            __syncthreads();
+            if (lane < R.cnt) load(J, C.start + R.off + lane);
+            __syncthreads();
+            const double xi = xl, yi = yl, zi = zl, hi = hi_l;
+            const uint32_t idi = I.id[act ? lane : 0];
+            const bool same = c == b;
+            for (int jj = 0; jj < R.cnt; ++jj) {
+                bool pair = false;
+                if (act && (!same || idi < J.id[jj])) {
+                    const double d2 = dist2_pair(xi, yi, zi, J.x[jj], J.y[jj], J.z[jj]);
+                    const double hs = hi + J.h[jj];
+                    pair = d2 < hs * hs;
+                }
+                const unsigned long long mask = __ballot(pair);
+                if (pair) queue[qn + __popcll(mask & lt)] = (uint16_t)(lane | (jj << 8));
+                qn += __popcll(mask);
+                my_pairs += pair ? 1 : 0;
+                if (qn >= kBucket) {
+                    process(kBucket);
+                    const int rest = qn - kBucket;
+                    const uint16_t moved = lane < rest ? queue[kBucket + lane] : 0;
+                    __syncthreads();
+                    if (lane < rest) queue[lane] = moved;
+                    qn = rest;
+                    __syncthreads();
+                }
             }
-            const unsigned long long mask = __ballot(pair);
-            if (pair) queue[qn + __popcll(mask & lt)] = (uint16_t)(lane | (jj << 8));
-            qn += __popcll(mask);
-            my_pairs += pair ? 1 : 0;
-            if (qn >= kBucket) {
-                process(kBucket);
-                const int rest = qn - kBucket;
-                const uint16_t moved = lane < rest ? queue[kBucket + lane] : 0;
-                __syncthreads();
-                if (lane < rest) queue[lane] = moved;
-                qn = rest;
-                __syncthreads();
+            if (qn > 0) {
+                process(qn);   // entries refer to this candidate range: flush now
+                qn = 0;
             }
-        }
-        if (qn > 0) {
-            process(qn);   // entries refer to this candidate bucket: flush now
-            qn = 0;
         }
     });
     // pairs tested by this bucket
@@ -360,7 +326,8 @@ hipError_t launch_scatter(const Plan& P, const sidm_state* s, Scratch& w, uint32
                           hipEvent_t after_pairs)
 {
     hipLaunchKernelGGL(k_pairs, dim3((unsigned)P.n_buckets), dim3(kBucket), 0, st, w.halos,
-                       w.buckets, w.nodes, w.box, w.hmax, P.n_buckets, w.sx, w.sy, w.sz, w.svx,
+                       w.buckets, w.nodes, w.box, w.hmax, w.sub, w.sub_n, P.n_buckets, w.sx,
+                       w.sy, w.sz, w.svx,
                        w.svy, w.svz, w.sh, w.sm, w.sid, w.perm, step, w.counters, w.events,
                        w.max_events, (unsigned long long*)w.ev_counts);
     if (after_pairs) (void)hipEventRecord(after_pairs, st);

@@ -218,7 +218,7 @@ __global__ __launch_bounds__(kStreamBlock) void k_permute(
     sx[p] = x[o]; sy[p] = y[o]; sz[p] = z[o];
     if (vx) { svx[p] = vx[o]; svy[p] = vy[o]; svz[p] = vz[o]; }
     sm[p] = m[o];
-    sid[p] = id[o];
+    if (id) sid[p] = id[o];
     sh[p] = h ? h[o] : 0.0;
     perm[p] = o;
 }
@@ -236,10 +236,53 @@ __device__ inline double wave_max(double v)
     return v;
 }
 
-// One wave per bucket.
+__device__ inline void range_box(int lo, int hi, int lane, double px, double py, double pz,
+                                 double* o)
+{
+    const bool in = lane >= lo && lane < hi;
+    o[0] = wave_min(in ? px : INFINITY);
+    o[1] = wave_min(in ? py : INFINITY);
+    o[2] = wave_min(in ? pz : INFINITY);
+    o[3] = wave_max(in ? px : -INFINITY);
+    o[4] = wave_max(in ? py : -INFINITY);
+    o[5] = wave_max(in ? pz : -INFINITY);
+}
+
+__device__ inline double box_diag2(const double* b)
+{
+    const double ex = b[3] - b[0], ey = b[4] - b[1], ez = b[5] - b[2];
+    return ex * ex + ey * ey + ez * ez;
+}
+
+// Split point of the lanes [lo, hi) at their coarsest internal Morton boundary,
+// kept only if it at least halves the count-weighted extent (count x box
+// diagonal summed over the pieces): a dense group is then separated from a few
+// far members even when the far piece stays large.  -1 if not kept.
+__device__ inline int split_range(int lo, int hi, int lane, unsigned long long key, double px,
+                                  double py, double pz, double* ba, double* bb)
+{
+    if (hi - lo < 2) return -1;
+    const unsigned long long kf = __shfl(key, lo, 64), kl = __shfl(key, hi - 1, 64);
+    if (kf == kl) return -1;
+    const int hb = 63 - __clzll((long long)(kf ^ kl));
+    const bool low = lane >= lo && lane < hi && !(((key ^ kf) >> hb) & 1ull);
+    const int s = lo + __popcll(__ballot(low));
+    if (s <= lo || s >= hi) return -1;
+    double full[6];
+    range_box(lo, hi, lane, px, py, pz, full);
+    range_box(lo, s, lane, px, py, pz, ba);
+    range_box(s, hi, lane, px, py, pz, bb);
+    const double before = (hi - lo) * sqrt(box_diag2(full));
+    const double after = (s - lo) * sqrt(box_diag2(ba)) + (hi - s) * sqrt(box_diag2(bb));
+    return after < 0.5 * before ? s : -1;
+}
+
+// One wave per bucket: the box, and up to kSubMax compact sub-ranges.
 __global__ __launch_bounds__(256) void k_bucket_boxes(
     const BucketInfo* __restrict__ buckets, int64_t nb, const double* __restrict__ sx,
-    const double* __restrict__ sy, const double* __restrict__ sz, double* __restrict__ box)
+    const double* __restrict__ sy, const double* __restrict__ sz,
+    const unsigned long long* __restrict__ skeys, double* __restrict__ box,
+    SubRange* __restrict__ sub, int* __restrict__ sub_n)
 {
     const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (b >= nb) return;
@@ -247,11 +290,48 @@ __global__ __launch_bounds__(256) void k_bucket_boxes(
     const BucketInfo B = buckets[b];
     const int64_t p = B.start + (lane < B.count ? lane : 0);
     const double px = sx[p], py = sy[p], pz = sz[p];
-    const double l0 = wave_min(px), l1 = wave_min(py), l2 = wave_min(pz);
-    const double u0 = wave_max(px), u1 = wave_max(py), u2 = wave_max(pz);
+    const unsigned long long key = skeys[p];
+    double full[6];
+    range_box(0, B.count, lane, px, py, pz, full);
+    if (lane == 0)
+        for (int q = 0; q < 6; ++q) box[6 * b + q] = full[q];
+    // up to two levels of splits
+    int lo[kSubMax], hi[kSubMax];
+    double bx[kSubMax][6];
+    int n = 1;
+    lo[0] = 0; hi[0] = B.count;
+    for (int q = 0; q < 6; ++q) bx[0][q] = full[q];
+    for (int level = 0; level < 2; ++level) {
+        const int m = n;
+        for (int r = 0; r < m; ++r) {
+            double ba[6], bb[6];
+            const int sp = split_range(lo[r], hi[r], lane, key, px, py, pz, ba, bb);
+            if (sp > 0 && n < kSubMax) {
+                lo[n] = sp; hi[n] = hi[r];
+                hi[r] = sp;
+                for (int q = 0; q < 6; ++q) { bx[r][q] = ba[q]; bx[n][q] = bb[q]; }
+                ++n;
+            }
+        }
+    }
     if (lane == 0) {
-        double* o = box + 6 * b;
-        o[0] = l0; o[1] = l1; o[2] = l2; o[3] = u0; o[4] = u1; o[5] = u2;
+        // sub-ranges in particle order
+        for (int a = 1; a < n; ++a)
+            for (int c = a; c > 0 && lo[c] < lo[c - 1]; --c) {
+                int t = lo[c]; lo[c] = lo[c - 1]; lo[c - 1] = t;
+                t = hi[c]; hi[c] = hi[c - 1]; hi[c - 1] = t;
+                for (int q = 0; q < 6; ++q) {
+                    const double v = bx[c][q]; bx[c][q] = bx[c - 1][q]; bx[c - 1][q] = v;
+                }
+            }
+        for (int r = 0; r < n; ++r) {
+            SubRange R;
+            R.off = lo[r];
+            R.cnt = hi[r] - lo[r];
+            for (int q = 0; q < 6; ++q) R.box[q] = bx[r][q];
+            sub[kSubMax * b + r] = R;
+        }
+        sub_n[b] = n;
     }
 }
 
@@ -324,8 +404,9 @@ hipError_t launch_cell_list(const Plan& P, const sidm_state* s, Scratch& w, hipS
     hipLaunchKernelGGL(k_permute, dim3(grid_of(n, kStreamBlock)), dim3(kStreamBlock), 0, st, n,
                        w.vals[cur], s->x, s->y, s->z, s->vx, s->vy, s->vz, s->m, s->id, s->h,
                        w.sx, w.sy, w.sz, w.svx, w.svy, w.svz, w.sm, w.sid, w.sh, w.perm);
+    w.skeys = w.keys[cur];
     hipLaunchKernelGGL(k_bucket_boxes, dim3(grid_of(P.n_buckets, 4)), dim3(256), 0, st, w.buckets,
-                       P.n_buckets, w.sx, w.sy, w.sz, w.box);
+                       P.n_buckets, w.sx, w.sy, w.sz, w.skeys, w.box, w.sub, w.sub_n);
     for (int l = 1; l < P.n_levels; ++l) {
         const int64_t t0 = P.level_task_off[l - 1], nt = P.level_task_off[l] - t0;
         if (nt > 0)

@@ -12,13 +12,6 @@
 #include "sidm_internal.hpp"
 
 namespace sidm {
-hipError_t launch_gravity(bool mixed, const double* x, const double* y, const double* z,
-                          const double* m, const HaloDev* d_halos, int n_halos,
-                          const StreamBlock* d_blocks, int64_t n_blocks, const GravItem* d_items,
-                          int64_t n_items, double* bsum, double* cref, float4* xm32,
-                          double4* partial, double* ax, double* ay, double* az, double* pot,
-                          double* vx, double* vy, double* vz, int kick, hipStream_t st,
-                          hipEvent_t tile_begin, hipEvent_t tile_end);
 hipError_t launch_kick_drift(const StreamBlock* d_blocks, int64_t n_blocks, const HaloDev* d_halos,
                              double* x, double* y, double* z, double* vx, double* vy, double* vz,
                              const double* ax, const double* ay, const double* az, hipStream_t st);
@@ -33,6 +26,8 @@ hipError_t launch_diag(const StreamBlock* d_blocks, int64_t n_blocks, const Halo
 #include "sidm_plan.hpp"
 
 namespace sidm {
+hipError_t launch_gravity(bool mixed, const Plan& P, Scratch& w, const sidm_state* s, int kick,
+                          hipStream_t st, hipEvent_t tile_begin, hipEvent_t tile_end);
 hipError_t launch_cell_list(const Plan& plan, const sidm_state* s, Scratch& w, hipStream_t st);
 hipError_t launch_knn(const Plan& plan, const sidm_state* s, Scratch& w, uint32_t* nbr, int k_max,
                       hipStream_t st);
@@ -288,12 +283,9 @@ sidm_status sidm_gravity(sidm_ctx* c, const sidm_halo* halos, int32_t n_halos,
     DeviceGuard g(c->device);
     hipStream_t st = (hipStream_t)stream;
     if ((r = ensure_plan(c, halos, n_halos, st)) != SIDM_OK) return r;
-    const Plan& P = c->plan;
-    hipError_t e = launch_gravity(prec == SIDM_PREC_MIXED, s->x, s->y, s->z, s->m, c->w.halos,
-                                  n_halos, c->w.blocks, P.n_blocks, c->w.items, P.n_items,
-                                  c->w.bsum, c->w.cref, c->w.xm32, c->w.partial, s->ax, s->ay,
-                                  s->az, s->pot, nullptr, nullptr, nullptr, 0, st, nullptr,
-                                  nullptr);
+    hipError_t e = launch_cell_list(c->plan, s, c->w, st);
+    if (e == hipSuccess)
+        e = launch_gravity(prec == SIDM_PREC_MIXED, c->plan, c->w, s, 0, st, nullptr, nullptr);
     if (e != hipSuccess) return hip_fail(c, e, "gravity launch");
     c->err.clear();
     return SIDM_OK;
@@ -365,9 +357,9 @@ sidm_status sidm_kdk_step(sidm_ctx* c, const sidm_halo* halos, int32_t n_halos,
     hipStream_t st = (hipStream_t)stream;
     if ((r = ensure_plan(c, halos, n_halos, st)) != SIDM_OK) return r;
     const Plan& P = c->plan;
-    // events: 0 start, 1 after kick+drift, 2/3 around the gravity tiles,
-    // 4 after gravity, 5 after the cell list, 6 after kNN, 7 after the pair
-    // search, 8 after the kicks, 9 after the diagnostics
+    // events: 0 start, 1 after kick+drift, 5 after the cell list, 2/3 around
+    // the gravity tiles, 4 after gravity, 6 after kNN, 7 after the pair search,
+    // 8 after the kicks, 9 after the diagnostics
     hipEvent_t* E = c->ev;
     const bool tm = c->timing;
     auto mark = [&](int i) {
@@ -379,14 +371,12 @@ sidm_status sidm_kdk_step(sidm_ctx* c, const sidm_halo* halos, int32_t n_halos,
         e = launch_kick_drift(c->w.blocks, P.n_blocks, c->w.halos, s->x, s->y, s->z, s->vx,
                               s->vy, s->vz, s->ax, s->ay, s->az, st);
     mark(1);
-    if (e == hipSuccess)
-        e = launch_gravity(prec == SIDM_PREC_MIXED, s->x, s->y, s->z, s->m, c->w.halos, n_halos,
-                           c->w.blocks, P.n_blocks, c->w.items, P.n_items, c->w.bsum, c->w.cref,
-                           c->w.xm32, c->w.partial, s->ax, s->ay, s->az, s->pot, s->vx, s->vy,
-                           s->vz, 1, st, tm ? E[2] : nullptr, tm ? E[3] : nullptr);
-    mark(4);
     if (e == hipSuccess) e = launch_cell_list(P, s, c->w, st);
     mark(5);
+    if (e == hipSuccess)
+        e = launch_gravity(prec == SIDM_PREC_MIXED, P, c->w, s, 1, st, tm ? E[2] : nullptr,
+                           tm ? E[3] : nullptr);
+    mark(4);
     if (e == hipSuccess) e = launch_knn(P, s, c->w, nullptr, max_k(halos, n_halos), st);
     if (e == hipSuccess) e = launch_tree_hmax(P, c->w, st);
     mark(6);
@@ -445,7 +435,7 @@ sidm_status sidm_pass_times(sidm_ctx* c, double ms[SIDM_N_PASSES])
     DeviceGuard g(c->device);
     hipError_t e = hipEventSynchronize(c->ev[9]);
     if (e != hipSuccess) return hip_fail(c, e, "waiting for the timed step");
-    const int from[SIDM_N_PASSES] = {0, 1, 2, 4, 5, 6, 7, 8};
+    const int from[SIDM_N_PASSES] = {0, 5, 2, 1, 4, 6, 7, 8};
     const int to[SIDM_N_PASSES] = {1, 4, 3, 5, 6, 7, 8, 9};
     for (int p = 0; p < SIDM_N_PASSES; ++p) {
         float t = 0.f;

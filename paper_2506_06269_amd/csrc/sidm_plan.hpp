@@ -27,11 +27,24 @@ struct NodeTask {
     int32_t pad;
 };
 
-// Children of every node of the search tree (buckets have none).
+// Children of every node of the search tree (buckets have none) and the last
+// bucket of its subtree (buckets of a subtree are consecutive).
 struct NodeChild {
     int64_t child0;
+    int64_t last;
     int32_t nchild;
     int32_t pad;
+};
+
+// A bucket is cut into at most kSubMax compact sub-ranges at its coarsest
+// internal Morton boundaries when that shrinks their boxes: a bucket of 64
+// consecutive particles that straddles a coarse cell boundary is otherwise
+// spread over a large region.
+constexpr int kSubMax = 4;
+struct SubRange {
+    int32_t off;                  // first particle, relative to the bucket start
+    int32_t cnt;
+    double box[6];
 };
 
 struct Scratch {
@@ -50,9 +63,9 @@ struct Scratch {
     int64_t nodes_cap = 0;        // bucket boxes + tree nodes
     // gravity
     double* bsum = nullptr;       // 7 doubles per streaming block
-    double* cref = nullptr;       // 3 per halo
+    double* cref = nullptr;       // per halo: the common mass if all are equal, else 0
     double* bbox = nullptr;       // 6 per halo (min xyz, max xyz)
-    float4* xm32 = nullptr;
+    float4* xm32 = nullptr;       // FP32 positions relative to their tile centre, mass
     double4* partial = nullptr;
     int64_t partial_rows = 0;
     // cell list
@@ -66,6 +79,9 @@ struct Scratch {
     uint32_t* sid = nullptr;
     uint32_t* perm = nullptr;
     double* box = nullptr;        // 6 per node (buckets first)
+    SubRange* sub = nullptr;      // kSubMax per bucket
+    int* sub_n = nullptr;         // sub-ranges per bucket
+    unsigned long long* skeys = nullptr;   // sorted keys (one of keys[0..1])
     double* hmax = nullptr;       // 1 per node
     // scattering
     unsigned long long* owner = nullptr;
@@ -133,13 +149,14 @@ inline bool alloc_scratch(Scratch& w, int64_t N, int32_t H, int64_t max_events, 
     w.hist_cap = sort_blocks * (1 << kSortBits) + 1;
     bool ok = dalloc(w.halos, H) && dalloc(w.blocks, nb) && dalloc(w.items, w.items_cap) &&
               dalloc(w.buckets, w.buckets_cap) && dalloc(w.node_tasks, w.nodes_cap) && dalloc(w.nodes, w.nodes_cap) &&
-              dalloc(w.bsum, 7 * nb) && dalloc(w.cref, 3 * H) && dalloc(w.bbox, 6 * H) &&
-              dalloc(w.xm32, N) && dalloc(w.partial, w.partial_rows) && dalloc(w.keys[0], N) &&
+              dalloc(w.bsum, 7 * nb) && dalloc(w.cref, 4 * H) && dalloc(w.bbox, 6 * H) &&
+              dalloc(w.xm32, N) &&  dalloc(w.partial, w.partial_rows) && dalloc(w.keys[0], N) &&
               dalloc(w.keys[1], N) && dalloc(w.vals[0], N) && dalloc(w.vals[1], N) &&
               dalloc(w.hist, w.hist_cap) && dalloc(w.sx, N) && dalloc(w.sy, N) &&
               dalloc(w.sz, N) && dalloc(w.svx, N) && dalloc(w.svy, N) && dalloc(w.svz, N) &&
               dalloc(w.sh, N) && dalloc(w.sm, N) && dalloc(w.sid, N) && dalloc(w.perm, N) &&
               dalloc(w.box, 6 * w.nodes_cap) && dalloc(w.hmax, w.nodes_cap) &&
+              dalloc(w.sub, kSubMax * w.buckets_cap) && dalloc(w.sub_n, w.buckets_cap) &&
               dalloc(w.owner, N) && dalloc(w.counters, 1) && dalloc(w.ev_counts, 4 * H) &&
               dalloc(w.status, H);
     if (!ok) {
@@ -163,10 +180,11 @@ inline bool alloc_scratch(Scratch& w, int64_t N, int32_t H, int64_t max_events, 
 inline void free_scratch(Scratch& w)
 {
     dfree(w.halos); dfree(w.blocks); dfree(w.items); dfree(w.buckets); dfree(w.node_tasks); dfree(w.nodes);
-    dfree(w.bsum); dfree(w.cref); dfree(w.bbox); dfree(w.xm32); dfree(w.partial);
+    dfree(w.bsum); dfree(w.cref); dfree(w.bbox); dfree(w.xm32);  dfree(w.partial);
     dfree(w.keys[0]); dfree(w.keys[1]); dfree(w.vals[0]); dfree(w.vals[1]); dfree(w.hist);
     dfree(w.sx); dfree(w.sy); dfree(w.sz); dfree(w.svx); dfree(w.svy); dfree(w.svz);
     dfree(w.sh); dfree(w.sm); dfree(w.sid); dfree(w.perm); dfree(w.box); dfree(w.hmax);
+    dfree(w.sub); dfree(w.sub_n);
     dfree(w.owner); dfree(w.events); dfree(w.counters); dfree(w.ev_counts); dfree(w.status);
 }
 
@@ -275,9 +293,12 @@ inline bool build_plan(Plan& P, const Scratch& w, const sidm_halo* halos, int32_
         P.n_levels = std::max(P.n_levels, H.n_levels);
     }
     P.n_nodes = node_count;
-    P.nodes.assign((size_t)node_count, NodeChild{0, 0, 0});
+    P.nodes.assign((size_t)node_count, NodeChild{0, 0, 0, 0});
+    for (int64_t b = 0; b < P.n_buckets; ++b) P.nodes[(size_t)b].last = b;
     for (int l = 1; l <= kMaxLevels; ++l)
-        for (auto& t : per_level[l]) P.nodes[(size_t)t.node] = NodeChild{t.child0, t.nchild, 0};
+        for (auto& t : per_level[l])
+            P.nodes[(size_t)t.node] =
+                NodeChild{t.child0, P.nodes[(size_t)(t.child0 + t.nchild - 1)].last, t.nchild, 0};
     P.level_task_off.push_back(0);
     for (int l = 1; l < P.n_levels; ++l) {
         for (auto& t : per_level[l]) P.node_tasks.push_back(t);

@@ -124,7 +124,12 @@ def test_step_energy_conservation(S, orc, prec):
     print(f"prec {prec}: max |dE/E| over 32 steps = {worst:.3e}; last p = "
           f"({d['px']:.2e}, {d['py']:.2e}, {d['pz']:.2e})")
     assert worst < 1e-4
-    assert abs(d["px"]) + abs(d["py"]) + abs(d["pz"]) < 1e-9
+    # total momentum (zero initially) stays at roundoff of the force sums:
+    # exactly antisymmetric pair terms in FP64, one-sided FP32 sums in mixed
+    out = S.state_to_host(dev)
+    scale = np.sum(out["m"] * np.sqrt(out["vx"] ** 2 + out["vy"] ** 2 + out["vz"] ** 2))
+    bar = (1e-12 if prec == 0 else 1e-8) * scale
+    assert abs(d["px"]) + abs(d["py"]) + abs(d["pz"]) < bar
 
 
 def test_step_satellite_in_host(S, orc):
