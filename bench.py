@@ -37,6 +37,9 @@ def _args():
     ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="also run one plain device-to-device copy of BYTES bytes (a reference "
+                         "dispatch for scaling HBM byte counters)")
     return ap.parse_args()
 
 
@@ -156,6 +159,13 @@ def main():
     n = cfg["n"]
     s = W.make_state(cfg)
     inter = n * (n - 1)
+    if a.calibrate_copy > 0:
+        src = torch.ones(a.calibrate_copy // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     ms_mixed, de_mixed, passes, dlast, events = _run(S, torch, cfg, s, S.SIDM_PREC_MIXED,
                                                      a.steps, a.warmup, True)
