@@ -37,6 +37,9 @@ def _args():
     ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--workload", default="C2", choices=("C2", "C4", "C5"),
+                    help="C2 (default, the benchmark line): N=2^20 satellite; C4: 64-halo batch; "
+                         "C5: N=2^24 satellite, one step, per-pass rooflines")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="also run one plain device-to-device copy of BYTES bytes (a reference "
                          "dispatch for scaling HBM byte counters)")
@@ -47,19 +50,22 @@ def _energy(d):
     return d["K"] + d["W"] + d["Eext"]
 
 
-def _run(S, torch, cfg, s, prec, steps, warmup, timing):
-    n = cfg["n"]
-    halo = dict(n=n, eps=cfg["eps"], G=1.0, sigma_m=cfg["sigma_m"], dt=cfg["dt"], k=cfg["k"],
-                seed=cfg["seed"], host=cfg["host"])
+def _halo_of(cfg):
+    return dict(n=cfg["n"], eps=cfg["eps"], G=1.0, sigma_m=cfg["sigma_m"], dt=cfg["dt"],
+                k=cfg["k"], seed=cfg["seed"], host=cfg["host"])
+
+
+def _run(S, torch, halos, s, prec, steps, warmup, timing):
+    n = s["x"].size
     dev = S.state_to_device(s)
-    ctx = S.sidm_create(0, n, 1)
-    diag = S.diag_buffer(1)
-    S.sidm_gravity(ctx, [halo], dev, prec)
-    S.sidm_diagnostics(ctx, [halo], dev, diag)
-    e0 = _energy(S.read_diag(diag)[0])
+    ctx = S.sidm_create(0, n, len(halos))
+    diag = S.diag_buffer(len(halos))
+    S.sidm_gravity(ctx, halos, dev, prec)
+    S.sidm_diagnostics(ctx, halos, dev, diag)
+    e0 = sum(_energy(d) for d in S.read_diag(diag))
     step = 0
     for _ in range(warmup):
-        S.sidm_kdk_step(ctx, [halo], dev, step, prec, diag=diag)
+        S.sidm_kdk_step(ctx, halos, dev, step, prec, diag=diag)
         step += 1
     if timing:
         S.sidm_enable_timing(ctx, True)
@@ -68,16 +74,17 @@ def _run(S, torch, cfg, s, prec, steps, warmup, timing):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        S.sidm_kdk_step(ctx, [halo], dev, step, prec, diag=diag)
+        S.sidm_kdk_step(ctx, halos, dev, step, prec, diag=diag)
         step += 1
         if timing:
             for k, v in S.sidm_pass_times(ctx).items():
                 passes[k] = passes.get(k, 0.0) + v
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    d = S.read_diag(diag)[0]
-    events = d["n_events"]
-    rel_e = abs(_energy(d) - e0) / abs(e0)
+    dl = S.read_diag(diag)
+    d = dl[0]
+    events = sum(x["n_events"] for x in dl)
+    rel_e = abs(sum(_energy(x) for x in dl) - e0) / abs(e0)
     for k in passes:
         passes[k] /= steps
     S.sidm_destroy(ctx)
@@ -144,6 +151,73 @@ def _traffic(per_launch_flops):
         return None
 
 
+def _pass_rooflines(passes, n, inter, k):
+    """Per-pass rates for the one-step workloads: the gravity tiles against the
+    FP32 vector peak, the searches against HBM with their algorithmic bytes
+    (kNN: 24 B of position in + 8 B of h out per particle; pair pass: x, v, h, id
+    and m = 60 B per particle)."""
+    g = passes["gravity_tiles"] * 1e-3
+    return {
+        "gravity_tiles": {"bound": "alu", "achieved": FLOPS_PER_INTERACTION * inter / g / 1e12,
+                          "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                          "frac": FLOPS_PER_INTERACTION * inter / g / 1e12 / FP32_PEAK_TFLOPS},
+        "knn": {"algorithmic_GBps": 32 * n / (passes["knn"] * 1e-3) / 1e9, "peak": 8000.0,
+                "unit": "GB/s", "frac": 32 * n / (passes["knn"] * 1e-3) / 1e9 / 8000.0},
+        "pairs": {"algorithmic_GBps": 60 * n / (passes["pairs"] * 1e-3) / 1e9, "peak": 8000.0,
+                  "unit": "GB/s", "frac": 60 * n / (passes["pairs"] * 1e-3) / 1e9 / 8000.0},
+    }
+
+
+def _bench_c4(a, S, torch, W):
+    """64 independent halos in one call per pass (uneven N, sigma/m, k)."""
+    import numpy as np
+    hl = W.batch_c4()
+    total = sum(h["n"] for h in hl)
+    s = {f: np.zeros(total) for f in ("x", "y", "z", "vx", "vy", "vz", "m")}
+    s["id"] = np.zeros(total, dtype=np.uint32)
+    halos, off = [], 0
+    for h in hl:
+        p = W.nfw_halo(h["n"], seed=h["seed"])
+        for f in ("x", "y", "z", "vx", "vy", "vz", "m", "id"):
+            s[f][off:off + h["n"]] = p[f]
+        halos.append(dict(h, offset=off))
+        off += h["n"]
+    inter = sum(h["n"] * (h["n"] - 1) for h in hl)
+    ms, de, passes, _, events = _run(S, torch, halos, s, S.SIDM_PREC_MIXED, a.steps, a.warmup,
+                                     True)
+    out = {"metric": "gravity interactions/s + SIDM particle-updates/s (64-halo batch)",
+           "value": inter / ms, "unit": "gravity interactions/s", "n_gpus": 1,
+           "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32 gravity tiles (compensated), f64 elsewhere",
+           "data": "synthetic NFW halos", "config": {"workload": "C4: 64 NFW halos, N 4096..131072, "
+                                                                  "sigma/m {1,10,50}, k {16..128}",
+                                                     "n_total": total, "halos": 64},
+           "sidm_particle_updates_per_s": total / ms, "dE_over_E": de, "events_last_step": events,
+           "pass_ms": passes}
+    print(json.dumps(out), flush=True)
+
+
+def _bench_c5(a, S, torch, W):
+    """N = 2^24 satellite (eps = 0.002), one full step, per-pass rooflines."""
+    cfg = W.config("C5")
+    n = cfg["n"]
+    print(f"C5: generating N={n}", file=sys.stderr, flush=True)
+    s = W.make_state(cfg)
+    inter = n * (n - 1)
+    print("C5: initial forces and one timed step", file=sys.stderr, flush=True)
+    ms, de, passes, _, events = _run(S, torch, [_halo_of(cfg)], s, S.SIDM_PREC_MIXED, 1, 0, True)
+    out = {"metric": "gravity interactions/s + SIDM particle-updates/s (N=2^24, one step)",
+           "value": inter / ms, "unit": "gravity interactions/s", "n_gpus": 1, "steps": 1,
+           "warmup": 0, "ms_per_step": ms * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32 gravity tiles (compensated), f64 elsewhere",
+           "data": "synthetic NFW halo", "config": {"workload": "C5: NFW N=2^24 satellite, "
+                                                                "eps=0.002, k=64, sigma/m=10"},
+           "sidm_particle_updates_per_s": n / ms, "dE_over_E": de, "events_last_step": events,
+           "pass_ms": passes, "rooflines": _pass_rooflines(passes, n, inter, cfg["k"])}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = _args()
     if a.gpus != 1:
@@ -155,10 +229,15 @@ def main():
     import workloads as W
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
+    if a.workload == "C4":
+        return _bench_c4(a, S, torch, W)
+    if a.workload == "C5":
+        return _bench_c5(a, S, torch, W)
     cfg = W.config("C2")
     n = cfg["n"]
     s = W.make_state(cfg)
     inter = n * (n - 1)
+    halos = [_halo_of(cfg)]
     if a.calibrate_copy > 0:
         src = torch.ones(a.calibrate_copy // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -167,11 +246,11 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    ms_mixed, de_mixed, passes, dlast, events = _run(S, torch, cfg, s, S.SIDM_PREC_MIXED,
+    ms_mixed, de_mixed, passes, dlast, events = _run(S, torch, halos, s, S.SIDM_PREC_MIXED,
                                                      a.steps, a.warmup, True)
     fp64 = None
     if a.fp64_steps > 0:
-        ms64, de64, p64, _, _ = _run(S, torch, cfg, s, S.SIDM_PREC_FP64, a.fp64_steps, 1, True)
+        ms64, de64, p64, _, _ = _run(S, torch, halos, s, S.SIDM_PREC_FP64, a.fp64_steps, 1, True)
         fp64 = {"interactions_per_s": inter / ms64, "ms_per_step": ms64 * 1e3, "dE_over_E": de64,
                 "gravity_tiles_ms": p64.get("gravity_tiles"),
                 "gravity_tiles_frac_fp64_peak":

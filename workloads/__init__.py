@@ -58,8 +58,13 @@ class _Eddington:
         self.d2 = (ddrho * dpsi - drho * ddpsi) / dpsi ** 3
         # boundary term (d rho / d psi at psi = 0, i.e. r = c)
         self.d1_edge = float(self.d1[-1])
-        # f(E) on a log grid of binding energies
-        E = self.psi0 * np.logspace(-10, math.log10(0.999999), n_e)
+        # f(E) on a log grid of binding energies joined with E = psi(r) on a
+        # log grid of radii, which resolves the steep rise of f towards psi0
+        # (the cusp) where a log grid in E alone is far too coarse
+        E = np.unique(np.concatenate([
+            self.psi0 * np.logspace(-10, math.log10(0.999999), n_e),
+            _nfw_psi(np.logspace(-6, math.log10(c), 2 * n_e), c)[:-1]]))
+        E = E[(E > 0.0) & (E < self.psi0)]
         tg, tw = np.polynomial.legendre.leggauss(400)
         f = np.empty_like(E)
         lr_of_psi_x = self.psi[::-1]
@@ -77,15 +82,28 @@ class _Eddington:
         self.f = np.maximum(f, 0.0)
         self._logE = np.log(E)
         self._logf = np.log(np.maximum(self.f, 1e-300))
-        # rejection envelope of v^2 f(psi - v^2/2) as a function of psi
-        pg = self.psi0 * np.logspace(-10, math.log10(0.999999), 400)
-        env = np.empty_like(pg)
-        q = np.linspace(0.0, 1.0, 2001)[1:-1]
-        for k, p in enumerate(pg):
-            v2 = 2.0 * p * q * q
-            env[k] = np.max(v2 * self.df(p - 0.5 * v2))
-        self._env_logp = np.log(pg)
-        self._env_log = np.log(np.maximum(env, 1e-300))
+        # inverse cumulative distribution of the speed at radius r: with
+        # v = q sqrt(2 psi(r)), the density of q is q^2 f(psi (1 - q^2)); rows
+        # are tabulated on a log grid of r (fine where psi approaches psi0 in
+        # the cusp) and columns on s = u^(1/3) (u uniform), which keeps the
+        # q ~ u^(1/3) start of every row resolved
+        self._inv_logr = np.linspace(math.log(1e-6), math.log(c), 2048)
+        pg = _nfw_psi(np.exp(self._inv_logr), c)
+        q = np.linspace(0.0, 1.0, 4097)
+        dens = q[None, :] ** 2 * self.df(pg[:, None] * (1.0 - q[None, :] ** 2))
+        cdf = np.concatenate([np.zeros((pg.size, 1)),
+                              np.cumsum(0.5 * (dens[:, 1:] + dens[:, :-1]), axis=1)], axis=1)
+        tot = cdf[:, -1].copy()
+        cdf /= np.where(tot > 0.0, tot, 1.0)[:, None]
+        sg = np.linspace(0.0, 1.0, 1025)
+        self._inv_q = np.empty((pg.size, sg.size))
+        for k in range(pg.size):
+            if tot[k] > 0.0:
+                # cumsum of non-negative terms is non-decreasing, as np.interp needs
+                self._inv_q[k] = np.interp(sg ** 3, cdf[k], q)
+            else:
+                self._inv_q[k] = sg
+        self._inv_ns = sg.size - 1
 
     def df(self, e):
         e = np.asarray(e, dtype=np.float64)
@@ -93,9 +111,21 @@ class _Eddington:
                                left=-700.0))
         return np.where(e > 0.0, out, 0.0)
 
-    def envelope(self, psi):
-        lp = np.log(np.maximum(psi, 1e-300))
-        return 1.25 * np.exp(np.interp(lp, self._env_logp, self._env_log))
+    def speed_fraction(self, r, u):
+        """q = v / sqrt(2 psi(r)) for uniform u in [0, 1): bilinear lookup of
+        the inverse cumulative table in (log r, u^(1/3))."""
+        lr = np.log(np.maximum(r, 1e-300))
+        t = (lr - self._inv_logr[0]) / (self._inv_logr[1] - self._inv_logr[0])
+        t = np.clip(t, 0.0, self._inv_logr.size - 1.000001)
+        k = t.astype(np.int64)
+        ft = t - k
+        sc = np.cbrt(u) * self._inv_ns
+        j = np.minimum(sc.astype(np.int64), self._inv_ns - 1)
+        fs = sc - j
+        Q = self._inv_q
+        lo = Q[k, j] * (1.0 - fs) + Q[k, j + 1] * fs
+        hi = Q[k + 1, j] * (1.0 - fs) + Q[k + 1, j + 1] * fs
+        return lo * (1.0 - ft) + hi * ft
 
 
 _EDD_CACHE = {}
@@ -127,23 +157,8 @@ def nfw_halo(n, seed=0, r_cut=10.0):
     Mt = nfw_mass(rt) / Mc
     r = np.interp(rng.uniform(0.0, 1.0, n), Mt, rt)
     psi = _nfw_psi(r, r_cut)
-    # speeds by rejection from v^2 f(psi - v^2/2); the few particles within a
-    # hair of r_cut (where the distribution function vanishes) that fail 400
-    # trials get a speed uniform in the escape sphere
-    v = np.zeros(n)
-    todo = np.arange(n)
-    for _ in range(400):
-        if not todo.size:
-            break
-        p = psi[todo]
-        vmax = np.sqrt(2.0 * p)
-        vt = rng.uniform(0.0, 1.0, todo.size) * vmax
-        target = vt * vt * edd.df(p - 0.5 * vt * vt)
-        acc = rng.uniform(0.0, 1.0, todo.size) * edd.envelope(p) < target
-        v[todo[acc]] = vt[acc]
-        todo = todo[~acc]
-    if todo.size:
-        v[todo] = np.sqrt(2.0 * np.maximum(psi[todo], 0.0)) * rng.uniform(0.0, 1.0, todo.size) ** (1 / 3)
+    # speeds from the inverse cumulative distribution of v^2 f(psi - v^2/2)
+    v = np.sqrt(2.0 * np.maximum(psi, 0.0)) * edd.speed_fraction(r, rng.uniform(0.0, 1.0, n))
     ux, uy, uz = _isotropic(rng, n)
     wx, wy, wz = _isotropic(rng, n)
     s = dict(x=r * ux, y=r * uy, z=r * uz, vx=v * wx, vy=v * wy, vz=v * wz)
