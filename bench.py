@@ -55,7 +55,7 @@ def _halo_of(cfg):
                 k=cfg["k"], seed=cfg["seed"], host=cfg["host"])
 
 
-def _run(S, torch, halos, s, prec, steps, warmup, timing):
+def _run(S, torch, halos, s, prec, steps, warmup, timing, progress=False):
     n = s["x"].size
     dev = S.state_to_device(s)
     ctx = S.sidm_create(0, n, len(halos))
@@ -63,6 +63,8 @@ def _run(S, torch, halos, s, prec, steps, warmup, timing):
     S.sidm_gravity(ctx, halos, dev, prec)
     S.sidm_diagnostics(ctx, halos, dev, diag)
     e0 = sum(_energy(d) for d in S.read_diag(diag))
+    if progress:
+        print("initial forces done", file=sys.stderr, flush=True)
     step = 0
     for _ in range(warmup):
         S.sidm_kdk_step(ctx, halos, dev, step, prec, diag=diag)
@@ -206,7 +208,8 @@ def _bench_c5(a, S, torch, W):
     s = W.make_state(cfg)
     inter = n * (n - 1)
     print("C5: initial forces and one timed step", file=sys.stderr, flush=True)
-    ms, de, passes, _, events = _run(S, torch, [_halo_of(cfg)], s, S.SIDM_PREC_MIXED, 1, 0, True)
+    ms, de, passes, _, events = _run(S, torch, [_halo_of(cfg)], s, S.SIDM_PREC_MIXED, 1, 0, True,
+                                     progress=True)
     out = {"metric": "gravity interactions/s + SIDM particle-updates/s (N=2^24, one step)",
            "value": inter / ms, "unit": "gravity interactions/s", "n_gpus": 1, "steps": 1,
            "warmup": 0, "ms_per_step": ms * 1e3, "higher_is_better": True, "scaling": "weak",

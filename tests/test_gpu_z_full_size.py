@@ -1,0 +1,110 @@
+"""The N = 2^24 satellite (eps = 0.002, k = 64, sigma/m = 10, on its orbit in
+the host) at full size, in the launch configuration of its benchmark: kernel
+sizes, scattering events and, last (about a minute of GPU time for the N^2
+sums), the mixed-precision forces, each on sampled particles against the
+oracle's computation over all N."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    import paper_2506_06269_amd as S
+    assert torch.cuda.is_available()
+    S.lib()
+    return S
+
+
+@pytest.fixture(scope="module")
+def c5(S):
+    cfg = W.config("C5")
+    print(f"generating the N={cfg['n']} satellite", flush=True)
+    s = W.make_state(cfg)
+    halo = dict(n=cfg["n"], eps=cfg["eps"], G=1.0, k=cfg["k"], sigma_m=cfg["sigma_m"],
+                dt=cfg["dt"], seed=0, host=cfg["host"])
+    ctx = S.sidm_create(0, cfg["n"], 1)
+    yield cfg, s, halo, ctx
+    S.sidm_destroy(ctx)
+
+
+def test_full_size_knn_and_events(S, orc, c5):
+    """h of 256 sampled particles bit-exact against brute force over all N;
+    every one of the first 2000 GPU events is a valid decision (u < P by the
+    oracle's Lambda); the complete event lists of 128 sampled particles."""
+    import torch
+    cfg, s, halo, ctx = c5
+    n = cfg["n"]
+    dev = S.state_to_device(s)
+    S.sidm_knn_h(ctx, [halo], dev)
+    torch.cuda.synchronize()
+    h = dev["h"].cpu().numpy()
+    assert np.all(np.isfinite(h)) and np.all(h > 0)
+    q = np.random.default_rng(5).choice(n, 256, replace=False)
+    q = np.concatenate([q, [0, n - 1]])
+    ref = orc.knn(s["x"], s["y"], s["z"], s["id"], cfg["k"], query=q)
+    assert np.array_equal(h[q], ref)
+    print("kernel sizes match", flush=True)
+
+    t = dict(s, h=h)
+    ev = S.event_buffer(1 << 20)
+    cnt = S.sidm_scatter(ctx, [halo], dev, 2, events=ev, want_count=True)
+    torch.cuda.synchronize()
+    assert cnt <= (1 << 20)
+    events = S.read_events(ev, cnt)
+    print(f"events: {cnt}", flush=True)
+    assert cnt > 1000
+    idx_of = np.empty(n, dtype=np.int64)
+    idx_of[s["id"]] = np.arange(n)
+    for e in events[:2000]:
+        ia, ib = idx_of[e["a"]], idx_of[e["b"]]
+        u = orc.accept_u(0, 2, int(e["a"]), int(e["b"]))
+        d = np.sqrt((t["x"][ia] - t["x"][ib]) ** 2 + (t["y"][ia] - t["y"][ib]) ** 2 +
+                    (t["z"][ia] - t["z"][ib]) ** 2)
+        g = np.sqrt((t["vx"][ia] - t["vx"][ib]) ** 2 + (t["vy"][ia] - t["vy"][ib]) ** 2 +
+                    (t["vz"][ia] - t["vz"][ib]) ** 2)
+        P = cfg["sigma_m"] * t["m"][ib] * g * orc.lam(d, t["h"][ia], t["h"][ib]) * cfg["dt"]
+        assert u < P * (1 + 1e-12)
+    qs = np.random.default_rng(6).choice(n, 128, replace=False)
+    qmask = np.zeros(n, np.uint8)
+    qmask[qs] = 1
+    ref_ev, _, _ = orc.find_events(t["x"], t["y"], t["z"], t["vx"], t["vy"], t["vz"], t["m"],
+                                   t["id"], t["h"], cfg["sigma_m"], cfg["dt"], 0, 2, qmask=qmask)
+    qid = set(t["id"][qs].tolist())
+    gpu_q = {(int(a), int(b)) for a, b in zip(events["a"], events["b"]) if a in qid or b in qid}
+    assert gpu_q == set(zip(ref_ev["a"].tolist(), ref_ev["b"].tolist()))
+    del dev
+
+
+@pytest.mark.timeout(900)
+def test_full_size_gravity_mixed(S, orc, c5):
+    """Mixed-precision forces and potentials of 256 sampled particles (and the
+    first and last) against the oracle's FP64 sums over all N, normwise 1e-5."""
+    import torch
+    cfg, s, halo, ctx = c5
+    n = cfg["n"]
+    dev = S.state_to_device(s)
+    print("gravity over N^2 pairs", flush=True)
+    S.sidm_gravity(ctx, [halo], dev, S.SIDM_PREC_MIXED)
+    torch.cuda.synchronize()
+    out = S.state_to_host(dev)
+    q = np.random.default_rng(7).choice(n, 256, replace=False)
+    q = np.concatenate([q, [0, n - 1]])
+    ax, ay, az, pot, an = orc.gravity(s["x"], s["y"], s["z"], s["m"], 1.0, cfg["eps"], query=q,
+                                      want_norm=True)
+    H = halo["host"]
+    hx, hy, hz, hp = orc.host_nfw(s["x"][q], s["y"][q], s["z"][q], 1.0, H["rho_s"], H["r_s"],
+                                  H["center"])
+    ax, ay, az, pot = ax + hx, ay + hy, az + hz, pot + hp
+    an = an + np.sqrt(hx ** 2 + hy ** 2 + hz ** 2)
+    da = np.sqrt((out["ax"][q] - ax) ** 2 + (out["ay"][q] - ay) ** 2 +
+                 (out["az"][q] - az) ** 2) / an
+    dp = np.abs(out["pot"][q] - pot) / np.abs(pot)
+    print(f"N=2^24 sampled: max e_a={da.max():.3e} e_phi={dp.max():.3e}", flush=True)
+    assert da.max() < 1e-5
+    assert dp.max() < 1e-5
+    del dev
