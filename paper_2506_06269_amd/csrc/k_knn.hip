@@ -4,19 +4,21 @@
 //
 // One wavefront per bucket of 64 Morton-consecutive particles, one particle
 // per lane; the lanes of each compact sub-range of the bucket are resolved
-// together.  Candidates are staged sub-range by sub-range in LDS and every
-// lane reads the same candidate (broadcast), as in the gravity tiles.  A
-// candidate sub-range is visited only if it intersects the search sphere of
-// at least one lane.
+// together.  Candidates are read with wave-uniform loads (every lane
+// evaluates the same candidate), and a candidate sub-range is visited only if
+// it intersects the search sphere of at least one lane.
 // Selection works on values only, with a private 32-bin histogram per lane
-// (an LDS column, no atomics):
-//   1. each lane starts below an estimate from its 8th-nearest bucket-mate and
-//      grows the radius by 1.5 until the sphere holds k (counts at four radii
-//      in registers pick the smallest that does); a histogram of the
-//      distances in [0, u_i^2] then names the bin of the k-th;
-//   2. a visit restricted to that bin's shell collects its members (at most
-//      16) or, if it holds more, refines the bin by its own min..max range
-//      (again visiting only the shell); equal values end the refinement.
+// (an LDS column, written with LDS atomics that return nothing):
+//   1. a histogram of the distances within a starting radius: 1.15 times the
+//      kernel size the particle had before the call when that is a usable
+//      value (a warm start: the result does not depend on it), otherwise an
+//      estimate from the nearest members of its own sub-range; the radius
+//      grows until the sphere holds k others;
+//   2. a visit restricted to the shell of the bin that holds the k-th
+//      collects that bin's members (at most 16, kept sorted in registers) or,
+//      if it holds more, records their min..max, whose histogram (step 1 over
+//      that range) refines the choice; equal values end the refinement.
+// Typical cost: two visits of the candidates around the bucket.
 // Distances d2 = (dx*dx + dy*dy) + dz*dz are evaluated in FP64 without fused
 // multiply-add, the same expression the oracle uses, so h matches bit for bit.
 #include "sidm_tree.hpp"
@@ -27,15 +29,10 @@ constexpr int kKnnBins = 32;
 constexpr int kKnnSurv = 16;
 constexpr int kKnnLevels = 4;
 constexpr int kKnnGrow = 80;
+constexpr double kKnnWarm = 1.15 * 1.15;   // squared margin on the previous kernel size
 
 struct KnnLds {
-    double cx[kBucket], cy[kBucket], cz[kBucket];
-    uint32_t cpos[kBucket];
     uint32_t hist[kKnnBins][kBucket];
-    double surv[kKnnSurv][kBucket];
-    double lv_lo[kKnnLevels][kBucket];
-    double lv_inv[kKnnLevels][kBucket];
-    int lv_beta[kKnnLevels][kBucket];
     int64_t stack[kStackMax];
 };
 
@@ -53,20 +50,31 @@ __device__ inline double box_diag2_k(const double* b)
     return ex * ex + ey * ey + ez * ez;
 }
 
+// Bin of d2 among kKnnBins equal bins starting at lo (monotone in d2; NaN
+// products, from an infinite inv, fall in bin 0).
 __device__ inline int bin_of(double d2, double lo, double inv)
 {
-    int b = (int)((d2 - lo) * inv);
-    b = b < 0 ? 0 : b;
-    return b > kKnnBins - 1 ? kKnnBins - 1 : b;
+    const double t = (d2 - lo) * inv;
+    return t >= (double)(kKnnBins - 1) ? kKnnBins - 1 : (t > 0.0 ? (int)t : 0);
+}
+
+// Insertion of v into the ascending list best[0..kKnnSurv) (registers).
+__device__ inline void insert_sorted(double (&best)[kKnnSurv], double v)
+{
+#pragma unroll
+    for (int q = 0; q < kKnnSurv; ++q) {
+        const double lo = fmin(best[q], v);
+        v = fmax(best[q], v);
+        best[q] = lo;
+    }
 }
 
 __global__ __launch_bounds__(kBucket) void k_knn(
     const HaloDev* __restrict__ halos, const BucketInfo* __restrict__ buckets,
     const NodeChild* __restrict__ nodes, const double* __restrict__ box,
     const SubRange* __restrict__ sub, const int* __restrict__ sub_n, int64_t n_buckets,
-    const double* __restrict__ sx, const double* __restrict__ sy, const double* __restrict__ sz,
-    const uint32_t* __restrict__ perm, double* __restrict__ sh, double* __restrict__ h_out,
-    int* __restrict__ status)
+    const double4* __restrict__ sp4, const uint32_t* __restrict__ perm,
+    double* __restrict__ sh, double* __restrict__ h_out, int* __restrict__ status)
 {
     __shared__ KnnLds L;
     const int64_t b = blockIdx.x;
@@ -75,22 +83,16 @@ __global__ __launch_bounds__(kBucket) void k_knn(
     const HaloDev& H = halos[B.halo];
     const int k = H.k;
     const bool in_bucket = lane < B.count;
-    const uint32_t mypos = (uint32_t)(B.start + (in_bucket ? lane : 0));
-    const double xi = sx[mypos], yi = sy[mypos], zi = sz[mypos];
+    const int64_t mypos = B.start + (in_bucket ? lane : 0);
+    const double4 me = sp4[mypos];
+    const double xi = me.x, yi = me.y, zi = me.z;
+    const double hint = sh[mypos];   // the kernel size before the call
+    const double diag2 = box_diag2_k(box + 6 * H.level_off[H.n_levels - 1]);
     auto all_nodes = [](int64_t) { return true; };
 
-    // stage particles [p0, p0 + cnt) of the sorted order into LDS
-    auto stage = [&](int64_t p0, int cnt) {
-        __syncthreads();
-        if (lane < cnt) {
-            const int64_t p = p0 + lane;
-            L.cx[lane] = sx[p]; L.cy[lane] = sy[p]; L.cz[lane] = sz[p];
-            L.cpos[lane] = (uint32_t)p;
-        }
-        __syncthreads();
-    };
-    // visit every candidate sub-range within reach of a lane's sphere
-    // (radius^2 r2 of the lane, ignored when `off` is true for the lane)
+    // every candidate of the sub-ranges within reach of a lane's sphere
+    // (radius^2 r2 of the lane, ignored when `off` is true for the lane);
+    // body(p, c) runs on every lane for candidate p at c = (x, y, z, .)
     auto visit = [&](double r2, bool off, auto body) {
         tree_visit(H, nodes, n_buckets, L.stack,
                    [&](int64_t c) { return !off && point_box_dist2(xi, yi, zi, box + 6 * c) <= r2; },
@@ -98,34 +100,48 @@ __global__ __launch_bounds__(kBucket) void k_knn(
                        const int64_t c0 = buckets[c].start;
                        const int ns = sub_n[c];
                        for (int q = 0; q < ns; ++q) {
-                           const SubRange R = sub[kSubMax * c + q];
+                           const SubRange& R = sub[kSubMax * c + q];
                            if (!__ballot(!off && point_box_dist2(xi, yi, zi, R.box) <= r2)) continue;
-                           stage(c0 + R.off, R.cnt);
-                           if (!off) body(R.cnt);
+                           const int64_t p0 = c0 + R.off;
+                           const int cnt = R.cnt;
+                           for (int j = 0; j < cnt; ++j) body(p0 + j, sp4[p0 + j]);
                        }
                    });
     };
+    // histogram of the distances in [a, z] over kKnnBins bins from lo
+    auto histogram = [&](bool on, double a, double z, double lo, double inv) {
+        if (on)
+            for (int q = 0; q < kKnnBins; ++q) L.hist[q][lane] = 0u;
+        visit(z * (1.0 + 1e-9), !on, [&](int64_t p, const double4& c) {
+            const double d2 = dist2_exact(xi, yi, zi, c.x, c.y, c.z);
+            if (on && p != mypos && d2 >= a && d2 <= z)
+                atomicAdd(&L.hist[bin_of(d2, lo, inv)][lane], 1u);
+        });
+        __syncthreads();
+    };
 
-    // the lanes of each compact sub-range of this bucket are resolved together
     const int ngroups = sub_n[b];
     for (int g = 0; g < ngroups; ++g) {
         const SubRange G = sub[kSubMax * b + g];
         const bool act = in_bucket && lane >= G.off && lane < G.off + G.cnt;
 
-        // ---- 1. starting radius: distance to the m-th nearest member of the
-        // lane's own sub-range (m <= 8), scaled to k neighbours, started low
-        double u2;
-        {
+        // ---- starting radius
+        const bool warm = isfinite(hint) && hint > 0.0 && hint * hint <= diag2;
+        double u2 = kKnnWarm * hint * hint;
+        if (__ballot(act && !warm)) {
+            // the m-th nearest member of the lane's own sub-range (m <= 8),
+            // scaled to k neighbours
             constexpr int kM = 8;
             double best[kM];
 #pragma unroll
             for (int q = 0; q < kM; ++q) best[q] = INFINITY;
-            stage(B.start + G.off, G.cnt);
+            const int64_t p0 = B.start + G.off;
             for (int j = 0; j < G.cnt; ++j) {
-                if (L.cpos[j] == mypos) continue;
-                double v = dist2_exact(xi, yi, zi, L.cx[j], L.cy[j], L.cz[j]);
+                const double4 c = sp4[p0 + j];
+                if (p0 + j == mypos) continue;
+                double v = dist2_exact(xi, yi, zi, c.x, c.y, c.z);
 #pragma unroll
-                for (int q = 0; q < kM; ++q) {   // insertion into the sorted best list
+                for (int q = 0; q < kM; ++q) {
                     const double lo = fmin(best[q], v);
                     v = fmax(best[q], v);
                     best[q] = lo;
@@ -136,152 +152,97 @@ __global__ __launch_bounds__(kBucket) void k_knn(
 #pragma unroll
             for (int q = 0; q < kM; ++q)
                 if (q == m - 1) rm2 = best[q];
-            if (m >= 1 && rm2 > 0.0 && rm2 < INFINITY) {
-                // start below the estimate: a pass over a small sphere is
-                // cheap, one over a sphere far too large is not
-                u2 = 0.3 * 1.44 * rm2 * pow((double)k / (double)m, 2.0 / 3.0);
-            } else {
-                const double* rb = box + 6 * H.level_off[H.n_levels - 1];
-                u2 = box_diag2_k(rb) / cbrt((double)H.n * (double)H.n);
+            if (!warm) {
+                if (m >= 1 && rm2 > 0.0 && rm2 < INFINITY)
+                    u2 = 1.44 * rm2 * pow((double)k / (double)m, 2.0 / 3.0);
+                else
+                    u2 = diag2 / cbrt((double)H.n * (double)H.n);
+                if (!(u2 > 0.0)) u2 = 1.0;
             }
         }
-        bool done = !act;      // this lane's h is known
-        // grow the radius by 1.5 until the sphere holds k others; counts at four
-        // radii inside the sphere (registers only) give the smallest that does
-        bool found = !act;
-        int grow = 0;
-        while (__ballot(!found)) {
-            int c0 = 0, c1 = 0, c2 = 0, c3 = 0;
-            const double t0 = 0.55 * u2, t1 = 0.7 * u2, t2 = 0.85 * u2, t3 = u2;
-            visit(u2 * (1.0 + 1e-9), found, [&](int cnt) {
-                for (int j = 0; j < cnt; ++j) {
-                    const double d2 = dist2_exact(xi, yi, zi, L.cx[j], L.cy[j], L.cz[j]);
-                    const int self = L.cpos[j] == mypos;
-                    c0 += (d2 <= t0) - self;
-                    c1 += (d2 <= t1) - self;
-                    c2 += (d2 <= t2) - self;
-                    c3 += (d2 <= t3) - self;
-                }
-            });
-            if (!found) {
-                if (c3 >= k) {
-                    found = true;
-                    u2 = c0 >= k ? t0 : c1 >= k ? t1 : c2 >= k ? t2 : t3;
-                } else if (++grow > kKnnGrow) {
-                    found = done = true;
-                    atomicOr(&status[B.halo], SIDM_DEV_KNN_OVERFLOW);
-                } else if (u2 > 0.0) {
-                    u2 *= 2.25;
-                } else {
-                    u2 = box_diag2_k(box + 6 * H.level_off[H.n_levels - 1]) /
-                         cbrt((double)H.n * (double)H.n);
-                    if (!(u2 > 0.0)) u2 = 1.0;
-                }
-            }
-        }
-        // ---- 2. level-0 histogram of the distances in [0, u2]
-        const double inv0 = u2 > 0.0 ? (double)kKnnBins / u2 : 0.0;
-        for (int q = 0; q < kKnnBins; ++q) L.hist[q][lane] = 0;
-        L.lv_lo[0][lane] = 0.0;
-        L.lv_inv[0][lane] = inv0;
-        visit(u2 * (1.0 + 1e-9), done, [&](int cnt) {
-            for (int j = 0; j < cnt; ++j) {
-                if (L.cpos[j] == mypos) continue;
-                const double d2 = dist2_exact(xi, yi, zi, L.cx[j], L.cy[j], L.cz[j]);
-                if (d2 <= u2) atomicAdd(&L.hist[bin_of(d2, 0.0, inv0)][lane], 1u);
-            }
-        });
-        __syncthreads();
 
-        // ---- 3. select the bin of the k-th, collect or refine
-        bool ready = true;
-        int level = 0, below = 0;
-        double d2k = NAN;
-        auto member = [&](double d2, int upto) {
-            if (!(d2 <= u2)) return false;
-            for (int l = 0; l < upto; ++l)
-                if (bin_of(d2, L.lv_lo[l][lane], L.lv_inv[l][lane]) != L.lv_beta[l][lane])
-                    return false;
-            return true;
-        };
-        double cull2 = u2 * (1.0 + 1e-9);   // members of the current bin lie within
-        while (__ballot(!done)) {
-            if (__ballot(!done && !ready)) {
-                const double lo_l = L.lv_lo[level][lane], inv_l = L.lv_inv[level][lane];
-                const bool skip = done || ready;
-                if (!skip)
-                    for (int q = 0; q < kKnnBins; ++q) L.hist[q][lane] = 0;
-                visit(cull2, skip, [&](int cnt) {
-                    for (int j = 0; j < cnt; ++j) {
-                        if (L.cpos[j] == mypos) continue;
-                        const double d2 = dist2_exact(xi, yi, zi, L.cx[j], L.cy[j], L.cz[j]);
-                        if (member(d2, level))
-                            atomicAdd(&L.hist[bin_of(d2, lo_l, inv_l)][lane], 1u);
-                    }
-                });
-                ready = true;
-                __syncthreads();
+        // ---- 1. histogram of [0, u2]; grow until the sphere holds k others
+        bool need = act, failed = false;
+        int grow = 0;
+        while (__ballot(need)) {
+            histogram(need, 0.0, u2, 0.0, (double)kKnnBins / u2);
+            if (need) {
+                int tot = 0;
+                for (int q = 0; q < kKnnBins; ++q) tot += (int)L.hist[q][lane];
+                if (tot >= k) {
+                    need = false;
+                } else if (++grow > kKnnGrow) {
+                    need = false;
+                    failed = true;
+                    atomicOr(&status[B.halo], SIDM_DEV_KNN_OVERFLOW);
+                } else {
+                    double f = tot > 0 ? 1.44 * pow((double)k / (double)tot, 2.0 / 3.0) : 4.0;
+                    u2 *= fmin(fmax(f, 1.44), 16.0);
+                }
             }
-            int sel = -1, inb = 0, cum = below;
-            double shell2 = 0.0;   // members of the selected bin lie within this
+        }
+
+        // ---- 2. select the bin of the k-th, collect its members or refine.
+        // Members of the current set lie in [a, z]; its histogram uses bins
+        // (lo, inv); `below` counts the candidates under the selected bin.
+        bool done = !act || failed;
+        double a = 0.0, z = u2, lo = 0.0, inv = (double)kKnnBins / u2;
+        int below = 0, level = 0;
+        double d2k = NAN;
+        while (__ballot(!done)) {
+            int sel = -1, inb = 0;
+            double shell2 = 0.0;
             if (!done) {
+                int cum = below;
                 for (int q = 0; q < kKnnBins; ++q) {
                     const int hq = (int)L.hist[q][lane];
                     if (cum + hq >= k) { sel = q; inb = hq; break; }
                     cum += hq;
                 }
-                if (sel < 0) {   // cannot happen: the sphere holds at least k
-                    done = true;
-                    atomicOr(&status[B.halo], SIDM_DEV_KNN_OVERFLOW);
-                } else {
-                    L.lv_beta[level][lane] = sel;
-                    const double inv_l = L.lv_inv[level][lane];
-                    shell2 = inv_l > 0.0 ? L.lv_lo[level][lane] + (double)(sel + 1) / inv_l : u2;
-                    shell2 = fmin(u2, shell2) * (1.0 + 1e-9);
-                }
-            }
-            double mn = INFINITY, mxv = -INFINITY;
-            int ns = 0;
-            visit(shell2, done, [&](int cnt) {
-                for (int j = 0; j < cnt; ++j) {
-                    if (L.cpos[j] == mypos) continue;
-                    const double d2 = dist2_exact(xi, yi, zi, L.cx[j], L.cy[j], L.cz[j]);
-                    if (member(d2, level + 1)) {
-                        mn = fmin(mn, d2);
-                        mxv = fmax(mxv, d2);
-                        if (inb <= kKnnSurv && ns < kKnnSurv) L.surv[ns++][lane] = d2;
-                    }
-                }
-            });
-            if (!done) {
-                if (inb <= kKnnSurv) {
-                    for (int a = 1; a < ns; ++a) {   // insertion sort of the bin's members
-                        const double v = L.surv[a][lane];
-                        int q = a - 1;
-                        while (q >= 0 && L.surv[q][lane] > v) {
-                            L.surv[q + 1][lane] = L.surv[q][lane];
-                            --q;
-                        }
-                        L.surv[q + 1][lane] = v;
-                    }
-                    const int r = k - cum - 1;
-                    if (r >= 0 && r < ns) d2k = L.surv[r][lane];
-                    done = true;
-                } else if (mn == mxv) {
-                    d2k = mn;        // all members tie at the k-th distance
-                    done = true;
-                } else if (level + 1 >= kKnnLevels) {
+                if (sel < 0) {   // cannot happen: the set holds the k-th
                     done = true;
                     atomicOr(&status[B.halo], SIDM_DEV_KNN_OVERFLOW);
                 } else {
                     below = cum;
-                    ++level;
-                    L.lv_lo[level][lane] = mn;
-                    L.lv_inv[level][lane] = (double)kKnnBins / (mxv - mn);
-                    ready = false;
-                    cull2 = shell2;
+                    shell2 = inv > 0.0 && isfinite(inv) ? fmin(z, lo + (double)(sel + 1) / inv) : z;
                 }
             }
+            double best[kKnnSurv];
+#pragma unroll
+            for (int q = 0; q < kKnnSurv; ++q) best[q] = INFINITY;
+            double mn = INFINITY, mxv = -INFINITY;
+            const bool collect = !done && inb <= kKnnSurv;
+            visit(shell2 * (1.0 + 1e-9), done, [&](int64_t p, const double4& c) {
+                const double d2 = dist2_exact(xi, yi, zi, c.x, c.y, c.z);
+                if (!done && p != mypos && d2 >= a && d2 <= z && bin_of(d2, lo, inv) == sel) {
+                    mn = fmin(mn, d2);
+                    mxv = fmax(mxv, d2);
+                    if (collect) insert_sorted(best, d2);
+                }
+            });
+            bool refine = false;
+            if (!done) {
+                if (collect) {
+                    const int r = k - below - 1;
+#pragma unroll
+                    for (int q = 0; q < kKnnSurv; ++q)
+                        if (q == r) d2k = best[q];
+                    done = true;
+                } else if (mn == mxv) {
+                    d2k = mn;        // all members tie at the k-th distance
+                    done = true;
+                } else if (++level >= kKnnLevels) {
+                    done = true;
+                    atomicOr(&status[B.halo], SIDM_DEV_KNN_OVERFLOW);
+                } else {
+                    a = mn;
+                    z = mxv;
+                    lo = mn;
+                    inv = (double)kKnnBins / (mxv - mn);
+                    refine = true;
+                }
+            }
+            if (__ballot(refine)) histogram(refine, a, z, lo, inv);
         }
         if (act) {
             const double h = sqrt(d2k);
@@ -330,8 +291,8 @@ hipError_t launch_knn(const Plan& P, const sidm_state* s, Scratch& w, uint32_t* 
                       hipStream_t st)
 {
     hipLaunchKernelGGL(k_knn, dim3((unsigned)P.n_buckets), dim3(kBucket), 0, st, w.halos,
-                       w.buckets, w.nodes, w.box, w.sub, w.sub_n, P.n_buckets, w.sx, w.sy, w.sz,
-                       w.perm, w.sh, s->h, w.status);
+                       w.buckets, w.nodes, w.box, w.sub, w.sub_n, P.n_buckets, w.sp4, w.perm,
+                       w.sh, s->h, w.status);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !nbr) return e;
     double* rowd2 = nullptr;

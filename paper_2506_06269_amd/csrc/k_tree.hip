@@ -208,14 +208,17 @@ __global__ __launch_bounds__(kStreamBlock) void k_permute(
     const double* __restrict__ y, const double* __restrict__ z, const double* __restrict__ vx,
     const double* __restrict__ vy, const double* __restrict__ vz, const double* __restrict__ m,
     const uint32_t* __restrict__ id, const double* __restrict__ h, double* __restrict__ sx,
-    double* __restrict__ sy, double* __restrict__ sz, double* __restrict__ svx,
+    double* __restrict__ sy, double* __restrict__ sz, double4* __restrict__ sp4,
+    double* __restrict__ svx,
     double* __restrict__ svy, double* __restrict__ svz, double* __restrict__ sm,
     uint32_t* __restrict__ sid, double* __restrict__ sh, uint32_t* __restrict__ perm)
 {
     const int64_t p = (int64_t)blockIdx.x * kStreamBlock + threadIdx.x;
     if (p >= n) return;
     const uint32_t o = order[p];
-    sx[p] = x[o]; sy[p] = y[o]; sz[p] = z[o];
+    const double px = x[o], py = y[o], pz = z[o];
+    sx[p] = px; sy[p] = py; sz[p] = pz;
+    sp4[p] = make_double4(px, py, pz, 0.0);
     if (vx) { svx[p] = vx[o]; svy[p] = vy[o]; svz[p] = vz[o]; }
     sm[p] = m[o];
     if (id) sid[p] = id[o];
@@ -403,7 +406,7 @@ hipError_t launch_cell_list(const Plan& P, const sidm_state* s, Scratch& w, hipS
     }
     hipLaunchKernelGGL(k_permute, dim3(grid_of(n, kStreamBlock)), dim3(kStreamBlock), 0, st, n,
                        w.vals[cur], s->x, s->y, s->z, s->vx, s->vy, s->vz, s->m, s->id, s->h,
-                       w.sx, w.sy, w.sz, w.svx, w.svy, w.svz, w.sm, w.sid, w.sh, w.perm);
+                       w.sx, w.sy, w.sz, w.sp4, w.svx, w.svy, w.svz, w.sm, w.sid, w.sh, w.perm);
     w.skeys = w.keys[cur];
     hipLaunchKernelGGL(k_bucket_boxes, dim3(grid_of(P.n_buckets, 4)), dim3(256), 0, st, w.buckets,
                        P.n_buckets, w.sx, w.sy, w.sz, w.skeys, w.box, w.sub, w.sub_n);

@@ -74,6 +74,7 @@ struct Scratch {
     uint32_t* hist = nullptr;
     int64_t hist_cap = 0;
     double *sx = nullptr, *sy = nullptr, *sz = nullptr;
+    double4* sp4 = nullptr;       // sorted positions as (x, y, z, 0): one load per candidate
     double *svx = nullptr, *svy = nullptr, *svz = nullptr;
     double *sh = nullptr, *sm = nullptr;
     uint32_t* sid = nullptr;
@@ -153,7 +154,7 @@ inline bool alloc_scratch(Scratch& w, int64_t N, int32_t H, int64_t max_events, 
               dalloc(w.xm32, N) &&  dalloc(w.partial, w.partial_rows) && dalloc(w.keys[0], N) &&
               dalloc(w.keys[1], N) && dalloc(w.vals[0], N) && dalloc(w.vals[1], N) &&
               dalloc(w.hist, w.hist_cap) && dalloc(w.sx, N) && dalloc(w.sy, N) &&
-              dalloc(w.sz, N) && dalloc(w.svx, N) && dalloc(w.svy, N) && dalloc(w.svz, N) &&
+              dalloc(w.sz, N) && dalloc(w.sp4, N) && dalloc(w.svx, N) && dalloc(w.svy, N) && dalloc(w.svz, N) &&
               dalloc(w.sh, N) && dalloc(w.sm, N) && dalloc(w.sid, N) && dalloc(w.perm, N) &&
               dalloc(w.box, 6 * w.nodes_cap) && dalloc(w.hmax, w.nodes_cap) &&
               dalloc(w.sub, kSubMax * w.buckets_cap) && dalloc(w.sub_n, w.buckets_cap) &&
@@ -182,7 +183,7 @@ inline void free_scratch(Scratch& w)
     dfree(w.halos); dfree(w.blocks); dfree(w.items); dfree(w.buckets); dfree(w.node_tasks); dfree(w.nodes);
     dfree(w.bsum); dfree(w.cref); dfree(w.bbox); dfree(w.xm32);  dfree(w.partial);
     dfree(w.keys[0]); dfree(w.keys[1]); dfree(w.vals[0]); dfree(w.vals[1]); dfree(w.hist);
-    dfree(w.sx); dfree(w.sy); dfree(w.sz); dfree(w.svx); dfree(w.svy); dfree(w.svz);
+    dfree(w.sx); dfree(w.sy); dfree(w.sz); dfree(w.sp4); dfree(w.svx); dfree(w.svy); dfree(w.svz);
     dfree(w.sh); dfree(w.sm); dfree(w.sid); dfree(w.perm); dfree(w.box); dfree(w.hmax);
     dfree(w.sub); dfree(w.sub_n);
     dfree(w.owner); dfree(w.events); dfree(w.counters); dfree(w.ev_counts); dfree(w.status);

@@ -7,6 +7,15 @@ namespace sidm {
 
 constexpr int kStackMax = 96;
 
+// A value every lane of the wave holds, moved to a scalar register so that the
+// loads it addresses are issued once per wave.
+__device__ inline int64_t wave_uniform(int64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // Squared distance from point p to an axis-aligned box (lo xyz, hi xyz).
 __device__ inline double point_box_dist2(double px, double py, double pz,
                                          const double* __restrict__ b)
@@ -38,7 +47,7 @@ __device__ inline void tree_visit(const HaloDev& H, const NodeChild* __restrict_
     int sp = 1;
     __syncthreads();
     while (sp > 0) {
-        const int64_t node = stack[sp - 1];
+        const int64_t node = wave_uniform(stack[sp - 1]);
         --sp;
         const NodeChild N = nodes[node];
         unsigned hits = 0u;
