@@ -423,6 +423,19 @@ __global__ __launch_bounds__(kStreamBlock) void k_grav_finalize(
 }
 
 // ---------------------------------------------------------------- launchers
+// Blocks of the mixed-precision tiles that the device holds at once (compute
+// units times resident blocks per unit), or 0 if unknown.
+int64_t gravity_slots(int device)
+{
+    int cus = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+        return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_grav_mixed<4>, kGravThreads, 0) !=
+        hipSuccess)
+        return 0;
+    return (int64_t)cus * per_cu;
+}
+
 // Expects the cell list of the current positions (sorted copies sx, sy, sz, sm
 // and perm) to be in place.
 hipError_t launch_gravity(bool mixed, const Plan& P, Scratch& w, const sidm_state* s, int kick,

@@ -28,6 +28,7 @@ hipError_t launch_diag(const StreamBlock* d_blocks, int64_t n_blocks, const Halo
 namespace sidm {
 hipError_t launch_gravity(bool mixed, const Plan& P, Scratch& w, const sidm_state* s, int kick,
                           hipStream_t st, hipEvent_t tile_begin, hipEvent_t tile_end);
+int64_t gravity_slots(int device);
 hipError_t launch_cell_list(const Plan& plan, const sidm_state* s, Scratch& w, hipStream_t st);
 hipError_t launch_knn(const Plan& plan, const sidm_state* s, Scratch& w, uint32_t* nbr, int k_max,
                       hipStream_t st);
@@ -242,6 +243,7 @@ sidm_status sidm_create(sidm_ctx** out, int device, int64_t max_particles, int32
         delete c;
         return SIDM_ERR_NOMEM;
     }
+    c->w.grav_slots = gravity_slots(device);
     *out = c;
     return SIDM_OK;
 }

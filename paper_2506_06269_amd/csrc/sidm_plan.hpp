@@ -4,6 +4,7 @@
 #pragma once
 
 #include <algorithm>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -68,6 +69,7 @@ struct Scratch {
     float4* xm32 = nullptr;       // FP32 positions relative to their tile centre, mass
     double4* partial = nullptr;
     int64_t partial_rows = 0;
+    int64_t grav_slots = 0;       // resident blocks of the gravity tiles on the whole device
     // cell list
     unsigned long long* keys[2] = {nullptr, nullptr};
     uint32_t* vals[2] = {nullptr, nullptr};
@@ -189,9 +191,12 @@ inline void free_scratch(Scratch& w)
     dfree(w.owner); dfree(w.events); dfree(w.counters); dfree(w.ev_counts); dfree(w.status);
 }
 
-// Number of j-splits for the gravity sum of each halo: enough work items to
-// fill the chip (a few blocks per CU), within the partial-row budget.
-inline void choose_splits(std::vector<HaloDev>& hd, int64_t partial_rows)
+// Number of j-splits for the gravity sum of each halo.  Work items (one
+// block of kGravThreads * 4 i-particles against one j-range) are started
+// largest first on `slots` resident blocks; the split whose simulated
+// finishing time is smallest wins (ties go to fewer splits, which write fewer
+// partial rows).  Without an occupancy figure, enough items to fill the chip.
+inline void choose_splits(std::vector<HaloDev>& hd, int64_t partial_rows, int64_t slots)
 {
     const int64_t kIBlock = kGravThreads * 4;
     int64_t iblocks = 0, ntot = 0;
@@ -199,12 +204,46 @@ inline void choose_splits(std::vector<HaloDev>& hd, int64_t partial_rows)
         iblocks += (H.n + kIBlock - 1) / kIBlock;
         ntot += H.n;
     }
-    const int64_t target = 2048;
-    int64_t split = std::max<int64_t>(1, (target + iblocks - 1) / iblocks);
-    split = std::min<int64_t>(split, std::max<int64_t>(1, partial_rows / std::max<int64_t>(ntot, 1)));
+    const int64_t smax = std::min<int64_t>(4, std::max<int64_t>(1, partial_rows / std::max<int64_t>(ntot, 1)));
+    int64_t best = 1;
+    if (slots <= 0) {
+        best = std::min<int64_t>(smax, std::max<int64_t>(1, (2048 + iblocks - 1) / iblocks));
+    } else {
+        double best_t = 0.0;
+        std::vector<int64_t> cost;
+        std::vector<double> load;
+        for (int64_t sp = 1; sp <= smax; ++sp) {
+            cost.clear();
+            for (auto& H : hd) {
+                const int64_t tiles = (H.n + kGravTileJ - 1) / kGravTileJ;
+                const int64_t s_h = std::max<int64_t>(1, std::min<int64_t>(sp, tiles));
+                const int64_t ib = (H.n + kIBlock - 1) / kIBlock;
+                for (int64_t q = 0; q < s_h; ++q) {
+                    const int64_t t0 = tiles * q / s_h, t1 = tiles * (q + 1) / s_h;
+                    const int64_t c = (t1 - t0) * kGravTileJ + kGravTileJ / 4;   // + epilogue
+                    for (int64_t i = 0; i < ib; ++i) cost.push_back(c);
+                }
+            }
+            std::sort(cost.begin(), cost.end(), std::greater<int64_t>());
+            // list scheduling: each item goes to the slot that frees first
+            load.assign((size_t)std::min<int64_t>(slots, (int64_t)cost.size()), 0.0);
+            std::make_heap(load.begin(), load.end(), std::greater<double>());
+            double t_end = 0.0;
+            for (int64_t c : cost) {
+                std::pop_heap(load.begin(), load.end(), std::greater<double>());
+                load.back() += (double)c;
+                t_end = std::max(t_end, load.back());
+                std::push_heap(load.begin(), load.end(), std::greater<double>());
+            }
+            if (sp == 1 || t_end < best_t * (1.0 - 5e-3)) {
+                best_t = t_end;
+                best = sp;
+            }
+        }
+    }
     for (auto& H : hd) {
         const int64_t tiles = (H.n + kGravTileJ - 1) / kGravTileJ;
-        H.grav_split = (int32_t)std::max<int64_t>(1, std::min<int64_t>(split, tiles));
+        H.grav_split = (int32_t)std::max<int64_t>(1, std::min<int64_t>(best, tiles));
     }
 }
 
@@ -306,7 +345,7 @@ inline bool build_plan(Plan& P, const Scratch& w, const sidm_halo* halos, int32_
         P.level_task_off.push_back((int64_t)P.node_tasks.size());
     }
     // gravity work items
-    choose_splits(P.halos, w.partial_rows);
+    choose_splits(P.halos, w.partial_rows, w.grav_slots);
     int64_t prow = 0;
     const int64_t kIBlock = kGravThreads * 4;
     for (int h = 0; h < n_halos; ++h) {
