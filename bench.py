@@ -37,9 +37,12 @@ def _args():
     ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--workload", default="C2", choices=("C2", "C4", "C5"),
-                    help="C2 (default, the benchmark line): N=2^20 satellite; C4: 64-halo batch; "
-                         "C5: N=2^24 satellite, one step, per-pass rooflines")
+    ap.add_argument("--workload", default="C2", choices=("C2", "C3", "C4", "C5"),
+                    help="C2 (default, the benchmark line): N=2^20 satellite; C3: the same halo "
+                         "for --steps steps in one --precision with |dE/E| and central density; "
+                         "C4: 64-halo batch; C5: N=2^24 satellite, one step, per-pass rooflines")
+    ap.add_argument("--precision", default="mixed", choices=("mixed", "fp64"),
+                    help="precision of the C3 run")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="also run one plain device-to-device copy of BYTES bytes (a reference "
                          "dispatch for scaling HBM byte counters)")
@@ -170,6 +173,59 @@ def _pass_rooflines(passes, n, inter, k):
     }
 
 
+def _bench_c3(a, S, torch, W):
+    """The N = 2^20 satellite for --steps steps in one precision: throughput,
+    |dE/E| every 100 steps and the central density within 0.1 r_s of the
+    potential minimum (Sec. 3) at the start and every 100 steps."""
+    cfg = W.config("C3")
+    n, radius = cfg["n"], 0.1
+    s = W.make_state(cfg)
+    halo = _halo_of(cfg)
+    prec = S.SIDM_PREC_FP64 if a.precision == "fp64" else S.SIDM_PREC_MIXED
+    dev = S.state_to_device(s)
+    ctx = S.sidm_create(0, n, 1)
+    diag = S.diag_buffer(1)
+    S.sidm_gravity(ctx, [halo], dev, prec)
+    S.sidm_diagnostics(ctx, [halo], dev, diag)
+    e0 = _energy(S.read_diag(diag)[0])
+    vol = 4.0 / 3.0 * math.pi * radius ** 3
+
+    def center(step):
+        c = S.sidm_central_density(ctx, [halo], dev, radius)[0]
+        return dict(step=step, count=c["count"], rho=c["mass"] / vol, index=c["index"])
+
+    centers, energy = [center(0)], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for step in range(a.steps):
+        S.sidm_kdk_step(ctx, [halo], dev, step, prec, diag=diag)
+        if (step + 1) % 100 == 0 or step + 1 == a.steps:
+            d = S.read_diag(diag)[0]
+            energy.append(dict(step=step + 1, dE_over_E=abs(_energy(d) - e0) / abs(e0),
+                               events=d["n_events"], status=d["status"]))
+            centers.append(center(step + 1))
+            print(f"C3 {a.precision} step {step + 1}: |dE/E| {energy[-1]['dE_over_E']:.3e} "
+                  f"rho(<{radius}) {centers[-1]['rho']:.4g} ({centers[-1]['count']}) "
+                  f"{time.perf_counter() - t0:.0f} s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / a.steps
+    S.sidm_destroy(ctx)
+    inter = n * (n - 1)
+    out = {"metric": f"C3 {a.precision}: gravity interactions/s over {a.steps} steps, |dE/E|, "
+                     f"central density", "value": inter / ms, "unit": "gravity interactions/s",
+           "n_gpus": 1, "steps": a.steps, "warmup": 0, "ms_per_step": ms * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64" if a.precision == "fp64" else "f32 gravity tiles (compensated), "
+                                                         "f64 elsewhere",
+           "data": "synthetic NFW halo",
+           "config": {"workload": "C3: NFW N=2^20 satellite in the host, eps=0.01, k=64, "
+                                  "sigma/m=10, dt=1e-3", "precision": a.precision},
+           "dE_over_E": energy[-1]["dE_over_E"] if energy else None,
+           "max_dE_over_E": max((e["dE_over_E"] for e in energy), default=None),
+           "energy": energy, "central_density": centers, "radius": radius}
+    print(json.dumps(out), flush=True)
+
+
 def _bench_c4(a, S, torch, W):
     """64 independent halos in one call per pass (uneven N, sigma/m, k)."""
     import numpy as np
@@ -232,6 +288,8 @@ def main():
     import workloads as W
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
+    if a.workload == "C3":
+        return _bench_c3(a, S, torch, W)
     if a.workload == "C4":
         return _bench_c4(a, S, torch, W)
     if a.workload == "C5":

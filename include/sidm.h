@@ -146,8 +146,10 @@ const char *sidm_last_error(const sidm_ctx *ctx);
  * over the particles of the same halo (Sec. 2: softened gravity, here in the
  * Plummer form; Sec. 4.1 Eq. nfw_potential for the host, a = -grad Phi).
  * Writes state->ax/ay/az/pot; reads x, y, z, m.  SIDM_PREC_MIXED evaluates the
- * pair terms in FP32 on positions re-centred in FP64 on the halo's mean
- * position, accumulated with compensation, and returns FP64. */
+ * pair terms in FP32 on positions taken, in FP64, relative to the centre of
+ * each compact group of at most 64 spatially sorted particles (the i-particle
+ * is moved into the frame of each j group once), sums each tile of 256 terms
+ * plainly and the tile sums with compensation, and returns FP64. */
 sidm_status sidm_gravity(sidm_ctx *ctx, const sidm_halo *halos, int32_t n_halos,
                          const sidm_state *state, sidm_precision prec, void *stream);
 
@@ -203,6 +205,26 @@ sidm_status sidm_kdk_step(sidm_ctx *ctx, const sidm_halo *halos, int32_t n_halos
  * same halos. */
 sidm_status sidm_diagnostics(sidm_ctx *ctx, const sidm_halo *halos, int32_t n_halos,
                              const sidm_state *state, sidm_diag *diag, void *stream);
+
+/* ---- central density -------------------------------------------------------
+ * Sec. 3 takes the minimum of the gravitational potential as the halo centre.
+ * For each halo: the centre is the particle with the lowest self-potential
+ * pot - Phi_host(x) (first array index on ties; NaN values never), and the
+ * central density is counted around it: the particles of the halo with
+ * d2 <= radius^2 from the centre (d2 as in sidm_knn_h; the centre included),
+ * their number and total mass.  pot must hold the total potential at x (after
+ * sidm_gravity or a step).  radius: HOST array, one radius > 0 per halo.
+ * out: DEVICE, n_halos entries; index = -1 if no potential is finite.  Copies
+ * the radii to the device (not for use inside graph capture). */
+typedef struct {
+    double x, y, z;             /* position of the centre particle                  */
+    double mass;                /* mass within the radius                           */
+    int64_t index;              /* array index of the centre particle               */
+    int64_t count;              /* particles within the radius                      */
+} sidm_center;
+sidm_status sidm_central_density(sidm_ctx *ctx, const sidm_halo *halos, int32_t n_halos,
+                                 const sidm_state *state, const double *radius,
+                                 sidm_center *out, void *stream);
 
 /* ---- pass timing ---------------------------------------------------------
  * When enabled, sidm_kdk_step records HIP events on its stream around each

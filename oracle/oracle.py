@@ -63,6 +63,13 @@ def _declare(L):
                                   _dp, C.c_double, C.c_double, C.c_uint64, C.c_uint32,
                                   _u8p, C.c_void_p, C.c_int64, _i64p, _i64p]
     L.orc_find_events.restype = C.c_int64
+    L.orc_knn_grid.argtypes = [C.c_int64, _dp, _dp, _dp, _u32p, C.c_int32, _dp]
+    L.orc_find_events_sweep.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _u32p,
+                                        _dp, C.c_double, C.c_double, C.c_uint64, C.c_uint32,
+                                        C.c_void_p, C.c_int64, _i64p, _i64p]
+    L.orc_find_events_sweep.restype = C.c_int64
+    L.orc_central_density.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp, C.c_double, _i64p,
+                                      _i64p, _dp]
     L.orc_kick_pair.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
                                 C.c_double, C.c_double, _dp, _dp]
     L.orc_apply_events.argtypes = [C.c_int64, C.c_void_p, _dp, _dp, _dp, _dp,
@@ -160,6 +167,15 @@ def knn(x, y, z, ids, k, query=None, want_list=False):
     return (h, nbr) if want_list else h
 
 
+def knn_grid(x, y, z, ids, k):
+    """h of every particle from the grid search (equal to knn's)."""
+    x, y, z = _f64(x), _f64(y), _f64(z)
+    ids = np.ascontiguousarray(ids, dtype=np.uint32)
+    h = np.zeros(x.size)
+    lib().orc_knn_grid(x.size, _d(x), _d(y), _d(z), ids.ctypes.data_as(_u32p), int(k), _d(h))
+    return h
+
+
 # ---------------------------------------------------------------- scatter
 def find_events(x, y, z, vx, vy, vz, m, ids, h, sigma_m, dt, seed, step, qmask=None):
     """Events (structured array in (a, b) order), pair count, count of P > 1."""
@@ -179,6 +195,31 @@ def find_events(x, y, z, vx, vy, vz, m, ids, h, sigma_m, dt, seed, step, qmask=N
     found2 = lib().orc_find_events(*args, ev.ctypes.data, found, None, None)
     assert found2 == found
     return ev[:found], int(npairs.value), int(npgt1.value)
+
+
+def find_events_sweep(x, y, z, vx, vy, vz, m, ids, h, sigma_m, dt, seed, step):
+    """find_events over all pairs, from the x-sorted sweep (equal results)."""
+    arrs = [_f64(a) for a in (x, y, z, vx, vy, vz, m)]
+    ids = np.ascontiguousarray(ids, dtype=np.uint32)
+    h = _f64(h)
+    n = arrs[0].size
+    npairs, npgt1 = C.c_int64(0), C.c_int64(0)
+    args = [n] + [_d(a) for a in arrs] + [ids.ctypes.data_as(_u32p), _d(h), float(sigma_m),
+                                          float(dt), int(seed), int(step)]
+    found = lib().orc_find_events_sweep(*args, None, 0, C.byref(npairs), C.byref(npgt1))
+    ev = np.zeros(max(found, 1), dtype=EVENT_DTYPE)
+    found2 = lib().orc_find_events_sweep(*args, ev.ctypes.data, found, None, None)
+    assert found2 == found
+    return ev[:found], int(npairs.value), int(npgt1.value)
+
+
+def central_density(x, y, z, m, phi_self, radius):
+    """(centre index, count, mass) within `radius` of the lowest-phi particle."""
+    x, y, z, m, phi_self = (_f64(a) for a in (x, y, z, m, phi_self))
+    c, cnt, mass = C.c_int64(0), C.c_int64(0), C.c_double(0.0)
+    lib().orc_central_density(x.size, _d(x), _d(y), _d(z), _d(m), _d(phi_self), float(radius),
+                              C.byref(c), C.byref(cnt), C.byref(mass))
+    return int(c.value), int(cnt.value), float(mass.value)
 
 
 def kick_pair(seed, step, a, b, ma, mb, va, vb):

@@ -485,6 +485,277 @@ void orc_diag(int64_t n, const double *vx, const double *vy, const double *vz,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Exact searches for long runs.  They return exactly what the brute-force
+ * definitions above return (the tests require equality): only the order in
+ * which candidates are examined changes, never the expression of a distance,
+ * the (d2, id) order or the pair test. */
+
+typedef struct {
+    double lo[3], c;        /* origin and cell size                               */
+    int64_t nc[3];          /* cells per axis                                      */
+    int64_t *start;         /* particles of cell q: item[start[q] .. start[q + 1]) */
+    int64_t *item;
+} orc_grid;
+
+static int64_t grid_axis(const orc_grid *g, double v, int a)
+{
+    double t = floor((v - g->lo[a]) / g->c);
+    if (!(t >= 0.0)) return 0;
+    if (t > (double)(g->nc[a] - 1)) return g->nc[a] - 1;
+    return (int64_t)t;
+}
+
+static int64_t grid_cell(const orc_grid *g, int64_t cx, int64_t cy, int64_t cz)
+{
+    return (cz * g->nc[1] + cy) * g->nc[0] + cx;
+}
+
+/* Uniform grid over the bounding box with about `per_cell` particles per cell
+ * on average (at most about 8 cells per particle). */
+static void grid_build(orc_grid *g, int64_t n, const double *x, const double *y,
+                       const double *z, double per_cell)
+{
+    const double *p[3] = {x, y, z};
+    double hi[3], ext = 0.0, vol = 1.0;
+    for (int a = 0; a < 3; ++a) {
+        g->lo[a] = INFINITY;
+        hi[a] = -INFINITY;
+        for (int64_t i = 0; i < n; ++i) {
+            if (p[a][i] < g->lo[a]) g->lo[a] = p[a][i];
+            if (p[a][i] > hi[a]) hi[a] = p[a][i];
+        }
+        if (hi[a] - g->lo[a] > ext) ext = hi[a] - g->lo[a];
+    }
+    if (!(ext > 0.0)) ext = 1.0;
+    for (int a = 0; a < 3; ++a) {
+        double e = hi[a] - g->lo[a];
+        vol *= e > 1e-6 * ext ? e : 1e-6 * ext;
+    }
+    g->c = cbrt(vol * per_cell / (double)n);
+    for (;;) {
+        double cells = 1.0;
+        for (int a = 0; a < 3; ++a) {
+            g->nc[a] = (int64_t)floor((hi[a] - g->lo[a]) / g->c) + 1;
+            cells *= (double)g->nc[a];
+        }
+        if (cells <= 8.0 * (double)n + 64.0) break;
+        g->c *= 1.25;
+    }
+    int64_t ncell = g->nc[0] * g->nc[1] * g->nc[2];
+    int64_t *cell = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    g->start = (int64_t *)calloc((size_t)ncell + 1, sizeof(int64_t));
+    g->item = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) {
+        cell[i] = grid_cell(g, grid_axis(g, x[i], 0), grid_axis(g, y[i], 1), grid_axis(g, z[i], 2));
+        ++g->start[cell[i] + 1];
+    }
+    for (int64_t q = 0; q < ncell; ++q) g->start[q + 1] += g->start[q];
+    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)ncell);
+    memcpy(fill, g->start, sizeof(int64_t) * (size_t)ncell);
+    for (int64_t i = 0; i < n; ++i) g->item[fill[cell[i]]++] = i;
+    free(fill);
+    free(cell);
+}
+
+static void grid_free(orc_grid *g)
+{
+    free(g->start);
+    free(g->item);
+}
+
+/* The k nearest neighbours by (d2, id) as orc_knn, searching cubic shells of
+ * cells around the particle's cell: after shell s every unvisited particle is
+ * at least s cell sizes away, so the search stops once the k-th distance is
+ * below that. */
+void orc_knn_grid(int64_t n, const double *x, const double *y, const double *z,
+                  const uint32_t *id, int32_t k, double *h)
+{
+    orc_grid g;
+    grid_build(&g, n, x, y, z, k > 8 ? (double)k / 8.0 : 1.0);
+#pragma omp parallel
+    {
+        double *bd = (double *)malloc(sizeof(double) * (size_t)k);
+        uint32_t *bi = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)k);
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t i = 0; i < n; ++i) {
+            const int64_t hx = grid_axis(&g, x[i], 0), hy = grid_axis(&g, y[i], 1),
+                          hz = grid_axis(&g, z[i], 2);
+            int32_t cnt = 0;
+            for (int64_t s = 0;; ++s) {
+                for (int64_t cx = hx - s; cx <= hx + s; ++cx) {
+                    if (cx < 0 || cx >= g.nc[0]) continue;
+                    for (int64_t cy = hy - s; cy <= hy + s; ++cy) {
+                        if (cy < 0 || cy >= g.nc[1]) continue;
+                        const int face = (cx == hx - s || cx == hx + s || cy == hy - s || cy == hy + s);
+                        for (int64_t cz = hz - s; cz <= hz + s; cz += face ? 1 : 2 * s) {
+                            if (cz >= 0 && cz < g.nc[2]) {
+                                const int64_t q = grid_cell(&g, cx, cy, cz);
+                                for (int64_t t = g.start[q]; t < g.start[q + 1]; ++t) {
+                                    const int64_t j = g.item[t];
+                                    if (j == i) continue;
+                                    double dx = x[j] - x[i], dy = y[j] - y[i], dz = z[j] - z[i];
+                                    double d2 = (dx * dx + dy * dy) + dz * dz;
+                                    if (cnt == k && !key_less(d2, id[j], bd[k - 1], bi[k - 1])) continue;
+                                    int32_t pos = cnt < k ? cnt : k - 1;
+                                    while (pos > 0 && key_less(d2, id[j], bd[pos - 1], bi[pos - 1])) {
+                                        bd[pos] = bd[pos - 1];
+                                        bi[pos] = bi[pos - 1];
+                                        --pos;
+                                    }
+                                    bd[pos] = d2;
+                                    bi[pos] = id[j];
+                                    if (cnt < k) ++cnt;
+                                }
+                            }
+                            if (s == 0) break;
+                        }
+                    }
+                }
+                const double reach = (double)s * g.c;
+                if (cnt == k && bd[k - 1] < reach * reach * (1.0 - 1e-9)) break;
+                if (hx - s <= 0 && hx + s >= g.nc[0] - 1 && hy - s <= 0 && hy + s >= g.nc[1] - 1 &&
+                    hz - s <= 0 && hz + s >= g.nc[2] - 1)
+                    break;
+            }
+            h[i] = sqrt(bd[k - 1]);
+        }
+        free(bd);
+        free(bi);
+    }
+    grid_free(&g);
+}
+
+typedef struct {
+    double v;
+    int64_t i;
+} orc_key;
+
+static int cmp_key(const void *pa, const void *pb)
+{
+    const orc_key *a = (const orc_key *)pa, *b = (const orc_key *)pb;
+    if (a->v != b->v) return a->v < b->v ? -1 : 1;
+    return a->i < b->i ? -1 : (a->i > b->i);
+}
+
+/* The events of orc_find_events (all pairs, no query set) with the same pair
+ * test and arithmetic.  A pair with d < h_i + h_j has d < 2 max(h_i, h_j), so
+ * it is found from its member with the larger h (the larger index on ties)
+ * among the particles whose x lies within twice that h: a sweep over the
+ * particles sorted by x. */
+int64_t orc_find_events_sweep(int64_t n, const double *x, const double *y, const double *z,
+                              const double *vx, const double *vy, const double *vz,
+                              const double *m, const uint32_t *id, const double *h,
+                              double sigma_m, double dt, uint64_t seed, uint32_t step,
+                              orc_event *ev, int64_t cap, int64_t *n_pairs, int64_t *n_p_gt1)
+{
+    orc_key *ord = (orc_key *)malloc(sizeof(orc_key) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) {
+        ord[i].v = x[i];
+        ord[i].i = i;
+    }
+    qsort(ord, (size_t)n, sizeof(orc_key), cmp_key);
+    int64_t found = 0, pairs = 0, pgt1 = 0;
+    orc_event *all = NULL;
+    int64_t all_cap = 0;
+#pragma omp parallel
+    {
+        int64_t my_pairs = 0, my_pgt1 = 0, my_n = 0, my_cap = 64;
+        orc_event *mine = (orc_event *)malloc(sizeof(orc_event) * (size_t)my_cap);
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t i = 0; i < n; ++i) {
+            const double R = 2.0 * h[i] * (1.0 + 1e-9);
+            /* first position with x >= x_i - R */
+            int64_t lo = 0, hi = n;
+            while (lo < hi) {
+                int64_t mid = lo + (hi - lo) / 2;
+                if (ord[mid].v < x[i] - R) lo = mid + 1;
+                else hi = mid;
+            }
+            for (int64_t t = lo; t < n && ord[t].v <= x[i] + R; ++t) {
+                const int64_t j = ord[t].i;
+                if (j == i) continue;
+                if (!(h[j] < h[i] || (h[j] == h[i] && j < i))) continue;
+                const int64_t lo_i = i < j ? i : j, hi_i = i < j ? j : i;
+                double dx = x[hi_i] - x[lo_i], dy = y[hi_i] - y[lo_i], dz = z[hi_i] - z[lo_i];
+                double d2 = (dx * dx + dy * dy) + dz * dz;
+                double hs = h[lo_i] + h[hi_i];
+                if (!(d2 < hs * hs)) continue;
+                ++my_pairs;
+                int64_t ia = id[lo_i] < id[hi_i] ? lo_i : hi_i;
+                int64_t ib = id[lo_i] < id[hi_i] ? hi_i : lo_i;
+                uint32_t a = id[ia], b = id[ib];
+                double u = orc_accept_u(seed, step, a, b);
+                double gx = vx[ia] - vx[ib], gy = vy[ia] - vy[ib], gz = vz[ia] - vz[ib];
+                double gg = sqrt((gx * gx + gy * gy) + gz * gz);
+                double lam = orc_lambda(sqrt(d2), h[ia], h[ib]);
+                double P = sigma_m * m[ib] * gg * lam * dt;
+                if (P > 1.0) ++my_pgt1;
+                if (u < P) {
+                    if (my_n == my_cap) {
+                        my_cap *= 2;
+                        mine = (orc_event *)realloc(mine, sizeof(orc_event) * (size_t)my_cap);
+                    }
+                    orc_event e = {a, b, ia, ib, u, P};
+                    mine[my_n++] = e;
+                }
+            }
+        }
+#pragma omp critical
+        {
+            if (found + my_n > all_cap) {
+                all_cap = 2 * (found + my_n) + 64;
+                all = (orc_event *)realloc(all, sizeof(orc_event) * (size_t)all_cap);
+            }
+            memcpy(all + found, mine, sizeof(orc_event) * (size_t)my_n);
+            found += my_n;
+            pairs += my_pairs;
+            pgt1 += my_pgt1;
+        }
+        free(mine);
+    }
+    free(ord);
+    if (found > 0) qsort(all, (size_t)found, sizeof(orc_event), cmp_event);
+    int64_t stored = found < cap ? found : cap;
+    if (stored > 0 && ev) memcpy(ev, all, sizeof(orc_event) * (size_t)stored);
+    free(all);
+    if (n_pairs) *n_pairs = pairs;
+    if (n_p_gt1) *n_p_gt1 = pgt1;
+    return found;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Central density (Sec. 3: the halo centre is the minimum of the
+ * gravitational potential).  Reading: the centre is the particle with the
+ * lowest self-potential phi (first index on ties); the density is the mass
+ * within `radius` of it (that particle included, d2 as in the kNN) over the
+ * sphere's volume. */
+void orc_central_density(int64_t n, const double *x, const double *y, const double *z,
+                         const double *m, const double *phi, double radius,
+                         int64_t *center, int64_t *count, double *mass)
+{
+    int64_t c = -1;
+    for (int64_t i = 0; i < n; ++i)
+        if (phi[i] == phi[i] && (c < 0 || phi[i] < phi[c])) c = i;
+    *center = c;
+    *count = 0;
+    *mass = 0.0;
+    if (c < 0) return;
+    const double r2 = radius * radius;
+    neum acc = {0.0, 0.0};
+    int64_t cnt = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        double dx = x[j] - x[c], dy = y[j] - y[c], dz = z[j] - z[c];
+        double d2 = (dx * dx + dy * dy) + dz * dz;
+        if (d2 <= r2) {
+            ++cnt;
+            neum_add(&acc, m[j]);
+        }
+    }
+    *count = cnt;
+    *mass = neum_get(&acc);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Total acceleration and potential at the current positions: self-gravity plus
  * the static host. */
 static void accel_total(int64_t n, const double *x, const double *y, const double *z,
@@ -533,17 +804,17 @@ int64_t orc_kdk_step(int64_t n, double *x, double *y, double *z,
         vy[i] += ay[i] * hdt;
         vz[i] += az[i] * hdt;
     }
-    orc_knn(n, x, y, z, id, p->k, n, NULL, h, NULL);
+    orc_knn_grid(n, x, y, z, id, p->k, h);
     if (p->sigma_m == 0.0) return 0;
     int64_t cap = ev_cap > 0 ? ev_cap : 0;
     orc_event *buf = ev;
-    int64_t found = orc_find_events(n, x, y, z, vx, vy, vz, m, id, h, p->sigma_m, p->dt,
-                                    p->seed, step, NULL, buf, cap, NULL, NULL);
+    int64_t found = orc_find_events_sweep(n, x, y, z, vx, vy, vz, m, id, h, p->sigma_m, p->dt,
+                                          p->seed, step, buf, cap, NULL, NULL);
     if (found > cap) {
         /* not enough room to hold the ordered list: collect it privately */
         buf = (orc_event *)malloc(sizeof(orc_event) * (size_t)found);
-        orc_find_events(n, x, y, z, vx, vy, vz, m, id, h, p->sigma_m, p->dt,
-                        p->seed, step, NULL, buf, found, NULL, NULL);
+        orc_find_events_sweep(n, x, y, z, vx, vy, vz, m, id, h, p->sigma_m, p->dt,
+                              p->seed, step, buf, found, NULL, NULL);
     }
     orc_apply_events(found, buf, m, vx, vy, vz, p->seed, step);
     if (buf != ev) {

@@ -76,6 +76,11 @@ void orc_knn(int64_t n, const double *x, const double *y, const double *z,
              const uint32_t *id, int32_t k, int64_t nq, const int64_t *q,
              double *h, uint32_t *nbr);
 
+/* The same h as orc_knn for every particle (all queried), bit for bit, from a
+ * search over cubic shells of a uniform grid. */
+void orc_knn_grid(int64_t n, const double *x, const double *y, const double *z,
+                  const uint32_t *id, int32_t k, double *h);
+
 /* ---- pairwise scattering (paper Sec. 2 and Sec. 3.5) ---- */
 
 typedef struct {
@@ -98,6 +103,14 @@ int64_t orc_find_events(int64_t n, const double *x, const double *y, const doubl
                         const uint8_t *qmask, orc_event *ev, int64_t cap,
                         int64_t *n_pairs, int64_t *n_p_gt1);
 
+/* The same events, pair count and P > 1 count as orc_find_events without a
+ * query set, from a sweep over the particles sorted by x. */
+int64_t orc_find_events_sweep(int64_t n, const double *x, const double *y, const double *z,
+                              const double *vx, const double *vy, const double *vz,
+                              const double *m, const uint32_t *id, const double *h,
+                              double sigma_m, double dt, uint64_t seed, uint32_t step,
+                              orc_event *ev, int64_t cap, int64_t *n_pairs, int64_t *n_p_gt1);
+
 /* Elastic isotropic scattering of one pair in its centre-of-mass frame, using
  * the direction draw at counter (a, b, step, 1).  Updates the two velocities. */
 void orc_kick_pair(uint64_t seed, uint32_t step, uint32_t a, uint32_t b,
@@ -114,6 +127,13 @@ void orc_apply_events(int64_t n_ev, const orc_event *ev, const double *m,
 void orc_diag(int64_t n, const double *vx, const double *vy, const double *vz,
               const double *m, const double *pot, const double *pext, double out[6]);
 
+/* Central density (Sec. 3: the centre is the potential minimum): the
+ * particle c with the lowest phi (self-potential; first index on ties), and
+ * the number and total mass of the particles with d2 <= radius^2 from it. */
+void orc_central_density(int64_t n, const double *x, const double *y, const double *z,
+                         const double *m, const double *phi, double radius,
+                         int64_t *center, int64_t *count, double *mass);
+
 /* ---- one kick-drift-kick step with SIDM at the synchronised point ---- */
 
 typedef struct {
@@ -124,7 +144,7 @@ typedef struct {
     double host_rho_s, host_r_s, host_c[3];
 } orc_params;
 
-/* Full-N brute-force step for one halo.  On entry a/pot hold the acceleration
+/* Full-N step for one halo (exact searches: orc_knn_grid, orc_find_events_sweep).  On entry a/pot hold the acceleration
  * and potential at x (self + host).  Performs K(dt/2), D(dt), gravity + host,
  * K(dt/2), h from kNN, events, ordered kicks.  Writes h; returns the number of
  * events (or -1 if more than `ev_cap` events were found; ev may be NULL when

@@ -37,7 +37,7 @@ SIDM_DEV_NONFINITE = 4
 
 EXPORTED = ("sidm_create", "sidm_destroy", "sidm_set_event_capacity", "sidm_status_string",
             "sidm_last_error", "sidm_gravity", "sidm_knn_h", "sidm_scatter", "sidm_kdk_step",
-            "sidm_diagnostics", "sidm_enable_timing", "sidm_pass_times")
+            "sidm_diagnostics", "sidm_central_density", "sidm_enable_timing", "sidm_pass_times")
 PASS_NAMES = ("kick_drift", "gravity", "gravity_tiles", "cell_list", "knn", "pairs", "kicks",
               "diag")
 
@@ -62,7 +62,13 @@ class SidmDiag(C.Structure):
                 ("n_p_gt1", C.c_int64), ("status", C.c_int32), ("reserved", C.c_int32)]
 
 
+class SidmCenter(C.Structure):
+    _fields_ = [("x", C.c_double), ("y", C.c_double), ("z", C.c_double), ("mass", C.c_double),
+                ("index", C.c_int64), ("count", C.c_int64)]
+
+
 DIAG_BYTES = C.sizeof(SidmDiag)
+CENTER_BYTES = C.sizeof(SidmCenter)
 EVENT_BYTES = 16
 DIAG_FIELDS = [f for f, _ in SidmDiag._fields_]
 
@@ -99,6 +105,7 @@ def lib():
         L.sidm_scatter.argtypes = [vp, hp, i32, sp, u32, vp, i64, C.POINTER(i64), vp]
         L.sidm_kdk_step.argtypes = [vp, hp, i32, sp, u32, C.c_int, vp, vp]
         L.sidm_diagnostics.argtypes = [vp, hp, i32, sp, vp, vp]
+        L.sidm_central_density.argtypes = [vp, hp, i32, sp, C.POINTER(C.c_double), vp, vp]
         L.sidm_enable_timing.argtypes = [vp, C.c_int]
         L.sidm_pass_times.argtypes = [vp, C.POINTER(C.c_double)]
         for name in EXPORTED:
@@ -235,6 +242,32 @@ def sidm_diagnostics(ctx, halos, state, diag, stream=None):
     S = make_state(state)
     _check(ctx, lib().sidm_diagnostics(ctx.handle, H, len(halos), C.byref(S),
                                        C.c_void_p(diag.data_ptr()), _stream(stream)))
+
+
+def sidm_central_density(ctx, halos, state, radius, out=None, stream=None):
+    """Centre (lowest self-potential) and the number and mass within `radius`
+    (one value or one per halo) of it, per halo.  Returns a list of dicts
+    (synchronises) unless a device buffer `out` is given."""
+    H = make_halos(halos)
+    S = make_state(state)
+    r = list(radius) if hasattr(radius, "__len__") else [float(radius)] * len(halos)
+    rad = (C.c_double * len(halos))(*[float(v) for v in r])
+    buf = out if out is not None else center_buffer(len(halos))
+    _check(ctx, lib().sidm_central_density(ctx.handle, H, len(halos), C.byref(S), rad,
+                                           C.c_void_p(buf.data_ptr()), _stream(stream)))
+    if out is not None:
+        return None
+    raw = bytes(buf.cpu().numpy().tobytes())
+    res = []
+    for i in range(len(halos)):
+        c = SidmCenter.from_buffer_copy(raw[i * CENTER_BYTES:(i + 1) * CENTER_BYTES])
+        res.append({f: getattr(c, f) for f, _ in SidmCenter._fields_})
+    return res
+
+
+def center_buffer(n_halos, device="cuda"):
+    import torch
+    return torch.zeros(n_halos * CENTER_BYTES, dtype=torch.uint8, device=device)
 
 
 def sidm_enable_timing(ctx, on=True):

@@ -131,4 +131,168 @@ hipError_t launch_diag(const StreamBlock* d_blocks, int64_t n_blocks, const Halo
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- central density
+// Sec. 3 takes the minimum of the gravitational potential as the halo centre:
+// the centre is the particle with the lowest self-potential pot - Phi_host
+// (first index on ties, NaN never), and the central density counts the
+// particles of the halo within a radius of it.
+
+// Per streaming block: lowest self-potential and its index (as a double).
+__global__ __launch_bounds__(kStreamBlock) void k_center_block(
+    const StreamBlock* __restrict__ blocks, const HaloDev* __restrict__ halos,
+    const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
+    const double* __restrict__ pot, double* __restrict__ bsum)
+{
+    __shared__ double val[kStreamBlock];
+    __shared__ int64_t idx[kStreamBlock];
+    const StreamBlock B = blocks[blockIdx.x];
+    const HaloDev& H = halos[B.halo];
+    const int t = threadIdx.x;
+    double v = INFINITY;
+    int64_t i = -1;
+    if (t < B.count) {
+        const int64_t p = B.start + t;
+        double pe = 0.0;
+        if (H.host_kind == 1) host_pot_only(H, x[p], y[p], z[p], pe);
+        const double ps = pot[p] - pe;
+        if (ps == ps) { v = ps; i = p; }
+    }
+    val[t] = v;
+    idx[t] = i;
+    __syncthreads();
+    for (int s = kStreamBlock / 2; s > 0; s >>= 1) {
+        if (t < s) {
+            const double vo = val[t + s];
+            const int64_t io = idx[t + s];
+            if (io >= 0 && (idx[t] < 0 || vo < val[t] || (vo == val[t] && io < idx[t]))) {
+                val[t] = vo;
+                idx[t] = io;
+            }
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        bsum[7 * blockIdx.x + 0] = val[0];
+        bsum[7 * blockIdx.x + 1] = (double)idx[0];
+    }
+}
+
+// Per halo: the centre over its blocks; writes index and position.
+__global__ __launch_bounds__(kStreamBlock) void k_center_halo(
+    const HaloDev* __restrict__ halos, const double* __restrict__ bsum,
+    const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
+    sidm_center* __restrict__ out)
+{
+    __shared__ double val[kStreamBlock];
+    __shared__ int64_t idx[kStreamBlock];
+    const HaloDev& H = halos[blockIdx.x];
+    const int t = threadIdx.x;
+    const int64_t nb = (H.n + kStreamBlock - 1) / kStreamBlock;
+    double v = INFINITY;
+    int64_t i = -1;
+    for (int64_t b = t; b < nb; b += kStreamBlock) {
+        const double vo = bsum[7 * (H.stream_block0 + b) + 0];
+        const int64_t io = (int64_t)bsum[7 * (H.stream_block0 + b) + 1];
+        if (io >= 0 && (i < 0 || vo < v || (vo == v && io < i))) { v = vo; i = io; }
+    }
+    val[t] = v;
+    idx[t] = i;
+    __syncthreads();
+    for (int s = kStreamBlock / 2; s > 0; s >>= 1) {
+        if (t < s) {
+            const double vo = val[t + s];
+            const int64_t io = idx[t + s];
+            if (io >= 0 && (idx[t] < 0 || vo < val[t] || (vo == val[t] && io < idx[t]))) {
+                val[t] = vo;
+                idx[t] = io;
+            }
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        sidm_center c;
+        c.index = idx[0];
+        c.x = c.index >= 0 ? x[c.index] : NAN;
+        c.y = c.index >= 0 ? y[c.index] : NAN;
+        c.z = c.index >= 0 ? z[c.index] : NAN;
+        c.mass = 0.0;
+        c.count = 0;
+        out[blockIdx.x] = c;
+    }
+}
+
+// Per streaming block: number and mass of the particles within the radius.
+__global__ __launch_bounds__(kStreamBlock) void k_center_count_block(
+    const StreamBlock* __restrict__ blocks, const double* __restrict__ radius,
+    const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
+    const double* __restrict__ m, const sidm_center* __restrict__ out, double* __restrict__ bsum)
+{
+    __shared__ double cnt[kStreamBlock], mass[kStreamBlock];
+    const StreamBlock B = blocks[blockIdx.x];
+    const sidm_center C = out[B.halo];
+    const int t = threadIdx.x;
+    double c = 0.0, w = 0.0;
+    if (t < B.count && C.index >= 0) {
+#pragma clang fp contract(off)
+        const int64_t p = B.start + t;
+        const double r = radius[B.halo];
+        const double dx = x[p] - C.x, dy = y[p] - C.y, dz = z[p] - C.z;
+        const double d2 = (dx * dx + dy * dy) + dz * dz;
+        if (d2 <= r * r) { c = 1.0; w = m[p]; }
+    }
+    cnt[t] = c;
+    mass[t] = w;
+    __syncthreads();
+    for (int s = kStreamBlock / 2; s > 0; s >>= 1) {
+        if (t < s) { cnt[t] += cnt[t + s]; mass[t] += mass[t + s]; }
+        __syncthreads();
+    }
+    if (t == 0) {
+        bsum[7 * blockIdx.x + 2] = cnt[0];
+        bsum[7 * blockIdx.x + 3] = mass[0];
+    }
+}
+
+__global__ __launch_bounds__(kStreamBlock) void k_center_count_halo(
+    const HaloDev* __restrict__ halos, const double* __restrict__ bsum,
+    sidm_center* __restrict__ out)
+{
+    __shared__ double cnt[kStreamBlock], mass[kStreamBlock];
+    const HaloDev& H = halos[blockIdx.x];
+    const int t = threadIdx.x;
+    const int64_t nb = (H.n + kStreamBlock - 1) / kStreamBlock;
+    double c = 0.0, w = 0.0;
+    for (int64_t b = t; b < nb; b += kStreamBlock) {
+        c += bsum[7 * (H.stream_block0 + b) + 2];
+        w += bsum[7 * (H.stream_block0 + b) + 3];
+    }
+    cnt[t] = c;
+    mass[t] = w;
+    __syncthreads();
+    for (int s = kStreamBlock / 2; s > 0; s >>= 1) {
+        if (t < s) { cnt[t] += cnt[t + s]; mass[t] += mass[t + s]; }
+        __syncthreads();
+    }
+    if (t == 0) {
+        out[blockIdx.x].count = (int64_t)cnt[0];
+        out[blockIdx.x].mass = mass[0];
+    }
+}
+
+hipError_t launch_center(const StreamBlock* d_blocks, int64_t n_blocks, const HaloDev* d_halos,
+                         int n_halos, const double* radius, const double* x, const double* y,
+                         const double* z, const double* m, const double* pot, double* bsum,
+                         sidm_center* out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_center_block, dim3((unsigned)n_blocks), dim3(kStreamBlock), 0, st,
+                       d_blocks, d_halos, x, y, z, pot, bsum);
+    hipLaunchKernelGGL(k_center_halo, dim3(n_halos), dim3(kStreamBlock), 0, st, d_halos, bsum, x,
+                       y, z, out);
+    hipLaunchKernelGGL(k_center_count_block, dim3((unsigned)n_blocks), dim3(kStreamBlock), 0, st,
+                       d_blocks, radius, x, y, z, m, out, bsum);
+    hipLaunchKernelGGL(k_center_count_halo, dim3(n_halos), dim3(kStreamBlock), 0, st, d_halos,
+                       bsum, out);
+    return hipGetLastError();
+}
+
 }  // namespace sidm

@@ -21,6 +21,10 @@ hipError_t launch_diag(const StreamBlock* d_blocks, int64_t n_blocks, const Halo
                        const double* pot, double* bsum, const long long* ev_counts,
                        const int* status, sidm_diag* diag, hipStream_t st);
 
+hipError_t launch_center(const StreamBlock* d_blocks, int64_t n_blocks, const HaloDev* d_halos,
+                         int n_halos, const double* radius, const double* x, const double* y,
+                         const double* z, const double* m, const double* pot, double* bsum,
+                         sidm_center* out, hipStream_t st);
 }  // namespace sidm
 
 #include "sidm_plan.hpp"
@@ -49,6 +53,7 @@ struct sidm_ctx {
     Scratch w;
     Plan plan;
     std::vector<sidm_halo> plan_key;
+    std::vector<double> radius;       // host copy of the last central-density radii
     bool plan_valid = false;
     bool timing = false;
     bool timed = false;               // the last step recorded its events
@@ -412,6 +417,36 @@ sidm_status sidm_diagnostics(sidm_ctx* c, const sidm_halo* halos, int32_t n_halo
                                s->vx, s->vy, s->vz, s->m, s->pot, c->w.bsum, c->w.ev_counts,
                                c->w.status, diag, st);
     if (e != hipSuccess) return hip_fail(c, e, "diagnostics launch");
+    c->err.clear();
+    return SIDM_OK;
+}
+
+sidm_status sidm_central_density(sidm_ctx* c, const sidm_halo* halos, int32_t n_halos,
+                                 const sidm_state* s, const double* radius, sidm_center* out,
+                                 void* stream)
+{
+    sidm_status r = validate(c, halos, n_halos, s, 0);
+    if (r != SIDM_OK) return r;
+    if (!out || !radius || !s->pot) {
+        set_err(c, "radius, out and pot are required");
+        return SIDM_ERR_INVALID;
+    }
+    for (int h = 0; h < n_halos; ++h)
+        if (!(radius[h] > 0.0) || !std::isfinite(radius[h])) {
+            set_err(c, "halo %d: radius must be positive and finite", h);
+            return SIDM_ERR_INVALID;
+        }
+    DeviceGuard g(c->device);
+    hipStream_t st = (hipStream_t)stream;
+    if ((r = ensure_plan(c, halos, n_halos, st)) != SIDM_OK) return r;
+    const Plan& P = c->plan;
+    c->radius.assign(radius, radius + n_halos);
+    hipError_t e = hipMemcpyAsync(c->w.radius, c->radius.data(), sizeof(double) * (size_t)n_halos,
+                                  hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(c, e, "radius upload");
+    e = launch_center(c->w.blocks, P.n_blocks, c->w.halos, n_halos, c->w.radius, s->x, s->y,
+                      s->z, s->m, s->pot, c->w.bsum, out, st);
+    if (e != hipSuccess) return hip_fail(c, e, "central density launch");
     c->err.clear();
     return SIDM_OK;
 }
