@@ -78,6 +78,9 @@ typedef struct {
     double host_rho_s;          /* host NFW density parameter                       */
     double host_r_s;            /* host NFW scale radius, > 0 when host_kind == 1   */
     double host_center[3];      /* host centre                                      */
+    double sigma_w;             /* velocity scale w of the cross-section: sigma(v) =
+                                   sigma_m [1 + (v/w)^2]^-2 with v the pair's relative
+                                   speed (Sec. 3.8 Eq. vel_dep); 0: independent of v  */
 } sidm_halo;
 
 /* Particle state (device pointers, length n_total each). */
@@ -167,7 +170,10 @@ sidm_status sidm_knn_h(sidm_ctx *ctx, const sidm_halo *halos, int32_t n_halos,
 /* ---- scattering ----------------------------------------------------------------
  * Tests every unordered pair {i, j} of a halo with d2_ij < (h_i + h_j)^2 once:
  * a = min id, b = max id,
- *   P_ab = (sigma/m) m_b |v_a - v_b| Lambda(|x_a - x_b|; h_a, h_b) dt,
+ *   P_ab = (sigma(g)/m) m_b g Lambda(|x_a - x_b|; h_a, h_b) dt,  g = |v_a - v_b|,
+ * with sigma(g)/m = sigma_m, or sigma_m [1 + (g/w)^2]^-2 when sigma_w = w > 0 (the
+ * velocity-dependent viscosity cross-section of Sec. 3.8, which for isotropic
+ * scattering equals the total cross-section),
  * Lambda = integral of W(|x - x_a|, h_a) W(|x - x_b|, h_b) d^3x with W the
  * cubic spline of compact support h (Sec. 2, Monaghan 1985; Sec. 3.5).  The
  * accept draw is u = top 53 bits of Philox4x32-10 words (w0, w1) at counter

@@ -23,7 +23,7 @@ class OrcParams(C.Structure):
     _fields_ = [("G", C.c_double), ("eps", C.c_double), ("sigma_m", C.c_double),
                 ("dt", C.c_double), ("k", C.c_int32), ("seed", C.c_uint64),
                 ("host_kind", C.c_int32), ("host_rho_s", C.c_double),
-                ("host_r_s", C.c_double), ("host_c", C.c_double * 3)]
+                ("host_r_s", C.c_double), ("host_c", C.c_double * 3), ("sigma_w", C.c_double)]
 
 
 def lib():
@@ -59,13 +59,16 @@ def _declare(L):
                                C.c_double, _dp, _dp, _dp, _dp, _dp]
     L.orc_knn.argtypes = [C.c_int64, _dp, _dp, _dp, _u32p, C.c_int32, C.c_int64,
                           _i64p, _dp, _u32p]
+    L.orc_sigma.argtypes = [C.c_double, C.c_double, C.c_double]
+    L.orc_sigma.restype = C.c_double
     L.orc_find_events.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _u32p,
-                                  _dp, C.c_double, C.c_double, C.c_uint64, C.c_uint32,
+                                  _dp, C.c_double, C.c_double, C.c_double, C.c_uint64, C.c_uint32,
                                   _u8p, C.c_void_p, C.c_int64, _i64p, _i64p]
     L.orc_find_events.restype = C.c_int64
     L.orc_knn_grid.argtypes = [C.c_int64, _dp, _dp, _dp, _u32p, C.c_int32, _dp]
     L.orc_find_events_sweep.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _u32p,
-                                        _dp, C.c_double, C.c_double, C.c_uint64, C.c_uint32,
+                                        _dp, C.c_double, C.c_double, C.c_double, C.c_uint64,
+                                        C.c_uint32,
                                         C.c_void_p, C.c_int64, _i64p, _i64p]
     L.orc_find_events_sweep.restype = C.c_int64
     L.orc_central_density.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp, C.c_double, _i64p,
@@ -177,7 +180,12 @@ def knn_grid(x, y, z, ids, k):
 
 
 # ---------------------------------------------------------------- scatter
-def find_events(x, y, z, vx, vy, vz, m, ids, h, sigma_m, dt, seed, step, qmask=None):
+def sigma(sigma_m, sigma_w, g):
+    return lib().orc_sigma(float(sigma_m), float(sigma_w), float(g))
+
+
+def find_events(x, y, z, vx, vy, vz, m, ids, h, sigma_m, dt, seed, step, qmask=None,
+                sigma_w=0.0):
     """Events (structured array in (a, b) order), pair count, count of P > 1."""
     arrs = [_f64(a) for a in (x, y, z, vx, vy, vz, m)]
     ids = np.ascontiguousarray(ids, dtype=np.uint32)
@@ -189,7 +197,7 @@ def find_events(x, y, z, vx, vy, vz, m, ids, h, sigma_m, dt, seed, step, qmask=N
         qm = qmask.ctypes.data_as(_u8p)
     npairs, npgt1 = C.c_int64(0), C.c_int64(0)
     args = [n] + [_d(a) for a in arrs] + [ids.ctypes.data_as(_u32p), _d(h), float(sigma_m),
-                                          float(dt), int(seed), int(step), qm]
+                                          float(sigma_w), float(dt), int(seed), int(step), qm]
     found = lib().orc_find_events(*args, None, 0, C.byref(npairs), C.byref(npgt1))
     ev = np.zeros(max(found, 1), dtype=EVENT_DTYPE)
     found2 = lib().orc_find_events(*args, ev.ctypes.data, found, None, None)
@@ -197,7 +205,7 @@ def find_events(x, y, z, vx, vy, vz, m, ids, h, sigma_m, dt, seed, step, qmask=N
     return ev[:found], int(npairs.value), int(npgt1.value)
 
 
-def find_events_sweep(x, y, z, vx, vy, vz, m, ids, h, sigma_m, dt, seed, step):
+def find_events_sweep(x, y, z, vx, vy, vz, m, ids, h, sigma_m, dt, seed, step, sigma_w=0.0):
     """find_events over all pairs, from the x-sorted sweep (equal results)."""
     arrs = [_f64(a) for a in (x, y, z, vx, vy, vz, m)]
     ids = np.ascontiguousarray(ids, dtype=np.uint32)
@@ -205,7 +213,7 @@ def find_events_sweep(x, y, z, vx, vy, vz, m, ids, h, sigma_m, dt, seed, step):
     n = arrs[0].size
     npairs, npgt1 = C.c_int64(0), C.c_int64(0)
     args = [n] + [_d(a) for a in arrs] + [ids.ctypes.data_as(_u32p), _d(h), float(sigma_m),
-                                          float(dt), int(seed), int(step)]
+                                          float(sigma_w), float(dt), int(seed), int(step)]
     found = lib().orc_find_events_sweep(*args, None, 0, C.byref(npairs), C.byref(npgt1))
     ev = np.zeros(max(found, 1), dtype=EVENT_DTYPE)
     found2 = lib().orc_find_events_sweep(*args, ev.ctypes.data, found, None, None)
@@ -247,9 +255,10 @@ def diag(vx, vy, vz, m, pot, pext=None):
 
 
 # ---------------------------------------------------------------- step
-def make_params(G=1.0, eps=0.01, sigma_m=1.0, dt=1e-3, k=32, seed=0, host=None):
+def make_params(G=1.0, eps=0.01, sigma_m=1.0, dt=1e-3, k=32, seed=0, host=None, sigma_w=0.0):
     p = OrcParams()
     p.G, p.eps, p.sigma_m, p.dt, p.k, p.seed = G, eps, sigma_m, dt, k, seed
+    p.sigma_w = float(sigma_w)
     if host is None:
         p.host_kind = 0
         p.host_rho_s, p.host_r_s = 0.0, 1.0

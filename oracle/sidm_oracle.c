@@ -349,10 +349,23 @@ static int cmp_event(const void *pa, const void *pb)
     return 0;
 }
 
+/* Cross-section per unit mass at the pair's relative speed g (Sec. 3.8,
+ * Eq. vel_dep): sigma_m [1 + (g/w)^2]^-2, the viscosity cross-section, which the
+ * paper normalises to equal the total cross-section for isotropic scattering.
+ * Reading: g = |v_a - v_b| with the velocities at the start of the pass; w <= 0
+ * means velocity independent. */
+double orc_sigma(double sigma_m, double w, double g)
+{
+    if (!(w > 0.0)) return sigma_m;
+    double t = g / w;
+    double q = 1.0 + t * t;
+    return sigma_m / (q * q);
+}
+
 int64_t orc_find_events(int64_t n, const double *x, const double *y, const double *z,
                         const double *vx, const double *vy, const double *vz,
                         const double *m, const uint32_t *id, const double *h,
-                        double sigma_m, double dt, uint64_t seed, uint32_t step,
+                        double sigma_m, double sigma_w, double dt, uint64_t seed, uint32_t step,
                         const uint8_t *qmask, orc_event *ev, int64_t cap,
                         int64_t *n_pairs, int64_t *n_p_gt1)
 {
@@ -386,7 +399,7 @@ int64_t orc_find_events(int64_t n, const double *x, const double *y, const doubl
                 double gx = vx[ia] - vx[ib], gy = vy[ia] - vy[ib], gz = vz[ia] - vz[ib];
                 double g = sqrt((gx * gx + gy * gy) + gz * gz);
                 double lam = orc_lambda(sqrt(d2), h[ia], h[ib]);
-                double P = sigma_m * m[ib] * g * lam * dt;
+                double P = orc_sigma(sigma_m, sigma_w, g) * m[ib] * g * lam * dt;
                 if (P > 1.0) ++my_pgt1;
                 if (u < P) {
                     if (my_n == my_cap) {
@@ -645,8 +658,9 @@ static int cmp_key(const void *pa, const void *pb)
 int64_t orc_find_events_sweep(int64_t n, const double *x, const double *y, const double *z,
                               const double *vx, const double *vy, const double *vz,
                               const double *m, const uint32_t *id, const double *h,
-                              double sigma_m, double dt, uint64_t seed, uint32_t step,
-                              orc_event *ev, int64_t cap, int64_t *n_pairs, int64_t *n_p_gt1)
+                              double sigma_m, double sigma_w, double dt, uint64_t seed,
+                              uint32_t step, orc_event *ev, int64_t cap, int64_t *n_pairs,
+                              int64_t *n_p_gt1)
 {
     orc_key *ord = (orc_key *)malloc(sizeof(orc_key) * (size_t)(n > 0 ? n : 1));
     for (int64_t i = 0; i < n; ++i) {
@@ -688,7 +702,7 @@ int64_t orc_find_events_sweep(int64_t n, const double *x, const double *y, const
                 double gx = vx[ia] - vx[ib], gy = vy[ia] - vy[ib], gz = vz[ia] - vz[ib];
                 double gg = sqrt((gx * gx + gy * gy) + gz * gz);
                 double lam = orc_lambda(sqrt(d2), h[ia], h[ib]);
-                double P = sigma_m * m[ib] * gg * lam * dt;
+                double P = orc_sigma(sigma_m, sigma_w, gg) * m[ib] * gg * lam * dt;
                 if (P > 1.0) ++my_pgt1;
                 if (u < P) {
                     if (my_n == my_cap) {
@@ -808,12 +822,13 @@ int64_t orc_kdk_step(int64_t n, double *x, double *y, double *z,
     if (p->sigma_m == 0.0) return 0;
     int64_t cap = ev_cap > 0 ? ev_cap : 0;
     orc_event *buf = ev;
-    int64_t found = orc_find_events_sweep(n, x, y, z, vx, vy, vz, m, id, h, p->sigma_m, p->dt,
-                                          p->seed, step, buf, cap, NULL, NULL);
+    int64_t found = orc_find_events_sweep(n, x, y, z, vx, vy, vz, m, id, h, p->sigma_m,
+                                          p->sigma_w, p->dt, p->seed, step, buf, cap, NULL,
+                                          NULL);
     if (found > cap) {
         /* not enough room to hold the ordered list: collect it privately */
         buf = (orc_event *)malloc(sizeof(orc_event) * (size_t)found);
-        orc_find_events_sweep(n, x, y, z, vx, vy, vz, m, id, h, p->sigma_m, p->dt,
+        orc_find_events_sweep(n, x, y, z, vx, vy, vz, m, id, h, p->sigma_m, p->sigma_w, p->dt,
                               p->seed, step, buf, found, NULL, NULL);
     }
     orc_apply_events(found, buf, m, vx, vy, vz, p->seed, step);

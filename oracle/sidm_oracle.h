@@ -83,6 +83,10 @@ void orc_knn_grid(int64_t n, const double *x, const double *y, const double *z,
 
 /* ---- pairwise scattering (paper Sec. 2 and Sec. 3.5) ---- */
 
+/* Cross-section per unit mass at relative speed g (Sec. 3.8, Eq. vel_dep):
+ * sigma_m [1 + (g/w)^2]^-2 for w > 0, else sigma_m. */
+double orc_sigma(double sigma_m, double w, double g);
+
 typedef struct {
     uint32_t a, b;     /* ids, a < b                                 */
     int64_t ia, ib;    /* halo-local indices of the particles a, b  */
@@ -90,7 +94,8 @@ typedef struct {
 } orc_event;
 
 /* Tests every unordered pair {i, j} with d2_ij < (h_i + h_j)^2 once, with
- * a = min id, b = max id, P_ab = (sigma/m) m_b |v_a - v_b| Lambda_ab dt and the
+ * a = min id, b = max id, P_ab = (sigma(g)/m) m_b g Lambda_ab dt with g = |v_a - v_b|
+ * and sigma(g)/m = orc_sigma(sigma_m, sigma_w, g), and the
  * accept draw u of orc_accept_u; an event is u < P.  When `q` is non-NULL only
  * pairs with at least one endpoint in the query set (flag array `qmask` of
  * length n) are tested.  Writes up to `cap` events in (a, b) order and returns
@@ -99,7 +104,7 @@ typedef struct {
 int64_t orc_find_events(int64_t n, const double *x, const double *y, const double *z,
                         const double *vx, const double *vy, const double *vz,
                         const double *m, const uint32_t *id, const double *h,
-                        double sigma_m, double dt, uint64_t seed, uint32_t step,
+                        double sigma_m, double sigma_w, double dt, uint64_t seed, uint32_t step,
                         const uint8_t *qmask, orc_event *ev, int64_t cap,
                         int64_t *n_pairs, int64_t *n_p_gt1);
 
@@ -108,8 +113,9 @@ int64_t orc_find_events(int64_t n, const double *x, const double *y, const doubl
 int64_t orc_find_events_sweep(int64_t n, const double *x, const double *y, const double *z,
                               const double *vx, const double *vy, const double *vz,
                               const double *m, const uint32_t *id, const double *h,
-                              double sigma_m, double dt, uint64_t seed, uint32_t step,
-                              orc_event *ev, int64_t cap, int64_t *n_pairs, int64_t *n_p_gt1);
+                              double sigma_m, double sigma_w, double dt, uint64_t seed,
+                              uint32_t step, orc_event *ev, int64_t cap, int64_t *n_pairs,
+                              int64_t *n_p_gt1);
 
 /* Elastic isotropic scattering of one pair in its centre-of-mass frame, using
  * the direction draw at counter (a, b, step, 1).  Updates the two velocities. */
@@ -142,6 +148,7 @@ typedef struct {
     uint64_t seed;
     int32_t host_kind;          /* 0 none, 1 NFW                             */
     double host_rho_s, host_r_s, host_c[3];
+    double sigma_w;             /* velocity scale of sigma(v); 0: constant   */
 } orc_params;
 
 /* Full-N step for one halo (exact searches: orc_knn_grid, orc_find_events_sweep).  On entry a/pot hold the acceleration

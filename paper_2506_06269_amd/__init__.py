@@ -47,7 +47,7 @@ class SidmHalo(C.Structure):
                 ("eps", C.c_double), ("sigma_m", C.c_double), ("dt", C.c_double),
                 ("k", C.c_int32), ("host_kind", C.c_int32), ("seed", C.c_uint64),
                 ("host_rho_s", C.c_double), ("host_r_s", C.c_double),
-                ("host_center", C.c_double * 3)]
+                ("host_center", C.c_double * 3), ("sigma_w", C.c_double)]
 
 
 class SidmState(C.Structure):
@@ -151,6 +151,7 @@ def make_halos(halos):
         arr[i].G = float(h.get("G", 1.0))
         arr[i].eps = float(h["eps"])
         arr[i].sigma_m = float(h.get("sigma_m", 0.0))
+        arr[i].sigma_w = float(h.get("sigma_w", 0.0))
         arr[i].dt = float(h.get("dt", 0.0))
         arr[i].k = int(h.get("k", 0))
         arr[i].seed = int(h.get("seed", 0))

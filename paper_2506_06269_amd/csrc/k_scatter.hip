@@ -57,6 +57,17 @@ struct PairSide {
     uint32_t id[kBucket], orig[kBucket];
 };
 
+// Cross-section per unit mass at relative speed g: sigma_m, or with a velocity
+// scale w > 0 the form of Sec. 3.8 (Eq. vel_dep), sigma_m [1 + (g/w)^2]^-2.
+__device__ inline double sigma_at(const HaloDev& H, double g)
+{
+#pragma clang fp contract(off)
+    if (!(H.sigma_w > 0.0)) return H.sigma_m;
+    const double t = g / H.sigma_w;
+    const double q = 1.0 + t * t;
+    return H.sigma_m / (q * q);
+}
+
 __global__ __launch_bounds__(kBucket) void k_pairs(
     const HaloDev* __restrict__ halos, const BucketInfo* __restrict__ buckets,
     const NodeChild* __restrict__ nodes, const double* __restrict__ box,
@@ -106,12 +117,13 @@ __global__ __launch_bounds__(kBucket) void k_pairs(
             const double hm = fmax(ha, hbb);
             const double mb = iswap ? I.m[il] : J.m[jl];
             // Lambda <= min(W_a(0), W_b(0)) = 8 / (pi max(h)^3)
-            const double pub = H.sigma_m * mb * g * (kInvPi8 / (hm * hm * hm)) * H.dt;
+            const double sg = sigma_at(H, g);
+            const double pub = sg * mb * g * (kInvPi8 / (hm * hm * hm)) * H.dt;
             if (u < pub) {
                 const double d =
                     sqrt(dist2_pair(I.x[il], I.y[il], I.z[il], J.x[jl], J.y[jl], J.z[jl]));
                 const double lam = iswap ? kernel_overlap(d, hbb, ha) : kernel_overlap(d, ha, hbb);
-                const double P = H.sigma_m * mb * g * lam * H.dt;
+                const double P = sg * mb * g * lam * H.dt;
                 if (P > 1.0) atomicAdd(&ev_counts[4 * B.halo + 3], 1ull);
                 if (u < P) {
                     const unsigned long long slot = atomicAdd(&counters->n_events_total, 1ull);

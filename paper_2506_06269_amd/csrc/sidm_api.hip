@@ -143,6 +143,11 @@ sidm_status validate(sidm_ctx* c, const sidm_halo* halos, int32_t n_halos, const
             set_err(c, "halo %d: dt must be finite and > 0 (dt=%g)", h, H.dt);
             return SIDM_ERR_INVALID;
         }
+        if ((need & (NEED_SCATTER | NEED_STEP)) &&
+            (!(H.sigma_w >= 0.0) || !std::isfinite(H.sigma_w))) {
+            set_err(c, "halo %d: sigma_w must be finite and >= 0", h);
+            return SIDM_ERR_INVALID;
+        }
         if ((need & (NEED_SCATTER | NEED_STEP)) && (!(H.sigma_m >= 0.0) || !std::isfinite(H.sigma_m))) {
             set_err(c, "halo %d: sigma_m must be finite and >= 0", h);
             return SIDM_ERR_INVALID;

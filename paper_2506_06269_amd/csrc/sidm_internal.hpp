@@ -25,7 +25,7 @@ constexpr int kSortBlock = 256;
 // Per-halo parameters and derived layout, uploaded once per halo configuration.
 struct HaloDev {
     int64_t offset, n;
-    double G, eps, eps2, sigma_m, dt;
+    double G, eps, eps2, sigma_m, sigma_w, dt;
     int32_t k, host_kind;
     uint64_t seed;
     double host_K, host_r_s, host_c[3];   // host_K = 4 pi G rho_s r_s^3

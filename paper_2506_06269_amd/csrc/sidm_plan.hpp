@@ -279,6 +279,7 @@ inline bool build_plan(Plan& P, const Scratch& w, const sidm_halo* halos, int32_
         H.eps = S.eps;
         H.eps2 = S.eps * S.eps;
         H.sigma_m = S.sigma_m;
+        H.sigma_w = S.sigma_w;
         H.dt = S.dt;
         H.k = S.k;
         H.host_kind = S.host_kind;

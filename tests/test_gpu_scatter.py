@@ -52,7 +52,7 @@ def _check_schedule(events):
 def _compare_events(orc, s, halo, gpu_events, step):
     ref, npairs, _ = orc.find_events(s["x"], s["y"], s["z"], s["vx"], s["vy"], s["vz"], s["m"],
                                      s["id"], s["h"], halo["sigma_m"], halo["dt"],
-                                     halo.get("seed", 0), step)
+                                     halo.get("seed", 0), step, sigma_w=halo.get("sigma_w", 0.0))
     g = set(zip(gpu_events["a"].tolist(), gpu_events["b"].tolist()))
     r = set(zip(ref["a"].tolist(), ref["b"].tolist()))
     diff = g ^ r
@@ -62,11 +62,13 @@ def _compare_events(orc, s, halo, gpu_events, step):
     return ref, npairs, len(diff)
 
 
-@pytest.mark.parametrize("n,k,sigma,seed", [(8192, 32, 1.0, 0), (4096, 16, 300.0, 1),
-                                            (1000, 64, 2000.0, 2), (3000, 128, 50.0, 3)])
-def test_scatter_events_and_kicks(S, orc, n, k, sigma, seed):
+@pytest.mark.parametrize("n,k,sigma,seed,w", [(8192, 32, 1.0, 0, 0.0), (4096, 16, 300.0, 1, 0.0),
+                                              (1000, 64, 2000.0, 2, 0.0), (3000, 128, 50.0, 3, 0.0),
+                                              (4096, 32, 3000.0, 4, 1.0), (2000, 64, 2e4, 5, 0.3)])
+def test_scatter_events_and_kicks(S, orc, n, k, sigma, seed, w):
+    """w > 0: the velocity-dependent cross-section of Sec. 3.8 (Eq. vel_dep)."""
     s = _prepare(orc, W.nfw_halo(n, seed=seed + 10), k)
-    halo = dict(n=n, eps=0.01, k=k, sigma_m=sigma, dt=1e-3, seed=seed)
+    halo = dict(n=n, eps=0.01, k=k, sigma_m=sigma, dt=1e-3, seed=seed, sigma_w=w)
     step = 7
     out, ev, count = _gpu_scatter(S, [halo], s, step)
     print(f"n={n} k={k} sigma={sigma}: {count} events, max round "
@@ -156,13 +158,15 @@ def test_scatter_deterministic(S, orc):
 
 
 def test_scatter_batched_halos(S, orc):
-    """Two halos with repeated ids, different seeds and cross-sections."""
+    """Two halos with repeated ids, different seeds and cross-sections (the
+    second velocity dependent)."""
     p1 = _prepare(orc, W.nfw_halo(3000, seed=30), 16)
     p2 = _prepare(orc, W.nfw_halo(2500, seed=31), 64)
     s = {f: np.concatenate([p1[f], p2[f]]) for f in ("x", "y", "z", "vx", "vy", "vz", "m", "h")}
     s["id"] = np.concatenate([p1["id"], p2["id"]]).astype(np.uint32)
     halos = [dict(n=3000, offset=0, eps=0.01, k=16, sigma_m=300.0, dt=1e-3, seed=11),
-             dict(n=2500, offset=3000, eps=0.01, k=64, sigma_m=50.0, dt=2e-3, seed=12)]
+             dict(n=2500, offset=3000, eps=0.01, k=64, sigma_m=500.0, dt=2e-3, seed=12,
+                  sigma_w=0.8)]
     out, ev, cnt = _gpu_scatter(S, halos, s, 2)
     _check_schedule(ev)
     for h, p, (o, n) in zip(halos, (p1, p2), ((0, 3000), (3000, 2500))):

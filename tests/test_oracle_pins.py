@@ -398,6 +398,45 @@ def test_scattering_rate_maxwell_box(orc):
     assert abs(count - expect) < 4 * sd, (count, expect)
 
 
+def test_sigma_velocity_dependence(orc):
+    """Sec. 3.8 Eq. vel_dep: sigma(0) = sigma_0, sigma(w) = sigma_0 / 4, the
+    (w/v)^4 tail, and w = 0 for a constant cross-section."""
+    assert orc.sigma(7.0, 2.0, 0.0) == 7.0
+    assert orc.sigma(7.0, 2.0, 2.0) == pytest.approx(7.0 / 4.0, rel=1e-15)
+    assert orc.sigma(7.0, 2.0, 2e4) == pytest.approx(7.0 * (2.0 / 2e4) ** 4, rel=1e-7)
+    assert orc.sigma(7.0, 0.0, 123.0) == 7.0
+
+
+def test_scattering_rate_maxwell_box_velocity_dependent(orc):
+    """As the constant-sigma rate pin, with sigma(v) = sigma_0 [1 + (v/w)^2]^-2:
+    the expected number of events per interior particle and step is
+    rho dt <v sigma(v)> over the Maxwellian distribution of relative speeds
+    (dispersion sqrt(2) sigma_v per component), by quadrature."""
+    from scipy.integrate import quad
+    n, k = 8192, 64
+    s = W.maxwell_box(n, seed=22)
+    rho = s["m"][0] * (n - 1)
+    h = np.full(n, (k * 3 / (4 * math.pi * n)) ** (1 / 3))
+    margin = 2 * h[0]
+    inner = ((s["x"] > margin) & (s["x"] < 1 - margin) & (s["y"] > margin) & (s["y"] < 1 - margin)
+             & (s["z"] > margin) & (s["z"] < 1 - margin))
+    qmask = inner.astype(np.uint8)
+    sigma0, w, dt, steps = 12.0, 1.0, 0.04, 8
+    sr = math.sqrt(2.0)
+    fv = lambda v: math.sqrt(2 / math.pi) * v * v / sr ** 3 * math.exp(-v * v / (2 * sr * sr))
+    mean_vs, _ = quad(lambda v: v * sigma0 / (1 + (v / w) ** 2) ** 2 * fv(v), 0, np.inf)
+    count = 0
+    for step in range(steps):
+        ev, _, _ = orc.find_events(s["x"], s["y"], s["z"], s["vx"], s["vy"], s["vz"], s["m"],
+                                   s["id"], h, sigma0, dt, 5, step, qmask=qmask, sigma_w=w)
+        count += int(np.sum(inner[ev["ia"]])) + int(np.sum(inner[ev["ib"]]))
+    expect = inner.sum() * steps * rho * mean_vs * dt
+    sd = math.sqrt(2 * expect)
+    assert abs(count - expect) < 4 * sd, (count, expect)
+    # the constant cross-section gives the 4 sigma_v / sqrt(pi) mean for comparison
+    assert mean_vs < sigma0 * 4 / math.sqrt(math.pi) * 0.5
+
+
 # ------------------------------------------------------------------ step
 def _two_body(orc, dt, t_end):
     s = dict(x=np.array([-0.5, 0.5]), y=np.zeros(2), z=np.zeros(2),
