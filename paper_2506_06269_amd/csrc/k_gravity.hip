@@ -258,6 +258,52 @@ __global__ __launch_bounds__(kGravThreads) void k_grav_mixed(
 }
 
 // ---------------------------------------------------------------- FP64 tiles
+// 1/sqrt(r2) for finite r2 > 0: the hardware estimate refined by one Newton
+// step, y1 = y0 + y0 (1 - r2 y0^2) / 2, which squares the estimate's relative
+// error (the general routine also handles 0, inf, NaN and denormals, which the
+// softened r2 >= eps^2 never is).
+__device__ inline double rsqrt_pos(double r2)
+{
+    const double y0 = __builtin_amdgcn_rsq(r2);
+    const double e = fma(-r2 * y0, y0, 1.0);
+    return fma(0.5 * y0, e, y0);
+}
+
+// Pair terms of one LDS tile for IREG i-particles in FP64 (see tile_f32).
+template <int IREG, bool EQM, bool DIAG>
+__device__ inline void tile_f64(const double4* __restrict__ tile, const double* xi,
+                                const double* yi, const double* zi, double eps2, int64_t j0,
+                                int64_t i0, int t, double* px, double* py, double* pz, double* pp)
+{
+#pragma unroll 2
+    for (int jj = 0; jj < kGravTileJ; ++jj) {
+        const double4 q = tile[jj];
+#pragma unroll
+        for (int r = 0; r < IREG; ++r) {
+            const double dx = q.x - xi[r];
+            const double dy = q.y - yi[r];
+            const double dz = q.z - zi[r];
+            const double r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
+            double rinv = rsqrt_pos(r2);
+            if (DIAG && j0 + jj == i0 + (int64_t)r * kGravThreads + t) rinv = 0.0;
+            if (EQM) {
+                const double rinv3 = rinv * (rinv * rinv);
+                px[r] = fma(rinv3, dx, px[r]);
+                py[r] = fma(rinv3, dy, py[r]);
+                pz[r] = fma(rinv3, dz, pz[r]);
+                pp[r] += rinv;
+            } else {
+                const double mr = q.w * rinv;
+                const double mr3 = mr * (rinv * rinv);
+                px[r] = fma(mr3, dx, px[r]);
+                py[r] = fma(mr3, dy, py[r]);
+                pz[r] = fma(mr3, dz, pz[r]);
+                pp[r] += mr;
+            }
+        }
+    }
+}
+
 template <int IREG, bool EQM>
 __device__ inline void grav_fp64_body(const double* __restrict__ x, const double* __restrict__ y,
                                       const double* __restrict__ z, const double* __restrict__ m,
@@ -283,7 +329,9 @@ __device__ inline void grav_fp64_body(const double* __restrict__ x, const double
         cx[r] = cy[r] = cz[r] = cp[r] = 0.0;
     }
     for (int64_t j0 = it.j0; j0 < it.j1; j0 += kGravTileJ) {
-        double4 pj = make_double4(1.0e300, 1.0e300, 1.0e300, 0.0);  // padding: no contribution
+        // padding: r2 ~ 1e300 stays finite, r^-3 underflows to 0 and r^-1 ~ 1e-150
+        // cannot change a potential sum
+        double4 pj = make_double4(1.0e150, 1.0e150, 1.0e150, 0.0);
         if (j0 + t < it.j1) {
             const int64_t p = H.sbase + (j0 - H.offset) + t;
             pj = make_double4(x[p], y[p], z[p], m[p]);
@@ -295,33 +343,10 @@ __device__ inline void grav_fp64_body(const double* __restrict__ x, const double
 #pragma unroll
         for (int r = 0; r < IREG; ++r) px[r] = py[r] = pz[r] = pp[r] = 0.0;
         const bool diag = j0 < it.i0 + (int64_t)IREG * kGravThreads && j0 + kGravTileJ > it.i0;
-#pragma unroll 2
-        for (int jj = 0; jj < kGravTileJ; ++jj) {
-            const double4 q = tile[jj];
-#pragma unroll
-            for (int r = 0; r < IREG; ++r) {
-                const double dx = q.x - xi[r];
-                const double dy = q.y - yi[r];
-                const double dz = q.z - zi[r];
-                const double r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
-                double rinv = rsqrt(r2);
-                if (diag && j0 + jj == it.i0 + (int64_t)r * kGravThreads + t) rinv = 0.0;
-                if (EQM) {
-                    const double rinv3 = rinv * (rinv * rinv);
-                    px[r] = fma(rinv3, dx, px[r]);
-                    py[r] = fma(rinv3, dy, py[r]);
-                    pz[r] = fma(rinv3, dz, pz[r]);
-                    pp[r] += rinv;
-                } else {
-                    const double mr = q.w * rinv;
-                    const double mr3 = mr * (rinv * rinv);
-                    px[r] = fma(mr3, dx, px[r]);
-                    py[r] = fma(mr3, dy, py[r]);
-                    pz[r] = fma(mr3, dz, pz[r]);
-                    pp[r] += mr;
-                }
-            }
-        }
+        if (diag)
+            tile_f64<IREG, EQM, true>(tile, xi, yi, zi, eps2, j0, it.i0, t, px, py, pz, pp);
+        else
+            tile_f64<IREG, EQM, false>(tile, xi, yi, zi, eps2, j0, it.i0, t, px, py, pz, pp);
 #pragma unroll
         for (int r = 0; r < IREG; ++r) {
             double yk, tk;
