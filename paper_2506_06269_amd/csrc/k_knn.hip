@@ -104,7 +104,16 @@ __global__ __launch_bounds__(kBucket) void k_knn(
                            if (!__ballot(!off && point_box_dist2(xi, yi, zi, R.box) <= r2)) continue;
                            const int64_t p0 = c0 + R.off;
                            const int cnt = R.cnt;
-                           for (int j = 0; j < cnt; ++j) body(p0 + j, sp4[p0 + j]);
+                           // four candidates' loads in flight before the first use
+                           int j = 0;
+                           for (; j + 4 <= cnt; j += 4) {
+                               double4 c[4];
+#pragma unroll
+                               for (int u = 0; u < 4; ++u) c[u] = sp4[p0 + j + u];
+#pragma unroll
+                               for (int u = 0; u < 4; ++u) body(p0 + j + u, c[u]);
+                           }
+                           for (; j < cnt; ++j) body(p0 + j, sp4[p0 + j]);
                        }
                    });
     };
