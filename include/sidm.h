@@ -73,14 +73,25 @@ typedef struct {
                                    velocity independent: Sec. 2)                    */
     double dt;                  /* fixed time step, > 0                             */
     int32_t k;                  /* N_ngb, 1 <= k <= min(n - 1, SIDM_MAX_K)          */
-    int32_t host_kind;          /* 0: isolated; 1: static NFW host (Sec. 4.1)       */
+    int32_t host_kind;          /* 0: isolated; 1: static NFW host; 2: the Milky-Way
+                                   host of Sec. 4.1 (NFW + Hernquist bulge + four
+                                   Miyamoto-Nagai discs)                            */
     uint64_t seed;              /* Philox key of the scattering draws               */
-    double host_rho_s;          /* host NFW density parameter                       */
-    double host_r_s;            /* host NFW scale radius, > 0 when host_kind == 1   */
-    double host_center[3];      /* host centre                                      */
+    double host_rho_s;          /* host NFW density parameter (Eq. nfw_potential)   */
+    double host_r_s;            /* host NFW scale radius, > 0 when rho_s != 0       */
+    double host_center[3];      /* host centre; the discs lie in its z = 0 plane    */
     double sigma_w;             /* velocity scale w of the cross-section: sigma(v) =
                                    sigma_m [1 + (v/w)^2]^-2 with v the pair's relative
                                    speed (Sec. 3.8 Eq. vel_dep); 0: independent of v  */
+    double host_hern_M;         /* host_kind 2: Hernquist bulge mass and scale length */
+    double host_hern_a;         /*   (Eq. hernquist_potential); M = 0: none          */
+    double host_disk[4][3];     /* host_kind 2: Miyamoto-Nagai discs (M, a, b)
+                                   (Eq. disk_potential); M = 0: unused slot         */
+    double boundary_r;          /* reflecting sphere (Sec. 2): after the drift, a
+                                   particle farther than boundary_r from
+                                   boundary_center that moves outwards has its
+                                   radial velocity reversed; 0: none                */
+    double boundary_center[3];
 } sidm_halo;
 
 /* Particle state (device pointers, length n_total each). */

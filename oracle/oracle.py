@@ -23,7 +23,10 @@ class OrcParams(C.Structure):
     _fields_ = [("G", C.c_double), ("eps", C.c_double), ("sigma_m", C.c_double),
                 ("dt", C.c_double), ("k", C.c_int32), ("seed", C.c_uint64),
                 ("host_kind", C.c_int32), ("host_rho_s", C.c_double),
-                ("host_r_s", C.c_double), ("host_c", C.c_double * 3), ("sigma_w", C.c_double)]
+                ("host_r_s", C.c_double), ("host_c", C.c_double * 3), ("sigma_w", C.c_double),
+                ("host_hern_M", C.c_double), ("host_hern_a", C.c_double),
+                ("host_disk", (C.c_double * 3) * 4), ("boundary_r", C.c_double),
+                ("boundary_c", C.c_double * 3)]
 
 
 def lib():
@@ -65,6 +68,11 @@ def _declare(L):
                                   _dp, C.c_double, C.c_double, C.c_double, C.c_uint64, C.c_uint32,
                                   _u8p, C.c_void_p, C.c_int64, _i64p, _i64p]
     L.orc_find_events.restype = C.c_int64
+    L.orc_host_hernquist.argtypes = [C.c_int64, _dp, _dp, _dp, C.c_double, C.c_double,
+                                     C.c_double, C.POINTER(C.c_double), _dp, _dp, _dp, _dp]
+    L.orc_host_disk.argtypes = [C.c_int64, _dp, _dp, _dp, C.c_double, C.c_double, C.c_double,
+                                C.c_double, C.POINTER(C.c_double), _dp, _dp, _dp, _dp]
+    L.orc_host_field.argtypes = [C.c_int64, _dp, _dp, _dp, C.c_void_p, _dp, _dp, _dp, _dp]
     L.orc_knn_grid.argtypes = [C.c_int64, _dp, _dp, _dp, _u32p, C.c_int32, _dp]
     L.orc_find_events_sweep.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _u32p,
                                         _dp, C.c_double, C.c_double, C.c_double, C.c_uint64,
@@ -151,6 +159,32 @@ def host_nfw(x, y, z, G, rho_s, r_s, c):
     lib().orc_host_nfw(n, _d(x), _d(y), _d(z), float(G), float(rho_s), float(r_s),
                        cc, _d(ax), _d(ay), _d(az), _d(pot))
     return ax, ay, az, pot
+
+
+def host_hernquist(x, y, z, G, M, a, c):
+    x, y, z = _f64(x), _f64(y), _f64(z)
+    out = [np.zeros(x.size) for _ in range(4)]
+    cc = (C.c_double * 3)(*[float(v) for v in c])
+    lib().orc_host_hernquist(x.size, _d(x), _d(y), _d(z), float(G), float(M), float(a), cc,
+                             *[_d(o) for o in out])
+    return tuple(out)
+
+
+def host_disk(x, y, z, G, M, a, b, c):
+    x, y, z = _f64(x), _f64(y), _f64(z)
+    out = [np.zeros(x.size) for _ in range(4)]
+    cc = (C.c_double * 3)(*[float(v) for v in c])
+    lib().orc_host_disk(x.size, _d(x), _d(y), _d(z), float(G), float(M), float(a), float(b), cc,
+                        *[_d(o) for o in out])
+    return tuple(out)
+
+
+def host_field(x, y, z, p):
+    """Total host acceleration and potential of parameter set p."""
+    x, y, z = _f64(x), _f64(y), _f64(z)
+    out = [np.zeros(x.size) for _ in range(4)]
+    lib().orc_host_field(x.size, _d(x), _d(y), _d(z), C.addressof(p), *[_d(o) for o in out])
+    return tuple(out)
 
 
 # ---------------------------------------------------------------- kNN
@@ -255,27 +289,38 @@ def diag(vx, vy, vz, m, pot, pext=None):
 
 
 # ---------------------------------------------------------------- step
-def make_params(G=1.0, eps=0.01, sigma_m=1.0, dt=1e-3, k=32, seed=0, host=None, sigma_w=0.0):
+def make_params(G=1.0, eps=0.01, sigma_m=1.0, dt=1e-3, k=32, seed=0, host=None, sigma_w=0.0,
+                boundary=None):
+    """host: None, an NFW dict (rho_s, r_s, center), or with "hern" = (M, a)
+    and "disks" = [(M, a, b), ...] the Milky-Way host.  boundary: None or a
+    dict (r, center) for the reflecting sphere."""
     p = OrcParams()
     p.G, p.eps, p.sigma_m, p.dt, p.k, p.seed = G, eps, sigma_m, dt, k, seed
     p.sigma_w = float(sigma_w)
+    if boundary is not None:
+        p.boundary_r = float(boundary["r"])
+        p.boundary_c = (C.c_double * 3)(*[float(v) for v in boundary.get("center", (0, 0, 0))])
     if host is None:
         p.host_kind = 0
         p.host_rho_s, p.host_r_s = 0.0, 1.0
         p.host_c = (C.c_double * 3)(0.0, 0.0, 0.0)
     else:
-        p.host_kind = 1
+        p.host_kind = 2 if ("hern" in host or "disks" in host) else 1
         p.host_rho_s, p.host_r_s = float(host["rho_s"]), float(host["r_s"])
         p.host_c = (C.c_double * 3)(*[float(v) for v in host["center"]])
+        if "hern" in host:
+            p.host_hern_M, p.host_hern_a = (float(v) for v in host["hern"])
+        for d, disk in enumerate(host.get("disks", ())):
+            for c in range(3):
+                p.host_disk[d][c] = float(disk[c])
     return p
 
 
 def total_accel(s, p):
     """a and pot (self + host) at the state's positions, written into s."""
     ax, ay, az, pot = gravity(s["x"], s["y"], s["z"], s["m"], p.G, p.eps)
-    if p.host_kind == 1:
-        hx, hy, hz, hp = host_nfw(s["x"], s["y"], s["z"], p.G, p.host_rho_s, p.host_r_s,
-                                  list(p.host_c))
+    if p.host_kind != 0:
+        hx, hy, hz, hp = host_field(s["x"], s["y"], s["z"], p)
         ax, ay, az, pot = ax + hx, ay + hy, az + hz, pot + hp
     s["ax"], s["ay"], s["az"], s["pot"] = ax, ay, az, pot
     return s

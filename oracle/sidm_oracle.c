@@ -293,6 +293,79 @@ void orc_host_nfw(int64_t n, const double *x, const double *y, const double *z,
 /* k nearest neighbours by brute force (Sec. 2: kernel size set by the next
  * N_ngb neighbours).  Reading: h_i is the exact distance of the k-th nearest
  * other particle, ties broken by id. */
+/* Hernquist bulge (Sec. 4.1, Eq. hernquist_potential): Phi = -G M / (r + a);
+ * a = -dPhi/dr r_hat = -G M d / (r (r + a)^2). */
+void orc_host_hernquist(int64_t n, const double *x, const double *y, const double *z,
+                        double G, double M, double a, const double c[3],
+                        double *ax, double *ay, double *az, double *pot)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double dx = x[i] - c[0], dy = y[i] - c[1], dz = z[i] - c[2];
+        double r = sqrt((dx * dx + dy * dy) + dz * dz);
+        pot[i] = -G * M / (r + a);
+        if (r == 0.0) {
+            ax[i] = ay[i] = az[i] = 0.0;
+            continue;
+        }
+        double f = -G * M / (r * (r + a) * (r + a));
+        ax[i] = f * dx;
+        ay[i] = f * dy;
+        az[i] = f * dz;
+    }
+}
+
+/* Miyamoto-Nagai disc (Sec. 4.1, Eq. disk_potential) in the z = 0 plane of c:
+ * with zeta = sqrt(z^2 + b^2) and D^2 = R^2 + (a + zeta)^2, Phi = -G M / D and
+ * a = -grad Phi = -G M (x, y, z (a + zeta) / zeta) / D^3. */
+void orc_host_disk(int64_t n, const double *x, const double *y, const double *z,
+                   double G, double M, double a, double b, const double c[3],
+                   double *ax, double *ay, double *az, double *pot)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double dx = x[i] - c[0], dy = y[i] - c[1], dz = z[i] - c[2];
+        double zeta = sqrt(dz * dz + b * b);
+        double D2 = (dx * dx + dy * dy) + (a + zeta) * (a + zeta);
+        double D = sqrt(D2);
+        pot[i] = -G * M / D;
+        double f = -G * M / (D2 * D);
+        ax[i] = f * dx;
+        ay[i] = f * dy;
+        az[i] = zeta > 0.0 ? f * dz * (a + zeta) / zeta : 0.0;
+    }
+}
+
+void orc_host_field(int64_t n, const double *x, const double *y, const double *z,
+                    const orc_params *p, double *ax, double *ay, double *az, double *pot)
+{
+    for (int64_t i = 0; i < n; ++i) ax[i] = ay[i] = az[i] = pot[i] = 0.0;
+    if (p->host_kind == 0 || n == 0) return;
+    double *t = (double *)malloc(sizeof(double) * (size_t)n * 4);
+    double *tx = t, *ty = t + n, *tz = t + 2 * n, *tp = t + 3 * n;
+    for (int comp = 0; comp < 6; ++comp) {
+        if (comp == 0) {
+            if (p->host_rho_s == 0.0) continue;
+            orc_host_nfw(n, x, y, z, p->G, p->host_rho_s, p->host_r_s, p->host_c, tx, ty, tz, tp);
+        } else if (p->host_kind != 2) {
+            break;
+        } else if (comp == 1) {
+            if (p->host_hern_M == 0.0) continue;
+            orc_host_hernquist(n, x, y, z, p->G, p->host_hern_M, p->host_hern_a, p->host_c,
+                               tx, ty, tz, tp);
+        } else {
+            const double *d = p->host_disk[comp - 2];
+            if (d[0] == 0.0) continue;
+            orc_host_disk(n, x, y, z, p->G, d[0], d[1], d[2], p->host_c, tx, ty, tz, tp);
+        }
+        for (int64_t i = 0; i < n; ++i) {
+            ax[i] += tx[i];
+            ay[i] += ty[i];
+            az[i] += tz[i];
+            pot[i] += tp[i];
+        }
+    }
+    free(t);
+}
+
 static int key_less(double d2a, uint32_t ida, double d2b, uint32_t idb)
 {
     return d2a < d2b || (d2a == d2b && ida < idb);
@@ -777,10 +850,10 @@ static void accel_total(int64_t n, const double *x, const double *y, const doubl
                         double *ax, double *ay, double *az, double *pot)
 {
     orc_gravity(n, x, y, z, m, p->G, p->eps, n, NULL, ax, ay, az, pot, NULL);
-    if (p->host_kind == 1) {
+    if (p->host_kind != 0) {
         double *hx = (double *)malloc(sizeof(double) * (size_t)n * 4);
         double *hy = hx + n, *hz = hy + n, *hp = hz + n;
-        orc_host_nfw(n, x, y, z, p->G, p->host_rho_s, p->host_r_s, p->host_c, hx, hy, hz, hp);
+        orc_host_field(n, x, y, z, p, hx, hy, hz, hp);
         for (int64_t i = 0; i < n; ++i) {
             ax[i] += hx[i];
             ay[i] += hy[i];
@@ -811,6 +884,22 @@ int64_t orc_kdk_step(int64_t n, double *x, double *y, double *z,
         x[i] += vx[i] * p->dt;
         y[i] += vy[i] * p->dt;
         z[i] += vz[i] * p->dt;
+    }
+    /* reflecting sphere (Sec. 2): a particle beyond the radius that moves
+     * outwards gets its radial velocity reversed, v -> v - 2 (v.d) d / |d|^2 */
+    if (p->boundary_r > 0.0) {
+        for (int64_t i = 0; i < n; ++i) {
+            double dx = x[i] - p->boundary_c[0], dy = y[i] - p->boundary_c[1];
+            double dz = z[i] - p->boundary_c[2];
+            double d2 = (dx * dx + dy * dy) + dz * dz;
+            double vd = (vx[i] * dx + vy[i] * dy) + vz[i] * dz;
+            if (d2 > p->boundary_r * p->boundary_r && vd > 0.0) {
+                double f = 2.0 * vd / d2;
+                vx[i] -= f * dx;
+                vy[i] -= f * dy;
+                vz[i] -= f * dz;
+            }
+        }
     }
     accel_total(n, x, y, z, m, p, ax, ay, az, pot);
     for (int64_t i = 0; i < n; ++i) {

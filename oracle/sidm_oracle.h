@@ -66,6 +66,26 @@ void orc_host_nfw(int64_t n, const double *x, const double *y, const double *z,
                   double G, double rho_s, double r_s, const double c[3],
                   double *ax, double *ay, double *az, double *pot);
 
+struct orc_params_s;   /* the step parameters, defined below */
+
+/* Hernquist bulge (Sec. 4.1, Eq. hernquist_potential): Phi = -G M / (r + a). */
+void orc_host_hernquist(int64_t n, const double *x, const double *y, const double *z,
+                        double G, double M, double a, const double c[3],
+                        double *ax, double *ay, double *az, double *pot);
+
+/* Miyamoto-Nagai disc in the z = 0 plane of centre c (Sec. 4.1, Eq. disk_potential):
+ * Phi = -G M / sqrt(R^2 + (a + sqrt(z^2 + b^2))^2). */
+void orc_host_disk(int64_t n, const double *x, const double *y, const double *z,
+                   double G, double M, double a, double b, const double c[3],
+                   double *ax, double *ay, double *az, double *pot);
+
+/* The host field of a parameter set: nothing (host_kind 0), the NFW halo (1),
+ * or the Milky-Way host of Sec. 4.1 (2: NFW + Hernquist + four discs).
+ * Writes (not adds) a and the potential. */
+void orc_host_field(int64_t n, const double *x, const double *y, const double *z,
+                    const struct orc_params_s *p, double *ax, double *ay, double *az,
+                    double *pot);
+
 /* ---- kernel size from the N_ngb nearest neighbours (paper Sec. 2) ---- */
 
 /* Brute force: for each queried i, order j != i by (d2_ij, id_j) with
@@ -142,13 +162,16 @@ void orc_central_density(int64_t n, const double *x, const double *y, const doub
 
 /* ---- one kick-drift-kick step with SIDM at the synchronised point ---- */
 
-typedef struct {
+typedef struct orc_params_s {
     double G, eps, sigma_m, dt;
     int32_t k;
     uint64_t seed;
     int32_t host_kind;          /* 0 none, 1 NFW                             */
     double host_rho_s, host_r_s, host_c[3];
     double sigma_w;             /* velocity scale of sigma(v); 0: constant   */
+    double host_hern_M, host_hern_a;      /* host_kind 2: Hernquist bulge */
+    double host_disk[4][3];     /* host_kind 2: Miyamoto-Nagai discs (M, a, b) */
+    double boundary_r, boundary_c[3];     /* reflecting sphere; r = 0: none */
 } orc_params;
 
 /* Full-N step for one halo (exact searches: orc_knn_grid, orc_find_events_sweep).  On entry a/pot hold the acceleration

@@ -47,7 +47,10 @@ class SidmHalo(C.Structure):
                 ("eps", C.c_double), ("sigma_m", C.c_double), ("dt", C.c_double),
                 ("k", C.c_int32), ("host_kind", C.c_int32), ("seed", C.c_uint64),
                 ("host_rho_s", C.c_double), ("host_r_s", C.c_double),
-                ("host_center", C.c_double * 3), ("sigma_w", C.c_double)]
+                ("host_center", C.c_double * 3), ("sigma_w", C.c_double),
+                ("host_hern_M", C.c_double), ("host_hern_a", C.c_double),
+                ("host_disk", (C.c_double * 3) * 4), ("boundary_r", C.c_double),
+                ("boundary_center", C.c_double * 3)]
 
 
 class SidmState(C.Structure):
@@ -156,13 +159,23 @@ def make_halos(halos):
         arr[i].k = int(h.get("k", 0))
         arr[i].seed = int(h.get("seed", 0))
         if host is not None:
-            arr[i].host_kind = 1
+            arr[i].host_kind = 2 if ("hern" in host or "disks" in host) else 1
             arr[i].host_rho_s = float(host["rho_s"])
             arr[i].host_r_s = float(host["r_s"])
             for c in range(3):
                 arr[i].host_center[c] = float(host["center"][c])
+            if "hern" in host:
+                arr[i].host_hern_M, arr[i].host_hern_a = (float(v) for v in host["hern"])
+            for d, disk in enumerate(host.get("disks", ())):
+                for c in range(3):
+                    arr[i].host_disk[d][c] = float(disk[c])
         else:
             arr[i].host_kind = int(h.get("host_kind", 0))
+        bnd = h.get("boundary")
+        if bnd is not None:
+            arr[i].boundary_r = float(bnd["r"])
+            for c in range(3):
+                arr[i].boundary_center[c] = float(bnd.get("center", (0.0, 0.0, 0.0))[c])
     return arr
 
 

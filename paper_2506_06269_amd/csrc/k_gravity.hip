@@ -20,6 +20,7 @@
 // partial row per i; a finalize pass adds the rows of an i in a fixed order,
 // scales by G, adds the host, optionally applies the closing half kick, and
 // scatters to the caller's (unsorted) arrays.
+#include "sidm_host.hpp"
 #include "sidm_plan.hpp"
 
 namespace sidm {
@@ -384,30 +385,6 @@ __global__ __launch_bounds__(kGravThreads) void k_grav_fp64(
 }
 
 // ---------------------------------------------------------------- host + finalize
-// NFW host (Sec. 4.1, Eq. nfw_potential): Phi = -K ln(1 + s)/r with s = r/r_s,
-// K = 4 pi G rho_s r_s^3; the force follows from the enclosed mass,
-// a = -K [ln(1+s) - s/(1+s)] (x - c) / r^3 (series in s below 1e-4).
-__device__ inline void host_nfw(const HaloDev& H, double px, double py, double pz,
-                                double& ax, double& ay, double& az, double& phi)
-{
-    const double dx = px - H.host_c[0], dy = py - H.host_c[1], dz = pz - H.host_c[2];
-    const double r2 = dx * dx + dy * dy + dz * dz;
-    if (r2 == 0.0) {
-        ax = ay = az = 0.0;
-        phi = -H.host_K / H.host_r_s;
-        return;
-    }
-    const double r = sqrt(r2);
-    const double s = r / H.host_r_s;
-    const double l1p = log1p(s);
-    double mu;
-    if (s < 1e-4) mu = s * s * (0.5 - s * (2.0 / 3.0 - s * (0.75 - 0.8 * s)));
-    else mu = l1p - s / (1.0 + s);
-    const double f = -H.host_K * mu / (r2 * r);
-    ax = f * dx; ay = f * dy; az = f * dz;
-    phi = -H.host_K * l1p / r;
-}
-
 // Sums the partial rows of each i in slot order, scales by G, adds the host,
 // optionally kicks v by a * dt/2 (and refreshes the sorted copy of v that the
 // scattering pass reads), and writes to the caller's particle order.
@@ -433,9 +410,9 @@ __global__ __launch_bounds__(kStreamBlock) void k_grav_finalize(
         sx += q.x; sy += q.y; sz += q.z; sp += q.w;
     }
     double gx = H.G * sx, gy = H.G * sy, gz = H.G * sz, gp = -H.G * sp;
-    if (H.host_kind == 1) {
+    if (H.host_kind != 0) {
         double hx, hy, hz, hp;
-        host_nfw(H, x[o], y[o], z[o], hx, hy, hz, hp);
+        host_field(H, x[o], y[o], z[o], hx, hy, hz, hp);
         gx += hx; gy += hy; gz += hz; gp += hp;
     }
     ax[o] = gx; ay[o] = gy; az[o] = gz; pot[o] = gp;

@@ -1,7 +1,7 @@
 // k_stream.hip -- streaming FP64 passes of the leapfrog and the energy and
 // momentum reductions (kick-drift-kick with a fixed step; the paper's energy
 // error is measured relative to the absolute initial energy, App. B).
-#include "sidm_internal.hpp"
+#include "sidm_host.hpp"
 
 namespace sidm {
 
@@ -21,22 +21,22 @@ __global__ __launch_bounds__(kStreamBlock) void k_kick_drift(
     const double ux = vx[i] + ax[i] * hdt;
     const double uy = vy[i] + ay[i] * hdt;
     const double uz = vz[i] + az[i] * hdt;
-    vx[i] = ux; vy[i] = uy; vz[i] = uz;
-    x[i] += ux * H.dt;
-    y[i] += uy * H.dt;
-    z[i] += uz * H.dt;
-}
-
-__device__ inline void host_pot_only(const HaloDev& H, double px, double py, double pz,
-                                     double& phi)
-{
-    const double dx = px - H.host_c[0], dy = py - H.host_c[1], dz = pz - H.host_c[2];
-    const double r = sqrt(dx * dx + dy * dy + dz * dz);
-    if (r == 0.0) {
-        phi = -H.host_K / H.host_r_s;
-        return;
+    const double px = x[i] + ux * H.dt, py = y[i] + uy * H.dt, pz = z[i] + uz * H.dt;
+    x[i] = px; y[i] = py; z[i] = pz;
+    if (H.bnd_r > 0.0) {
+        // reflecting sphere (Sec. 2): outward motion beyond the radius is
+        // turned inward, v -> v - 2 (v.d) d / |d|^2 (|v| kept)
+#pragma clang fp contract(off)
+        const double dx = px - H.bnd_c[0], dy = py - H.bnd_c[1], dz = pz - H.bnd_c[2];
+        const double d2 = (dx * dx + dy * dy) + dz * dz;
+        const double vd = (ux * dx + uy * dy) + uz * dz;
+        if (d2 > H.bnd_r * H.bnd_r && vd > 0.0) {
+            const double f = 2.0 * vd / d2;
+            vx[i] = ux - f * dx; vy[i] = uy - f * dy; vz[i] = uz - f * dz;
+            return;
+        }
     }
-    phi = -H.host_K * log1p(r / H.host_r_s) / r;
+    vx[i] = ux; vy[i] = uy; vz[i] = uz;
 }
 
 // Per-block partial sums of K, W, Eext, px, py, pz and a non-finite flag.
@@ -56,7 +56,7 @@ __global__ __launch_bounds__(kStreamBlock) void k_diag_block(
         const double mi = m[i];
         const double ux = vx[i], uy = vy[i], uz = vz[i];
         double pe = 0.0;
-        if (H.host_kind == 1) host_pot_only(H, x[i], y[i], z[i], pe);
+        if (H.host_kind != 0) pe = host_potential(H, x[i], y[i], z[i]);
         v[0] = 0.5 * mi * ((ux * ux + uy * uy) + uz * uz);
         v[1] = 0.5 * mi * (pot[i] - pe);
         v[2] = mi * pe;
@@ -153,7 +153,7 @@ __global__ __launch_bounds__(kStreamBlock) void k_center_block(
     if (t < B.count) {
         const int64_t p = B.start + t;
         double pe = 0.0;
-        if (H.host_kind == 1) host_pot_only(H, x[p], y[p], z[p], pe);
+        if (H.host_kind != 0) pe = host_potential(H, x[p], y[p], z[p]);
         const double ps = pot[p] - pe;
         if (ps == ps) { v = ps; i = p; }
     }

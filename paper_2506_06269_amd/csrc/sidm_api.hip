@@ -158,12 +158,33 @@ sidm_status validate(sidm_ctx* c, const sidm_halo* halos, int32_t n_halos, const
                     (long long)H.n);
             return SIDM_ERR_INVALID;
         }
-        if (H.host_kind != 0 && H.host_kind != 1) {
-            set_err(c, "halo %d: host_kind must be 0 or 1", h);
+        if (H.host_kind < 0 || H.host_kind > 2) {
+            set_err(c, "halo %d: host_kind must be 0, 1 or 2", h);
             return SIDM_ERR_UNSUPPORTED;
         }
-        if (H.host_kind == 1 && (!(H.host_r_s > 0.0) || !std::isfinite(H.host_rho_s))) {
+        if (H.host_kind != 0 && (!(H.host_r_s > 0.0) || !std::isfinite(H.host_r_s) ||
+                                 !std::isfinite(H.host_rho_s))) {
             set_err(c, "halo %d: host needs r_s > 0 and finite rho_s", h);
+            return SIDM_ERR_INVALID;
+        }
+        if (H.host_kind == 2) {
+            if (!std::isfinite(H.host_hern_M) ||
+                (H.host_hern_M != 0.0 && !(H.host_hern_a > 0.0 && std::isfinite(H.host_hern_a)))) {
+                set_err(c, "halo %d: the Hernquist bulge needs a finite mass and a > 0", h);
+                return SIDM_ERR_INVALID;
+            }
+            for (int d = 0; d < 4; ++d) {
+                const double* D = H.host_disk[d];
+                if (!std::isfinite(D[0]) ||
+                    (D[0] != 0.0 && !(D[1] >= 0.0 && D[2] >= 0.0 && D[1] + D[2] > 0.0 &&
+                                      std::isfinite(D[1]) && std::isfinite(D[2])))) {
+                    set_err(c, "halo %d: disc %d needs a finite mass, a, b >= 0, a + b > 0", h, d);
+                    return SIDM_ERR_INVALID;
+                }
+            }
+        }
+        if (!(H.boundary_r >= 0.0) || !std::isfinite(H.boundary_r)) {
+            set_err(c, "halo %d: boundary_r must be finite and >= 0", h);
             return SIDM_ERR_INVALID;
         }
         ranges.push_back({H.offset, H.offset + H.n});

@@ -29,6 +29,9 @@ struct HaloDev {
     int32_t k, host_kind;
     uint64_t seed;
     double host_K, host_r_s, host_c[3];   // host_K = 4 pi G rho_s r_s^3
+    double hern_GM, hern_a;               // host_kind 2: Hernquist bulge
+    double disk_GM[4], disk_a[4], disk_b[4];   // host_kind 2: Miyamoto-Nagai discs
+    double bnd_r, bnd_c[3];               // reflecting sphere (bnd_r = 0: none)
     // search tree: level 0 are the buckets, node ranges per level (global index
     // into the box arrays)
     int64_t level_off[kMaxLevels + 1];

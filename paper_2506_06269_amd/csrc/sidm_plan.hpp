@@ -287,6 +287,17 @@ inline bool build_plan(Plan& P, const Scratch& w, const sidm_halo* halos, int32_
         H.host_r_s = S.host_r_s > 0 ? S.host_r_s : 1.0;
         H.host_K = 4.0 * M_PI * S.G * S.host_rho_s * H.host_r_s * H.host_r_s * H.host_r_s;
         for (int c = 0; c < 3; ++c) H.host_c[c] = S.host_center[c];
+        if (S.host_kind == 2) {
+            H.hern_GM = S.G * S.host_hern_M;
+            H.hern_a = S.host_hern_a;
+            for (int d = 0; d < 4; ++d) {
+                H.disk_GM[d] = S.G * S.host_disk[d][0];
+                H.disk_a[d] = S.host_disk[d][1];
+                H.disk_b[d] = S.host_disk[d][2];
+            }
+        }
+        H.bnd_r = S.boundary_r;
+        for (int c = 0; c < 3; ++c) H.bnd_c[c] = S.boundary_center[c];
         H.sbase = sbase[h];
         H.rank = P.rank_of[h];
         // streaming blocks

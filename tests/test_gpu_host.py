@@ -1,0 +1,106 @@
+"""GPU parity of the Milky-Way host (Sec. 4.1: NFW + Hernquist bulge + four
+Miyamoto-Nagai discs) and of the reflecting sphere (Sec. 2) against the
+oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    import paper_2506_06269_amd as S
+    assert torch.cuda.is_available()
+    S.lib()
+    return S
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_gravity_in_milky_way_host(S, orc, prec):
+    """A satellite at the paper's initial position in the Milky-Way field:
+    forces and potentials (self + host) normwise against the oracle."""
+    import torch
+    n = 4096
+    s = W.place_on_mw_orbit(W.nfw_halo(n, seed=41))
+    host = W.mw_host_params()
+    halo = dict(n=n, eps=0.01, G=1.0, host=host)
+    dev = S.state_to_device(s)
+    ctx = S.sidm_create(0, n, 1)
+    S.sidm_gravity(ctx, [halo], dev, prec)
+    torch.cuda.synchronize()
+    out = S.state_to_host(dev)
+    ax, ay, az, pot, an = orc.gravity(s["x"], s["y"], s["z"], s["m"], 1.0, 0.01, want_norm=True)
+    p = orc.make_params(host=host)
+    hx, hy, hz, hp = orc.host_field(s["x"], s["y"], s["z"], p)
+    ax, ay, az, pot = ax + hx, ay + hy, az + hz, pot + hp
+    an = an + np.sqrt(hx ** 2 + hy ** 2 + hz ** 2)
+    ea = np.sqrt((out["ax"] - ax) ** 2 + (out["ay"] - ay) ** 2 + (out["az"] - az) ** 2) / an
+    ep = np.abs(out["pot"] - pot) / np.abs(pot)
+    tol = 1e-12 if prec == 0 else 1e-5
+    print(f"prec {prec}: max e_a {ea.max():.3e} e_phi {ep.max():.3e}")
+    assert ea.max() < tol and ep.max() < tol
+    # the host dominates the force on the satellite's centre of mass
+    assert np.linalg.norm([np.mean(hx), np.mean(hy), np.mean(hz)]) > 0.1
+
+
+def test_step_with_host_and_reflecting_sphere(S, orc):
+    """FP64 steps of a halo in the Milky-Way field whose outer particles cross
+    a reflecting sphere of radius 3 about its centre: step-wise parity with
+    the oracle (positions, velocities 1e-12; identical events)."""
+    import torch
+    n = 3000
+    s = W.nfw_halo(n, seed=42)
+    centre = (58.16 * W.KPC, 40.12 * W.KPC, 101.41 * W.KPC)
+    s = W.place_on_mw_orbit(s)
+    host = W.mw_host_params()
+    bnd = dict(r=3.0, center=centre)
+    halo = dict(n=n, eps=0.01, k=32, sigma_m=20.0, dt=2e-3, seed=3, host=host, boundary=bnd)
+    p = orc.make_params(eps=0.01, sigma_m=20.0, dt=2e-3, k=32, seed=3, host=host, boundary=bnd)
+    dev = S.state_to_device(s)
+    ctx = S.sidm_create(0, n, 1)
+    S.sidm_gravity(ctx, [halo], dev, 0)
+    diag = S.diag_buffer(1)
+    torch.cuda.synchronize()
+    r = np.sqrt((s["x"] - centre[0]) ** 2 + (s["y"] - centre[1]) ** 2 + (s["z"] - centre[2]) ** 2)
+    assert np.count_nonzero(r > 3.0) > 50
+    reflected = 0
+    for step in range(3):
+        ref = {k: v.copy() for k, v in S.state_to_host(dev).items()}
+        before = {k: v.copy() for k, v in ref.items()}
+        ev = orc.kdk_step(ref, p, step)
+        S.sidm_kdk_step(ctx, [halo], dev, step, 0, diag=diag)
+        torch.cuda.synchronize()
+        out = S.state_to_host(dev)
+        d = S.read_diag(diag)[0]
+        assert d["n_events"] == ev.size
+        for c in ("x", "y", "z", "vx", "vy", "vz"):
+            assert np.max(np.abs(out[c] - ref[c])) <= 1e-12 * np.max(np.abs(ref[c])), (step, c)
+        # outward radial velocities beyond the sphere were turned inward
+        dx = out["x"] - centre[0]
+        dy = out["y"] - centre[1]
+        dz = out["z"] - centre[2]
+        vr_before = ((before["vx"] * (before["x"] - centre[0]) + before["vy"] *
+                      (before["y"] - centre[1]) + before["vz"] * (before["z"] - centre[2])))
+        reflected += int(np.count_nonzero((dx * dx + dy * dy + dz * dz > 9.0) & (vr_before > 0)))
+        # external energy of the diagnostics: sum m Phi_host
+        _, _, _, hp = orc.host_field(out["x"], out["y"], out["z"], p)
+        assert d["Eext"] == pytest.approx(float(np.sum(out["m"] * hp)), rel=1e-12)
+    assert reflected > 0
+
+
+def test_host_arguments_rejected(S):
+    s = W.nfw_halo(256, seed=43)
+    dev = S.state_to_device(s)
+    ctx = S.sidm_create(0, 256, 1)
+    bad_hosts = [dict(W.mw_host_params(), hern=(10.0, 0.0)),
+                 dict(W.mw_host_params(), disks=[(5.0, 0.0, 0.0)]),
+                 dict(W.mw_host_params(), r_s=0.0)]
+    for h in bad_hosts:
+        with pytest.raises(S.SidmError):
+            S.sidm_gravity(ctx, [dict(n=256, eps=0.01, host=h)], dev, 0)
+    with pytest.raises(S.SidmError):
+        S.sidm_kdk_step(ctx, [dict(n=256, eps=0.01, k=8, dt=1e-3, boundary=dict(r=-1.0))], dev,
+                        0, 0)

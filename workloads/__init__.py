@@ -258,6 +258,40 @@ def place_on_orbit(s, R=ORBIT_R):
     return s
 
 
+# ----------------------------------------------------------------- Milky-Way host
+# Code units of the satellite (Sec. 2): length r_s = 1.28 kpc, density
+# rho_0 = 4.42e7 Msun/kpc^3, G = 1, hence mass rho_0 r_s^3 and velocity
+# sqrt(G rho_0 r_s^2) with G = 4.30091e-6 kpc (km/s)^2 / Msun.
+KPC = 1.0 / 1.28
+MSUN = 1.0 / (4.42e7 * 1.28 ** 3)
+KMS = 1.0 / math.sqrt(4.30091e-6 * 4.42e7 * 1.28 ** 2)
+
+
+def mw_host_params():
+    """The Milky-Way host of Sec. 4.1 in code units: NFW halo (rho_s, r_s),
+    Hernquist bulge (M, a) and four Miyamoto-Nagai discs (M, a, b): thin and
+    thick stellar, thin and thick gas."""
+    disks = [(3.52e10, 2.5, 0.3), (1.05e10, 3.02, 0.9), (1.2e9, 1.5, 0.045), (1.1e10, 7.0, 0.085)]
+    return dict(rho_s=8.54e6 * MSUN / KPC ** 3, r_s=19.6 * KPC, center=(0.0, 0.0, 0.0),
+                hern=(9.23e9 * MSUN, 1.3 * KPC),
+                disks=[(M * MSUN, a * KPC, b * KPC) for M, a, b in disks])
+
+
+def place_on_mw_orbit(s):
+    """The satellite's initial position and velocity of Sec. 4.1 relative to
+    the Milky-Way host's centre."""
+    s = dict(s)
+    for c, (x, v) in zip("xyz", zip((58.16, 40.12, 101.41), (45.94, 83.42, 53.12))):
+        s[c] = s[c] + x * KPC
+        s["v" + c] = s["v" + c] + v * KMS
+    return s
+
+
+def mw_boundary():
+    """The reflecting sphere of Sec. 2: 200 kpc about the host centre."""
+    return dict(r=200.0 * KPC, center=(0.0, 0.0, 0.0))
+
+
 # ----------------------------------------------------------------- configs
 NFW_MASS_10 = float(nfw_mass(10.0))
 
