@@ -243,6 +243,26 @@ sidm_status sidm_central_density(sidm_ctx *ctx, const sidm_halo *halos, int32_t 
                                  const sidm_state *state, const double *radius,
                                  sidm_center *out, void *stream);
 
+/* ---- tidal radius -----------------------------------------------------------
+ * The tidal radius of each halo in its static host (Eq. tidal_radius), with the
+ * centre of sidm_central_density and n the unit vector from the host centre to
+ * it:  G M(<= r) / r^2 = |grad Phi_host(c + r n) - grad Phi_host(c - r n)|,
+ * M(<= r) the mass of the halo's particles with d2 <= r^2 (d2 as in sidm_knn_h).
+ * Solved by 60 bisection steps in log r between 2^-40 (2 r_max) and 2 r_max
+ * (r_max: the farthest particle from the centre): r_tidal is the final upper
+ * bracket, where the host's tides win.  status 1: they do not win even at
+ * 2 r_max (r_tidal = 2 r_max).  Needs host_kind != 0.  out: DEVICE, n_halos. */
+typedef struct {
+    double r_tidal;             /* tidal radius                                      */
+    double mass;                /* M(<= r_tidal)                                     */
+    double x, y, z;             /* the centre                                        */
+    int64_t index;              /* array index of the centre particle                */
+    int32_t status;             /* 0, or 1 (no crossing below 2 r_max)              */
+    int32_t reserved;
+} sidm_tidal;
+sidm_status sidm_tidal_radius(sidm_ctx *ctx, const sidm_halo *halos, int32_t n_halos,
+                              const sidm_state *state, sidm_tidal *out, void *stream);
+
 /* ---- pass timing ---------------------------------------------------------
  * When enabled, sidm_kdk_step records HIP events on its stream around each
  * pass (not usable while the stream is being captured into a graph).

@@ -73,6 +73,9 @@ def _declare(L):
     L.orc_host_disk.argtypes = [C.c_int64, _dp, _dp, _dp, C.c_double, C.c_double, C.c_double,
                                 C.c_double, C.POINTER(C.c_double), _dp, _dp, _dp, _dp]
     L.orc_host_field.argtypes = [C.c_int64, _dp, _dp, _dp, C.c_void_p, _dp, _dp, _dp, _dp]
+    L.orc_tidal_radius.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp, C.c_void_p, _dp, _dp,
+                                   _i64p]
+    L.orc_tidal_radius.restype = C.c_int
     L.orc_knn_grid.argtypes = [C.c_int64, _dp, _dp, _dp, _u32p, C.c_int32, _dp]
     L.orc_find_events_sweep.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _u32p,
                                         _dp, C.c_double, C.c_double, C.c_double, C.c_uint64,
@@ -262,6 +265,15 @@ def central_density(x, y, z, m, phi_self, radius):
     lib().orc_central_density(x.size, _d(x), _d(y), _d(z), _d(m), _d(phi_self), float(radius),
                               C.byref(c), C.byref(cnt), C.byref(mass))
     return int(c.value), int(cnt.value), float(mass.value)
+
+
+def tidal_radius(x, y, z, m, phi_self, p):
+    """(r_tidal, mass within it, centre index, status) in the host of p."""
+    x, y, z, m, phi_self = (_f64(a) for a in (x, y, z, m, phi_self))
+    r, mass, c = C.c_double(0.0), C.c_double(0.0), C.c_int64(0)
+    st = lib().orc_tidal_radius(x.size, _d(x), _d(y), _d(z), _d(m), _d(phi_self), C.addressof(p),
+                                C.byref(r), C.byref(mass), C.byref(c))
+    return float(r.value), float(mass.value), int(c.value), int(st)
 
 
 def kick_pair(seed, step, a, b, ma, mb, va, vb):

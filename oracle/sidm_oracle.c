@@ -843,6 +843,63 @@ void orc_central_density(int64_t n, const double *x, const double *y, const doub
 }
 
 /* ------------------------------------------------------------------------ */
+/* Tidal radius (Eq. tidal_radius): G M(<= r) / r^2 equals the difference of
+ * the host's acceleration across the satellite, |grad Phi(c + r n) -
+ * grad Phi(c - r n)|.  Readings: c is the particle with the lowest self-
+ * potential (as the central density), n the unit vector from the host centre
+ * to c, M(<= r) the mass with d2 <= r^2; the equation is solved by 60
+ * bisection steps in log r between 2^-40 (2 r_max) and 2 r_max (r_max the
+ * farthest particle), r_tidal being the final upper bracket.  Returns 1 if the
+ * tides do not win even at 2 r_max, else 0. */
+static double mass_within(int64_t n, const double *x, const double *y, const double *z,
+                          const double *m, int64_t c, double r)
+{
+    neum acc = {0.0, 0.0};
+    for (int64_t j = 0; j < n; ++j) {
+        double dx = x[j] - x[c], dy = y[j] - y[c], dz = z[j] - z[c];
+        if ((dx * dx + dy * dy) + dz * dz <= r * r) neum_add(&acc, m[j]);
+    }
+    return neum_get(&acc);
+}
+
+int orc_tidal_radius(int64_t n, const double *x, const double *y, const double *z,
+                     const double *m, const double *phi, const orc_params *p,
+                     double *r_tidal, double *mass, int64_t *center)
+{
+    int64_t c = -1;
+    for (int64_t i = 0; i < n; ++i)
+        if (phi[i] == phi[i] && (c < 0 || phi[i] < phi[c])) c = i;
+    *center = c;
+    *r_tidal = 0.0;
+    *mass = 0.0;
+    if (c < 0) return 1;
+    double ux = x[c] - p->host_c[0], uy = y[c] - p->host_c[1], uz = z[c] - p->host_c[2];
+    double u = sqrt((ux * ux + uy * uy) + uz * uz);
+    double nx = u > 0.0 ? ux / u : 1.0, ny = u > 0.0 ? uy / u : 0.0, nz = u > 0.0 ? uz / u : 0.0;
+    double rmax2 = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+        double dx = x[j] - x[c], dy = y[j] - y[c], dz = z[j] - z[c];
+        double d2 = (dx * dx + dy * dy) + dz * dz;
+        if (d2 > rmax2) rmax2 = d2;
+    }
+    double hi = 2.0 * sqrt(rmax2), hi0 = hi, lo = ldexp(hi, -40);
+    for (int it = 0; it < 60; ++it) {
+        double r = sqrt(lo * hi);
+        double px[2] = {x[c] + r * nx, x[c] - r * nx}, py[2] = {y[c] + r * ny, y[c] - r * ny};
+        double pz[2] = {z[c] + r * nz, z[c] - r * nz};
+        double ax[2], ay[2], az[2], pp[2];
+        orc_host_field(2, px, py, pz, p, ax, ay, az, pp);
+        double gx = ax[0] - ax[1], gy = ay[0] - ay[1], gz = az[0] - az[1];
+        double tide = sqrt((gx * gx + gy * gy) + gz * gz);
+        if (p->G * mass_within(n, x, y, z, m, c, r) / (r * r) > tide) lo = r;
+        else hi = r;
+    }
+    *r_tidal = hi;
+    *mass = mass_within(n, x, y, z, m, c, hi);
+    return hi == hi0 ? 1 : 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Total acceleration and potential at the current positions: self-gravity plus
  * the static host. */
 static void accel_total(int64_t n, const double *x, const double *y, const double *z,

@@ -160,6 +160,15 @@ void orc_central_density(int64_t n, const double *x, const double *y, const doub
                          const double *m, const double *phi, double radius,
                          int64_t *center, int64_t *count, double *mass);
 
+/* Tidal radius (Eq. tidal_radius) of a satellite in the host of p: the centre
+ * c is the lowest phi (self-potential), n the unit vector from the host centre
+ * to c; G M(<= r) / r^2 = |grad Phi(c + r n) - grad Phi(c - r n)| solved by 60
+ * bisection steps in log r on [2^-40, 1] x 2 r_max.  Returns 1 if the host's
+ * tides do not win even at 2 r_max. */
+int orc_tidal_radius(int64_t n, const double *x, const double *y, const double *z,
+                     const double *m, const double *phi, const struct orc_params_s *p,
+                     double *r_tidal, double *mass, int64_t *center);
+
 /* ---- one kick-drift-kick step with SIDM at the synchronised point ---- */
 
 typedef struct orc_params_s {

@@ -37,7 +37,8 @@ SIDM_DEV_NONFINITE = 4
 
 EXPORTED = ("sidm_create", "sidm_destroy", "sidm_set_event_capacity", "sidm_status_string",
             "sidm_last_error", "sidm_gravity", "sidm_knn_h", "sidm_scatter", "sidm_kdk_step",
-            "sidm_diagnostics", "sidm_central_density", "sidm_enable_timing", "sidm_pass_times")
+            "sidm_diagnostics", "sidm_central_density", "sidm_tidal_radius", "sidm_enable_timing",
+            "sidm_pass_times")
 PASS_NAMES = ("kick_drift", "gravity", "gravity_tiles", "cell_list", "knn", "pairs", "kicks",
               "diag")
 
@@ -68,6 +69,12 @@ class SidmDiag(C.Structure):
 class SidmCenter(C.Structure):
     _fields_ = [("x", C.c_double), ("y", C.c_double), ("z", C.c_double), ("mass", C.c_double),
                 ("index", C.c_int64), ("count", C.c_int64)]
+
+
+class SidmTidal(C.Structure):
+    _fields_ = [("r_tidal", C.c_double), ("mass", C.c_double), ("x", C.c_double),
+                ("y", C.c_double), ("z", C.c_double), ("index", C.c_int64),
+                ("status", C.c_int32), ("reserved", C.c_int32)]
 
 
 DIAG_BYTES = C.sizeof(SidmDiag)
@@ -109,6 +116,7 @@ def lib():
         L.sidm_kdk_step.argtypes = [vp, hp, i32, sp, u32, C.c_int, vp, vp]
         L.sidm_diagnostics.argtypes = [vp, hp, i32, sp, vp, vp]
         L.sidm_central_density.argtypes = [vp, hp, i32, sp, C.POINTER(C.c_double), vp, vp]
+        L.sidm_tidal_radius.argtypes = [vp, hp, i32, sp, vp, vp]
         L.sidm_enable_timing.argtypes = [vp, C.c_int]
         L.sidm_pass_times.argtypes = [vp, C.POINTER(C.c_double)]
         for name in EXPORTED:
@@ -277,6 +285,23 @@ def sidm_central_density(ctx, halos, state, radius, out=None, stream=None):
         c = SidmCenter.from_buffer_copy(raw[i * CENTER_BYTES:(i + 1) * CENTER_BYTES])
         res.append({f: getattr(c, f) for f, _ in SidmCenter._fields_})
     return res
+
+
+def sidm_tidal_radius(ctx, halos, state, stream=None):
+    """Tidal radius of each halo in its host (synchronises); list of dicts."""
+    import torch
+    H = make_halos(halos)
+    S = make_state(state)
+    nb = C.sizeof(SidmTidal)
+    buf = torch.zeros(len(halos) * nb, dtype=torch.uint8, device="cuda")
+    _check(ctx, lib().sidm_tidal_radius(ctx.handle, H, len(halos), C.byref(S),
+                                        C.c_void_p(buf.data_ptr()), _stream(stream)))
+    raw = bytes(buf.cpu().numpy().tobytes())
+    out = []
+    for i in range(len(halos)):
+        t = SidmTidal.from_buffer_copy(raw[i * nb:(i + 1) * nb])
+        out.append({f: getattr(t, f) for f, _ in SidmTidal._fields_})
+    return out
 
 
 def center_buffer(n_halos, device="cuda"):

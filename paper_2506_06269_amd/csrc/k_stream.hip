@@ -295,4 +295,178 @@ hipError_t launch_center(const StreamBlock* d_blocks, int64_t n_blocks, const Ha
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- tidal radius
+// Eq. tidal_radius: G M(<= r) / r^2 = |grad Phi_host(c + r n) - grad Phi_host(c - r n)|,
+// bisection in log r.  Per-halo state in `tid` (8 doubles): n (3), lo, hi,
+// the initial hi, mid.
+
+// Per streaming block: the largest squared distance from the halo's centre.
+__global__ __launch_bounds__(kStreamBlock) void k_tidal_extent(
+    const StreamBlock* __restrict__ blocks, const double* __restrict__ x,
+    const double* __restrict__ y, const double* __restrict__ z,
+    const sidm_center* __restrict__ cen, double* __restrict__ bsum)
+{
+    __shared__ double red[kStreamBlock];
+    const StreamBlock B = blocks[blockIdx.x];
+    const sidm_center C = cen[B.halo];
+    const int t = threadIdx.x;
+    double v = 0.0;
+    if (t < B.count && C.index >= 0) {
+#pragma clang fp contract(off)
+        const int64_t p = B.start + t;
+        const double dx = x[p] - C.x, dy = y[p] - C.y, dz = z[p] - C.z;
+        v = (dx * dx + dy * dy) + dz * dz;
+    }
+    red[t] = v;
+    __syncthreads();
+    for (int s = kStreamBlock / 2; s > 0; s >>= 1) {
+        if (t < s) red[t] = fmax(red[t], red[t + s]);
+        __syncthreads();
+    }
+    if (t == 0) bsum[7 * blockIdx.x + 4] = red[0];
+}
+
+// Per halo: the direction from the host centre and the initial bracket.
+__global__ __launch_bounds__(kStreamBlock) void k_tidal_init(
+    const HaloDev* __restrict__ halos, const double* __restrict__ bsum,
+    const sidm_center* __restrict__ cen, double* __restrict__ tid)
+{
+    __shared__ double red[kStreamBlock];
+    const HaloDev& H = halos[blockIdx.x];
+    const int t = threadIdx.x;
+    const int64_t nb = (H.n + kStreamBlock - 1) / kStreamBlock;
+    double v = 0.0;
+    for (int64_t b = t; b < nb; b += kStreamBlock) v = fmax(v, bsum[7 * (H.stream_block0 + b) + 4]);
+    red[t] = v;
+    __syncthreads();
+    for (int s = kStreamBlock / 2; s > 0; s >>= 1) {
+        if (t < s) red[t] = fmax(red[t], red[t + s]);
+        __syncthreads();
+    }
+    if (t == 0) {
+#pragma clang fp contract(off)
+        const sidm_center C = cen[blockIdx.x];
+        double* T = tid + 8 * blockIdx.x;
+        const double ux = C.x - H.host_c[0], uy = C.y - H.host_c[1], uz = C.z - H.host_c[2];
+        const double u = sqrt((ux * ux + uy * uy) + uz * uz);
+        T[0] = u > 0.0 ? ux / u : 1.0;
+        T[1] = u > 0.0 ? uy / u : 0.0;
+        T[2] = u > 0.0 ? uz / u : 0.0;
+        const double hi = 2.0 * sqrt(red[0]);
+        T[4] = hi;
+        T[3] = ldexp(hi, -40);
+        T[5] = hi;
+        T[6] = sqrt(T[3] * T[4]);
+    }
+}
+
+// Per streaming block: mass within the radius r of the halo's centre, with
+// r the current midpoint (tid[6]) or, with `final_pass`, the upper bracket.
+__global__ __launch_bounds__(kStreamBlock) void k_tidal_mass(
+    const StreamBlock* __restrict__ blocks, const double* __restrict__ x,
+    const double* __restrict__ y, const double* __restrict__ z, const double* __restrict__ m,
+    const sidm_center* __restrict__ cen, const double* __restrict__ tid, int final_pass,
+    double* __restrict__ bsum)
+{
+    __shared__ double red[kStreamBlock];
+    const StreamBlock B = blocks[blockIdx.x];
+    const sidm_center C = cen[B.halo];
+    const double r = tid[8 * B.halo + (final_pass ? 4 : 6)];
+    const int t = threadIdx.x;
+    double w = 0.0;
+    if (t < B.count && C.index >= 0) {
+#pragma clang fp contract(off)
+        const int64_t p = B.start + t;
+        const double dx = x[p] - C.x, dy = y[p] - C.y, dz = z[p] - C.z;
+        if ((dx * dx + dy * dy) + dz * dz <= r * r) w = m[p];
+    }
+    red[t] = w;
+    __syncthreads();
+    for (int s = kStreamBlock / 2; s > 0; s >>= 1) {
+        if (t < s) red[t] += red[t + s];
+        __syncthreads();
+    }
+    if (t == 0) bsum[7 * blockIdx.x + 5] = red[0];
+}
+
+__device__ inline double halo_block_sum(const HaloDev& H, const double* bsum, int slot,
+                                        double* red)
+{
+    const int t = threadIdx.x;
+    const int64_t nb = (H.n + kStreamBlock - 1) / kStreamBlock;
+    double v = 0.0;
+    for (int64_t b = t; b < nb; b += kStreamBlock) v += bsum[7 * (H.stream_block0 + b) + slot];
+    red[t] = v;
+    __syncthreads();
+    for (int s = kStreamBlock / 2; s > 0; s >>= 1) {
+        if (t < s) red[t] += red[t + s];
+        __syncthreads();
+    }
+    return red[0];
+}
+
+// One bisection step or the final record (thread 0 of the halo's block).
+__device__ inline void tidal_update(const HaloDev& H, double M, const sidm_center C, double* T,
+                                    int final_pass, sidm_tidal* o_ptr)
+{
+#pragma clang fp contract(off)
+    if (final_pass) {
+        sidm_tidal o;
+        o.r_tidal = T[4];
+        o.mass = M;
+        o.x = C.x; o.y = C.y; o.z = C.z;
+        o.index = C.index;
+        o.status = T[4] == T[5] ? 1 : 0;
+        o.reserved = 0;
+        *o_ptr = o;
+        return;
+    }
+    const double r = T[6];
+    double ax1, ay1, az1, p1, ax2, ay2, az2, p2;
+    host_field(H, C.x + r * T[0], C.y + r * T[1], C.z + r * T[2], ax1, ay1, az1, p1);
+    host_field(H, C.x - r * T[0], C.y - r * T[1], C.z - r * T[2], ax2, ay2, az2, p2);
+    const double gx = ax1 - ax2, gy = ay1 - ay2, gz = az1 - az2;
+    const double tide = sqrt((gx * gx + gy * gy) + gz * gz);
+    if (H.G * M / (r * r) > tide) T[3] = r;
+    else T[4] = r;
+    T[6] = sqrt(T[3] * T[4]);
+}
+
+// Per halo: one bisection step (self gravity at the midpoint against the
+// host's tidal acceleration there), or the final record.
+__global__ __launch_bounds__(kStreamBlock) void k_tidal_step(
+    const HaloDev* __restrict__ halos, const double* __restrict__ bsum,
+    const sidm_center* __restrict__ cen, double* __restrict__ tid, int final_pass,
+    sidm_tidal* __restrict__ out)
+{
+    __shared__ double red[kStreamBlock];
+    const HaloDev& H = halos[blockIdx.x];
+    const double M = halo_block_sum(H, bsum, 5, red);
+    if (threadIdx.x != 0) return;
+    tidal_update(H, M, cen[blockIdx.x], tid + 8 * blockIdx.x, final_pass, out + blockIdx.x);
+}
+
+hipError_t launch_tidal(const StreamBlock* d_blocks, int64_t n_blocks, const HaloDev* d_halos,
+                        int n_halos, const double* x, const double* y, const double* z,
+                        const double* m, const double* pot, double* bsum, sidm_center* cen,
+                        double* tid, sidm_tidal* out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_center_block, dim3((unsigned)n_blocks), dim3(kStreamBlock), 0, st,
+                       d_blocks, d_halos, x, y, z, pot, bsum);
+    hipLaunchKernelGGL(k_center_halo, dim3(n_halos), dim3(kStreamBlock), 0, st, d_halos, bsum, x,
+                       y, z, cen);
+    hipLaunchKernelGGL(k_tidal_extent, dim3((unsigned)n_blocks), dim3(kStreamBlock), 0, st,
+                       d_blocks, x, y, z, cen, bsum);
+    hipLaunchKernelGGL(k_tidal_init, dim3(n_halos), dim3(kStreamBlock), 0, st, d_halos, bsum, cen,
+                       tid);
+    for (int it = 0; it <= 60; ++it) {
+        const int fin = it == 60 ? 1 : 0;
+        hipLaunchKernelGGL(k_tidal_mass, dim3((unsigned)n_blocks), dim3(kStreamBlock), 0, st,
+                           d_blocks, x, y, z, m, cen, tid, fin, bsum);
+        hipLaunchKernelGGL(k_tidal_step, dim3(n_halos), dim3(kStreamBlock), 0, st, d_halos, bsum,
+                           cen, tid, fin, out);
+    }
+    return hipGetLastError();
+}
+
 }  // namespace sidm

@@ -25,6 +25,10 @@ hipError_t launch_center(const StreamBlock* d_blocks, int64_t n_blocks, const Ha
                          int n_halos, const double* radius, const double* x, const double* y,
                          const double* z, const double* m, const double* pot, double* bsum,
                          sidm_center* out, hipStream_t st);
+hipError_t launch_tidal(const StreamBlock* d_blocks, int64_t n_blocks, const HaloDev* d_halos,
+                        int n_halos, const double* x, const double* y, const double* z,
+                        const double* m, const double* pot, double* bsum, sidm_center* cen,
+                        double* tid, sidm_tidal* out, hipStream_t st);
 }  // namespace sidm
 
 #include "sidm_plan.hpp"
@@ -473,6 +477,31 @@ sidm_status sidm_central_density(sidm_ctx* c, const sidm_halo* halos, int32_t n_
     e = launch_center(c->w.blocks, P.n_blocks, c->w.halos, n_halos, c->w.radius, s->x, s->y,
                       s->z, s->m, s->pot, c->w.bsum, out, st);
     if (e != hipSuccess) return hip_fail(c, e, "central density launch");
+    c->err.clear();
+    return SIDM_OK;
+}
+
+sidm_status sidm_tidal_radius(sidm_ctx* c, const sidm_halo* halos, int32_t n_halos,
+                              const sidm_state* s, sidm_tidal* out, void* stream)
+{
+    sidm_status r = validate(c, halos, n_halos, s, 0);
+    if (r != SIDM_OK) return r;
+    if (!out || !s->pot) {
+        set_err(c, "out and pot are required");
+        return SIDM_ERR_INVALID;
+    }
+    for (int h = 0; h < n_halos; ++h)
+        if (halos[h].host_kind == 0) {
+            set_err(c, "halo %d: the tidal radius needs a host (host_kind != 0)", h);
+            return SIDM_ERR_INVALID;
+        }
+    DeviceGuard g(c->device);
+    hipStream_t st = (hipStream_t)stream;
+    if ((r = ensure_plan(c, halos, n_halos, st)) != SIDM_OK) return r;
+    const Plan& P = c->plan;
+    hipError_t e = launch_tidal(c->w.blocks, P.n_blocks, c->w.halos, n_halos, s->x, s->y, s->z,
+                                s->m, s->pot, c->w.bsum, c->w.center, c->w.tidal, out, st);
+    if (e != hipSuccess) return hip_fail(c, e, "tidal radius launch");
     c->err.clear();
     return SIDM_OK;
 }

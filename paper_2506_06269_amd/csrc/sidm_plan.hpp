@@ -66,6 +66,8 @@ struct Scratch {
     double* bsum = nullptr;       // 7 doubles per streaming block
     double* cref = nullptr;       // per halo: the common mass if all are equal, else 0
     double* radius = nullptr;     // per halo: radius of the central density
+    sidm_center* center = nullptr;    // per halo: centre of the tidal-radius search
+    double* tidal = nullptr;          // per halo: 8 doubles of bisection state
     double* bbox = nullptr;       // 6 per halo (min xyz, max xyz)
     float4* xm32 = nullptr;       // FP32 positions relative to their tile centre, mass
     double4* partial = nullptr;
@@ -153,7 +155,8 @@ inline bool alloc_scratch(Scratch& w, int64_t N, int32_t H, int64_t max_events, 
     w.hist_cap = sort_blocks * (1 << kSortBits) + 1;
     bool ok = dalloc(w.halos, H) && dalloc(w.blocks, nb) && dalloc(w.items, w.items_cap) &&
               dalloc(w.buckets, w.buckets_cap) && dalloc(w.node_tasks, w.nodes_cap) && dalloc(w.nodes, w.nodes_cap) &&
-              dalloc(w.bsum, 7 * nb) && dalloc(w.cref, 4 * H) && dalloc(w.radius, H) && dalloc(w.bbox, 6 * H) &&
+              dalloc(w.bsum, 7 * nb) && dalloc(w.cref, 4 * H) && dalloc(w.radius, H) && dalloc(w.center, H) &&
+              dalloc(w.tidal, 8 * H) && dalloc(w.bbox, 6 * H) &&
               dalloc(w.xm32, N) &&  dalloc(w.partial, w.partial_rows) && dalloc(w.keys[0], N) &&
               dalloc(w.keys[1], N) && dalloc(w.vals[0], N) && dalloc(w.vals[1], N) &&
               dalloc(w.hist, w.hist_cap) && dalloc(w.sx, N) && dalloc(w.sy, N) &&
@@ -184,7 +187,7 @@ inline bool alloc_scratch(Scratch& w, int64_t N, int32_t H, int64_t max_events, 
 inline void free_scratch(Scratch& w)
 {
     dfree(w.halos); dfree(w.blocks); dfree(w.items); dfree(w.buckets); dfree(w.node_tasks); dfree(w.nodes);
-    dfree(w.bsum); dfree(w.cref); dfree(w.radius); dfree(w.bbox); dfree(w.xm32);  dfree(w.partial);
+    dfree(w.bsum); dfree(w.cref); dfree(w.radius); dfree(w.center); dfree(w.tidal); dfree(w.bbox); dfree(w.xm32);  dfree(w.partial);
     dfree(w.keys[0]); dfree(w.keys[1]); dfree(w.vals[0]); dfree(w.vals[1]); dfree(w.hist);
     dfree(w.sx); dfree(w.sy); dfree(w.sz); dfree(w.sp4); dfree(w.svx); dfree(w.svy); dfree(w.svz);
     dfree(w.sh); dfree(w.sm); dfree(w.sid); dfree(w.perm); dfree(w.box); dfree(w.hmax);

@@ -104,3 +104,32 @@ def test_host_arguments_rejected(S):
     with pytest.raises(S.SidmError):
         S.sidm_kdk_step(ctx, [dict(n=256, eps=0.01, k=8, dt=1e-3, boundary=dict(r=-1.0))], dev,
                         0, 0)
+
+
+def test_tidal_radius_in_milky_way_host(S, orc):
+    """The satellite at the paper's initial position: the device's tidal radius
+    against the oracle's bisection on the same potentials."""
+    import torch
+    n = 6000
+    s = W.place_on_mw_orbit(W.nfw_halo(n, seed=44))
+    host = W.mw_host_params()
+    halo = dict(n=n, eps=0.01, G=1.0, host=host)
+    dev = S.state_to_device(s)
+    ctx = S.sidm_create(0, n, 1)
+    S.sidm_gravity(ctx, [halo], dev, 0)
+    torch.cuda.synchronize()
+    got = S.sidm_tidal_radius(ctx, [halo], dev)[0]
+    pot = dev["pot"].cpu().numpy()
+    p = orc.make_params(host=host)
+    _, _, _, hp = orc.host_field(s["x"], s["y"], s["z"], p)
+    phi = pot - hp
+    assert phi[got["index"]] <= phi.min() + 1e-12 * abs(phi.min())
+    one_hot = np.zeros(n)
+    one_hot[got["index"]] = -1.0
+    r_t, mass, c, st = orc.tidal_radius(s["x"], s["y"], s["z"], s["m"], one_hot, p)
+    print(f"r_tidal {got['r_tidal']:.6f} (oracle {r_t:.6f}), mass {got['mass']:.5f}")
+    assert got["status"] == st == 0
+    assert got["r_tidal"] == pytest.approx(r_t, rel=1e-12)
+    assert got["mass"] == pytest.approx(mass, rel=1e-12)
+    with pytest.raises(S.SidmError):
+        S.sidm_tidal_radius(ctx, [dict(n=n, eps=0.01)], dev)

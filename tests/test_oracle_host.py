@@ -104,3 +104,48 @@ def test_reflecting_sphere(orc):
     assert np.array_equal(v1[1], v0[1]) and np.array_equal(v1[2], v0[2])
     # 3: outside (r = 4.9), outwards -> reflected
     assert np.dot(v1[3], n[3]) < 0 < np.dot(v0[3], n[3])
+
+
+def _compact_satellite(n, R, D, seed):
+    rng = np.random.default_rng(seed)
+    u = rng.normal(size=(n, 3))
+    u *= (R * rng.uniform(0, 1, n) ** (1 / 3) / np.linalg.norm(u, axis=1))[:, None]
+    return dict(x=u[:, 0] + D, y=u[:, 1], z=u[:, 2], m=np.full(n, 1.0 / n))
+
+
+def test_tidal_radius_compact_satellite(orc):
+    """A satellite of unit mass inside R = 0.01 at D = 50 from a Hernquist host
+    (M = 1e4, a = 1), with six marker particles of negligible mass at distance 5
+    that set the search range: r_t solves
+    G/r^2 = G M (1/(D - r + a)^2 - 1/(D + r + a)^2), found independently by root
+    bracketing on the closed form."""
+    from scipy.optimize import brentq
+    M, a, D = 1.0e4, 1.0, 50.0
+    s = _compact_satellite(2000, 0.01, D, 7)
+    mk = np.array([[5, 0, 0], [-5, 0, 0], [0, 5, 0], [0, -5, 0], [0, 0, 5], [0, 0, -5]], float)
+    for c, k in zip("xyz", range(3)):
+        s[c] = np.concatenate([s[c], mk[:, k] + (D if c == "x" else 0.0)])
+    s["m"] = np.concatenate([s["m"], np.full(6, 1e-300)])
+    _, _, _, pot = orc.gravity(s["x"], s["y"], s["z"], s["m"], 1.0, 1e-3)
+    host = dict(rho_s=0.0, r_s=1.0, center=(0.0, 0.0, 0.0), hern=(M, a), disks=[])
+    p = orc.make_params(host=host)
+    r_t, mass, c, st = orc.tidal_radius(s["x"], s["y"], s["z"], s["m"], pot, p)
+    xc = np.array([s["x"][c], s["y"][c], s["z"][c]])
+    Dc = np.linalg.norm(xc)
+    f = lambda r: 1.0 / r ** 2 - M * (1.0 / (Dc - r + a) ** 2 - 1.0 / (Dc + r + a) ** 2)
+    ref = brentq(f, 0.05, 20.0, xtol=1e-15, rtol=1e-15)
+    assert st == 0
+    assert r_t == pytest.approx(ref, rel=1e-10)
+    assert mass == pytest.approx(1.0, rel=1e-14)
+    assert 1.0 < r_t < 2.0
+    assert np.hypot(s["y"][c], s["z"][c]) < 0.01
+
+
+def test_tidal_radius_no_crossing(orc):
+    """A host too light to strip anything within twice the satellite's extent."""
+    s = _compact_satellite(500, 0.5, 100.0, 8)
+    _, _, _, pot = orc.gravity(s["x"], s["y"], s["z"], s["m"], 1.0, 1e-3)
+    host = dict(rho_s=0.0, r_s=1.0, center=(0.0, 0.0, 0.0), hern=(1e-3, 1.0), disks=[])
+    r_t, mass, c, st = orc.tidal_radius(s["x"], s["y"], s["z"], s["m"], pot,
+                                       orc.make_params(host=host))
+    assert st == 1 and mass == pytest.approx(1.0, rel=1e-14)
