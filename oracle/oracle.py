@@ -26,7 +26,8 @@ class OrcParams(C.Structure):
                 ("host_r_s", C.c_double), ("host_c", C.c_double * 3), ("sigma_w", C.c_double),
                 ("host_hern_M", C.c_double), ("host_hern_a", C.c_double),
                 ("host_disk", (C.c_double * 3) * 4), ("boundary_r", C.c_double),
-                ("boundary_c", C.c_double * 3)]
+                ("boundary_c", C.c_double * 3), ("eta", C.c_double), ("dt_min", C.c_double),
+                ("max_bin", C.c_int32)]
 
 
 def lib():
@@ -73,6 +74,9 @@ def _declare(L):
     L.orc_host_disk.argtypes = [C.c_int64, _dp, _dp, _dp, C.c_double, C.c_double, C.c_double,
                                 C.c_double, C.POINTER(C.c_double), _dp, _dp, _dp, _dp]
     L.orc_host_field.argtypes = [C.c_int64, _dp, _dp, _dp, C.c_void_p, _dp, _dp, _dp, _dp]
+    L.orc_bin.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, C.c_int32,
+                          C.c_double, C.c_double, C.c_double]
+    L.orc_bin.restype = C.c_int32
     L.orc_tidal_radius.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp, C.c_void_p, _dp, _dp,
                                    _i64p]
     L.orc_tidal_radius.restype = C.c_int
@@ -302,13 +306,18 @@ def diag(vx, vy, vz, m, pot, pext=None):
 
 # ---------------------------------------------------------------- step
 def make_params(G=1.0, eps=0.01, sigma_m=1.0, dt=1e-3, k=32, seed=0, host=None, sigma_w=0.0,
-                boundary=None):
+                boundary=None, steps=None):
     """host: None, an NFW dict (rho_s, r_s, center), or with "hern" = (M, a)
     and "disks" = [(M, a, b), ...] the Milky-Way host.  boundary: None or a
-    dict (r, center) for the reflecting sphere."""
+    dict (r, center) for the reflecting sphere.  steps: None (one KDK step of
+    dt) or a dict (eta, max_bin, dt_min) for a cycle of block time steps."""
     p = OrcParams()
     p.G, p.eps, p.sigma_m, p.dt, p.k, p.seed = G, eps, sigma_m, dt, k, seed
     p.sigma_w = float(sigma_w)
+    if steps is not None:
+        p.eta = float(steps["eta"])
+        p.max_bin = int(steps["max_bin"])
+        p.dt_min = float(steps.get("dt_min", 0.0))
     if boundary is not None:
         p.boundary_r = float(boundary["r"])
         p.boundary_c = (C.c_double * 3)(*[float(v) for v in boundary.get("center", (0, 0, 0))])
@@ -326,6 +335,13 @@ def make_params(G=1.0, eps=0.01, sigma_m=1.0, dt=1e-3, k=32, seed=0, host=None, 
             for c in range(3):
                 p.host_disk[d][c] = float(disk[c])
     return p
+
+
+def time_bin(p, ax, ay, az):
+    """orc_bin for each particle: the time-step bin from the accelerations."""
+    ax, ay, az = (np.asarray(v, dtype=np.float64) for v in (ax, ay, az))
+    return np.array([lib().orc_bin(p.dt, p.eta, p.eps, p.dt_min, p.max_bin, a, b, c)
+                     for a, b, c in zip(ax, ay, az)], dtype=np.int32)
 
 
 def total_accel(s, p):

@@ -921,6 +921,130 @@ static void accel_total(int64_t n, const double *x, const double *y, const doubl
     }
 }
 
+/* Block time steps (Sec. 2: individual time steps with the gravitational
+ * criterion eta, Springel 2005 eq. 34, and a minimum step dt_min; the paper
+ * traces an energy error to the way steps change, Sec. 3.1).  Readings: a
+ * particle's step is s = dt / 2^b, the longest one with s^2 |a| <= 2 eta eps
+ * (b <= max_bin), lengthened again while it is shorter than dt_min.  One
+ * cycle of length dt starts and ends synchronised and is cut into T = 2^max_bin
+ * ticks: every particle drifts each tick; a particle is active at tick k when k
+ * is a multiple of its step in ticks; an active particle gets its forces at
+ * the current positions, its closing half kick with the old step, a new bin
+ * from the criterion (a longer step only when k is a multiple of it) and,
+ * before the cycle ends, its opening half kick with the new step. */
+int32_t orc_bin(double dt, double eta, double eps, double dt_min, int32_t max_bin,
+                double ax, double ay, double az)
+{
+    /* s^2 |a| <= 2 eta eps, squared on both sides: no square root, so the
+     * integer decision is a fixed sequence of IEEE products and sums */
+    const double a2 = (ax * ax + ay * ay) + az * az;
+    const double lim = 2.0 * eta * eps;
+    const double lim2 = lim * lim;
+    int32_t b = 0;
+    for (;;) {
+        const double s = ldexp(dt, -b);
+        const double s2 = s * s;
+        if (b >= max_bin || !((s2 * s2) * a2 > lim2)) break;
+        ++b;
+    }
+    while (b > 0 && ldexp(dt, -b) < dt_min) --b;
+    return b;
+}
+
+/* reflecting sphere (Sec. 2): a particle beyond the radius that moves
+ * outwards gets its radial velocity reversed, v -> v - 2 (v.d) d / |d|^2 */
+static void reflect(int64_t n, const double *x, const double *y, const double *z, double *vx,
+                    double *vy, double *vz, const orc_params *p)
+{
+    if (!(p->boundary_r > 0.0)) return;
+    for (int64_t i = 0; i < n; ++i) {
+        double dx = x[i] - p->boundary_c[0], dy = y[i] - p->boundary_c[1];
+        double dz = z[i] - p->boundary_c[2];
+        double d2 = (dx * dx + dy * dy) + dz * dz;
+        double vd = (vx[i] * dx + vy[i] * dy) + vz[i] * dz;
+        if (d2 > p->boundary_r * p->boundary_r && vd > 0.0) {
+            double f = 2.0 * vd / d2;
+            vx[i] -= f * dx;
+            vy[i] -= f * dy;
+            vz[i] -= f * dz;
+        }
+    }
+}
+
+static void half_kick(int64_t i, double *vx, double *vy, double *vz, const double *ax,
+                      const double *ay, const double *az, double dt, int32_t b)
+{
+    double h = 0.5 * ldexp(dt, -b);
+    vx[i] += ax[i] * h;
+    vy[i] += ay[i] * h;
+    vz[i] += az[i] * h;
+}
+
+/* One cycle of block time steps; on entry and exit every particle is
+ * synchronised and (ax, ay, az, pot) hold the forces at the positions. */
+static void block_cycle(int64_t n, double *x, double *y, double *z, double *vx, double *vy,
+                        double *vz, const double *m, double *ax, double *ay, double *az,
+                        double *pot, const orc_params *p)
+{
+    const int32_t B = p->max_bin;
+    const int64_t T = (int64_t)1 << B;
+    const double tau = ldexp(p->dt, -B);
+    const size_t nn = (size_t)(n > 0 ? n : 1);
+    int32_t *bin = (int32_t *)malloc(sizeof(int32_t) * nn);
+    int64_t *act = (int64_t *)malloc(sizeof(int64_t) * nn);
+    double *w = (double *)malloc(sizeof(double) * nn * 11);
+    double *gx = w, *gy = gx + n, *gz = gy + n, *gp = gz + n;
+    double *qx = gp + n, *qy = qx + n, *qz = qy + n;
+    double *hx = qz + n, *hy = hx + n, *hz = hy + n, *hp = hz + n;
+    for (int64_t i = 0; i < n; ++i) {
+        bin[i] = orc_bin(p->dt, p->eta, p->eps, p->dt_min, B, ax[i], ay[i], az[i]);
+        half_kick(i, vx, vy, vz, ax, ay, az, p->dt, bin[i]);
+    }
+    for (int64_t k = 1; k <= T; ++k) {
+        for (int64_t i = 0; i < n; ++i) {
+            x[i] += vx[i] * tau;
+            y[i] += vy[i] * tau;
+            z[i] += vz[i] * tau;
+        }
+        reflect(n, x, y, z, vx, vy, vz, p);
+        int64_t na = 0;
+        for (int64_t i = 0; i < n; ++i)
+            if ((k & (((int64_t)1 << (B - bin[i])) - 1)) == 0) act[na++] = i;
+        if (na == 0) continue;
+        orc_gravity(n, x, y, z, m, p->G, p->eps, na, act, gx, gy, gz, gp, NULL);
+        if (p->host_kind != 0) {
+            for (int64_t t = 0; t < na; ++t) {
+                qx[t] = x[act[t]];
+                qy[t] = y[act[t]];
+                qz[t] = z[act[t]];
+            }
+            orc_host_field(na, qx, qy, qz, p, hx, hy, hz, hp);
+            for (int64_t t = 0; t < na; ++t) {
+                gx[t] += hx[t];
+                gy[t] += hy[t];
+                gz[t] += hz[t];
+                gp[t] += hp[t];
+            }
+        }
+        for (int64_t t = 0; t < na; ++t) {
+            const int64_t i = act[t];
+            ax[i] = gx[t];
+            ay[i] = gy[t];
+            az[i] = gz[t];
+            pot[i] = gp[t];
+            half_kick(i, vx, vy, vz, ax, ay, az, p->dt, bin[i]);
+            if (k == T) continue;
+            int32_t nb = orc_bin(p->dt, p->eta, p->eps, p->dt_min, B, ax[i], ay[i], az[i]);
+            while (nb < bin[i] && (k & (((int64_t)1 << (B - nb)) - 1)) != 0) ++nb;
+            bin[i] = nb;
+            half_kick(i, vx, vy, vz, ax, ay, az, p->dt, bin[i]);
+        }
+    }
+    free(bin);
+    free(act);
+    free(w);
+}
+
 /* One step: K(dt/2) D(dt) [forces] K(dt/2), then the SIDM pass at the
  * synchronised point (reading: the paper does not state where scattering sits
  * inside the step; placing it after the closing kick keeps x fixed during the
@@ -932,6 +1056,10 @@ int64_t orc_kdk_step(int64_t n, double *x, double *y, double *z,
                      orc_event *ev, int64_t ev_cap)
 {
     double hdt = 0.5 * p->dt;
+    if (p->eta > 0.0) {
+        block_cycle(n, x, y, z, vx, vy, vz, m, ax, ay, az, pot, p);
+        goto synchronised;
+    }
     for (int64_t i = 0; i < n; ++i) {
         vx[i] += ax[i] * hdt;
         vy[i] += ay[i] * hdt;
@@ -942,28 +1070,14 @@ int64_t orc_kdk_step(int64_t n, double *x, double *y, double *z,
         y[i] += vy[i] * p->dt;
         z[i] += vz[i] * p->dt;
     }
-    /* reflecting sphere (Sec. 2): a particle beyond the radius that moves
-     * outwards gets its radial velocity reversed, v -> v - 2 (v.d) d / |d|^2 */
-    if (p->boundary_r > 0.0) {
-        for (int64_t i = 0; i < n; ++i) {
-            double dx = x[i] - p->boundary_c[0], dy = y[i] - p->boundary_c[1];
-            double dz = z[i] - p->boundary_c[2];
-            double d2 = (dx * dx + dy * dy) + dz * dz;
-            double vd = (vx[i] * dx + vy[i] * dy) + vz[i] * dz;
-            if (d2 > p->boundary_r * p->boundary_r && vd > 0.0) {
-                double f = 2.0 * vd / d2;
-                vx[i] -= f * dx;
-                vy[i] -= f * dy;
-                vz[i] -= f * dz;
-            }
-        }
-    }
+    reflect(n, x, y, z, vx, vy, vz, p);
     accel_total(n, x, y, z, m, p, ax, ay, az, pot);
     for (int64_t i = 0; i < n; ++i) {
         vx[i] += ax[i] * hdt;
         vy[i] += ay[i] * hdt;
         vz[i] += az[i] * hdt;
     }
+synchronised:
     orc_knn_grid(n, x, y, z, id, p->k, h);
     if (p->sigma_m == 0.0) return 0;
     int64_t cap = ev_cap > 0 ? ev_cap : 0;

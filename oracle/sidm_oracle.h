@@ -181,9 +181,20 @@ typedef struct orc_params_s {
     double host_hern_M, host_hern_a;      /* host_kind 2: Hernquist bulge */
     double host_disk[4][3];     /* host_kind 2: Miyamoto-Nagai discs (M, a, b) */
     double boundary_r, boundary_c[3];     /* reflecting sphere; r = 0: none */
+    double eta;                 /* > 0: block time steps with this criterion  */
+    double dt_min;              /* smallest allowed step (0: none)            */
+    int32_t max_bin;            /* steps dt / 2^b, 0 <= b <= max_bin          */
 } orc_params;
 
-/* Full-N step for one halo (exact searches: orc_knn_grid, orc_find_events_sweep).  On entry a/pot hold the acceleration
+/* Time-step bin of one particle (Sec. 2: the gravitational criterion of
+ * Springel 2005, eq. 34, s <= sqrt(2 eta eps / |a|)): the smallest b in
+ * [0, max_bin] with (s^2)^2 |a|^2 <= (2 eta eps)^2 for s = dt / 2^b (else
+ * max_bin), then decreased while dt / 2^b < dt_min. */
+int32_t orc_bin(double dt, double eta, double eps, double dt_min, int32_t max_bin,
+                double ax, double ay, double az);
+
+/* Full-N step for one halo (exact searches: orc_knn_grid, orc_find_events_sweep).
+ * With eta > 0 the step is one cycle of block time steps (see the source).  On entry a/pot hold the acceleration
  * and potential at x (self + host).  Performs K(dt/2), D(dt), gravity + host,
  * K(dt/2), h from kNN, events, ordered kicks.  Writes h; returns the number of
  * events (or -1 if more than `ev_cap` events were found; ev may be NULL when
