@@ -44,6 +44,7 @@ extern "C" {
 
 #define SIDM_ABI_VERSION 1
 #define SIDM_MAX_K 128          /* largest supported neighbour number N_ngb */
+#define SIDM_MAX_BIN 16         /* deepest block time-step bin             */
 
 typedef struct sidm_ctx sidm_ctx;
 
@@ -92,6 +93,13 @@ typedef struct {
                                    boundary_center that moves outwards has its
                                    radial velocity reversed; 0: none                */
     double boundary_center[3];
+    double eta;                 /* > 0: sidm_kdk_step runs one cycle of block time
+                                   steps of total length dt (see there); 0: one
+                                   fixed step                                       */
+    double dt_min;              /* smallest allowed block step, >= 0 (Sec. 2)     */
+    int32_t max_bin;            /* block steps dt / 2^b, 0 <= b <= max_bin <=
+                                   SIDM_MAX_BIN; must be 0 when eta = 0             */
+    int32_t reserved;           /* set to 0                                        */
 } sidm_halo;
 
 /* Particle state (device pointers, length n_total each). */
@@ -211,7 +219,26 @@ sidm_status sidm_scatter(sidm_ctx *ctx, const sidm_halo *halos, int32_t n_halos,
  * sidm_gravity once after loading the initial conditions).
  * K(dt/2) D(dt) gravity+host K(dt/2), then h from the k nearest neighbours,
  * then the scattering pass of sidm_scatter with this `step`.  diag (nullable,
- * device, n_halos entries) receives the energy and momentum after the step. */
+ * device, n_halos entries) receives the energy and momentum after the step.
+ *
+ * Block time steps (Sec. 2: individual steps from the gravitational criterion
+ * eta of Springel 2005 eq. 34 and a minimum step dt_min; Sec. 3.1 on the
+ * energy error of changing steps).  When any halo has eta > 0 the call runs
+ * one cycle of length dt for every halo; a halo with eta = 0 takes one fixed
+ * step in it.  A particle's step is s = dt / 2^b with b the smallest value in
+ * [0, max_bin] for which (s^2)^2 |a|^2 <= (2 eta eps)^2 (s^2 |a| <= 2 eta eps
+ * without a square root), else max_bin, then decreased while s < dt_min.  The
+ * cycle is 2^max_bin ticks of dt / 2^max_bin: every particle drifts each tick
+ * (reflecting sphere included); a particle is active at tick k when k is a
+ * multiple of its step in ticks, and then gets new forces, its closing half
+ * kick with the old step, a new bin (a longer step only when k is a multiple
+ * of it) and, before the end, its opening half kick with the new step.  The
+ * cycle starts and ends synchronised; h and the scattering pass (probabilities
+ * over dt) follow at its end.  Gravity tiles whose i-particles are all
+ * inactive are skipped.  Halos with different max_bin share the call's ticks
+ * (a halo with max_bin B steps on every 2^(Bmax - B)-th).  With timing on, the
+ * pass of the gravity tiles covers all ticks (drift, cell list, tiles, kicks)
+ * and the kick+drift pass the opening kick. */
 sidm_status sidm_kdk_step(sidm_ctx *ctx, const sidm_halo *halos, int32_t n_halos,
                           const sidm_state *state, uint32_t step, sidm_precision prec,
                           sidm_diag *diag, void *stream);

@@ -51,7 +51,8 @@ class SidmHalo(C.Structure):
                 ("host_center", C.c_double * 3), ("sigma_w", C.c_double),
                 ("host_hern_M", C.c_double), ("host_hern_a", C.c_double),
                 ("host_disk", (C.c_double * 3) * 4), ("boundary_r", C.c_double),
-                ("boundary_center", C.c_double * 3)]
+                ("boundary_center", C.c_double * 3), ("eta", C.c_double), ("dt_min", C.c_double),
+                ("max_bin", C.c_int32), ("reserved", C.c_int32)]
 
 
 class SidmState(C.Structure):
@@ -184,6 +185,11 @@ def make_halos(halos):
             arr[i].boundary_r = float(bnd["r"])
             for c in range(3):
                 arr[i].boundary_center[c] = float(bnd.get("center", (0.0, 0.0, 0.0))[c])
+        steps = h.get("steps")
+        if steps is not None:
+            arr[i].eta = float(steps["eta"])
+            arr[i].max_bin = int(steps["max_bin"])
+            arr[i].dt_min = float(steps.get("dt_min", 0.0))
     return arr
 
 

@@ -21,6 +21,7 @@
 // scales by G, adds the host, optionally applies the closing half kick, and
 // scatters to the caller's (unsorted) arrays.
 #include "sidm_host.hpp"
+#include "sidm_steps.hpp"
 #include "sidm_plan.hpp"
 
 namespace sidm {
@@ -241,16 +242,39 @@ __device__ inline void grav_mixed_body(const float4* __restrict__ xm32,
     }
 }
 
+// Block time steps: whether any i-particle of the item is active at this tick
+// (tick 0: not a cycle, every item runs).  Uniform over the block.
+template <int IREG>
+__device__ inline bool item_active(const GravItem& it, const HaloDev& H,
+                                   const int8_t* __restrict__ bin,
+                                   const uint32_t* __restrict__ perm, int tick, int bmax)
+{
+    if (tick == 0) return true;
+    const int kl = local_tick(H, tick, bmax);
+    int any = 0;
+    if (kl > 0) {
+        const int64_t il0 = it.i0 - H.offset;
+#pragma unroll
+        for (int r = 0; r < IREG; ++r) {
+            const int64_t li = il0 + (int64_t)r * kGravThreads + threadIdx.x;
+            if (li < H.n && bin_active(H, bin[perm[H.sbase + li]], kl)) any = 1;
+        }
+    }
+    return __syncthreads_or(any) != 0;
+}
+
 template <int IREG>
 __global__ __launch_bounds__(kGravThreads) void k_grav_mixed(
     const float4* __restrict__ xm32, const SubRange* __restrict__ sub,
     const int* __restrict__ sub_n, const GravItem* __restrict__ items,
     const HaloDev* __restrict__ halos,
-    const double* __restrict__ cmass, double4* __restrict__ partial)
+    const double* __restrict__ cmass, double4* __restrict__ partial,
+    const int8_t* __restrict__ bin, const uint32_t* __restrict__ perm, int tick, int bmax)
 {
     __shared__ float4 tile[kGravTileJ];
     const GravItem it = items[blockIdx.x];
     const HaloDev& H = halos[it.halo];
+    if (!item_active<IREG>(it, H, bin, perm, tick, bmax)) return;
     const double meq = cmass[it.halo];
     if (meq > 0.0)
         grav_mixed_body<IREG, true>(xm32, sub, sub_n, it, H, (double)(float)meq, partial, tile);
@@ -372,11 +396,13 @@ __global__ __launch_bounds__(kGravThreads) void k_grav_fp64(
     const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
     const double* __restrict__ m, const GravItem* __restrict__ items,
     const HaloDev* __restrict__ halos, const double* __restrict__ cmass,
-    double4* __restrict__ partial)
+    double4* __restrict__ partial, const int8_t* __restrict__ bin,
+    const uint32_t* __restrict__ perm, int tick, int bmax)
 {
     __shared__ double4 tile[kGravTileJ];
     const GravItem it = items[blockIdx.x];
     const HaloDev& H = halos[it.halo];
+    if (!item_active<IREG>(it, H, bin, perm, tick, bmax)) return;
     const double meq = cmass[it.halo];
     if (meq > 0.0)
         grav_fp64_body<IREG, true>(x, y, z, m, it, H, meq, partial, tile);
@@ -387,7 +413,11 @@ __global__ __launch_bounds__(kGravThreads) void k_grav_fp64(
 // ---------------------------------------------------------------- host + finalize
 // Sums the partial rows of each i in slot order, scales by G, adds the host,
 // optionally kicks v by a * dt/2 (and refreshes the sorted copy of v that the
-// scattering pass reads), and writes to the caller's particle order.
+// scattering pass reads), and writes to the caller's particle order.  In a
+// cycle of block steps (tick > 0) only the particles active at the tick are
+// written: closing half kick with the old step, then (before the cycle's
+// end) the new bin, lengthened only to a step the tick is a multiple of, and
+// the opening half kick with it.
 __global__ __launch_bounds__(kStreamBlock) void k_grav_finalize(
     const StreamBlock* __restrict__ blocks, const HaloDev* __restrict__ halos,
     const double4* __restrict__ partial, const uint32_t* __restrict__ perm,
@@ -395,7 +425,7 @@ __global__ __launch_bounds__(kStreamBlock) void k_grav_finalize(
     double* __restrict__ ax, double* __restrict__ ay, double* __restrict__ az,
     double* __restrict__ pot, double* __restrict__ vx, double* __restrict__ vy,
     double* __restrict__ vz, double* __restrict__ svx, double* __restrict__ svy,
-    double* __restrict__ svz, int kick)
+    double* __restrict__ svz, int kick, int8_t* __restrict__ bin, int tick, int bmax)
 {
     const StreamBlock B = blocks[blockIdx.x];
     const int t = threadIdx.x;
@@ -404,6 +434,12 @@ __global__ __launch_bounds__(kStreamBlock) void k_grav_finalize(
     const int64_t li = (B.start - H.offset) + t;
     const int64_t p = H.sbase + li;
     const int64_t o = perm[p];
+    int kl = 0, b = 0;
+    if (tick > 0) {
+        kl = local_tick(H, tick, bmax);
+        b = bin[o];
+        if (!bin_active(H, b, kl)) return;
+    }
     double sx = 0, sy = 0, sz = 0, sp = 0;
     for (int s = 0; s < H.grav_split; ++s) {
         const double4 q = partial[H.part_base + (int64_t)s * H.n + li];
@@ -416,7 +452,19 @@ __global__ __launch_bounds__(kStreamBlock) void k_grav_finalize(
         gx += hx; gy += hy; gz += hz; gp += hp;
     }
     ax[o] = gx; ay[o] = gy; az[o] = gz; pot[o] = gp;
-    if (kick) {
+    if (tick > 0) {
+        double h = half_step(H, b);
+        double ux = vx[o] + gx * h, uy = vy[o] + gy * h, uz = vz[o] + gz * h;
+        if (kl < (1 << H.max_bin)) {
+            int nb = time_bin(H, gx, gy, gz);
+            while (nb < b && (kl & ((1 << (H.max_bin - nb)) - 1)) != 0) ++nb;
+            bin[o] = (int8_t)nb;
+            h = half_step(H, nb);
+            ux = ux + gx * h; uy = uy + gy * h; uz = uz + gz * h;
+        }
+        vx[o] = ux; vy[o] = uy; vz[o] = uz;
+        svx[p] = ux; svy[p] = uy; svz[p] = uz;
+    } else if (kick) {
         const double hdt = 0.5 * H.dt;
         const double ux = vx[o] + gx * hdt, uy = vy[o] + gy * hdt, uz = vz[o] + gz * hdt;
         vx[o] = ux; vy[o] = uy; vz[o] = uz;
@@ -439,9 +487,11 @@ int64_t gravity_slots(int device)
 }
 
 // Expects the cell list of the current positions (sorted copies sx, sy, sz, sm
-// and perm) to be in place.
+// and perm) to be in place.  tick > 0: tick of a cycle of 2^bmax block steps
+// (bins in w.bin).
 hipError_t launch_gravity(bool mixed, const Plan& P, Scratch& w, const sidm_state* s, int kick,
-                          hipStream_t st, hipEvent_t tile_begin, hipEvent_t tile_end)
+                          hipStream_t st, hipEvent_t tile_begin, hipEvent_t tile_end, int tick,
+                          int bmax)
 {
     const unsigned nb = (unsigned)P.n_blocks;
     hipLaunchKernelGGL(k_block_mass_range, dim3(nb), dim3(kStreamBlock), 0, st, s->m, w.blocks,
@@ -453,17 +503,19 @@ hipError_t launch_gravity(bool mixed, const Plan& P, Scratch& w, const sidm_stat
                            w.sm, w.blocks, w.halos, w.sub, w.sub_n, w.xm32);
         if (tile_begin) (void)hipEventRecord(tile_begin, st);
         hipLaunchKernelGGL((k_grav_mixed<4>), dim3((unsigned)P.n_items), dim3(kGravThreads), 0,
-                           st, w.xm32, w.sub, w.sub_n, w.items, w.halos, w.cref, w.partial);
+                           st, w.xm32, w.sub, w.sub_n, w.items, w.halos, w.cref, w.partial, w.bin,
+                           w.perm, tick, bmax);
         if (tile_end) (void)hipEventRecord(tile_end, st);
     } else {
         if (tile_begin) (void)hipEventRecord(tile_begin, st);
         hipLaunchKernelGGL((k_grav_fp64<4>), dim3((unsigned)P.n_items), dim3(kGravThreads), 0, st,
-                           w.sx, w.sy, w.sz, w.sm, w.items, w.halos, w.cref, w.partial);
+                           w.sx, w.sy, w.sz, w.sm, w.items, w.halos, w.cref, w.partial, w.bin,
+                           w.perm, tick, bmax);
         if (tile_end) (void)hipEventRecord(tile_end, st);
     }
     hipLaunchKernelGGL(k_grav_finalize, dim3(nb), dim3(kStreamBlock), 0, st, w.blocks, w.halos,
                        w.partial, w.perm, s->x, s->y, s->z, s->ax, s->ay, s->az, s->pot, s->vx,
-                       s->vy, s->vz, w.svx, w.svy, w.svz, kick);
+                       s->vy, s->vz, w.svx, w.svy, w.svz, kick, w.bin, tick, bmax);
     return hipGetLastError();
 }
 

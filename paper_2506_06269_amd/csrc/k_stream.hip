@@ -1,9 +1,27 @@
 // k_stream.hip -- streaming FP64 passes of the leapfrog and the energy and
-// momentum reductions (kick-drift-kick with a fixed step; the paper's energy
-// error is measured relative to the absolute initial energy, App. B).
+// momentum reductions (kick-drift-kick with a fixed step or block steps; the
+// paper's energy error is measured relative to the absolute initial energy,
+// App. B).
 #include "sidm_host.hpp"
+#include "sidm_steps.hpp"
 
 namespace sidm {
+
+// Reflecting sphere (Sec. 2): at the drifted position p, outward motion beyond
+// the radius is turned inward, v -> v - 2 (v.d) d / |d|^2 (|v| kept).
+__device__ inline void reflect(const HaloDev& H, double px, double py, double pz, double& ux,
+                               double& uy, double& uz)
+{
+#pragma clang fp contract(off)
+    if (!(H.bnd_r > 0.0)) return;
+    const double dx = px - H.bnd_c[0], dy = py - H.bnd_c[1], dz = pz - H.bnd_c[2];
+    const double d2 = (dx * dx + dy * dy) + dz * dz;
+    const double vd = (ux * dx + uy * dy) + uz * dz;
+    if (d2 > H.bnd_r * H.bnd_r && vd > 0.0) {
+        const double f = 2.0 * vd / d2;
+        ux = ux - f * dx; uy = uy - f * dy; uz = uz - f * dz;
+    }
+}
 
 // v += a dt/2 ; x += v dt   (opening half kick fused with the drift)
 __global__ __launch_bounds__(kStreamBlock) void k_kick_drift(
@@ -18,25 +36,58 @@ __global__ __launch_bounds__(kStreamBlock) void k_kick_drift(
     const HaloDev& H = halos[B.halo];
     const int64_t i = B.start + t;
     const double hdt = 0.5 * H.dt;
-    const double ux = vx[i] + ax[i] * hdt;
-    const double uy = vy[i] + ay[i] * hdt;
-    const double uz = vz[i] + az[i] * hdt;
+    double ux = vx[i] + ax[i] * hdt;
+    double uy = vy[i] + ay[i] * hdt;
+    double uz = vz[i] + az[i] * hdt;
     const double px = x[i] + ux * H.dt, py = y[i] + uy * H.dt, pz = z[i] + uz * H.dt;
     x[i] = px; y[i] = py; z[i] = pz;
-    if (H.bnd_r > 0.0) {
-        // reflecting sphere (Sec. 2): outward motion beyond the radius is
-        // turned inward, v -> v - 2 (v.d) d / |d|^2 (|v| kept)
-#pragma clang fp contract(off)
-        const double dx = px - H.bnd_c[0], dy = py - H.bnd_c[1], dz = pz - H.bnd_c[2];
-        const double d2 = (dx * dx + dy * dy) + dz * dz;
-        const double vd = (ux * dx + uy * dy) + uz * dz;
-        if (d2 > H.bnd_r * H.bnd_r && vd > 0.0) {
-            const double f = 2.0 * vd / d2;
-            vx[i] = ux - f * dx; vy[i] = uy - f * dy; vz[i] = uz - f * dz;
-            return;
-        }
-    }
+    reflect(H, px, py, pz, ux, uy, uz);
     vx[i] = ux; vy[i] = uy; vz[i] = uz;
+}
+
+// Start of a cycle of block steps: the bin of every particle from its
+// acceleration, and its opening half kick v += a s/2.
+__global__ __launch_bounds__(kStreamBlock) void k_open_kick(
+    const StreamBlock* __restrict__ blocks, const HaloDev* __restrict__ halos,
+    double* __restrict__ vx, double* __restrict__ vy, double* __restrict__ vz,
+    const double* __restrict__ ax, const double* __restrict__ ay, const double* __restrict__ az,
+    int8_t* __restrict__ bin)
+{
+    const StreamBlock B = blocks[blockIdx.x];
+    const int t = threadIdx.x;
+    if (t >= B.count) return;
+    const HaloDev& H = halos[B.halo];
+    const int64_t i = B.start + t;
+    const double gx = ax[i], gy = ay[i], gz = az[i];
+    const int b = time_bin(H, gx, gy, gz);
+    bin[i] = (int8_t)b;
+    const double h = half_step(H, b);
+    vx[i] = vx[i] + gx * h;
+    vy[i] = vy[i] + gy * h;
+    vz[i] = vz[i] + gz * h;
+}
+
+// One tick of a cycle: x += v dt / 2^max_bin for every particle of the halos
+// that step at this tick, then the reflecting sphere.
+__global__ __launch_bounds__(kStreamBlock) void k_tick_drift(
+    const StreamBlock* __restrict__ blocks, const HaloDev* __restrict__ halos,
+    double* __restrict__ x, double* __restrict__ y, double* __restrict__ z,
+    double* __restrict__ vx, double* __restrict__ vy, double* __restrict__ vz, int tick, int bmax)
+{
+    const StreamBlock B = blocks[blockIdx.x];
+    const int t = threadIdx.x;
+    if (t >= B.count) return;
+    const HaloDev& H = halos[B.halo];
+    if (local_tick(H, tick, bmax) == 0) return;
+    const int64_t i = B.start + t;
+    const double tau = ldexp(H.dt, -H.max_bin);
+    double ux = vx[i], uy = vy[i], uz = vz[i];
+    const double px = x[i] + ux * tau, py = y[i] + uy * tau, pz = z[i] + uz * tau;
+    x[i] = px; y[i] = py; z[i] = pz;
+    if (H.bnd_r > 0.0) {
+        reflect(H, px, py, pz, ux, uy, uz);
+        vx[i] = ux; vy[i] = uy; vz[i] = uz;
+    }
 }
 
 // Per-block partial sums of K, W, Eext, px, py, pz and a non-finite flag.
@@ -115,6 +166,24 @@ hipError_t launch_kick_drift(const StreamBlock* d_blocks, int64_t n_blocks, cons
 {
     hipLaunchKernelGGL(k_kick_drift, dim3((unsigned)n_blocks), dim3(kStreamBlock), 0, st, d_blocks,
                        d_halos, x, y, z, vx, vy, vz, ax, ay, az);
+    return hipGetLastError();
+}
+
+hipError_t launch_open_kick(const StreamBlock* d_blocks, int64_t n_blocks, const HaloDev* d_halos,
+                            double* vx, double* vy, double* vz, const double* ax, const double* ay,
+                            const double* az, int8_t* bin, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_open_kick, dim3((unsigned)n_blocks), dim3(kStreamBlock), 0, st, d_blocks,
+                       d_halos, vx, vy, vz, ax, ay, az, bin);
+    return hipGetLastError();
+}
+
+hipError_t launch_tick_drift(const StreamBlock* d_blocks, int64_t n_blocks, const HaloDev* d_halos,
+                             double* x, double* y, double* z, double* vx, double* vy, double* vz,
+                             int tick, int bmax, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_tick_drift, dim3((unsigned)n_blocks), dim3(kStreamBlock), 0, st, d_blocks,
+                       d_halos, x, y, z, vx, vy, vz, tick, bmax);
     return hipGetLastError();
 }
 

@@ -15,6 +15,12 @@ namespace sidm {
 hipError_t launch_kick_drift(const StreamBlock* d_blocks, int64_t n_blocks, const HaloDev* d_halos,
                              double* x, double* y, double* z, double* vx, double* vy, double* vz,
                              const double* ax, const double* ay, const double* az, hipStream_t st);
+hipError_t launch_open_kick(const StreamBlock* d_blocks, int64_t n_blocks, const HaloDev* d_halos,
+                            double* vx, double* vy, double* vz, const double* ax, const double* ay,
+                            const double* az, int8_t* bin, hipStream_t st);
+hipError_t launch_tick_drift(const StreamBlock* d_blocks, int64_t n_blocks, const HaloDev* d_halos,
+                             double* x, double* y, double* z, double* vx, double* vy, double* vz,
+                             int tick, int bmax, hipStream_t st);
 hipError_t launch_diag(const StreamBlock* d_blocks, int64_t n_blocks, const HaloDev* d_halos,
                        int n_halos, const double* x, const double* y, const double* z,
                        const double* vx, const double* vy, const double* vz, const double* m,
@@ -35,7 +41,8 @@ hipError_t launch_tidal(const StreamBlock* d_blocks, int64_t n_blocks, const Hal
 
 namespace sidm {
 hipError_t launch_gravity(bool mixed, const Plan& P, Scratch& w, const sidm_state* s, int kick,
-                          hipStream_t st, hipEvent_t tile_begin, hipEvent_t tile_end);
+                          hipStream_t st, hipEvent_t tile_begin, hipEvent_t tile_end, int tick = 0,
+                          int bmax = 0);
 int64_t gravity_slots(int device);
 hipError_t launch_cell_list(const Plan& plan, const sidm_state* s, Scratch& w, hipStream_t st);
 hipError_t launch_knn(const Plan& plan, const sidm_state* s, Scratch& w, uint32_t* nbr, int k_max,
@@ -189,6 +196,13 @@ sidm_status validate(sidm_ctx* c, const sidm_halo* halos, int32_t n_halos, const
         }
         if (!(H.boundary_r >= 0.0) || !std::isfinite(H.boundary_r)) {
             set_err(c, "halo %d: boundary_r must be finite and >= 0", h);
+            return SIDM_ERR_INVALID;
+        }
+        if (!(H.eta >= 0.0) || !std::isfinite(H.eta) || !(H.dt_min >= 0.0) ||
+            !std::isfinite(H.dt_min) || H.max_bin < 0 || H.max_bin > SIDM_MAX_BIN ||
+            (H.eta == 0.0 && H.max_bin != 0)) {
+            set_err(c, "halo %d: block steps need finite eta >= 0, dt_min >= 0 and "
+                       "0 <= max_bin <= %d (max_bin = 0 when eta = 0)", h, SIDM_MAX_BIN);
             return SIDM_ERR_INVALID;
         }
         ranges.push_back({H.offset, H.offset + H.n});
@@ -402,17 +416,39 @@ sidm_status sidm_kdk_step(sidm_ctx* c, const sidm_halo* halos, int32_t n_halos,
     auto mark = [&](int i) {
         if (tm) (void)hipEventRecord(E[i], st);
     };
+    // block time steps: the deepest bin of the halos that use them
+    int bmax = -1;
+    for (int32_t h = 0; h < n_halos; ++h)
+        if (halos[h].eta > 0.0) bmax = std::max(bmax, (int)halos[h].max_bin);
     mark(0);
     hipError_t e = launch_reset(P, c->w, st);
-    if (e == hipSuccess)
-        e = launch_kick_drift(c->w.blocks, P.n_blocks, c->w.halos, s->x, s->y, s->z, s->vx,
-                              s->vy, s->vz, s->ax, s->ay, s->az, st);
-    mark(1);
-    if (e == hipSuccess) e = launch_cell_list(P, s, c->w, st);
-    mark(5);
-    if (e == hipSuccess)
-        e = launch_gravity(prec == SIDM_PREC_MIXED, P, c->w, s, 1, st, tm ? E[2] : nullptr,
-                           tm ? E[3] : nullptr);
+    if (bmax < 0) {
+        if (e == hipSuccess)
+            e = launch_kick_drift(c->w.blocks, P.n_blocks, c->w.halos, s->x, s->y, s->z, s->vx,
+                                  s->vy, s->vz, s->ax, s->ay, s->az, st);
+        mark(1);
+        if (e == hipSuccess) e = launch_cell_list(P, s, c->w, st);
+        mark(5);
+        if (e == hipSuccess)
+            e = launch_gravity(prec == SIDM_PREC_MIXED, P, c->w, s, 1, st, tm ? E[2] : nullptr,
+                               tm ? E[3] : nullptr);
+    } else {
+        if (e == hipSuccess)
+            e = launch_open_kick(c->w.blocks, P.n_blocks, c->w.halos, s->vx, s->vy, s->vz, s->ax,
+                                 s->ay, s->az, c->w.bin, st);
+        mark(1);
+        mark(5);
+        mark(2);
+        for (int tick = 1; tick <= (1 << bmax) && e == hipSuccess; ++tick) {
+            e = launch_tick_drift(c->w.blocks, P.n_blocks, c->w.halos, s->x, s->y, s->z, s->vx,
+                                  s->vy, s->vz, tick, bmax, st);
+            if (e == hipSuccess) e = launch_cell_list(P, s, c->w, st);
+            if (e == hipSuccess)
+                e = launch_gravity(prec == SIDM_PREC_MIXED, P, c->w, s, 1, st, nullptr, nullptr,
+                                   tick, bmax);
+        }
+        mark(3);
+    }
     mark(4);
     if (e == hipSuccess) e = launch_knn(P, s, c->w, nullptr, max_k(halos, n_halos), st);
     if (e == hipSuccess) e = launch_tree_hmax(P, c->w, st);

@@ -32,6 +32,8 @@ struct HaloDev {
     double hern_GM, hern_a;               // host_kind 2: Hernquist bulge
     double disk_GM[4], disk_a[4], disk_b[4];   // host_kind 2: Miyamoto-Nagai discs
     double bnd_r, bnd_c[3];               // reflecting sphere (bnd_r = 0: none)
+    double eta, dt_min;                   // block time steps (eta = 0: one fixed step)
+    int32_t max_bin, pad1;
     // search tree: level 0 are the buckets, node ranges per level (global index
     // into the box arrays)
     int64_t level_off[kMaxLevels + 1];

@@ -82,6 +82,7 @@ struct Scratch {
     double4* sp4 = nullptr;       // sorted positions as (x, y, z, 0): one load per candidate
     double *svx = nullptr, *svy = nullptr, *svz = nullptr;
     double *sh = nullptr, *sm = nullptr;
+    int8_t* bin = nullptr;        // block time-step bin per particle (caller's order)
     uint32_t* sid = nullptr;
     uint32_t* perm = nullptr;
     double* box = nullptr;        // 6 per node (buckets first)
@@ -161,7 +162,7 @@ inline bool alloc_scratch(Scratch& w, int64_t N, int32_t H, int64_t max_events, 
               dalloc(w.keys[1], N) && dalloc(w.vals[0], N) && dalloc(w.vals[1], N) &&
               dalloc(w.hist, w.hist_cap) && dalloc(w.sx, N) && dalloc(w.sy, N) &&
               dalloc(w.sz, N) && dalloc(w.sp4, N) && dalloc(w.svx, N) && dalloc(w.svy, N) && dalloc(w.svz, N) &&
-              dalloc(w.sh, N) && dalloc(w.sm, N) && dalloc(w.sid, N) && dalloc(w.perm, N) &&
+              dalloc(w.sh, N) && dalloc(w.sm, N) && dalloc(w.bin, N) && dalloc(w.sid, N) && dalloc(w.perm, N) &&
               dalloc(w.box, 6 * w.nodes_cap) && dalloc(w.hmax, w.nodes_cap) &&
               dalloc(w.sub, kSubMax * w.buckets_cap) && dalloc(w.sub_n, w.buckets_cap) &&
               dalloc(w.owner, N) && dalloc(w.counters, 1) && dalloc(w.ev_counts, 4 * H) &&
@@ -190,7 +191,7 @@ inline void free_scratch(Scratch& w)
     dfree(w.bsum); dfree(w.cref); dfree(w.radius); dfree(w.center); dfree(w.tidal); dfree(w.bbox); dfree(w.xm32);  dfree(w.partial);
     dfree(w.keys[0]); dfree(w.keys[1]); dfree(w.vals[0]); dfree(w.vals[1]); dfree(w.hist);
     dfree(w.sx); dfree(w.sy); dfree(w.sz); dfree(w.sp4); dfree(w.svx); dfree(w.svy); dfree(w.svz);
-    dfree(w.sh); dfree(w.sm); dfree(w.sid); dfree(w.perm); dfree(w.box); dfree(w.hmax);
+    dfree(w.sh); dfree(w.sm); dfree(w.bin); dfree(w.sid); dfree(w.perm); dfree(w.box); dfree(w.hmax);
     dfree(w.sub); dfree(w.sub_n);
     dfree(w.owner); dfree(w.events); dfree(w.counters); dfree(w.ev_counts); dfree(w.status);
 }
@@ -301,6 +302,9 @@ inline bool build_plan(Plan& P, const Scratch& w, const sidm_halo* halos, int32_
         }
         H.bnd_r = S.boundary_r;
         for (int c = 0; c < 3; ++c) H.bnd_c[c] = S.boundary_center[c];
+        H.eta = S.eta;
+        H.dt_min = S.dt_min;
+        H.max_bin = S.eta > 0.0 ? S.max_bin : 0;
         H.sbase = sbase[h];
         H.rank = P.rank_of[h];
         // streaming blocks

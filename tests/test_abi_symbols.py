@@ -56,10 +56,10 @@ def test_struct_layouts_match_header():
 #include <stddef.h>
 #include "sidm.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(sidm_halo), sizeof(sidm_state),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(sidm_halo), sizeof(sidm_state),
          sizeof(sidm_diag), sizeof(sidm_event), offsetof(sidm_halo, seed),
          offsetof(sidm_diag, n_events), offsetof(sidm_diag, status), sizeof(sidm_center),
-         offsetof(sidm_center, index));
+         offsetof(sidm_center, index), offsetof(sidm_halo, eta), offsetof(sidm_halo, max_bin));
   return 0; }
 '''
     d = tempfile.mkdtemp()
@@ -69,4 +69,5 @@ int main(void) {
     got = [int(v) for v in subprocess.run([exe], capture_output=True, text=True).stdout.split()]
     assert got == [C.sizeof(S.SidmHalo), C.sizeof(S.SidmState), C.sizeof(S.SidmDiag),
                    S.EVENT_BYTES, S.SidmHalo.seed.offset, S.SidmDiag.n_events.offset,
-                   S.SidmDiag.status.offset, C.sizeof(S.SidmCenter), S.SidmCenter.index.offset]
+                   S.SidmDiag.status.offset, C.sizeof(S.SidmCenter), S.SidmCenter.index.offset,
+                   S.SidmHalo.eta.offset, S.SidmHalo.max_bin.offset]
