@@ -37,10 +37,12 @@ def _args():
     ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--workload", default="C2", choices=("C2", "C3", "C4", "C5"),
+    ap.add_argument("--workload", default="C2", choices=("C2", "C3", "C4", "C5", "BLK"),
                     help="C2 (default, the benchmark line): N=2^20 satellite; C3: the same halo "
                          "for --steps steps in one --precision with |dE/E| and central density; "
-                         "C4: 64-halo batch; C5: N=2^24 satellite, one step, per-pass rooflines")
+                         "C4: 64-halo batch; C5: N=2^24 satellite, one step, per-pass rooflines; "
+                         "BLK: N=2^20 isolated halo, --steps cycles of block time steps against "
+                         "fixed steps of the deepest bin over the same time")
     ap.add_argument("--precision", default="mixed", choices=("mixed", "fp64"),
                     help="precision of the C3 run")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
@@ -277,6 +279,40 @@ def _bench_c5(a, S, torch, W):
     print(json.dumps(out), flush=True)
 
 
+def _bench_blk(a, S, torch, W):
+    """Block time steps on the N = 2^20 isolated halo: --steps cycles of 1/16,
+    then fixed steps of 1/256 (the deepest bin the criterion fills here) over
+    the same simulated time, both in mixed precision from the same state;
+    simulated time per second and |dE/E| of each."""
+    cfg = W.config("BLK")
+    n = cfg["n"]
+    s = W.make_state(cfg)
+    halo = dict(_halo_of(cfg), steps=cfg["steps_param"])
+    ms_c, de_c, passes, d, ev = _run(S, torch, [halo], s, S.SIDM_PREC_MIXED, a.steps, a.warmup,
+                                     True, progress=True)
+    print(f"BLK: {a.steps} cycles, {ms_c * 1e3:.1f} ms each, |dE/E| {de_c:.3e}", file=sys.stderr,
+          flush=True)
+    sub = 16
+    fixed = dict(_halo_of(cfg), dt=cfg["dt"] / sub)
+    ms_f, de_f, p_f, _, _ = _run(S, torch, [fixed], s, S.SIDM_PREC_MIXED, a.steps * sub,
+                                 a.warmup * sub, True, progress=True)
+    out = {"metric": "simulated time per second, block time steps vs fixed steps (N=2^20)",
+           "value": cfg["dt"] / ms_c, "unit": "code time units/s", "n_gpus": 1,
+           "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms_c * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32 gravity tiles (compensated), f64 elsewhere",
+           "data": "synthetic NFW halo",
+           "config": {"workload": "BLK: isolated NFW N=2^20, eps=0.01, k=64, sigma/m=1, block "
+                                  "steps eta=0.025, cycle 1/16 in up to 64 ticks",
+                      "n": n, "cycle": cfg["dt"], **cfg["steps_param"]},
+           "dE_over_E": de_c, "events_last_cycle": ev, "status": d["status"], "pass_ms": passes,
+           "fixed_step": {"dt": cfg["dt"] / sub, "steps": a.steps * sub,
+                          "ms_per_step": ms_f * 1e3, "time_per_s": cfg["dt"] / sub / ms_f,
+                          "dE_over_E": de_f, "pass_ms": p_f},
+           "speedup_vs_fixed": (ms_f * sub) / ms_c}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = _args()
     if a.gpus != 1:
@@ -294,6 +330,8 @@ def main():
         return _bench_c4(a, S, torch, W)
     if a.workload == "C5":
         return _bench_c5(a, S, torch, W)
+    if a.workload == "BLK":
+        return _bench_blk(a, S, torch, W)
     cfg = W.config("C2")
     n = cfg["n"]
     s = W.make_state(cfg)

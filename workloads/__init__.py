@@ -15,6 +15,8 @@ Workloads (the paper's halo at the sizes used for testing and timing):
   C3  C2's halo, FP64 vs mixed precision, with an N = 2^16 oracle companion
   C4  64 independent halos, N log-uniform in 2^12..2^17, mixed sigma/m and k
   C5  NFW N = 2^24, eps 0.002, k 64, sigma/m 10, in the host
+  BLK isolated NFW N = 2^20 with block time steps (eta 0.025, cycles of 1/16
+      in up to 2^6 ticks), sigma/m 1, k 64
 """
 import math
 
@@ -297,7 +299,7 @@ NFW_MASS_10 = float(nfw_mass(10.0))
 
 
 def config(name):
-    """Run parameters of the named workload (C1..C5)."""
+    """Run parameters of the named workload (C1..C5, BLK)."""
     base = dict(G=1.0, eps=0.01, dt=1e-3, r_cut=10.0, seed=0)
     if name == "C1":
         return dict(base, name=name, n=8192, sigma_m=1.0, k=32, steps=32, precision="fp64",
@@ -311,6 +313,12 @@ def config(name):
     if name == "C5":
         return dict(base, name=name, n=1 << 24, eps=0.002, sigma_m=10.0, k=64, steps=1,
                     precision="mixed", host=host_params())
+    if name == "BLK":
+        # Table 1's gravitational step parameter eta = 0.025 with a cycle of
+        # 1/16 (about 4.4 Myr in the code units of the workloads) whose deepest
+        # bin, 1/1024, is about the fixed step of C1..C5
+        return dict(base, name=name, n=1 << 20, dt=1.0 / 16, sigma_m=1.0, k=64, steps=4,
+                    precision="mixed", host=None, steps_param=dict(eta=0.025, max_bin=6))
     raise KeyError(name)
 
 
