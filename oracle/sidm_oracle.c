@@ -260,6 +260,260 @@ void orc_gravity(int64_t n, const double *x, const double *y, const double *z,
     }
 }
 
+/* ---- tree gravity ---- */
+typedef struct {
+    int64_t first, count;       /* sorted particle range                       */
+    int64_t child0;             /* first child (node index), -1 for a bucket   */
+    int32_t nchild, pad;
+    double box[6];              /* lo xyz, hi xyz                              */
+    double M, Mx, My, Mz;       /* mass and first moments                      */
+} tree_node;
+
+typedef struct {
+    uint64_t key;
+    int64_t idx;
+} key_idx;
+
+static int cmp_key_idx(const void *a, const void *b)
+{
+    const key_idx *p = (const key_idx *)a, *q = (const key_idx *)b;
+    if (p->key != q->key) return p->key < q->key ? -1 : 1;
+    return (p->idx > q->idx) - (p->idx < q->idx);
+}
+
+static uint64_t spread_bits3(unsigned v)
+{
+    uint64_t r = 0;
+    for (int b = 0; b < 16; ++b)
+        if (v & (1u << b)) r |= (uint64_t)1 << (3 * b);
+    return r;
+}
+
+static unsigned quantise16(double v, double lo, double inv)
+{
+    double q = (v - lo) * inv;
+    q = fmin(fmax(q, 0.0), 65535.0);
+    return (unsigned)q;
+}
+
+typedef struct {
+    const double *sx, *sy, *sz, *sm;    /* sorted copies                     */
+    const int64_t *sidx;                /* sorted -> caller index            */
+    tree_node *nodes;
+    double G, eps2, alpha2, a2min;
+    const double *gbox;
+    /* the source list of one group */
+    double *lx, *ly, *lz, *lm;
+    int64_t *lidx;
+    int64_t len;
+} tree_walk;
+
+static int boxes_disjoint(const double *a, const double *b)
+{
+    for (int c = 0; c < 3; ++c)
+        if (a[c] > b[3 + c] || a[3 + c] < b[c]) return 1;
+    return 0;
+}
+
+static int tree_accept(const tree_walk *W, const tree_node *nd)
+{
+    if (!boxes_disjoint(nd->box, W->gbox)) return 0;
+    if (nd->M == 0.0) return 1;
+    double d[3];
+    for (int k = 0; k < 3; ++k) {
+        double lo = W->gbox[k] - nd->box[3 + k], hi = nd->box[k] - W->gbox[3 + k];
+        d[k] = fmax(fmax(lo, hi), 0.0);
+    }
+    double r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+    double l = fmax(fmax(nd->box[3] - nd->box[0], nd->box[4] - nd->box[1]),
+                    nd->box[5] - nd->box[2]);
+    double q = ((W->G * nd->M) * l) * l;
+    double lhs = q * q;
+    double r4 = r2 * r2;
+    double rhs = ((W->alpha2 * W->a2min) * r4) * r4;
+    return lhs <= rhs;
+}
+
+static void tree_visit(tree_walk *W, int64_t node)
+{
+    tree_node *nd = &W->nodes[node];
+    if (tree_accept(W, nd)) {
+        if (nd->M == 0.0) return;
+        W->lx[W->len] = nd->Mx / nd->M;
+        W->ly[W->len] = nd->My / nd->M;
+        W->lz[W->len] = nd->Mz / nd->M;
+        W->lm[W->len] = nd->M;
+        W->lidx[W->len] = -1;
+        W->len++;
+        return;
+    }
+    if (nd->child0 < 0) {
+        for (int64_t p = nd->first; p < nd->first + nd->count; ++p) {
+            W->lx[W->len] = W->sx[p];
+            W->ly[W->len] = W->sy[p];
+            W->lz[W->len] = W->sz[p];
+            W->lm[W->len] = W->sm[p];
+            W->lidx[W->len] = p;
+            W->len++;
+        }
+        return;
+    }
+    for (int32_t k = 0; k < nd->nchild; ++k) tree_visit(W, nd->child0 + k);
+}
+
+void orc_tree_gravity(int64_t n, const double *x, const double *y, const double *z,
+                      const double *m, const double *ax_old, const double *ay_old,
+                      const double *az_old, double G, double eps, double alpha,
+                      double *ax, double *ay, double *az, double *pot, int64_t *terms)
+{
+    const int64_t B = 64, F = 8;
+    if (terms) *terms = 0;
+    if (n <= 0) return;
+    /* Morton order over the bounding box */
+    double lo[3] = {x[0], y[0], z[0]}, hi[3] = {x[0], y[0], z[0]};
+    for (int64_t i = 0; i < n; ++i) {
+        const double p[3] = {x[i], y[i], z[i]};
+        for (int c = 0; c < 3; ++c) {
+            lo[c] = fmin(lo[c], p[c]);
+            hi[c] = fmax(hi[c], p[c]);
+        }
+    }
+    double ext = fmax(fmax(hi[0] - lo[0], hi[1] - lo[1]), hi[2] - lo[2]);
+    double inv = ext > 0.0 ? 65535.0 / ext : 0.0;
+    key_idx *ki = (key_idx *)malloc(sizeof(key_idx) * (size_t)n);
+    for (int64_t i = 0; i < n; ++i) {
+        ki[i].key = spread_bits3(quantise16(x[i], lo[0], inv)) |
+                    (spread_bits3(quantise16(y[i], lo[1], inv)) << 1) |
+                    (spread_bits3(quantise16(z[i], lo[2], inv)) << 2);
+        ki[i].idx = i;
+    }
+    qsort(ki, (size_t)n, sizeof(key_idx), cmp_key_idx);
+    double *sorted = (double *)malloc(sizeof(double) * (size_t)n * 4);
+    double *sx = sorted, *sy = sx + n, *sz = sy + n, *sm = sz + n;
+    int64_t *sidx = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    for (int64_t p = 0; p < n; ++p) {
+        const int64_t i = ki[p].idx;
+        sx[p] = x[i];
+        sy[p] = y[i];
+        sz[p] = z[i];
+        sm[p] = m[i];
+        sidx[p] = i;
+    }
+    free(ki);
+    /* buckets, then levels of F consecutive nodes up to one root */
+    const int64_t nb = (n + B - 1) / B;
+    int64_t cap = nb, level_n = nb;
+    while (level_n > 1) {
+        level_n = (level_n + F - 1) / F;
+        cap += level_n;
+    }
+    tree_node *nodes = (tree_node *)calloc((size_t)cap, sizeof(tree_node));
+    for (int64_t b = 0; b < nb; ++b) {
+        tree_node *nd = &nodes[b];
+        nd->first = b * B;
+        nd->count = (b + 1) * B <= n ? B : n - b * B;
+        nd->child0 = -1;
+        for (int c = 0; c < 3; ++c) {
+            nd->box[c] = INFINITY;
+            nd->box[3 + c] = -INFINITY;
+        }
+        for (int64_t p = nd->first; p < nd->first + nd->count; ++p) {
+            const double q[3] = {sx[p], sy[p], sz[p]};
+            for (int c = 0; c < 3; ++c) {
+                nd->box[c] = fmin(nd->box[c], q[c]);
+                nd->box[3 + c] = fmax(nd->box[3 + c], q[c]);
+            }
+            nd->M += sm[p];
+            nd->Mx += sm[p] * sx[p];
+            nd->My += sm[p] * sy[p];
+            nd->Mz += sm[p] * sz[p];
+        }
+    }
+    int64_t off = 0, cnt = nb, top = nb;
+    while (cnt > 1) {
+        const int64_t nn = (cnt + F - 1) / F;
+        for (int64_t j = 0; j < nn; ++j) {
+            tree_node *nd = &nodes[top + j];
+            nd->child0 = off + j * F;
+            nd->nchild = (int32_t)((j + 1) * F <= cnt ? F : cnt - j * F);
+            const tree_node *c0 = &nodes[nd->child0];
+            const tree_node *cl = &nodes[nd->child0 + nd->nchild - 1];
+            nd->first = c0->first;
+            nd->count = cl->first + cl->count - c0->first;
+            for (int c = 0; c < 3; ++c) {
+                nd->box[c] = INFINITY;
+                nd->box[3 + c] = -INFINITY;
+            }
+            for (int32_t k = 0; k < nd->nchild; ++k) {
+                const tree_node *ch = &nodes[nd->child0 + k];
+                for (int c = 0; c < 3; ++c) {
+                    nd->box[c] = fmin(nd->box[c], ch->box[c]);
+                    nd->box[3 + c] = fmax(nd->box[3 + c], ch->box[3 + c]);
+                }
+                nd->M += ch->M;
+                nd->Mx += ch->Mx;
+                nd->My += ch->My;
+                nd->Mz += ch->Mz;
+            }
+        }
+        off = top;
+        top += nn;
+        cnt = nn;
+    }
+    const int64_t root = top - 1;
+    /* one walk per group (bucket), then the members' sums over its list */
+    tree_walk W;
+    W.sx = sx; W.sy = sy; W.sz = sz; W.sm = sm; W.sidx = sidx;
+    W.nodes = nodes;
+    W.G = G;
+    W.eps2 = eps * eps;
+    W.alpha2 = alpha * alpha;
+    double *lbuf = (double *)malloc(sizeof(double) * (size_t)(n + cap) * 4);
+    W.lx = lbuf; W.ly = lbuf + (n + cap); W.lz = W.ly + (n + cap); W.lm = W.lz + (n + cap);
+    W.lidx = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + cap));
+    int64_t total = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+        const tree_node *g = &nodes[b];
+        double a2min = INFINITY;
+        for (int64_t p = g->first; p < g->first + g->count; ++p) {
+            const int64_t i = sidx[p];
+            const double a2 = (ax_old[i] * ax_old[i] + ay_old[i] * ay_old[i]) +
+                              az_old[i] * az_old[i];
+            a2min = fmin(a2min, a2);
+        }
+        W.a2min = a2min;
+        W.gbox = g->box;
+        W.len = 0;
+        tree_visit(&W, root);
+        total += W.len;
+        for (int64_t p = g->first; p < g->first + g->count; ++p) {
+            neum gx = {0, 0}, gy = {0, 0}, gz = {0, 0}, gp = {0, 0};
+            for (int64_t t = 0; t < W.len; ++t) {
+                if (W.lidx[t] == p) continue;
+                const double dx = W.lx[t] - sx[p], dy = W.ly[t] - sy[p], dz = W.lz[t] - sz[p];
+                const double r2 = dx * dx + dy * dy + dz * dz + W.eps2;
+                const double rinv = 1.0 / sqrt(r2);
+                const double w = W.lm[t] * rinv * rinv * rinv;
+                neum_add(&gx, w * dx);
+                neum_add(&gy, w * dy);
+                neum_add(&gz, w * dz);
+                neum_add(&gp, -W.lm[t] * rinv);
+            }
+            const int64_t i = sidx[p];
+            ax[i] = G * neum_get(&gx);
+            ay[i] = G * neum_get(&gy);
+            az[i] = G * neum_get(&gz);
+            pot[i] = G * neum_get(&gp);
+        }
+    }
+    if (terms) *terms = total;
+    free(lbuf);
+    free(W.lidx);
+    free(nodes);
+    free(sorted);
+    free(sidx);
+}
+
 /* NFW host (Sec. 4.1, Eq. nfw_potential).  With s = r/r_s and
  * K = 4 pi G rho_s r_s^3:  Phi = -K ln(1+s)/r, and the enclosed mass gives
  * a = -K [ln(1+s) - s/(1+s)] (x - c)/r^3.  For s < 1e-4 the bracket uses its

@@ -59,6 +59,33 @@ void orc_gravity(int64_t n, const double *x, const double *y, const double *z,
                  int64_t nq, const int64_t *q,
                  double *ax, double *ay, double *az, double *pot, double *anorm);
 
+/* Tree gravity (Sec. 2: the gravity tree with the relative opening criterion
+ * alpha of Springel 2005, eq. 18; reading of the tree and of the criterion
+ * for groups below).  The tree: particles ordered by their 48-bit Morton key
+ * over the bounding box (16 bits per axis, q = (v - lo) * (65535 / ext)
+ * clamped to [0, 65535] and truncated; ext the box's largest side), ties in
+ * index order; leaves are buckets of 64 consecutive particles, a node of the
+ * next level holds 8 consecutive nodes of the level below, up to one root.
+ * Each node has its particles' bounding box, mass M and first moments
+ * (sums in particle order for a bucket, in child order above).  A group is a
+ * bucket: a node is accepted for all of its members when its box and the
+ * group's box are disjoint and (G M l^2)^2 <= alpha^2 |a_old|^2 r^8, with l the
+ * node box's largest side, |a_old|^2 the smallest (ax^2 + ay^2) + az^2 of the
+ * group's previous accelerations and r^2 the squared distance between the
+ * group's box and the node's box (the criterion G M l^2 <= alpha |a_old| r^4,
+ * squared, for every member and every particle of the node: a node's centre
+ * of mass can lie far from some of its particles).  Otherwise the
+ * node is opened; an opened bucket contributes its particles.  Forces and
+ * potentials: Plummer-softened pair terms with the accepted nodes' monopoles
+ * and the contributed particles (self excluded), Neumaier sums.  alpha = 0
+ * opens every node: the direct sum.  Writes ax, ay, az, pot in the caller's
+ * order; `terms` (nullable) receives the number of source terms summed over
+ * groups (accepted nodes plus contributed particles per group). */
+void orc_tree_gravity(int64_t n, const double *x, const double *y, const double *z,
+                      const double *m, const double *ax_old, const double *ay_old,
+                      const double *az_old, double G, double eps, double alpha,
+                      double *ax, double *ay, double *az, double *pot, int64_t *terms);
+
 /* Static NFW host (paper Sec. 4.1, Eq. nfw_potential) centred at c:
  * Phi(r) = -4 pi G rho_s r_s^3 ln(1 + r/r_s) / r and a = -grad Phi.
  * Writes (not adds) the host acceleration and potential for n particles. */

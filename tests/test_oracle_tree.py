@@ -1,0 +1,99 @@
+"""Pins of the oracle's tree gravity (Sec. 2: the gravity tree with the
+relative opening criterion alpha of Springel 2005; Table 1 and Sec. 2 give
+alpha = 5e-4).  The tree, groups and criterion are defined in the oracle's
+header; the pins: alpha = 0 opens every node and is the direct sum, with
+exactly one term per particle and group; with every disjoint node accepted
+and a softening far above the system's size every particle still feels the
+whole mass but itself once (complete, non-overlapping cover; node masses);
+the error against the direct sum shrinks with alpha and stays within a few
+alpha of |a| at the paper's value; a compact cluster far away acts as its
+monopole."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+
+def _rel_err(t, d):
+    num = np.sqrt((t[0] - d[0]) ** 2 + (t[1] - d[1]) ** 2 + (t[2] - d[2]) ** 2)
+    return num / np.sqrt(d[0] ** 2 + d[1] ** 2 + d[2] ** 2)
+
+
+@pytest.mark.parametrize("n", [1, 2, 64, 65, 1000, 3000])
+def test_alpha_zero_is_the_direct_sum(orc, n):
+    s = W.nfw_halo(max(n, 2), seed=82)
+    x, y, z, m = (s[k][:n] for k in ("x", "y", "z", "m"))
+    d = orc.gravity(x, y, z, m, 1.3, 0.02, want_norm=True)
+    t = orc.tree_gravity(x, y, z, m, (d[0], d[1], d[2]), 1.3, 0.02, 0.0)
+    groups = (n + 63) // 64
+    assert t[4] == groups * n
+    if n > 1:
+        err = np.sqrt((t[0] - d[0]) ** 2 + (t[1] - d[1]) ** 2 + (t[2] - d[2]) ** 2) / d[4]
+        assert err.max() < 1e-13
+        assert np.max(np.abs(t[3] - d[3]) / np.abs(d[3])) < 1e-13
+    else:
+        assert t[0][0] == t[1][0] == t[2][0] == t[3][0] == 0.0
+
+
+def test_cover_is_complete_and_disjoint(orc):
+    """a_old = 1e30 accepts every node whose box is disjoint from the group's;
+    with eps = 1e5 every term is m / eps to 1e-8, so pot_i = -G (M - m_i)/eps:
+    each other particle counted exactly once, through a node or itself."""
+    n = 5000
+    s = W.nfw_halo(n, seed=83)
+    m = s["m"] * (1.0 + 0.5 * np.random.default_rng(1).random(n))   # unequal masses
+    big = np.full(n, 1e30)
+    eps = 1e5
+    t = orc.tree_gravity(s["x"], s["y"], s["z"], m, (big, big, big), 1.0, eps, 5e-4)
+    want = -(m.sum() - m) / eps
+    assert np.max(np.abs(t[3] - want) / np.abs(want)) < 1e-8
+    assert t[4] < 0.2 * ((n + 63) // 64) * n        # most of the mass came through nodes
+
+
+def test_error_shrinks_with_alpha(orc):
+    n = 20000
+    s = W.nfw_halo(n, seed=84)
+    d = orc.gravity(s["x"], s["y"], s["z"], s["m"], 1.0, 0.01)
+    med, mx, terms = [], [], []
+    for alpha in (2.5e-2, 2.5e-3, 5e-4, 5e-5):
+        t = orc.tree_gravity(s["x"], s["y"], s["z"], s["m"], d[:3], 1.0, 0.01, alpha)
+        e = _rel_err(t, d)
+        med.append(np.median(e))
+        mx.append(e.max())
+        terms.append(t[4])
+        if alpha == 5e-4:
+            assert np.median(e) < 2 * alpha and e.max() < 10 * alpha
+            ep = np.abs(t[3] - d[3]) / np.abs(d[3])
+            assert ep.max() < 10 * alpha
+    print("median", med, "max", mx, "terms", terms)
+    assert med == sorted(med, reverse=True) and mx == sorted(mx, reverse=True)
+    assert terms == sorted(terms)
+    assert terms[0] < 0.6 * terms[-1]
+
+
+def test_distant_cluster_acts_as_its_monopole(orc):
+    """Two Plummer clusters 1000 apart: the force of the far cluster on each
+    member of the near one is G M_far (c - x)/|c - x|^3 to its quadrupole
+    order (a/R)^2 ~ 1e-6, where c is the far cluster's centre of mass."""
+    a = W.plummer(2000, seed=85, a=1.0, M=1.0)
+    b = W.plummer(3000, seed=86, a=1.0, M=2.0)
+    shift = np.array([1000.0, 0.0, 0.0])
+    x = np.concatenate([a["x"], b["x"] + shift[0]])
+    y = np.concatenate([a["y"], b["y"]])
+    z = np.concatenate([a["z"], b["z"]])
+    m = np.concatenate([a["m"], b["m"]])
+    d = orc.gravity(x, y, z, m, 1.0, 0.01)
+    t = orc.tree_gravity(x, y, z, m, d[:3], 1.0, 0.01, 5e-4)
+    near = orc.gravity(a["x"], a["y"], a["z"], a["m"], 1.0, 0.01)
+    cm = np.array([np.sum(b["m"] * (b[k] + s)) / np.sum(b["m"])
+                   for k, s in (("x", shift[0]), ("y", 0.0), ("z", 0.0))])
+    dx = cm[0] - a["x"]
+    dy = cm[1] - a["y"]
+    dz = cm[2] - a["z"]
+    r3 = (dx * dx + dy * dy + dz * dz + 1e-4) ** 1.5
+    Mb = np.sum(b["m"])
+    far = (Mb * dx / r3, Mb * dy / r3, Mb * dz / r3)
+    n1 = a["x"].size
+    for c in range(3):
+        got = t[c][:n1] - near[c]
+        assert np.max(np.abs(got - far[c])) < 1e-5 * np.max(np.abs(far[0]))
