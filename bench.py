@@ -37,12 +37,15 @@ def _args():
     ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--workload", default="C2", choices=("C2", "C3", "C4", "C5", "BLK"),
+    ap.add_argument("--workload", default="C2", choices=("C2", "C3", "C4", "C5", "BLK", "TREE"),
                     help="C2 (default, the benchmark line): N=2^20 satellite; C3: the same halo "
                          "for --steps steps in one --precision with |dE/E| and central density; "
                          "C4: 64-halo batch; C5: N=2^24 satellite, one step, per-pass rooflines; "
                          "BLK: N=2^20 isolated halo, --steps cycles of block time steps against "
-                         "fixed steps of the deepest bin over the same time")
+                         "fixed steps of the deepest bin over the same time; TREE: the satellite "
+                         "(N=--tree-n) with tree gravity, alpha=5e-4, against the direct sum")
+    ap.add_argument("--tree-n", type=int, default=1 << 20,
+                    help="TREE: particles (2^20: the C2 set-up; 2^24: the C5 set-up)")
     ap.add_argument("--precision", default="mixed", choices=("mixed", "fp64"),
                     help="precision of the C3 run")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
@@ -313,6 +316,82 @@ def _bench_blk(a, S, torch, W):
     print(json.dumps(out), flush=True)
 
 
+def _bench_tree(a, S, torch, W):
+    """Tree gravity (relative criterion, alpha = 5e-4, Sec. 2) on the satellite
+    in the host: force errors of the first tree evaluation against the GPU's
+    direct sum on the same state, then --steps steps with the tree and with the
+    direct sum from the same state (mixed precision), time and |dE/E| of each.
+    The first tree evaluation takes a_old from a tree pass that accepts every
+    node whose box is disjoint from the group's (a_old = 1e300)."""
+    import numpy as np
+    cfg = W.config("C5" if a.tree_n > (1 << 22) else "C2")
+    n = a.tree_n
+    s = W.make_state(cfg, n=n)
+    base = _halo_of(dict(cfg, n=n))
+    tree = dict(base, tree_alpha=5e-4)
+    prec = S.SIDM_PREC_MIXED
+    dev = S.state_to_device(s)
+    ctx = S.sidm_create(0, n, 1)
+    diag = S.diag_buffer(1)
+    for f in ("ax", "ay", "az"):
+        dev[f].fill_(1e300)
+    S.sidm_gravity(ctx, [tree], dev, prec)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S.sidm_gravity(ctx, [tree], dev, prec)
+    S.sidm_diagnostics(ctx, [tree], dev, diag)
+    torch.cuda.synchronize()
+    t_tree = time.perf_counter() - t0
+    terms = S.read_diag(diag)[0]["n_grav_terms"]
+    # every member of a group sums its group's whole source list
+    per_particle = terms * 64 / n
+    at = [dev[f].cpu().numpy().copy() for f in ("ax", "ay", "az")]
+    print(f"TREE: first tree forces {t_tree * 1e3:.1f} ms, {per_particle:.0f} source terms per "
+          f"particle", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    S.sidm_gravity(ctx, [base], dev, prec)
+    torch.cuda.synchronize()
+    t_direct = time.perf_counter() - t0
+    ad = [dev[f].cpu().numpy() for f in ("ax", "ay", "az")]
+    err = np.sqrt(sum((x - y) ** 2 for x, y in zip(at, ad))) / np.sqrt(sum(y * y for y in ad))
+    S.sidm_destroy(ctx)
+    print(f"TREE: direct forces {t_direct * 1e3:.1f} ms; error median {np.median(err):.2e} "
+          f"p99 {np.percentile(err, 99):.2e} max {err.max():.2e}", file=sys.stderr, flush=True)
+    s_tree = dict(s, ax=ad[0], ay=ad[1], az=ad[2])
+    ms_t, de_t, p_t, d_t, _ = _run(S, torch, [tree], s_tree, prec, a.steps, a.warmup, True)
+    print(f"TREE: {a.steps} tree steps {ms_t * 1e3:.1f} ms each, |dE/E| {de_t:.2e}",
+          file=sys.stderr, flush=True)
+    direct = {"gravity_ms": t_direct * 1e3}
+    if n <= (1 << 22):
+        # full direct-sum steps from the same state (at N = 2^24 one direct step
+        # takes about 80 s; there the direct gravity time above stands for it)
+        ms_d, de_d, p_d, _, _ = _run(S, torch, [base], s, prec, a.steps, a.warmup, True)
+        direct.update(steps=a.steps, ms_per_step=ms_d * 1e3, dE_over_E=de_d, pass_ms=p_d)
+    inter = n * (n - 1)
+    out = {"metric": "gravity interactions/s (direct-sum equivalent) with tree gravity, "
+                     "alpha=5e-4",
+           "value": inter / ms_t, "unit": "direct-equivalent gravity interactions/s",
+           "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms_t * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32 tree pair terms (compensated), f64 decisions and elsewhere",
+           "data": "synthetic NFW halo",
+           "config": {"workload": f"TREE: NFW N={n} satellite in the host, eps={cfg['eps']}, "
+                                  f"k=64, sigma/m=10, dt=1e-3, tree alpha=5e-4",
+                      "n": n, "tree_alpha": 5e-4},
+           "source_terms_per_particle": per_particle,
+           "tree_interactions_per_s": per_particle * n / (p_t["gravity_tiles"] * 1e-3),
+           "force_error": {
+               "median": float(np.median(err)), "p99": float(np.percentile(err, 99)),
+               "max": float(err.max())},
+           "first_forces_ms": {"tree": t_tree * 1e3, "direct": t_direct * 1e3},
+           "dE_over_E": de_t, "pass_ms": p_t, "events_last_step": d_t["n_events"],
+           "direct": direct,
+           "gravity_speedup_vs_direct": t_direct / t_tree,
+           "step_speedup_vs_direct": direct["ms_per_step"] / (ms_t * 1e3)
+           if "ms_per_step" in direct else None}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = _args()
     if a.gpus != 1:
@@ -332,6 +411,8 @@ def main():
         return _bench_c5(a, S, torch, W)
     if a.workload == "BLK":
         return _bench_blk(a, S, torch, W)
+    if a.workload == "TREE":
+        return _bench_tree(a, S, torch, W)
     cfg = W.config("C2")
     n = cfg["n"]
     s = W.make_state(cfg)

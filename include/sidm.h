@@ -100,6 +100,9 @@ typedef struct {
     int32_t max_bin;            /* block steps dt / 2^b, 0 <= b <= max_bin <=
                                    SIDM_MAX_BIN; must be 0 when eta = 0             */
     int32_t reserved;           /* set to 0                                        */
+    double tree_alpha;          /* > 0: self-gravity through the tree with this
+                                   relative opening parameter (Sec. 2, Table 1:
+                                   5e-4; see sidm_gravity); 0: direct sum          */
 } sidm_halo;
 
 /* Particle state (device pointers, length n_total each). */
@@ -134,6 +137,10 @@ typedef struct {
     int64_t n_p_gt1;            /* pairs with P > 1 (accepted with certainty)       */
     int32_t status;             /* SIDM_DEV_* bits                                  */
     int32_t reserved;
+    int64_t n_grav_terms;       /* tree halos: source terms (accepted nodes plus
+                                   particles of opened buckets) summed over the
+                                   groups by the tree walks since the step (or the
+                                   sidm_gravity call) began; 0 for direct sums      */
 } sidm_diag;
 
 #define SIDM_DEV_EVENT_OVERFLOW 1   /* more events than the context can hold: no

@@ -27,7 +27,7 @@ class OrcParams(C.Structure):
                 ("host_hern_M", C.c_double), ("host_hern_a", C.c_double),
                 ("host_disk", (C.c_double * 3) * 4), ("boundary_r", C.c_double),
                 ("boundary_c", C.c_double * 3), ("eta", C.c_double), ("dt_min", C.c_double),
-                ("max_bin", C.c_int32)]
+                ("max_bin", C.c_int32), ("tree_alpha", C.c_double)]
 
 
 def lib():
@@ -323,14 +323,16 @@ def diag(vx, vy, vz, m, pot, pext=None):
 
 # ---------------------------------------------------------------- step
 def make_params(G=1.0, eps=0.01, sigma_m=1.0, dt=1e-3, k=32, seed=0, host=None, sigma_w=0.0,
-                boundary=None, steps=None):
+                boundary=None, steps=None, tree_alpha=0.0):
     """host: None, an NFW dict (rho_s, r_s, center), or with "hern" = (M, a)
     and "disks" = [(M, a, b), ...] the Milky-Way host.  boundary: None or a
     dict (r, center) for the reflecting sphere.  steps: None (one KDK step of
-    dt) or a dict (eta, max_bin, dt_min) for a cycle of block time steps."""
+    dt) or a dict (eta, max_bin, dt_min) for a cycle of block time steps.
+    tree_alpha > 0: self-gravity through the tree (a_old = the state's a)."""
     p = OrcParams()
     p.G, p.eps, p.sigma_m, p.dt, p.k, p.seed = G, eps, sigma_m, dt, k, seed
     p.sigma_w = float(sigma_w)
+    p.tree_alpha = float(tree_alpha)
     if steps is not None:
         p.eta = float(steps["eta"])
         p.max_bin = int(steps["max_bin"])

@@ -1156,11 +1156,32 @@ int orc_tidal_radius(int64_t n, const double *x, const double *y, const double *
 /* ------------------------------------------------------------------------ */
 /* Total acceleration and potential at the current positions: self-gravity plus
  * the static host. */
+/* Self-gravity of all particles: the direct sum, or the tree with the
+ * accelerations held in (ax, ay, az) on entry as a_old. */
+static void self_gravity(int64_t n, const double *x, const double *y, const double *z,
+                         const double *m, const orc_params *p, double *ax, double *ay,
+                         double *az, double *pot)
+{
+    if (p->tree_alpha > 0.0) {
+        double *t = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1) * 4);
+        double *tx = t, *ty = t + n, *tz = t + 2 * n, *tp = t + 3 * n;
+        orc_tree_gravity(n, x, y, z, m, ax, ay, az, p->G, p->eps, p->tree_alpha, tx, ty, tz,
+                         tp, NULL);
+        memcpy(ax, tx, sizeof(double) * (size_t)n);
+        memcpy(ay, ty, sizeof(double) * (size_t)n);
+        memcpy(az, tz, sizeof(double) * (size_t)n);
+        memcpy(pot, tp, sizeof(double) * (size_t)n);
+        free(t);
+        return;
+    }
+    orc_gravity(n, x, y, z, m, p->G, p->eps, n, NULL, ax, ay, az, pot, NULL);
+}
+
 static void accel_total(int64_t n, const double *x, const double *y, const double *z,
                         const double *m, const orc_params *p,
                         double *ax, double *ay, double *az, double *pot)
 {
-    orc_gravity(n, x, y, z, m, p->G, p->eps, n, NULL, ax, ay, az, pot, NULL);
+    self_gravity(n, x, y, z, m, p, ax, ay, az, pot);
     if (p->host_kind != 0) {
         double *hx = (double *)malloc(sizeof(double) * (size_t)n * 4);
         double *hy = hx + n, *hz = hy + n, *hp = hz + n;
@@ -1265,7 +1286,27 @@ static void block_cycle(int64_t n, double *x, double *y, double *z, double *vx, 
         for (int64_t i = 0; i < n; ++i)
             if ((k & (((int64_t)1 << (B - bin[i])) - 1)) == 0) act[na++] = i;
         if (na == 0) continue;
-        orc_gravity(n, x, y, z, m, p->G, p->eps, na, act, gx, gy, gz, gp, NULL);
+        if (p->tree_alpha > 0.0) {
+            /* the tree for everyone (a_old: the last accelerations of each
+             * particle), kept for the active ones */
+            double *t = (double *)malloc(sizeof(double) * nn * 8);
+            double *tx = t, *ty = t + n, *tz = t + 2 * n, *tp = t + 3 * n;
+            double *ox = t + 4 * n, *oy = t + 5 * n, *oz = t + 6 * n;
+            memcpy(ox, ax, sizeof(double) * (size_t)n);
+            memcpy(oy, ay, sizeof(double) * (size_t)n);
+            memcpy(oz, az, sizeof(double) * (size_t)n);
+            orc_tree_gravity(n, x, y, z, m, ox, oy, oz, p->G, p->eps, p->tree_alpha, tx, ty, tz,
+                             tp, NULL);
+            for (int64_t t2 = 0; t2 < na; ++t2) {
+                gx[t2] = tx[act[t2]];
+                gy[t2] = ty[act[t2]];
+                gz[t2] = tz[act[t2]];
+                gp[t2] = tp[act[t2]];
+            }
+            free(t);
+        } else {
+            orc_gravity(n, x, y, z, m, p->G, p->eps, na, act, gx, gy, gz, gp, NULL);
+        }
         if (p->host_kind != 0) {
             for (int64_t t = 0; t < na; ++t) {
                 qx[t] = x[act[t]];

@@ -211,6 +211,8 @@ typedef struct orc_params_s {
     double eta;                 /* > 0: block time steps with this criterion  */
     double dt_min;              /* smallest allowed step (0: none)            */
     int32_t max_bin;            /* steps dt / 2^b, 0 <= b <= max_bin          */
+    double tree_alpha;          /* > 0: self-gravity by orc_tree_gravity with the
+                                   accelerations held on entry as a_old        */
 } orc_params;
 
 /* Time-step bin of one particle (Sec. 2: the gravitational criterion of

@@ -52,7 +52,7 @@ class SidmHalo(C.Structure):
                 ("host_hern_M", C.c_double), ("host_hern_a", C.c_double),
                 ("host_disk", (C.c_double * 3) * 4), ("boundary_r", C.c_double),
                 ("boundary_center", C.c_double * 3), ("eta", C.c_double), ("dt_min", C.c_double),
-                ("max_bin", C.c_int32), ("reserved", C.c_int32)]
+                ("max_bin", C.c_int32), ("reserved", C.c_int32), ("tree_alpha", C.c_double)]
 
 
 class SidmState(C.Structure):
@@ -64,7 +64,8 @@ class SidmDiag(C.Structure):
     _fields_ = [("K", C.c_double), ("W", C.c_double), ("Eext", C.c_double),
                 ("px", C.c_double), ("py", C.c_double), ("pz", C.c_double),
                 ("n_events", C.c_int64), ("n_rounds", C.c_int64), ("n_pairs", C.c_int64),
-                ("n_p_gt1", C.c_int64), ("status", C.c_int32), ("reserved", C.c_int32)]
+                ("n_p_gt1", C.c_int64), ("status", C.c_int32), ("reserved", C.c_int32),
+                ("n_grav_terms", C.c_int64)]
 
 
 class SidmCenter(C.Structure):
@@ -185,6 +186,7 @@ def make_halos(halos):
             arr[i].boundary_r = float(bnd["r"])
             for c in range(3):
                 arr[i].boundary_center[c] = float(bnd.get("center", (0.0, 0.0, 0.0))[c])
+        arr[i].tree_alpha = float(h.get("tree_alpha", 0.0))
         steps = h.get("steps")
         if steps is not None:
             arr[i].eta = float(steps["eta"])

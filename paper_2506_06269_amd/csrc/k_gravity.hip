@@ -283,17 +283,6 @@ __global__ __launch_bounds__(kGravThreads) void k_grav_mixed(
 }
 
 // ---------------------------------------------------------------- FP64 tiles
-// 1/sqrt(r2) for finite r2 > 0: the hardware estimate refined by one Newton
-// step, y1 = y0 + y0 (1 - r2 y0^2) / 2, which squares the estimate's relative
-// error (the general routine also handles 0, inf, NaN and denormals, which the
-// softened r2 >= eps^2 never is).
-__device__ inline double rsqrt_pos(double r2)
-{
-    const double y0 = __builtin_amdgcn_rsq(r2);
-    const double e = fma(-r2 * y0, y0, 1.0);
-    return fma(0.5 * y0, e, y0);
-}
-
 // Pair terms of one LDS tile for IREG i-particles in FP64 (see tile_f32).
 template <int IREG, bool EQM, bool DIAG>
 __device__ inline void tile_f64(const double4* __restrict__ tile, const double* xi,
@@ -489,6 +478,9 @@ int64_t gravity_slots(int device)
 // Expects the cell list of the current positions (sorted copies sx, sy, sz, sm
 // and perm) to be in place.  tick > 0: tick of a cycle of 2^bmax block steps
 // (bins in w.bin).
+hipError_t launch_tree_gravity(bool mixed, const Plan& P, Scratch& w, const sidm_state* s,
+                               int tick, int bmax, hipStream_t st);
+
 hipError_t launch_gravity(bool mixed, const Plan& P, Scratch& w, const sidm_state* s, int kick,
                           hipStream_t st, hipEvent_t tile_begin, hipEvent_t tile_end, int tick,
                           int bmax)
@@ -498,7 +490,17 @@ hipError_t launch_gravity(bool mixed, const Plan& P, Scratch& w, const sidm_stat
                        w.bsum);
     hipLaunchKernelGGL(k_halo_mass, dim3(P.n_halos), dim3(kStreamBlock), 0, st, w.halos, w.bsum,
                        w.cref);
-    if (mixed) {
+    if (P.has_tree) {
+        // tree halos: one partial row per particle from the walk
+        if (tile_begin) (void)hipEventRecord(tile_begin, st);
+        const hipError_t e = launch_tree_gravity(mixed, P, w, s, tick, bmax, st);
+        if (e != hipSuccess) return e;
+        tile_begin = nullptr;
+        if (P.n_items == 0 && tile_end) (void)hipEventRecord(tile_end, st);
+    }
+    if (P.n_items == 0) {
+        // no direct-sum halo
+    } else if (mixed) {
         hipLaunchKernelGGL(k_pack_frames, dim3(nb), dim3(kStreamBlock), 0, st, w.sx, w.sy, w.sz,
                            w.sm, w.blocks, w.halos, w.sub, w.sub_n, w.xm32);
         if (tile_begin) (void)hipEventRecord(tile_begin, st);

@@ -128,8 +128,8 @@ __global__ __launch_bounds__(kStreamBlock) void k_diag_block(
 // One block per halo: fixed-order sum of the block partials into sidm_diag.
 __global__ __launch_bounds__(kStreamBlock) void k_diag_halo(
     const HaloDev* __restrict__ halos, const double* __restrict__ bsum,
-    const long long* __restrict__ ev_counts, const int* __restrict__ status,
-    sidm_diag* __restrict__ diag)
+    const long long* __restrict__ ev_counts, const unsigned long long* __restrict__ tree_terms,
+    const int* __restrict__ status, sidm_diag* __restrict__ diag)
 {
     __shared__ double red[7][kStreamBlock];
     const HaloDev& H = halos[blockIdx.x];
@@ -156,6 +156,7 @@ __global__ __launch_bounds__(kStreamBlock) void k_diag_halo(
         d.n_p_gt1 = ev_counts ? ev_counts[4 * h + 3] : 0;
         d.status = (status ? status[h] : 0) | (red[6][0] > 0.0 ? SIDM_DEV_NONFINITE : 0);
         d.reserved = 0;
+        d.n_grav_terms = tree_terms ? (int64_t)tree_terms[h] : 0;
         diag[h] = d;
     }
 }
@@ -191,12 +192,13 @@ hipError_t launch_diag(const StreamBlock* d_blocks, int64_t n_blocks, const Halo
                        int n_halos, const double* x, const double* y, const double* z,
                        const double* vx, const double* vy, const double* vz, const double* m,
                        const double* pot, double* bsum, const long long* ev_counts,
-                       const int* status, sidm_diag* diag, hipStream_t st)
+                       const unsigned long long* tree_terms, const int* status, sidm_diag* diag,
+                       hipStream_t st)
 {
     hipLaunchKernelGGL(k_diag_block, dim3((unsigned)n_blocks), dim3(kStreamBlock), 0, st, d_blocks,
                        d_halos, x, y, z, vx, vy, vz, m, pot, bsum);
     hipLaunchKernelGGL(k_diag_halo, dim3(n_halos), dim3(kStreamBlock), 0, st, d_halos, bsum,
-                       ev_counts, status, diag);
+                       ev_counts, tree_terms, status, diag);
     return hipGetLastError();
 }
 

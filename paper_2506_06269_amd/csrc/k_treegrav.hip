@@ -1,0 +1,376 @@
+// k_treegrav.hip -- tree gravity (Sec. 2: a gravity tree opened with the
+// relative criterion alpha of Springel 2005, eq. 18; Table 1 runs use
+// alpha = 5e-4).
+//
+// The tree is the cell list's: the Morton-sorted particles of a halo cut into
+// buckets of kBucket, every kFanout consecutive nodes merged into a parent up
+// to one root, each node with its particles' bounding box.  This pass adds the
+// mass and first moments of every node (bucket sums in particle order, then
+// child sums in child order, no fused multiply-adds, so the centres of mass
+// are reproducible to the bit).
+//
+// A group is a bucket: one wave of 64 lanes, one member per lane, walks the
+// tree once for all members.  A node is accepted when its box and the group's
+// box are disjoint and (G M l^2)^2 <= alpha^2 |a_old|^2 r^8, with l the node
+// box's largest side, |a_old| the smallest previous acceleration of the
+// members and r the distance between the two boxes: the paper's criterion
+// G M l^2 <= alpha |a_old| r^4, squared (no square root in the decision) and
+// made to hold for every member and every particle of the node.  An accepted
+// node contributes its monopole; an opened bucket its particles.  Sources are
+// staged in an LDS list (the children of a popped node are tested by lanes
+// 0..7 at once, accepted ones appended by a ballot prefix); a full list is
+// summed by all lanes, each for its own member, with the self pair skipped in
+// the group's own bucket, and the list sums are folded into compensated
+// accumulators.  The result is one partial row per particle, finished by the
+// gravity finalize pass (G, host, kicks).
+//
+// FP64 form: positions and arithmetic in FP64.  Mixed form: the list holds
+// FP64 positions; each pair's separation is taken in FP64 and rounded to FP32,
+// the rest of the pair term is FP32, and the list sums are folded into FP32
+// Kahan accumulators.  (FP32 positions relative to the group's centre lose
+// close pairs in a sparse group: a bucket can span several length units, and
+// the rounding of both positions then reaches 1e-5 of the force.)  The
+// decisions are FP64 in both forms, so both sum the same terms.
+#include "sidm_plan.hpp"
+#include "sidm_steps.hpp"
+
+namespace sidm {
+
+constexpr int kTreeList = 192;                    // source list entries per group
+constexpr int kTreeStack = kFanout * (kMaxLevels + 2);
+
+// ---------------------------------------------------------------- moments
+__global__ __launch_bounds__(256) void k_tree_mom_bucket(
+    const BucketInfo* __restrict__ buckets, int64_t nb, const double* __restrict__ sx,
+    const double* __restrict__ sy, const double* __restrict__ sz, const double* __restrict__ sm,
+    double4* __restrict__ mom)
+{
+#pragma clang fp contract(off)
+    const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (b >= nb) return;
+    const BucketInfo B = buckets[b];
+    double M = 0.0, X = 0.0, Y = 0.0, Z = 0.0;
+    for (int q = 0; q < B.count; ++q) {
+        const int64_t p = B.start + q;
+        const double m = sm[p];
+        M += m;
+        X += m * sx[p];
+        Y += m * sy[p];
+        Z += m * sz[p];
+    }
+    mom[b] = make_double4(M, X, Y, Z);
+}
+
+__global__ __launch_bounds__(256) void k_tree_mom_node(const NodeTask* __restrict__ tasks,
+                                                       int64_t nt, double4* __restrict__ mom)
+{
+#pragma clang fp contract(off)
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= nt) return;
+    const NodeTask T = tasks[t];
+    double M = 0.0, X = 0.0, Y = 0.0, Z = 0.0;
+    for (int c = 0; c < T.nchild; ++c) {
+        const double4 q = mom[T.child0 + c];
+        M += q.x;
+        X += q.y;
+        Y += q.z;
+        Z += q.w;
+    }
+    mom[T.node] = make_double4(M, X, Y, Z);
+}
+
+// Zeroes the per-halo count of source terms.
+__global__ void k_tree_terms_reset(unsigned long long* __restrict__ terms, int n)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) terms[t] = 0ull;
+}
+
+// ---------------------------------------------------------------- criterion
+// Whether node c is accepted for a group with box gb (see the file header).
+__device__ inline bool tree_accept(const double* __restrict__ cb, double M, const double* gb,
+                                   double G, double alpha2, double a2min)
+{
+#pragma clang fp contract(off)
+    bool disjoint = false;
+    double d[3];
+    for (int k = 0; k < 3; ++k) {
+        if (cb[k] > gb[3 + k] || cb[3 + k] < gb[k]) disjoint = true;
+        const double lo = gb[k] - cb[3 + k], hi = cb[k] - gb[3 + k];
+        d[k] = fmax(fmax(lo, hi), 0.0);
+    }
+    if (!disjoint) return false;
+    if (M == 0.0) return true;
+    const double r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+    const double l = fmax(fmax(cb[3] - cb[0], cb[4] - cb[1]), cb[5] - cb[2]);
+    const double q = ((G * M) * l) * l;
+    const double lhs = q * q;
+    const double r4 = r2 * r2;
+    const double rhs = ((alpha2 * a2min) * r4) * r4;
+    return lhs <= rhs;
+}
+
+__device__ inline double wave_min(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// ---------------------------------------------------------------- list sums
+template <bool MIXED>
+struct TreeAcc;
+
+template <>
+struct TreeAcc<false> {
+    using Entry = double4;
+    double xi, yi, zi, eps2;
+    double sx = 0, sy = 0, sz = 0, sp = 0, cx = 0, cy = 0, cz = 0, cp = 0;
+
+    template <bool DIAG>
+    __device__ inline void run(const Entry* L, int a, int b, int self, double* p)
+    {
+        for (int jj = a; jj < b; ++jj) {
+            const double4 q = L[jj];
+            const double dx = q.x - xi, dy = q.y - yi, dz = q.z - zi;
+            const double r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
+            double rinv = rsqrt_pos(r2);
+            if (DIAG && jj == self) rinv = 0.0;
+            const double mr = q.w * rinv;
+            const double mr3 = mr * (rinv * rinv);
+            p[0] = fma(mr3, dx, p[0]);
+            p[1] = fma(mr3, dy, p[1]);
+            p[2] = fma(mr3, dz, p[2]);
+            p[3] += mr;
+        }
+    }
+    __device__ inline void sum(const Entry* L, int len, int self_lo, int self_n, int lane)
+    {
+        double p[4] = {0.0, 0.0, 0.0, 0.0};
+        if (self_lo < 0) {
+            run<false>(L, 0, len, -1, p);
+        } else {
+            run<false>(L, 0, self_lo, -1, p);
+            run<true>(L, self_lo, self_lo + self_n, self_lo + lane, p);
+            run<false>(L, self_lo + self_n, len, -1, p);
+        }
+        double y, t;
+        y = p[0] - cx; t = sx + y; cx = (t - sx) - y; sx = t;
+        y = p[1] - cy; t = sy + y; cy = (t - sy) - y; sy = t;
+        y = p[2] - cz; t = sz + y; cz = (t - sz) - y; sz = t;
+        y = p[3] - cp; t = sp + y; cp = (t - sp) - y; sp = t;
+    }
+    __device__ inline double4 result() const
+    {
+        return make_double4(sx - cx, sy - cy, sz - cz, sp - cp);
+    }
+};
+
+template <>
+struct TreeAcc<true> {
+    using Entry = double4;
+    double xi, yi, zi;
+    float eps2;
+    float sx = 0, sy = 0, sz = 0, sp = 0, cx = 0, cy = 0, cz = 0, cp = 0;
+
+    template <bool DIAG>
+    __device__ inline void run(const Entry* L, int a, int b, int self, float* p)
+    {
+#pragma unroll 4
+        for (int jj = a; jj < b; ++jj) {
+            const double4 q = L[jj];
+            const float dx = (float)(q.x - xi), dy = (float)(q.y - yi), dz = (float)(q.z - zi);
+            const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
+            float rinv = __builtin_amdgcn_rsqf(r2);
+            if (DIAG && jj == self) rinv = 0.f;
+            const float mr = (float)q.w * rinv;
+            const float mr3 = mr * (rinv * rinv);
+            p[0] = fmaf(mr3, dx, p[0]);
+            p[1] = fmaf(mr3, dy, p[1]);
+            p[2] = fmaf(mr3, dz, p[2]);
+            p[3] += mr;
+        }
+    }
+    __device__ inline void sum(const Entry* L, int len, int self_lo, int self_n, int lane)
+    {
+        float p[4] = {0.f, 0.f, 0.f, 0.f};
+        if (self_lo < 0) {
+            run<false>(L, 0, len, -1, p);
+        } else {
+            run<false>(L, 0, self_lo, -1, p);
+            run<true>(L, self_lo, self_lo + self_n, self_lo + lane, p);
+            run<false>(L, self_lo + self_n, len, -1, p);
+        }
+        float y, t;
+        y = p[0] - cx; t = sx + y; cx = (t - sx) - y; sx = t;
+        y = p[1] - cy; t = sy + y; cy = (t - sy) - y; sy = t;
+        y = p[2] - cz; t = sz + y; cz = (t - sz) - y; sz = t;
+        y = p[3] - cp; t = sp + y; cp = (t - sp) - y; sp = t;
+    }
+    __device__ inline double4 result() const
+    {
+        return make_double4((double)sx - (double)cx, (double)sy - (double)cy,
+                            (double)sz - (double)cz, (double)sp - (double)cp);
+    }
+};
+
+__device__ inline double4 make_entry(double x, double y, double z, double m)
+{
+    return make_double4(x, y, z, m);
+}
+
+// ---------------------------------------------------------------- walk
+// One block = one wave = one group.  tick > 0: tick of a cycle of block steps
+// (groups without an active member are skipped).
+template <bool MIXED>
+__global__ __launch_bounds__(64) void k_tree_walk(
+    const BucketInfo* __restrict__ buckets, const NodeChild* __restrict__ nodes,
+    const double* __restrict__ box, const double4* __restrict__ mom,
+    const HaloDev* __restrict__ halos, const double* __restrict__ sx,
+    const double* __restrict__ sy, const double* __restrict__ sz, const double* __restrict__ sm,
+    const uint32_t* __restrict__ perm, const double* __restrict__ ax_old,
+    const double* __restrict__ ay_old, const double* __restrict__ az_old,
+    const int8_t* __restrict__ bin, int tick, int bmax, double4* __restrict__ partial,
+    unsigned long long* __restrict__ terms)
+{
+    using Acc = TreeAcc<MIXED>;
+    using Entry = typename Acc::Entry;
+    __shared__ Entry list[kTreeList];
+    __shared__ int stack[kTreeStack];
+
+    const int64_t g = blockIdx.x;
+    const int lane = threadIdx.x;
+    const BucketInfo GB = buckets[g];
+    const HaloDev& H = halos[GB.halo];
+    if (!(H.tree_alpha > 0.0)) return;
+    const bool live = lane < GB.count;
+    const int64_t p = GB.start + (live ? lane : 0);
+    const int64_t o = perm[p];
+    if (tick > 0) {
+        const int kl = local_tick(H, tick, bmax);
+        const bool act = live && kl > 0 && bin_active(H, bin[o], kl);
+        if (!__syncthreads_or(act)) return;
+    }
+    double gb[6];
+    for (int q = 0; q < 6; ++q) gb[q] = box[6 * g + q];
+    double a2;
+    {
+#pragma clang fp contract(off)
+        const double ux = ax_old[o], uy = ay_old[o], uz = az_old[o];
+        a2 = live ? (ux * ux + uy * uy) + uz * uz : INFINITY;
+    }
+    const double a2min = wave_min(a2);
+    const double alpha2 = H.tree_alpha * H.tree_alpha;
+
+    Acc acc;
+    {
+        acc.xi = sx[p];
+        acc.yi = sy[p];
+        acc.zi = sz[p];
+        acc.eps2 = H.eps2;
+    }
+
+    const int64_t root = H.level_off[H.n_levels - 1];
+    int sp = 1, len = 0, self_lo = -1, self_n = 0;
+    unsigned long long total = 0;
+    if (lane == 0) stack[0] = (int)root;
+    __syncthreads();
+
+    auto flush = [&]() {
+        __syncthreads();
+        if (len > 0) acc.sum(list, len, self_lo, self_n, lane);
+        total += (unsigned long long)len;
+        len = 0;
+        self_lo = -1;
+        __syncthreads();
+    };
+
+    while (sp > 0) {
+        const int node = stack[sp - 1];
+        --sp;
+        const NodeChild nd = nodes[node];
+        if (nd.nchild == 0) {
+            // an opened bucket: its particles
+            const BucketInfo Bk = buckets[node];
+            if (len + Bk.count > kTreeList) flush();
+            if (lane < Bk.count) {
+                const int64_t q = Bk.start + lane;
+                list[len + lane] = make_entry(sx[q], sy[q], sz[q], sm[q]);
+            }
+            if (node == g) {
+                self_lo = len;
+                self_n = Bk.count;
+            }
+            len += Bk.count;
+            __syncthreads();
+            continue;
+        }
+        bool take = false, open = false;
+        Entry e{};
+        if (lane < nd.nchild) {
+            const int64_t c = nd.child0 + lane;
+            double cb[6];
+            for (int q = 0; q < 6; ++q) cb[q] = box[6 * c + q];
+            const double4 mm = mom[c];
+            if (tree_accept(cb, mm.x, gb, H.G, alpha2, a2min)) {
+                if (mm.x != 0.0) {
+                    take = true;
+                    e = make_entry(mm.y / mm.x, mm.z / mm.x, mm.w / mm.x, mm.x);
+                }
+            } else {
+                open = true;
+            }
+        }
+        const unsigned long long tm = __ballot(take);
+        const unsigned long long om = __ballot(open);
+        const int nt = __popcll(tm), no = __popcll(om);
+        if (len + nt > kTreeList) flush();
+        const unsigned long long below = (1ull << lane) - 1ull;
+        if (take) list[len + __popcll(tm & below)] = e;
+        len += nt;
+        // opened children: the lowest index on top of the stack
+        if (open) stack[sp + __popcll(om & ~below & ~(1ull << lane))] = (int)(nd.child0 + lane);
+        sp += no;
+        __syncthreads();
+    }
+    flush();
+    if (live) partial[H.part_base + (p - H.sbase)] = acc.result();
+    if (lane == 0) atomicAdd(&terms[GB.halo], total);
+}
+
+// ---------------------------------------------------------------- launcher
+static unsigned grid_of(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+// Expects the cell list and its boxes in place; writes partial row 0 of every
+// particle of a tree halo and adds each halo's source terms to w.tree_terms.
+hipError_t launch_tree_gravity(bool mixed, const Plan& P, Scratch& w, const sidm_state* s,
+                               int tick, int bmax, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_tree_mom_bucket, dim3(grid_of(P.n_buckets, 256)), dim3(256), 0, st,
+                       w.buckets, P.n_buckets, w.sx, w.sy, w.sz, w.sm, w.mom);
+    for (int l = 1; l < P.n_levels; ++l) {
+        const int64_t t0 = P.level_task_off[l - 1], nt = P.level_task_off[l] - t0;
+        if (nt > 0)
+            hipLaunchKernelGGL(k_tree_mom_node, dim3(grid_of(nt, 256)), dim3(256), 0, st,
+                               w.node_tasks + t0, nt, w.mom);
+    }
+    if (mixed)
+        hipLaunchKernelGGL(k_tree_walk<true>, dim3((unsigned)P.n_buckets), dim3(64), 0, st,
+                           w.buckets, w.nodes, w.box, w.mom, w.halos, w.sx, w.sy, w.sz, w.sm,
+                           w.perm, s->ax, s->ay, s->az, w.bin, tick, bmax, w.partial,
+                           w.tree_terms);
+    else
+        hipLaunchKernelGGL(k_tree_walk<false>, dim3((unsigned)P.n_buckets), dim3(64), 0, st,
+                           w.buckets, w.nodes, w.box, w.mom, w.halos, w.sx, w.sy, w.sz, w.sm,
+                           w.perm, s->ax, s->ay, s->az, w.bin, tick, bmax, w.partial,
+                           w.tree_terms);
+    return hipGetLastError();
+}
+
+hipError_t launch_tree_terms_reset(Scratch& w, int n_halos, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_tree_terms_reset, dim3(grid_of(n_halos, 64)), dim3(64), 0, st,
+                       w.tree_terms, n_halos);
+    return hipGetLastError();
+}
+
+}  // namespace sidm

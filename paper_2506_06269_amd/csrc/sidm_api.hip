@@ -25,7 +25,8 @@ hipError_t launch_diag(const StreamBlock* d_blocks, int64_t n_blocks, const Halo
                        int n_halos, const double* x, const double* y, const double* z,
                        const double* vx, const double* vy, const double* vz, const double* m,
                        const double* pot, double* bsum, const long long* ev_counts,
-                       const int* status, sidm_diag* diag, hipStream_t st);
+                       const unsigned long long* tree_terms, const int* status, sidm_diag* diag,
+                       hipStream_t st);
 
 hipError_t launch_center(const StreamBlock* d_blocks, int64_t n_blocks, const HaloDev* d_halos,
                          int n_halos, const double* radius, const double* x, const double* y,
@@ -49,6 +50,7 @@ hipError_t launch_knn(const Plan& plan, const sidm_state* s, Scratch& w, uint32_
                       hipStream_t st);
 hipError_t launch_tree_hmax(const Plan& plan, Scratch& w, hipStream_t st);
 hipError_t launch_reset(const Plan& plan, Scratch& w, hipStream_t st);
+hipError_t launch_tree_terms_reset(Scratch& w, int n_halos, hipStream_t st);
 hipError_t launch_scatter(const Plan& plan, const sidm_state* s, Scratch& w, uint32_t step,
                           sidm_event* out_events, int64_t out_cap, hipStream_t st,
                           hipEvent_t after_pairs);
@@ -198,6 +200,10 @@ sidm_status validate(sidm_ctx* c, const sidm_halo* halos, int32_t n_halos, const
             set_err(c, "halo %d: boundary_r must be finite and >= 0", h);
             return SIDM_ERR_INVALID;
         }
+        if (!(H.tree_alpha >= 0.0) || !std::isfinite(H.tree_alpha)) {
+            set_err(c, "halo %d: tree_alpha must be finite and >= 0", h);
+            return SIDM_ERR_INVALID;
+        }
         if (!(H.eta >= 0.0) || !std::isfinite(H.eta) || !(H.dt_min >= 0.0) ||
             !std::isfinite(H.dt_min) || H.max_bin < 0 || H.max_bin > SIDM_MAX_BIN ||
             (H.eta == 0.0 && H.max_bin != 0)) {
@@ -334,7 +340,8 @@ sidm_status sidm_gravity(sidm_ctx* c, const sidm_halo* halos, int32_t n_halos,
     DeviceGuard g(c->device);
     hipStream_t st = (hipStream_t)stream;
     if ((r = ensure_plan(c, halos, n_halos, st)) != SIDM_OK) return r;
-    hipError_t e = launch_cell_list(c->plan, s, c->w, st);
+    hipError_t e = launch_tree_terms_reset(c->w, n_halos, st);
+    if (e == hipSuccess) e = launch_cell_list(c->plan, s, c->w, st);
     if (e == hipSuccess)
         e = launch_gravity(prec == SIDM_PREC_MIXED, c->plan, c->w, s, 0, st, nullptr, nullptr);
     if (e != hipSuccess) return hip_fail(c, e, "gravity launch");
@@ -422,6 +429,7 @@ sidm_status sidm_kdk_step(sidm_ctx* c, const sidm_halo* halos, int32_t n_halos,
         if (halos[h].eta > 0.0) bmax = std::max(bmax, (int)halos[h].max_bin);
     mark(0);
     hipError_t e = launch_reset(P, c->w, st);
+    if (e == hipSuccess) e = launch_tree_terms_reset(c->w, n_halos, st);
     if (bmax < 0) {
         if (e == hipSuccess)
             e = launch_kick_drift(c->w.blocks, P.n_blocks, c->w.halos, s->x, s->y, s->z, s->vx,
@@ -457,8 +465,8 @@ sidm_status sidm_kdk_step(sidm_ctx* c, const sidm_halo* halos, int32_t n_halos,
     mark(8);
     if (e == hipSuccess && diag)
         e = launch_diag(c->w.blocks, P.n_blocks, c->w.halos, n_halos, s->x, s->y, s->z, s->vx,
-                        s->vy, s->vz, s->m, s->pot, c->w.bsum, c->w.ev_counts, c->w.status, diag,
-                        st);
+                        s->vy, s->vz, s->m, s->pot, c->w.bsum, c->w.ev_counts, c->w.tree_terms,
+                        c->w.status, diag, st);
     mark(9);
     c->timed = tm;
     if (e != hipSuccess) return hip_fail(c, e, "step launch");
@@ -481,6 +489,7 @@ sidm_status sidm_diagnostics(sidm_ctx* c, const sidm_halo* halos, int32_t n_halo
     const Plan& P = c->plan;
     hipError_t e = launch_diag(c->w.blocks, P.n_blocks, c->w.halos, n_halos, s->x, s->y, s->z,
                                s->vx, s->vy, s->vz, s->m, s->pot, c->w.bsum, c->w.ev_counts,
+                               c->w.tree_terms,
                                c->w.status, diag, st);
     if (e != hipSuccess) return hip_fail(c, e, "diagnostics launch");
     c->err.clear();

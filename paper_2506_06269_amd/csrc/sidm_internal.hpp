@@ -34,6 +34,7 @@ struct HaloDev {
     double bnd_r, bnd_c[3];               // reflecting sphere (bnd_r = 0: none)
     double eta, dt_min;                   // block time steps (eta = 0: one fixed step)
     int32_t max_bin, pad1;
+    double tree_alpha;                    // > 0: gravity through the tree walk
     // search tree: level 0 are the buckets, node ranges per level (global index
     // into the box arrays)
     int64_t level_off[kMaxLevels + 1];
@@ -75,5 +76,18 @@ struct DevCounters {
     unsigned long long n_events_total;    // events found (may exceed capacity)
     unsigned long long ticket;            // persistent-kernel work counter
 };
+
+#ifdef __HIPCC__
+// 1/sqrt(r2) for finite r2 > 0: the hardware estimate refined by one Newton
+// step, y1 = y0 + y0 (1 - r2 y0^2) / 2, which squares the estimate's relative
+// error (the general routine also handles 0, inf, NaN and denormals, which the
+// softened r2 >= eps^2 never is).
+__device__ inline double rsqrt_pos(double r2)
+{
+    const double y0 = __builtin_amdgcn_rsq(r2);
+    const double e = fma(-r2 * y0, y0, 1.0);
+    return fma(0.5 * y0, e, y0);
+}
+#endif
 
 }  // namespace sidm

@@ -83,6 +83,8 @@ struct Scratch {
     double *svx = nullptr, *svy = nullptr, *svz = nullptr;
     double *sh = nullptr, *sm = nullptr;
     int8_t* bin = nullptr;        // block time-step bin per particle (caller's order)
+    double4* mom = nullptr;       // per node: mass and first moments (tree gravity)
+    unsigned long long* tree_terms = nullptr;   // per halo: source terms of the tree walk
     uint32_t* sid = nullptr;
     uint32_t* perm = nullptr;
     double* box = nullptr;        // 6 per node (buckets first)
@@ -104,6 +106,7 @@ struct Plan {
     int64_t n_blocks = 0, n_items = 0, n_buckets = 0, n_nodes = 0;
     int n_levels = 1;                 // max levels over halos
     int key_bits = 48;
+    bool has_tree = false;            // some halo uses the tree walk
     int64_t sort_blocks = 0;
     std::vector<HaloDev> halos;
     std::vector<StreamBlock> blocks;
@@ -162,7 +165,8 @@ inline bool alloc_scratch(Scratch& w, int64_t N, int32_t H, int64_t max_events, 
               dalloc(w.keys[1], N) && dalloc(w.vals[0], N) && dalloc(w.vals[1], N) &&
               dalloc(w.hist, w.hist_cap) && dalloc(w.sx, N) && dalloc(w.sy, N) &&
               dalloc(w.sz, N) && dalloc(w.sp4, N) && dalloc(w.svx, N) && dalloc(w.svy, N) && dalloc(w.svz, N) &&
-              dalloc(w.sh, N) && dalloc(w.sm, N) && dalloc(w.bin, N) && dalloc(w.sid, N) && dalloc(w.perm, N) &&
+              dalloc(w.sh, N) && dalloc(w.sm, N) && dalloc(w.bin, N) &&
+              dalloc(w.mom, w.nodes_cap) && dalloc(w.tree_terms, H) && dalloc(w.sid, N) && dalloc(w.perm, N) &&
               dalloc(w.box, 6 * w.nodes_cap) && dalloc(w.hmax, w.nodes_cap) &&
               dalloc(w.sub, kSubMax * w.buckets_cap) && dalloc(w.sub_n, w.buckets_cap) &&
               dalloc(w.owner, N) && dalloc(w.counters, 1) && dalloc(w.ev_counts, 4 * H) &&
@@ -191,7 +195,7 @@ inline void free_scratch(Scratch& w)
     dfree(w.bsum); dfree(w.cref); dfree(w.radius); dfree(w.center); dfree(w.tidal); dfree(w.bbox); dfree(w.xm32);  dfree(w.partial);
     dfree(w.keys[0]); dfree(w.keys[1]); dfree(w.vals[0]); dfree(w.vals[1]); dfree(w.hist);
     dfree(w.sx); dfree(w.sy); dfree(w.sz); dfree(w.sp4); dfree(w.svx); dfree(w.svy); dfree(w.svz);
-    dfree(w.sh); dfree(w.sm); dfree(w.bin); dfree(w.sid); dfree(w.perm); dfree(w.box); dfree(w.hmax);
+    dfree(w.sh); dfree(w.sm); dfree(w.bin); dfree(w.mom); dfree(w.tree_terms); dfree(w.sid); dfree(w.perm); dfree(w.box); dfree(w.hmax);
     dfree(w.sub); dfree(w.sub_n);
     dfree(w.owner); dfree(w.events); dfree(w.counters); dfree(w.ev_counts); dfree(w.status);
 }
@@ -206,9 +210,11 @@ inline void choose_splits(std::vector<HaloDev>& hd, int64_t partial_rows, int64_
     const int64_t kIBlock = kGravThreads * 4;
     int64_t iblocks = 0, ntot = 0;
     for (auto& H : hd) {
+        if (H.tree_alpha > 0.0) continue;
         iblocks += (H.n + kIBlock - 1) / kIBlock;
         ntot += H.n;
     }
+    iblocks = std::max<int64_t>(iblocks, 1);
     const int64_t smax = std::min<int64_t>(4, std::max<int64_t>(1, partial_rows / std::max<int64_t>(ntot, 1)));
     int64_t best = 1;
     if (slots <= 0) {
@@ -220,6 +226,7 @@ inline void choose_splits(std::vector<HaloDev>& hd, int64_t partial_rows, int64_
         for (int64_t sp = 1; sp <= smax; ++sp) {
             cost.clear();
             for (auto& H : hd) {
+                if (H.tree_alpha > 0.0) continue;
                 const int64_t tiles = (H.n + kGravTileJ - 1) / kGravTileJ;
                 const int64_t s_h = std::max<int64_t>(1, std::min<int64_t>(sp, tiles));
                 const int64_t ib = (H.n + kIBlock - 1) / kIBlock;
@@ -248,7 +255,8 @@ inline void choose_splits(std::vector<HaloDev>& hd, int64_t partial_rows, int64_
     }
     for (auto& H : hd) {
         const int64_t tiles = (H.n + kGravTileJ - 1) / kGravTileJ;
-        H.grav_split = (int32_t)std::max<int64_t>(1, std::min<int64_t>(best, tiles));
+        H.grav_split = H.tree_alpha > 0.0 ? 1
+                                           : (int32_t)std::max<int64_t>(1, std::min<int64_t>(best, tiles));
     }
 }
 
@@ -305,6 +313,8 @@ inline bool build_plan(Plan& P, const Scratch& w, const sidm_halo* halos, int32_
         H.eta = S.eta;
         H.dt_min = S.dt_min;
         H.max_bin = S.eta > 0.0 ? S.max_bin : 0;
+        H.tree_alpha = S.tree_alpha;
+        if (S.tree_alpha > 0.0) P.has_tree = true;
         H.sbase = sbase[h];
         H.rank = P.rank_of[h];
         // streaming blocks
@@ -372,6 +382,7 @@ inline bool build_plan(Plan& P, const Scratch& w, const sidm_halo* halos, int32_
         HaloDev& H = P.halos[h];
         H.part_base = prow;
         prow += H.n * H.grav_split;
+        if (H.tree_alpha > 0.0) continue;   // the tree walk covers this halo
         const int64_t tiles = (H.n + kGravTileJ - 1) / kGravTileJ;
         for (int s = 0; s < H.grav_split; ++s) {
             const int64_t t0 = tiles * s / H.grav_split, t1 = tiles * (s + 1) / H.grav_split;

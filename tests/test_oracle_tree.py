@@ -97,3 +97,21 @@ def test_distant_cluster_acts_as_its_monopole(orc):
     for c in range(3):
         got = t[c][:n1] - near[c]
         assert np.max(np.abs(got - far[c])) < 1e-5 * np.max(np.abs(far[0]))
+
+
+def test_step_with_a_vanishing_alpha_is_the_direct_step(orc):
+    """tree_alpha = 1e-300 runs the step's tree path with every node opened
+    (r^8 alpha^2 underflows): the same step as the direct sum to rounding."""
+    n = 700
+    s = W.nfw_halo(n, seed=87)
+    p0 = orc.make_params(eps=0.02, sigma_m=5.0, dt=4e-3, k=16, seed=3)
+    p1 = orc.make_params(eps=0.02, sigma_m=5.0, dt=4e-3, k=16, seed=3, tree_alpha=1e-300)
+    orc.total_accel(s, p0)
+    a = {k: np.array(v, copy=True) for k, v in s.items()}
+    b = {k: np.array(v, copy=True) for k, v in s.items()}
+    for step in range(2):
+        ea = orc.kdk_step(a, p0, step)
+        eb = orc.kdk_step(b, p1, step)
+        assert ea.size == eb.size
+        for k in ("x", "y", "z", "vx", "vy", "vz", "ax", "ay", "az", "pot"):
+            assert np.max(np.abs(a[k] - b[k])) <= 1e-13 * np.max(np.abs(a[k])), k
