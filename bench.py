@@ -321,8 +321,9 @@ def _bench_tree(a, S, torch, W):
     in the host: force errors of the first tree evaluation against the GPU's
     direct sum on the same state, then --steps steps with the tree and with the
     direct sum from the same state (mixed precision), time and |dE/E| of each.
-    The first tree evaluation takes a_old from a tree pass that accepts every
-    node whose box is disjoint from the group's (a_old = 1e300)."""
+    The measured tree evaluation takes a_old from a tree pass whose own a_old
+    came from a pass that accepts every node whose box is disjoint from the
+    group's (a_old = 1e300)."""
     import numpy as np
     cfg = W.config("C5" if a.tree_n > (1 << 22) else "C2")
     n = a.tree_n
@@ -335,7 +336,8 @@ def _bench_tree(a, S, torch, W):
     diag = S.diag_buffer(1)
     for f in ("ax", "ay", "az"):
         dev[f].fill_(1e300)
-    S.sidm_gravity(ctx, [tree], dev, prec)
+    S.sidm_gravity(ctx, [tree], dev, prec)      # seed: every disjoint node accepted
+    S.sidm_gravity(ctx, [tree], dev, prec)      # a_old from the seed
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     S.sidm_gravity(ctx, [tree], dev, prec)
@@ -343,7 +345,7 @@ def _bench_tree(a, S, torch, W):
     torch.cuda.synchronize()
     t_tree = time.perf_counter() - t0
     terms = S.read_diag(diag)[0]["n_grav_terms"]
-    # every member of a group sums its group's whole source list
+    # every member of a group (a 64-particle bucket) sums its group's list
     per_particle = terms * 64 / n
     at = [dev[f].cpu().numpy().copy() for f in ("ax", "ay", "az")]
     print(f"TREE: first tree forces {t_tree * 1e3:.1f} ms, {per_particle:.0f} source terms per "

@@ -36,8 +36,11 @@
 
 namespace sidm {
 
-constexpr int kTreeList = 192;                    // source list entries per group
-constexpr int kTreeStack = kFanout * (kMaxLevels + 2);
+constexpr int kTreeList = 128;                    // source list entries per group
+// Popping kFanout nodes per round and pushing at most kFanout^2 children, the
+// stack holds at most (kFanout^2 - kFanout) nodes per level plus one round's
+// pushes: 56 * kMaxLevels + 64 = 624 for ten levels.
+constexpr int kTreeStack = (kFanout * kFanout - kFanout) * kMaxLevels + kFanout * kFanout;
 
 // ---------------------------------------------------------------- moments
 __global__ __launch_bounds__(256) void k_tree_mom_bucket(
@@ -235,7 +238,8 @@ __global__ __launch_bounds__(64) void k_tree_walk(
     using Acc = TreeAcc<MIXED>;
     using Entry = typename Acc::Entry;
     __shared__ Entry list[kTreeList];
-    __shared__ int stack[kTreeStack];
+    // pending inner nodes as (first child, number of children)
+    __shared__ int2 stack[kTreeStack];
 
     const int64_t g = blockIdx.x;
     const int lane = threadIdx.x;
@@ -270,10 +274,8 @@ __global__ __launch_bounds__(64) void k_tree_walk(
     }
 
     const int64_t root = H.level_off[H.n_levels - 1];
-    int sp = 1, len = 0, self_lo = -1, self_n = 0;
+    int sp = 0, len = 0, self_lo = -1, self_n = 0;
     unsigned long long total = 0;
-    if (lane == 0) stack[0] = (int)root;
-    __syncthreads();
 
     auto flush = [&]() {
         __syncthreads();
@@ -283,53 +285,85 @@ __global__ __launch_bounds__(64) void k_tree_walk(
         self_lo = -1;
         __syncthreads();
     };
-
-    while (sp > 0) {
-        const int node = stack[sp - 1];
-        --sp;
-        const NodeChild nd = nodes[node];
-        if (nd.nchild == 0) {
-            // an opened bucket: its particles
-            const BucketInfo Bk = buckets[node];
-            if (len + Bk.count > kTreeList) flush();
-            if (lane < Bk.count) {
-                const int64_t q = Bk.start + lane;
-                list[len + lane] = make_entry(sx[q], sy[q], sz[q], sm[q]);
-            }
-            if (node == g) {
-                self_lo = len;
-                self_n = Bk.count;
-            }
-            len += Bk.count;
-            __syncthreads();
-            continue;
+    // appends the particles of an opened bucket
+    auto append_bucket = [&](int64_t start, int cnt, bool self) {
+        if (len + cnt > kTreeList) flush();
+        if (lane < cnt) {
+            const int64_t q = start + lane;
+            list[len + lane] = make_entry(sx[q], sy[q], sz[q], sm[q]);
         }
-        bool take = false, open = false;
+        if (self) {
+            self_lo = len;
+            self_n = cnt;
+        }
+        len += cnt;
+    };
+
+    {
+        const NodeChild rc = nodes[root];
+        if (rc.nchild > 0) {
+            if (lane == 0) stack[0] = make_int2((int)rc.child0, rc.nchild);
+            sp = 1;
+        } else {
+            append_bucket(GB.start, GB.count, true);   // a halo of one bucket
+        }
+        __syncthreads();
+    }
+
+    // Each round pops up to kFanout pending nodes; lane 8 s + k tests child k of
+    // the s-th popped node, so one round of dependent loads serves 64 children.
+    while (sp > 0) {
+        const int npop = sp < kFanout ? sp : kFanout;
+        const int slot = lane / kFanout, ci = lane % kFanout;
+        int2 nd = make_int2(0, 0);
+        if (slot < npop) nd = stack[sp - 1 - slot];
+        sp -= npop;
+        bool take = false, open_inner = false, open_bucket = false, self = false;
         Entry e{};
-        if (lane < nd.nchild) {
-            const int64_t c = nd.child0 + lane;
+        int2 push = make_int2(0, 0);
+        int64_t bstart = 0;
+        int bcnt = 0;
+        if (slot < npop && ci < nd.y) {
+            const int64_t c = (int64_t)nd.x + ci;
             double cb[6];
             for (int q = 0; q < 6; ++q) cb[q] = box[6 * c + q];
             const double4 mm = mom[c];
+            const NodeChild cc = nodes[c];
             if (tree_accept(cb, mm.x, gb, H.G, alpha2, a2min)) {
                 if (mm.x != 0.0) {
                     take = true;
                     e = make_entry(mm.y / mm.x, mm.z / mm.x, mm.w / mm.x, mm.x);
                 }
+            } else if (cc.nchild > 0) {
+                open_inner = true;
+                push = make_int2((int)cc.child0, cc.nchild);
             } else {
-                open = true;
+                open_bucket = true;
+                const BucketInfo cbk = buckets[c];
+                bstart = cbk.start;
+                bcnt = cbk.count;
+                self = c == g;
             }
         }
-        const unsigned long long tm = __ballot(take);
-        const unsigned long long om = __ballot(open);
-        const int nt = __popcll(tm), no = __popcll(om);
-        if (len + nt > kTreeList) flush();
+        __syncthreads();   // the popped entries are read before pushes reuse them
         const unsigned long long below = (1ull << lane) - 1ull;
+        const unsigned long long tm = __ballot(take);
+        const int nt = __popcll(tm);
+        if (len + nt > kTreeList) flush();
         if (take) list[len + __popcll(tm & below)] = e;
         len += nt;
-        // opened children: the lowest index on top of the stack
-        if (open) stack[sp + __popcll(om & ~below & ~(1ull << lane))] = (int)(nd.child0 + lane);
-        sp += no;
+        const unsigned long long om = __ballot(open_inner);
+        if (open_inner) stack[sp + __popcll(om & below)] = push;
+        sp += __popcll(om);
+        unsigned long long bm = __ballot(open_bucket);
+        while (bm) {
+            const int src = __ffsll((long long)bm) - 1;
+            bm &= bm - 1ull;
+            const int64_t st = __shfl(bstart, src, 64);
+            const int cnt = __shfl(bcnt, src, 64);
+            const int sf = __shfl((int)self, src, 64);
+            append_bucket(st, cnt, sf != 0);
+        }
         __syncthreads();
     }
     flush();
