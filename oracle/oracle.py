@@ -60,7 +60,8 @@ def _declare(L):
     L.orc_gravity.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, C.c_double, C.c_double,
                               C.c_int64, _i64p, _dp, _dp, _dp, _dp, _dp]
     L.orc_tree_gravity.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp, C.c_double,
-                                   C.c_double, C.c_double, _dp, _dp, _dp, _dp, _i64p]
+                                   C.c_double, C.c_double, C.c_int64, _i64p, _dp, _dp, _dp, _dp,
+                                   _i64p]
     L.orc_host_nfw.argtypes = [C.c_int64, _dp, _dp, _dp, C.c_double, C.c_double,
                                C.c_double, _dp, _dp, _dp, _dp, _dp]
     L.orc_knn.argtypes = [C.c_int64, _dp, _dp, _dp, _u32p, C.c_int32, C.c_int64,
@@ -160,17 +161,23 @@ def gravity(x, y, z, m, G, eps, query=None, want_norm=False):
     return ax, ay, az, pot
 
 
-def tree_gravity(x, y, z, m, a_old, G, eps, alpha):
+def tree_gravity(x, y, z, m, a_old, G, eps, alpha, query=None):
     """Tree self-gravity (a, phi) with the relative opening criterion; a_old =
-    (ax, ay, az) of the previous force computation.  Returns ax, ay, az, pot
-    and the number of source terms summed over the groups."""
+    (ax, ay, az) of the previous force computation.  query: None (all) or
+    particle indices.  Returns ax, ay, az, pot (per query) and the number of
+    source terms summed over the groups walked."""
     x, y, z, m = _f64(x), _f64(y), _f64(z), _f64(m)
     ox, oy, oz = (_f64(v) for v in a_old)
     n = x.size
-    ax, ay, az, pot = (np.zeros(n) for _ in range(4))
+    if query is None:
+        nq, qp = n, None
+    else:
+        query = np.ascontiguousarray(query, dtype=np.int64)
+        nq, qp = query.size, query.ctypes.data_as(_i64p)
+    ax, ay, az, pot = (np.zeros(nq) for _ in range(4))
     terms = C.c_int64(0)
     lib().orc_tree_gravity(n, _d(x), _d(y), _d(z), _d(m), _d(ox), _d(oy), _d(oz), float(G),
-                           float(eps), float(alpha), _d(ax), _d(ay), _d(az), _d(pot),
+                           float(eps), float(alpha), nq, qp, _d(ax), _d(ay), _d(az), _d(pot),
                            C.byref(terms))
     return ax, ay, az, pot, int(terms.value)
 

@@ -363,8 +363,9 @@ static void tree_visit(tree_walk *W, int64_t node)
 
 void orc_tree_gravity(int64_t n, const double *x, const double *y, const double *z,
                       const double *m, const double *ax_old, const double *ay_old,
-                      const double *az_old, double G, double eps, double alpha,
-                      double *ax, double *ay, double *az, double *pot, int64_t *terms)
+                      const double *az_old, double G, double eps, double alpha, int64_t nq,
+                      const int64_t *q, double *ax, double *ay, double *az, double *pot,
+                      int64_t *terms)
 {
     const int64_t B = 64, F = 8;
     if (terms) *terms = 0;
@@ -461,54 +462,80 @@ void orc_tree_gravity(int64_t n, const double *x, const double *y, const double 
         cnt = nn;
     }
     const int64_t root = top - 1;
-    /* one walk per group (bucket), then the members' sums over its list */
-    tree_walk W;
-    W.sx = sx; W.sy = sy; W.sz = sz; W.sm = sm; W.sidx = sidx;
-    W.nodes = nodes;
-    W.G = G;
-    W.eps2 = eps * eps;
-    W.alpha2 = alpha * alpha;
-    double *lbuf = (double *)malloc(sizeof(double) * (size_t)(n + cap) * 4);
-    W.lx = lbuf; W.ly = lbuf + (n + cap); W.lz = W.ly + (n + cap); W.lm = W.lz + (n + cap);
-    W.lidx = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + cap));
+    /* the groups that hold a queried particle (all of them without q) */
+    const int64_t nqq = q ? nq : n;
+    int64_t *pos = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    for (int64_t p = 0; p < n; ++p) pos[sidx[p]] = p;
+    key_idx *qe = (key_idx *)malloc(sizeof(key_idx) * (size_t)(nqq > 0 ? nqq : 1));
+    for (int64_t k = 0; k < nqq; ++k) {
+        const int64_t p = pos[q ? q[k] : k];
+        qe[k].key = (uint64_t)(p / B);
+        qe[k].idx = k;
+    }
+    qsort(qe, (size_t)nqq, sizeof(key_idx), cmp_key_idx);
+    int64_t *gstart = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nqq + 1));
+    int64_t ng = 0;
+    for (int64_t k = 0; k < nqq; ++k)
+        if (k == 0 || qe[k].key != qe[k - 1].key) gstart[ng++] = k;
+    gstart[ng] = nqq;
+    /* one walk per group (bucket), then the queried members' sums over its list */
     int64_t total = 0;
-    for (int64_t b = 0; b < nb; ++b) {
-        const tree_node *g = &nodes[b];
-        double a2min = INFINITY;
-        for (int64_t p = g->first; p < g->first + g->count; ++p) {
-            const int64_t i = sidx[p];
-            const double a2 = (ax_old[i] * ax_old[i] + ay_old[i] * ay_old[i]) +
-                              az_old[i] * az_old[i];
-            a2min = fmin(a2min, a2);
-        }
-        W.a2min = a2min;
-        W.gbox = g->box;
-        W.len = 0;
-        tree_visit(&W, root);
-        total += W.len;
-        for (int64_t p = g->first; p < g->first + g->count; ++p) {
-            neum gx = {0, 0}, gy = {0, 0}, gz = {0, 0}, gp = {0, 0};
-            for (int64_t t = 0; t < W.len; ++t) {
-                if (W.lidx[t] == p) continue;
-                const double dx = W.lx[t] - sx[p], dy = W.ly[t] - sy[p], dz = W.lz[t] - sz[p];
-                const double r2 = dx * dx + dy * dy + dz * dz + W.eps2;
-                const double rinv = 1.0 / sqrt(r2);
-                const double w = W.lm[t] * rinv * rinv * rinv;
-                neum_add(&gx, w * dx);
-                neum_add(&gy, w * dy);
-                neum_add(&gz, w * dz);
-                neum_add(&gp, -W.lm[t] * rinv);
+#pragma omp parallel reduction(+ : total)
+    {
+        tree_walk W;
+        W.sx = sx; W.sy = sy; W.sz = sz; W.sm = sm; W.sidx = sidx;
+        W.nodes = nodes;
+        W.G = G;
+        W.eps2 = eps * eps;
+        W.alpha2 = alpha * alpha;
+        const size_t lc = (size_t)(n + cap);
+        double *lbuf = (double *)malloc(sizeof(double) * lc * 4);
+        W.lx = lbuf; W.ly = lbuf + lc; W.lz = W.ly + lc; W.lm = W.lz + lc;
+        W.lidx = (int64_t *)malloc(sizeof(int64_t) * lc);
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t gi = 0; gi < ng; ++gi) {
+            const tree_node *g = &nodes[qe[gstart[gi]].key];
+            double a2min = INFINITY;
+            for (int64_t p = g->first; p < g->first + g->count; ++p) {
+                const int64_t i = sidx[p];
+                const double a2 = (ax_old[i] * ax_old[i] + ay_old[i] * ay_old[i]) +
+                                  az_old[i] * az_old[i];
+                a2min = fmin(a2min, a2);
             }
-            const int64_t i = sidx[p];
-            ax[i] = G * neum_get(&gx);
-            ay[i] = G * neum_get(&gy);
-            az[i] = G * neum_get(&gz);
-            pot[i] = G * neum_get(&gp);
+            W.a2min = a2min;
+            W.gbox = g->box;
+            W.len = 0;
+            tree_visit(&W, root);
+            total += W.len;
+            for (int64_t k = gstart[gi]; k < gstart[gi + 1]; ++k) {
+                const int64_t out = qe[k].idx;
+                const int64_t p = pos[q ? q[out] : out];
+                neum gx = {0, 0}, gy = {0, 0}, gz = {0, 0}, gp = {0, 0};
+                for (int64_t t = 0; t < W.len; ++t) {
+                    if (W.lidx[t] == p) continue;
+                    const double dx = W.lx[t] - sx[p], dy = W.ly[t] - sy[p],
+                                 dz = W.lz[t] - sz[p];
+                    const double r2 = dx * dx + dy * dy + dz * dz + W.eps2;
+                    const double rinv = 1.0 / sqrt(r2);
+                    const double w = W.lm[t] * rinv * rinv * rinv;
+                    neum_add(&gx, w * dx);
+                    neum_add(&gy, w * dy);
+                    neum_add(&gz, w * dz);
+                    neum_add(&gp, -W.lm[t] * rinv);
+                }
+                ax[out] = G * neum_get(&gx);
+                ay[out] = G * neum_get(&gy);
+                az[out] = G * neum_get(&gz);
+                pot[out] = G * neum_get(&gp);
+            }
         }
+        free(lbuf);
+        free(W.lidx);
     }
     if (terms) *terms = total;
-    free(lbuf);
-    free(W.lidx);
+    free(pos);
+    free(qe);
+    free(gstart);
     free(nodes);
     free(sorted);
     free(sidx);
@@ -1165,8 +1192,8 @@ static void self_gravity(int64_t n, const double *x, const double *y, const doub
     if (p->tree_alpha > 0.0) {
         double *t = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1) * 4);
         double *tx = t, *ty = t + n, *tz = t + 2 * n, *tp = t + 3 * n;
-        orc_tree_gravity(n, x, y, z, m, ax, ay, az, p->G, p->eps, p->tree_alpha, tx, ty, tz,
-                         tp, NULL);
+        orc_tree_gravity(n, x, y, z, m, ax, ay, az, p->G, p->eps, p->tree_alpha, n, NULL, tx,
+                         ty, tz, tp, NULL);
         memcpy(ax, tx, sizeof(double) * (size_t)n);
         memcpy(ay, ty, sizeof(double) * (size_t)n);
         memcpy(az, tz, sizeof(double) * (size_t)n);
@@ -1295,8 +1322,8 @@ static void block_cycle(int64_t n, double *x, double *y, double *z, double *vx, 
             memcpy(ox, ax, sizeof(double) * (size_t)n);
             memcpy(oy, ay, sizeof(double) * (size_t)n);
             memcpy(oz, az, sizeof(double) * (size_t)n);
-            orc_tree_gravity(n, x, y, z, m, ox, oy, oz, p->G, p->eps, p->tree_alpha, tx, ty, tz,
-                             tp, NULL);
+            orc_tree_gravity(n, x, y, z, m, ox, oy, oz, p->G, p->eps, p->tree_alpha, n, NULL, tx,
+                             ty, tz, tp, NULL);
             for (int64_t t2 = 0; t2 < na; ++t2) {
                 gx[t2] = tx[act[t2]];
                 gy[t2] = ty[act[t2]];

@@ -78,13 +78,17 @@ void orc_gravity(int64_t n, const double *x, const double *y, const double *z,
  * node is opened; an opened bucket contributes its particles.  Forces and
  * potentials: Plummer-softened pair terms with the accepted nodes' monopoles
  * and the contributed particles (self excluded), Neumaier sums.  alpha = 0
- * opens every node: the direct sum.  Writes ax, ay, az, pot in the caller's
- * order; `terms` (nullable) receives the number of source terms summed over
- * groups (accepted nodes plus contributed particles per group). */
+ * opens every node: the direct sum.  q == NULL: writes ax, ay, az, pot of all
+ * n particles in the caller's order; otherwise of the nq particles q[k] at
+ * index k (the whole tree is built, only the groups holding them walk).
+ * `terms` (nullable) receives the number of source terms summed over the
+ * groups walked (accepted nodes plus contributed particles per group).  Uses
+ * OpenMP over the groups. */
 void orc_tree_gravity(int64_t n, const double *x, const double *y, const double *z,
                       const double *m, const double *ax_old, const double *ay_old,
-                      const double *az_old, double G, double eps, double alpha,
-                      double *ax, double *ay, double *az, double *pot, int64_t *terms);
+                      const double *az_old, double G, double eps, double alpha, int64_t nq,
+                      const int64_t *q, double *ax, double *ay, double *az, double *pot,
+                      int64_t *terms);
 
 /* Static NFW host (paper Sec. 4.1, Eq. nfw_potential) centred at c:
  * Phi(r) = -4 pi G rho_s r_s^3 ln(1 + r/r_s) / r and a = -grad Phi.

@@ -108,3 +108,44 @@ def test_full_size_gravity_mixed(S, orc, c5):
     assert da.max() < 1e-5
     assert dp.max() < 1e-5
     del dev
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_full_size_tree(S, orc, c5, prec):
+    """Tree gravity (alpha = 5e-4) at N = 2^24 as its benchmark runs it (a_old
+    from a pass that accepts every disjoint node, then a pass with those
+    accelerations): the forces and potentials of 256 sampled particles (and
+    the first and last) against the oracle's tree on the same a_old, normwise
+    against the direct-sum scale, 1e-5 (mixed) or 1e-12 (FP64)."""
+    import torch
+    cfg, s, halo, ctx = c5
+    n = cfg["n"]
+    tree = dict(halo, tree_alpha=5e-4)
+    dev = S.state_to_device(s)
+    for f in ("ax", "ay", "az"):
+        dev[f].fill_(1e300)
+    S.sidm_gravity(ctx, [tree], dev, prec)
+    torch.cuda.synchronize()
+    a_old = [dev[f].cpu().numpy().copy() for f in ("ax", "ay", "az")]
+    print(f"tree gravity, prec {prec}", flush=True)
+    S.sidm_gravity(ctx, [tree], dev, prec)
+    torch.cuda.synchronize()
+    out = S.state_to_host(dev)
+    q = np.random.default_rng(11).choice(n, 256, replace=False)
+    q = np.concatenate([q, [0, n - 1]])
+    tx, ty, tz, tp, _ = orc.tree_gravity(s["x"], s["y"], s["z"], s["m"], a_old, 1.0, cfg["eps"],
+                                         5e-4, query=q)
+    _, _, _, _, an = orc.gravity(s["x"], s["y"], s["z"], s["m"], 1.0, cfg["eps"], query=q,
+                                 want_norm=True)
+    H = halo["host"]
+    hx, hy, hz, hp = orc.host_nfw(s["x"][q], s["y"][q], s["z"][q], 1.0, H["rho_s"], H["r_s"],
+                                  H["center"])
+    tx, ty, tz, tp = tx + hx, ty + hy, tz + hz, tp + hp
+    an = an + np.sqrt(hx ** 2 + hy ** 2 + hz ** 2)
+    da = np.sqrt((out["ax"][q] - tx) ** 2 + (out["ay"][q] - ty) ** 2 +
+                 (out["az"][q] - tz) ** 2) / an
+    dp = np.abs(out["pot"][q] - tp) / np.abs(tp)
+    tol = 1e-5 if prec == 1 else 1e-12
+    print(f"N=2^24 tree sampled: max e_a={da.max():.3e} e_phi={dp.max():.3e}", flush=True)
+    assert da.max() < tol and dp.max() < tol
+    del dev

@@ -115,3 +115,18 @@ def test_step_with_a_vanishing_alpha_is_the_direct_step(orc):
         assert ea.size == eb.size
         for k in ("x", "y", "z", "vx", "vy", "vz", "ax", "ay", "az", "pot"):
             assert np.max(np.abs(a[k] - b[k])) <= 1e-13 * np.max(np.abs(a[k])), k
+
+
+def test_query_form_equals_the_full_form(orc):
+    """Forces of a sample of particles (repeats and the last one included)
+    equal those of the full evaluation bit for bit; the terms counted are
+    those of the groups walked."""
+    n = 6000
+    s = W.nfw_halo(n, seed=88)
+    d = orc.gravity(s["x"], s["y"], s["z"], s["m"], 1.0, 0.01)
+    full = orc.tree_gravity(s["x"], s["y"], s["z"], s["m"], d[:3], 1.0, 0.01, 5e-4)
+    q = np.array([0, 17, 17, n - 1, 2500, 4097, 1], dtype=np.int64)
+    part = orc.tree_gravity(s["x"], s["y"], s["z"], s["m"], d[:3], 1.0, 0.01, 5e-4, query=q)
+    for c in range(4):
+        assert np.array_equal(part[c], full[c][q])
+    assert 0 < part[4] < full[4]
