@@ -168,3 +168,40 @@ def test_block_step_arguments_rejected(S):
     for steps in bad:
         with pytest.raises(S.SidmError):
             S.sidm_kdk_step(ctx, [dict(base, steps=steps)], dev, 0, 0)
+
+
+def test_full_size_block_workload(S):
+    """The block-step benchmark's halo (isolated NFW N = 2^20, eps 0.01, k 64,
+    sigma/m 1, mixed precision), properties that hold at any size: eta > 0
+    with max_bin = 0 is the fixed step of the same dt bit for bit, and one
+    cycle of 1/16 in up to 64 ticks keeps |dE/E| below 1e-5 with a valid
+    status."""
+    import torch
+    cfg = W.config("BLK")
+    n = cfg["n"]
+    s = W.make_state(cfg)
+    base = dict(n=n, eps=cfg["eps"], G=1.0, sigma_m=cfg["sigma_m"], k=cfg["k"], seed=0)
+    fixed = dict(base, dt=1.0 / 1024)
+    zero = dict(fixed, steps=dict(eta=cfg["steps_param"]["eta"], max_bin=0))
+    ctx_a, dev_a = _start(S, s, [fixed], 1)
+    ctx_b, dev_b = _start(S, s, [zero], 1)
+    S.sidm_kdk_step(ctx_a, [fixed], dev_a, 0, 1)
+    S.sidm_kdk_step(ctx_b, [zero], dev_b, 0, 1)
+    torch.cuda.synchronize()
+    a, b = S.state_to_host(dev_a), S.state_to_host(dev_b)
+    for k in XV + ("ax", "ay", "az", "pot", "h"):
+        assert np.array_equal(a[k], b[k]), k
+    del dev_a, dev_b
+    cyc = dict(base, dt=cfg["dt"], steps=cfg["steps_param"])
+    ctx, dev = _start(S, s, [cyc], 1)
+    diag = S.diag_buffer(1)
+    S.sidm_diagnostics(ctx, [cyc], dev, diag)
+    d0 = S.read_diag(diag)[0]
+    S.sidm_kdk_step(ctx, [cyc], dev, 0, 1, diag=diag)
+    torch.cuda.synchronize()
+    d1 = S.read_diag(diag)[0]
+    e0 = d0["K"] + d0["W"]
+    e1 = d1["K"] + d1["W"]
+    print(f"one cycle at N=2^20: |dE/E| {abs(e1 - e0) / abs(e0):.2e}, events {d1['n_events']}")
+    assert abs(e1 - e0) / abs(e0) < 1e-5
+    assert d1["status"] == 0 and d1["n_events"] > 0
