@@ -178,7 +178,21 @@ const char *sidm_last_error(const sidm_ctx *ctx);
  * pair terms in FP32 on positions taken, in FP64, relative to the centre of
  * each compact group of at most 64 spatially sorted particles (the i-particle
  * is moved into the frame of each j group once), sums each tile of 256 terms
- * plainly and the tile sums with compensation, and returns FP64. */
+ * plainly and the tile sums with compensation, and returns FP64.
+ *
+ * Halos with tree_alpha > 0 take the self-gravity from a tree walk instead
+ * (Sec. 2: the relative opening criterion of Springel 2005, eq. 18): the tree
+ * is the Morton-ordered cell list (buckets of 64 particles, 8 children per
+ * node, bounding boxes, monopoles at the centres of mass); each bucket walks
+ * it once for its members and accepts a node when the two boxes are disjoint
+ * and G M l^2 <= tree_alpha |a_old| r^4 (l: the node box's largest side, r:
+ * the distance between the boxes, |a_old|: the smallest of the members'
+ * accelerations), else opens it; opened buckets contribute their particles.
+ * a_old is read from state->ax/ay/az as they are on entry (the previous step's
+ * accelerations in a run; zeros open every node and give the direct sum).
+ * The decisions are FP64 in both precisions; SIDM_PREC_MIXED forms each pair
+ * separation in FP64 and the rest of the pair term in FP32.  The number of
+ * source terms summed is reported in sidm_diag.n_grav_terms. */
 sidm_status sidm_gravity(sidm_ctx *ctx, const sidm_halo *halos, int32_t n_halos,
                          const sidm_state *state, sidm_precision prec, void *stream);
 
