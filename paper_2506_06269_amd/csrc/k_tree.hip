@@ -4,6 +4,7 @@
 // into buckets of kBucket consecutive particles, and the bucket bounding boxes
 // are merged kFanout at a time into a search tree per halo.
 #include "sidm_plan.hpp"
+#include "sidm_steps.hpp"
 
 namespace sidm {
 
@@ -85,7 +86,8 @@ __global__ __launch_bounds__(kStreamBlock) void k_morton_keys(
     const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
     const StreamBlock* __restrict__ blocks, const HaloDev* __restrict__ halos,
     const double* __restrict__ bbox, unsigned long long* __restrict__ keys,
-    uint32_t* __restrict__ vals)
+    uint32_t* __restrict__ vals, const int8_t* __restrict__ bin, int tick, int bmax,
+    int rank_shift)
 {
     const StreamBlock B = blocks[blockIdx.x];
     const int t = threadIdx.x;
@@ -99,7 +101,13 @@ __global__ __launch_bounds__(kStreamBlock) void k_morton_keys(
                                     (spread3(quant16(y[i], bb[1], inv)) << 1) |
                                     (spread3(quant16(z[i], bb[2], inv)) << 2);
     const int64_t pos = H.sbase + (i - H.offset);
-    keys[pos] = ((unsigned long long)H.rank << 48) | code;
+    // in a tick of block steps the inactive particles of a direct-sum halo sort
+    // after its active ones (bit 48), so the active ones fill whole i-blocks
+    unsigned long long later = 0ull;
+    if (rank_shift > 48 && tick > 0 && !(H.tree_alpha > 0.0) &&
+        !bin_active(H, bin[i], local_tick(H, tick, bmax)))
+        later = 1ull << 48;
+    keys[pos] = ((unsigned long long)H.rank << rank_shift) | later | code;
     vals[pos] = (uint32_t)i;
 }
 
@@ -381,7 +389,8 @@ __global__ __launch_bounds__(256) void k_node_hmax(const NodeTask* __restrict__ 
 // ---------------------------------------------------------------- launchers
 static unsigned grid_of(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
-hipError_t launch_cell_list(const Plan& P, const sidm_state* s, Scratch& w, hipStream_t st)
+hipError_t launch_cell_list(const Plan& P, const sidm_state* s, Scratch& w, hipStream_t st,
+                            int tick, int bmax)
 {
     const int64_t n = P.n_sorted;
     hipLaunchKernelGGL(k_block_bbox, dim3((unsigned)P.n_blocks), dim3(kStreamBlock), 0, st, s->x,
@@ -389,7 +398,8 @@ hipError_t launch_cell_list(const Plan& P, const sidm_state* s, Scratch& w, hipS
     hipLaunchKernelGGL(k_halo_bbox, dim3(P.n_halos), dim3(kStreamBlock), 0, st, w.halos, w.bsum,
                        w.bbox);
     hipLaunchKernelGGL(k_morton_keys, dim3((unsigned)P.n_blocks), dim3(kStreamBlock), 0, st, s->x,
-                       s->y, s->z, w.blocks, w.halos, w.bbox, w.keys[0], w.vals[0]);
+                       s->y, s->z, w.blocks, w.halos, w.bbox, w.keys[0], w.vals[0], w.bin,
+                       tick, bmax, P.rank_shift);
     int cur = 0;
     const int passes = (P.key_bits + kSortBits - 1) / kSortBits;
     const int64_t nblk = P.sort_blocks;

@@ -45,7 +45,8 @@ hipError_t launch_gravity(bool mixed, const Plan& P, Scratch& w, const sidm_stat
                           hipStream_t st, hipEvent_t tile_begin, hipEvent_t tile_end, int tick = 0,
                           int bmax = 0);
 int64_t gravity_slots(int device);
-hipError_t launch_cell_list(const Plan& plan, const sidm_state* s, Scratch& w, hipStream_t st);
+hipError_t launch_cell_list(const Plan& plan, const sidm_state* s, Scratch& w, hipStream_t st,
+                            int tick = 0, int bmax = 0);
 hipError_t launch_knn(const Plan& plan, const sidm_state* s, Scratch& w, uint32_t* nbr, int k_max,
                       hipStream_t st);
 hipError_t launch_tree_hmax(const Plan& plan, Scratch& w, hipStream_t st);
@@ -450,7 +451,7 @@ sidm_status sidm_kdk_step(sidm_ctx* c, const sidm_halo* halos, int32_t n_halos,
         for (int tick = 1; tick <= (1 << bmax) && e == hipSuccess; ++tick) {
             e = launch_tick_drift(c->w.blocks, P.n_blocks, c->w.halos, s->x, s->y, s->z, s->vx,
                                   s->vy, s->vz, tick, bmax, st);
-            if (e == hipSuccess) e = launch_cell_list(P, s, c->w, st);
+            if (e == hipSuccess) e = launch_cell_list(P, s, c->w, st, tick, bmax);
             if (e == hipSuccess)
                 e = launch_gravity(prec == SIDM_PREC_MIXED, P, c->w, s, 1, st, nullptr, nullptr,
                                    tick, bmax);

@@ -106,6 +106,7 @@ struct Plan {
     int64_t n_blocks = 0, n_items = 0, n_buckets = 0, n_nodes = 0;
     int n_levels = 1;                 // max levels over halos
     int key_bits = 48;
+    int rank_shift = 48;              // 49 when block steps order active particles first
     bool has_tree = false;            // some halo uses the tree walk
     int64_t sort_blocks = 0;
     std::vector<HaloDev> halos;
@@ -400,7 +401,10 @@ inline bool build_plan(Plan& P, const Scratch& w, const sidm_halo* halos, int32_
     P.n_blocks = (int64_t)P.blocks.size();
     int hb = 0;
     while ((1 << hb) < n_halos) ++hb;
-    P.key_bits = 48 + hb;
+    P.rank_shift = 48;
+    for (const auto& H : P.halos)
+        if (H.max_bin > 0 && !(H.tree_alpha > 0.0)) P.rank_shift = 49;
+    P.key_bits = P.rank_shift + hb;
     P.sort_blocks = (P.n_sorted + kSortBlock * kSortItems - 1) / (kSortBlock * kSortItems);
     if (prow > w.partial_rows || P.n_items > w.items_cap || P.n_blocks > w.blocks_cap ||
         P.n_buckets > w.buckets_cap || P.n_nodes > w.nodes_cap ||
