@@ -156,7 +156,7 @@ __device__ inline void grav_mixed_body(const float4* __restrict__ xm32,
                                        const SubRange* __restrict__ sub,
                                        const int* __restrict__ sub_n, const GravItem& it,
                                        const HaloDev& H, double mscale,
-                                       double4* __restrict__ partial, float4* tile)
+                                       double4* __restrict__ partial, float4* tile, int64_t pbase)
 {
     const int t = threadIdx.x;
     const float eps2 = (float)H.eps2;
@@ -233,7 +233,7 @@ __device__ inline void grav_mixed_body(const float4* __restrict__ xm32,
     for (int r = 0; r < IREG; ++r) {
         const int64_t li = il0 + (int64_t)r * kGravThreads + t;
         if (li >= H.n) continue;
-        const int64_t row = H.part_base + (int64_t)it.slot * H.n + li;
+        const int64_t row = pbase + (int64_t)it.slot * H.n + li;
         // the compensation holds the negated lost low part
         partial[row] = make_double4(mscale * ((double)sx[r] - (double)cx[r]),
                                     mscale * ((double)sy[r] - (double)cy[r]),
@@ -275,11 +275,13 @@ __global__ __launch_bounds__(kGravThreads) void k_grav_mixed(
     const GravItem it = items[blockIdx.x];
     const HaloDev& H = halos[it.halo];
     if (!item_active<IREG>(it, H, bin, perm, tick, bmax)) return;
+    const int64_t pbase = tick > 0 ? H.tick_part_base : H.part_base;
     const double meq = cmass[it.halo];
     if (meq > 0.0)
-        grav_mixed_body<IREG, true>(xm32, sub, sub_n, it, H, (double)(float)meq, partial, tile);
+        grav_mixed_body<IREG, true>(xm32, sub, sub_n, it, H, (double)(float)meq, partial, tile,
+                                    pbase);
     else
-        grav_mixed_body<IREG, false>(xm32, sub, sub_n, it, H, 1.0, partial, tile);
+        grav_mixed_body<IREG, false>(xm32, sub, sub_n, it, H, 1.0, partial, tile, pbase);
 }
 
 // ---------------------------------------------------------------- FP64 tiles
@@ -322,7 +324,7 @@ template <int IREG, bool EQM>
 __device__ inline void grav_fp64_body(const double* __restrict__ x, const double* __restrict__ y,
                                       const double* __restrict__ z, const double* __restrict__ m,
                                       const GravItem& it, const HaloDev& H, double mscale,
-                                      double4* __restrict__ partial, double4* tile)
+                                      double4* __restrict__ partial, double4* tile, int64_t pbase)
 {
     const int t = threadIdx.x;
     const double eps2 = H.eps2;
@@ -374,7 +376,7 @@ __device__ inline void grav_fp64_body(const double* __restrict__ x, const double
     for (int r = 0; r < IREG; ++r) {
         const int64_t li = il0 + (int64_t)r * kGravThreads + t;
         if (li >= H.n) continue;
-        const int64_t row = H.part_base + (int64_t)it.slot * H.n + li;
+        const int64_t row = pbase + (int64_t)it.slot * H.n + li;
         partial[row] = make_double4(mscale * (sx[r] - cx[r]), mscale * (sy[r] - cy[r]),
                                     mscale * (sz[r] - cz[r]), mscale * (sp[r] - cp[r]));
     }
@@ -392,11 +394,12 @@ __global__ __launch_bounds__(kGravThreads) void k_grav_fp64(
     const GravItem it = items[blockIdx.x];
     const HaloDev& H = halos[it.halo];
     if (!item_active<IREG>(it, H, bin, perm, tick, bmax)) return;
+    const int64_t pbase = tick > 0 ? H.tick_part_base : H.part_base;
     const double meq = cmass[it.halo];
     if (meq > 0.0)
-        grav_fp64_body<IREG, true>(x, y, z, m, it, H, meq, partial, tile);
+        grav_fp64_body<IREG, true>(x, y, z, m, it, H, meq, partial, tile, pbase);
     else
-        grav_fp64_body<IREG, false>(x, y, z, m, it, H, 1.0, partial, tile);
+        grav_fp64_body<IREG, false>(x, y, z, m, it, H, 1.0, partial, tile, pbase);
 }
 
 // ---------------------------------------------------------------- host + finalize
@@ -414,7 +417,8 @@ __global__ __launch_bounds__(kStreamBlock) void k_grav_finalize(
     double* __restrict__ ax, double* __restrict__ ay, double* __restrict__ az,
     double* __restrict__ pot, double* __restrict__ vx, double* __restrict__ vy,
     double* __restrict__ vz, double* __restrict__ svx, double* __restrict__ svy,
-    double* __restrict__ svz, int kick, int8_t* __restrict__ bin, int tick, int bmax)
+    double* __restrict__ svz, int kick, int8_t* __restrict__ bin, int tick, int bmax,
+    const double4* __restrict__ partial_tick)
 {
     const StreamBlock B = blocks[blockIdx.x];
     const int t = threadIdx.x;
@@ -429,9 +433,15 @@ __global__ __launch_bounds__(kStreamBlock) void k_grav_finalize(
         b = bin[o];
         if (!bin_active(H, b, kl)) return;
     }
+    // a tick of block steps (partial_tick given) keeps the rows of direct-sum
+    // halos apart
+    const bool trow = partial_tick != nullptr && !(H.tree_alpha > 0.0);
+    const double4* __restrict__ rows = trow ? partial_tick : partial;
+    const int64_t rbase = trow ? H.tick_part_base : H.part_base;
+    const int nrow = trow ? H.tick_split : H.grav_split;
     double sx = 0, sy = 0, sz = 0, sp = 0;
-    for (int s = 0; s < H.grav_split; ++s) {
-        const double4 q = partial[H.part_base + (int64_t)s * H.n + li];
+    for (int s = 0; s < nrow; ++s) {
+        const double4 q = rows[rbase + (int64_t)s * H.n + li];
         sx += q.x; sy += q.y; sz += q.z; sp += q.w;
     }
     double gx = H.G * sx, gy = H.G * sy, gz = H.G * sz, gp = -H.G * sp;
@@ -496,28 +506,34 @@ hipError_t launch_gravity(bool mixed, const Plan& P, Scratch& w, const sidm_stat
         const hipError_t e = launch_tree_gravity(mixed, P, w, s, tick, bmax, st);
         if (e != hipSuccess) return e;
         tile_begin = nullptr;
-        if (P.n_items == 0 && tile_end) (void)hipEventRecord(tile_end, st);
+        if (tick == 0 && P.n_items == 0 && tile_end) (void)hipEventRecord(tile_end, st);
     }
-    if (P.n_items == 0) {
+    // a tick of block steps runs the finer tick items into their own rows
+    const bool tk = tick > 0 && !P.items_tick.empty();
+    const GravItem* items = tk ? w.items_tick : w.items;
+    const int64_t n_items = tk ? (int64_t)P.items_tick.size() : P.n_items;
+    double4* rows = tk ? w.partial_tick : w.partial;
+    if (n_items == 0) {
         // no direct-sum halo
     } else if (mixed) {
         hipLaunchKernelGGL(k_pack_frames, dim3(nb), dim3(kStreamBlock), 0, st, w.sx, w.sy, w.sz,
                            w.sm, w.blocks, w.halos, w.sub, w.sub_n, w.xm32);
         if (tile_begin) (void)hipEventRecord(tile_begin, st);
-        hipLaunchKernelGGL((k_grav_mixed<4>), dim3((unsigned)P.n_items), dim3(kGravThreads), 0,
-                           st, w.xm32, w.sub, w.sub_n, w.items, w.halos, w.cref, w.partial, w.bin,
+        hipLaunchKernelGGL((k_grav_mixed<4>), dim3((unsigned)n_items), dim3(kGravThreads), 0,
+                           st, w.xm32, w.sub, w.sub_n, items, w.halos, w.cref, rows, w.bin,
                            w.perm, tick, bmax);
         if (tile_end) (void)hipEventRecord(tile_end, st);
     } else {
         if (tile_begin) (void)hipEventRecord(tile_begin, st);
-        hipLaunchKernelGGL((k_grav_fp64<4>), dim3((unsigned)P.n_items), dim3(kGravThreads), 0, st,
-                           w.sx, w.sy, w.sz, w.sm, w.items, w.halos, w.cref, w.partial, w.bin,
+        hipLaunchKernelGGL((k_grav_fp64<4>), dim3((unsigned)n_items), dim3(kGravThreads), 0, st,
+                           w.sx, w.sy, w.sz, w.sm, items, w.halos, w.cref, rows, w.bin,
                            w.perm, tick, bmax);
         if (tile_end) (void)hipEventRecord(tile_end, st);
     }
     hipLaunchKernelGGL(k_grav_finalize, dim3(nb), dim3(kStreamBlock), 0, st, w.blocks, w.halos,
                        w.partial, w.perm, s->x, s->y, s->z, s->ax, s->ay, s->az, s->pot, s->vx,
-                       s->vy, s->vz, w.svx, w.svy, w.svz, kick, w.bin, tick, bmax);
+                       s->vy, s->vz, w.svx, w.svy, w.svz, kick, w.bin, tick, bmax,
+                       tk ? w.partial_tick : nullptr);
     return hipGetLastError();
 }
 

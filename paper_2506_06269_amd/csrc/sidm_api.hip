@@ -241,7 +241,7 @@ sidm_status ensure_plan(sidm_ctx* c, const sidm_halo* halos, int32_t n_halos, hi
         return SIDM_ERR_INVALID;
     }
     std::string why;
-    if (!build_plan(c->plan, c->w, halos, n_halos, why)) {
+    if (!build_plan(c->plan, c->w, halos, n_halos, why) || !ensure_tick_tables(c->w, c->plan, why)) {
         set_err(c, "%s", why.c_str());
         return SIDM_ERR_CAPACITY;
     }

@@ -18,6 +18,7 @@ constexpr int kMaxLevels = 10;       // tree levels above the buckets
 constexpr int kStreamBlock = 256;    // threads per block of the streaming kernels
 constexpr int kGravThreads = 256;    // threads per gravity block
 constexpr int kGravTileJ = 256;      // j-particles per LDS tile
+constexpr int kTickSplit = 16;       // j-splits of a block-step tick
 constexpr int kSortBits = 8;         // radix digit width
 constexpr int kSortItems = 16;       // keys per thread per sort block
 constexpr int kSortBlock = 256;
@@ -35,6 +36,8 @@ struct HaloDev {
     double eta, dt_min;                   // block time steps (eta = 0: one fixed step)
     int32_t max_bin, pad1;
     double tree_alpha;                    // > 0: gravity through the tree walk
+    int64_t tick_part_base;               // block steps: first partial row of a tick
+    int32_t tick_split, pad3;             // block steps: j-splits of a tick
     // search tree: level 0 are the buckets, node ranges per level (global index
     // into the box arrays)
     int64_t level_off[kMaxLevels + 1];

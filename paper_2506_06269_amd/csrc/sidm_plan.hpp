@@ -72,6 +72,11 @@ struct Scratch {
     float4* xm32 = nullptr;       // FP32 positions relative to their tile centre, mass
     double4* partial = nullptr;
     int64_t partial_rows = 0;
+    // block-step ticks: finer j-splits (allocated with the first plan that needs them)
+    GravItem* items_tick = nullptr;
+    int64_t items_tick_cap = 0;
+    double4* partial_tick = nullptr;
+    int64_t partial_tick_rows = 0;
     int64_t grav_slots = 0;       // resident blocks of the gravity tiles on the whole device
     // cell list
     unsigned long long* keys[2] = {nullptr, nullptr};
@@ -112,6 +117,8 @@ struct Plan {
     std::vector<HaloDev> halos;
     std::vector<StreamBlock> blocks;
     std::vector<GravItem> items;
+    std::vector<GravItem> items_tick;     // block-step ticks (empty without block steps)
+    int64_t tick_rows = 0;                // partial rows the tick items need
     std::vector<BucketInfo> buckets;
     std::vector<NodeTask> node_tasks;
     std::vector<NodeChild> nodes;
@@ -196,6 +203,8 @@ inline void free_scratch(Scratch& w)
     dfree(w.bsum); dfree(w.cref); dfree(w.radius); dfree(w.center); dfree(w.tidal); dfree(w.bbox); dfree(w.xm32);  dfree(w.partial);
     dfree(w.keys[0]); dfree(w.keys[1]); dfree(w.vals[0]); dfree(w.vals[1]); dfree(w.hist);
     dfree(w.sx); dfree(w.sy); dfree(w.sz); dfree(w.sp4); dfree(w.svx); dfree(w.svy); dfree(w.svz);
+    dfree(w.items_tick); dfree(w.partial_tick);
+    w.items_tick_cap = w.partial_tick_rows = 0;
     dfree(w.sh); dfree(w.sm); dfree(w.bin); dfree(w.mom); dfree(w.tree_terms); dfree(w.sid); dfree(w.perm); dfree(w.box); dfree(w.hmax);
     dfree(w.sub); dfree(w.sub_n);
     dfree(w.owner); dfree(w.events); dfree(w.counters); dfree(w.ev_counts); dfree(w.status);
@@ -393,10 +402,38 @@ inline bool build_plan(Plan& P, const Scratch& w, const sidm_halo* halos, int32_
                 P.items.push_back({H.offset + i0, j0, j1, h, s});
         }
     }
-    // largest items first so that the uneven tail is short
+    // Block-step ticks: a tick may hold only a few active i-blocks (they come
+    // first in the tick's order), so its items cut j finer, into up to
+    // kTickSplit ranges, to keep the device busy; their partial rows are their own.
+    bool blocks = false;
+    for (const auto& H : P.halos)
+        if (H.max_bin > 0 && !(H.tree_alpha > 0.0)) blocks = true;
+    if (blocks) {
+        int64_t trow = 0;
+        for (int h = 0; h < n_halos; ++h) {
+            HaloDev& H = P.halos[h];
+            if (H.tree_alpha > 0.0) continue;
+            const int64_t tiles = (H.n + kGravTileJ - 1) / kGravTileJ;
+            H.tick_split = (int32_t)std::max<int64_t>(1, std::min<int64_t>(kTickSplit, tiles));
+            H.tick_part_base = trow;
+            trow += H.n * H.tick_split;
+            for (int s = 0; s < H.tick_split; ++s) {
+                const int64_t t0 = tiles * s / H.tick_split, t1 = tiles * (s + 1) / H.tick_split;
+                const int64_t j0 = H.offset + t0 * kGravTileJ;
+                const int64_t j1 = std::min<int64_t>(H.offset + H.n, H.offset + t1 * kGravTileJ);
+                for (int64_t i0 = 0; i0 < H.n; i0 += kIBlock)
+                    P.items_tick.push_back({H.offset + i0, j0, j1, h, s});
+            }
+        }
+        P.tick_rows = trow;
+    }
+    // largest items first so that the uneven tail is short; a tick's active
+    // i-blocks come first, so its items are ordered by i-block within a j size
     std::stable_sort(P.items.begin(), P.items.end(), [](const GravItem& a, const GravItem& b) {
         return (a.j1 - a.j0) > (b.j1 - b.j0);
     });
+    std::stable_sort(P.items_tick.begin(), P.items_tick.end(),
+                     [](const GravItem& a, const GravItem& b) { return a.i0 < b.i0; });
     P.n_items = (int64_t)P.items.size();
     P.n_blocks = (int64_t)P.blocks.size();
     int hb = 0;
@@ -411,6 +448,30 @@ inline bool build_plan(Plan& P, const Scratch& w, const sidm_halo* halos, int32_
         (int64_t)P.node_tasks.size() > w.nodes_cap) {
         why = "launch plan exceeds the context's table capacity";
         return false;
+    }
+    return true;
+}
+
+// Tables of block-step ticks, sized on the first plan that needs them.
+inline bool ensure_tick_tables(Scratch& w, const Plan& P, std::string& why)
+{
+    if ((int64_t)P.items_tick.size() > w.items_tick_cap) {
+        dfree(w.items_tick);
+        w.items_tick_cap = 0;
+        if (!dalloc(w.items_tick, (int64_t)P.items_tick.size())) {
+            why = "out of device memory for the block-step work items";
+            return false;
+        }
+        w.items_tick_cap = (int64_t)P.items_tick.size();
+    }
+    if (P.tick_rows > w.partial_tick_rows) {
+        dfree(w.partial_tick);
+        w.partial_tick_rows = 0;
+        if (!dalloc(w.partial_tick, P.tick_rows)) {
+            why = "out of device memory for the block-step partial rows";
+            return false;
+        }
+        w.partial_tick_rows = P.tick_rows;
     }
     return true;
 }
@@ -430,6 +491,9 @@ inline hipError_t upload_plan(const Plan& P, const Scratch& w)
                       hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(w.nodes, P.nodes.data(), sizeof(NodeChild) * P.nodes.size(),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess && !P.items_tick.empty())
+        e = hipMemcpy(w.items_tick, P.items_tick.data(), sizeof(GravItem) * P.items_tick.size(),
                       hipMemcpyHostToDevice);
     if (e == hipSuccess && !P.node_tasks.empty())
         e = hipMemcpy(w.node_tasks, P.node_tasks.data(), sizeof(NodeTask) * P.node_tasks.size(),
