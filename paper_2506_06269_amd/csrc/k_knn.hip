@@ -3,8 +3,7 @@
 // neighbours).
 //
 // One wavefront per bucket of 64 Morton-consecutive particles, one particle
-// per lane; the lanes of each compact sub-range of the bucket are resolved
-// together.  Candidates are read with wave-uniform loads (every lane
+// per lane, all lanes resolved together (each with its own search sphere).  Candidates are read with wave-uniform loads (every lane
 // evaluates the same candidate), and a candidate sub-range is visited only if
 // it intersects the search sphere of at least one lane.
 // Selection works on values only, with a private 32-bin histogram per lane
@@ -129,25 +128,32 @@ __global__ __launch_bounds__(kBucket) void k_knn(
         __syncthreads();
     };
 
-    const int ngroups = sub_n[b];
-    for (int g = 0; g < ngroups; ++g) {
-        const SubRange G = sub[kSubMax * b + g];
-        const bool act = in_bucket && lane >= G.off && lane < G.off + G.cnt;
+    {
+        const bool act = in_bucket;
 
         // ---- starting radius
         const bool warm = isfinite(hint) && hint > 0.0 && hint * hint <= diag2;
         double u2 = kKnnWarm * hint * hint;
         if (__ballot(act && !warm)) {
-            // the m-th nearest member of the lane's own sub-range (m <= 8),
-            // scaled to k neighbours
+            // the m-th nearest member of the lane's own compact sub-range
+            // (m <= 8), scaled to k neighbours (members of another sub-range
+            // of the bucket can be far away)
+            int go = 0, gc = B.count;
+            for (int g = 0; g < sub_n[b]; ++g) {
+                const SubRange R = sub[kSubMax * b + g];
+                if (lane >= R.off && lane < R.off + R.cnt) {
+                    go = R.off;
+                    gc = R.cnt;
+                }
+            }
             constexpr int kM = 8;
             double best[kM];
 #pragma unroll
             for (int q = 0; q < kM; ++q) best[q] = INFINITY;
-            const int64_t p0 = B.start + G.off;
-            for (int j = 0; j < G.cnt; ++j) {
+            const int64_t p0 = B.start;
+            for (int j = 0; j < B.count; ++j) {
                 const double4 c = sp4[p0 + j];
-                if (p0 + j == mypos) continue;
+                if (p0 + j == mypos || j < go || j >= go + gc) continue;
                 double v = dist2_exact(xi, yi, zi, c.x, c.y, c.z);
 #pragma unroll
                 for (int q = 0; q < kM; ++q) {
@@ -156,7 +162,7 @@ __global__ __launch_bounds__(kBucket) void k_knn(
                     best[q] = lo;
                 }
             }
-            const int m = min(min(kM, k), G.cnt - 1);
+            const int m = min(min(kM, k), gc - 1);
             double rm2 = 0.0;
 #pragma unroll
             for (int q = 0; q < kM; ++q)
