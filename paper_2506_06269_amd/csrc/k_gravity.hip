@@ -269,13 +269,15 @@ __global__ __launch_bounds__(kGravThreads) void k_grav_mixed(
     const int* __restrict__ sub_n, const GravItem* __restrict__ items,
     const HaloDev* __restrict__ halos,
     const double* __restrict__ cmass, double4* __restrict__ partial,
-    const int8_t* __restrict__ bin, const uint32_t* __restrict__ perm, int tick, int bmax)
+    const int8_t* __restrict__ bin, const uint32_t* __restrict__ perm, int tick, int bmax,
+    int tick_rows)
 {
     __shared__ float4 tile[kGravTileJ];
     const GravItem it = items[blockIdx.x];
     const HaloDev& H = halos[it.halo];
     if (!item_active<IREG>(it, H, bin, perm, tick, bmax)) return;
-    const int64_t pbase = tick > 0 ? H.tick_part_base : H.part_base;
+    // the items of a block-step tick (tick_rows) write their own partial rows
+    const int64_t pbase = tick_rows ? H.tick_part_base : H.part_base;
     const double meq = cmass[it.halo];
     if (meq > 0.0)
         grav_mixed_body<IREG, true>(xm32, sub, sub_n, it, H, (double)(float)meq, partial, tile,
@@ -388,13 +390,14 @@ __global__ __launch_bounds__(kGravThreads) void k_grav_fp64(
     const double* __restrict__ m, const GravItem* __restrict__ items,
     const HaloDev* __restrict__ halos, const double* __restrict__ cmass,
     double4* __restrict__ partial, const int8_t* __restrict__ bin,
-    const uint32_t* __restrict__ perm, int tick, int bmax)
+    const uint32_t* __restrict__ perm, int tick, int bmax, int tick_rows)
 {
     __shared__ double4 tile[kGravTileJ];
     const GravItem it = items[blockIdx.x];
     const HaloDev& H = halos[it.halo];
     if (!item_active<IREG>(it, H, bin, perm, tick, bmax)) return;
-    const int64_t pbase = tick > 0 ? H.tick_part_base : H.part_base;
+    // the items of a block-step tick (tick_rows) write their own partial rows
+    const int64_t pbase = tick_rows ? H.tick_part_base : H.part_base;
     const double meq = cmass[it.halo];
     if (meq > 0.0)
         grav_fp64_body<IREG, true>(x, y, z, m, it, H, meq, partial, tile, pbase);
@@ -521,13 +524,13 @@ hipError_t launch_gravity(bool mixed, const Plan& P, Scratch& w, const sidm_stat
         if (tile_begin) (void)hipEventRecord(tile_begin, st);
         hipLaunchKernelGGL((k_grav_mixed<4>), dim3((unsigned)n_items), dim3(kGravThreads), 0,
                            st, w.xm32, w.sub, w.sub_n, items, w.halos, w.cref, rows, w.bin,
-                           w.perm, tick, bmax);
+                           w.perm, tick, bmax, tk ? 1 : 0);
         if (tile_end) (void)hipEventRecord(tile_end, st);
     } else {
         if (tile_begin) (void)hipEventRecord(tile_begin, st);
         hipLaunchKernelGGL((k_grav_fp64<4>), dim3((unsigned)n_items), dim3(kGravThreads), 0, st,
                            w.sx, w.sy, w.sz, w.sm, items, w.halos, w.cref, rows, w.bin,
-                           w.perm, tick, bmax);
+                           w.perm, tick, bmax, tk ? 1 : 0);
         if (tile_end) (void)hipEventRecord(tile_end, st);
     }
     hipLaunchKernelGGL(k_grav_finalize, dim3(nb), dim3(kStreamBlock), 0, st, w.blocks, w.halos,
