@@ -62,3 +62,40 @@ def test_all_options_in_one_batch(S, orc):
                 err = np.max(np.abs(out[c][sl[h]] - ref[c])) / np.max(np.abs(ref[c]))
                 assert err <= 1e-12, (step, h, c, err)
         assert d[0]["n_grav_terms"] > 0 and d[1]["n_grav_terms"] == 0
+
+
+def test_tree_and_direct_block_steps_in_one_batch(S, orc):
+    """A tree halo and a direct-sum halo both with block steps (so the ticks
+    run their own work items), and a fixed-step halo, in one call."""
+    import torch
+    sizes = [4000, 3000, 2000]
+    parts = [W.nfw_halo(sizes[0], seed=123), W.nfw_halo(sizes[1], seed=124),
+             W.plummer(sizes[2], seed=125)]
+    s = {f: np.concatenate([q[f] for q in parts]) for f in ("x", "y", "z", "vx", "vy", "vz", "m")}
+    s["id"] = np.concatenate([q["id"] for q in parts]).astype(np.uint32)
+    offs = [0, sizes[0], sizes[0] + sizes[1]]
+    kws = [dict(eps=0.01, sigma_m=2.0, dt=1.0 / 32, k=32, seed=1, tree_alpha=5e-4,
+                steps=dict(eta=0.025, max_bin=3)),
+           dict(eps=0.01, sigma_m=2.0, dt=1.0 / 16, k=32, seed=2, steps=dict(eta=0.025, max_bin=4)),
+           dict(eps=0.02, sigma_m=5.0, dt=2e-3, k=16, seed=3)]
+    halos = [dict(kw, n=n, offset=o) for kw, n, o in zip(kws, sizes, offs)]
+    params = [orc.make_params(**kw) for kw in kws]
+    dev = S.state_to_device(s)
+    ctx = S.sidm_create(0, sum(sizes), 3)
+    S.sidm_gravity(ctx, [dict(h, tree_alpha=0.0) for h in halos], dev, 0)
+    diag = S.diag_buffer(3)
+    torch.cuda.synchronize()
+    for step in range(2):
+        before = S.state_to_host(dev)
+        S.sidm_kdk_step(ctx, halos, dev, step, 0, diag=diag)
+        torch.cuda.synchronize()
+        out = S.state_to_host(dev)
+        d = S.read_diag(diag)
+        for h, (n, o) in enumerate(zip(sizes, offs)):
+            sl = slice(o, o + n)
+            ref = {k: v[sl].copy() for k, v in before.items()}
+            ev = orc.kdk_step(ref, params[h], step)
+            assert d[h]["n_events"] == ev.size, (step, h)
+            for c in ("x", "y", "z", "vx", "vy", "vz"):
+                err = np.max(np.abs(out[c][sl] - ref[c])) / np.max(np.abs(ref[c]))
+                assert err <= 1e-12, (step, h, c, err)
