@@ -71,14 +71,20 @@ def test_c4_batch_sampled_parity(S, orc):
         assert np.max(np.abs(out["vx"][o:o + n] - vx)) <= 1e-12 * np.abs(vx).max()
 
 
-def test_graph_captured_step_matches_eager(S):
+@pytest.mark.parametrize("variant", ["fixed", "blocks_and_tree"])
+def test_graph_captured_step_matches_eager(S, variant):
     """A captured sidm_kdk_step replayed 3 times (with eager work and
     synchronisations between replays) against 3 eager steps from the same
     state.  The step counter is part of the captured arguments, so both sides
-    use the same step number each time."""
+    use the same step number each time.  The second variant captures cycles of
+    block time steps (the ticks' work items, a direct-sum halo) with a tree
+    halo beside it: some hundreds of launches per captured call."""
     import torch
     halo_list = [dict(n=3000, sigma_m=50.0, k=32, seed=1, G=1.0, eps=0.01, dt=1e-3, host=None),
                  dict(n=5000, sigma_m=10.0, k=64, seed=2, G=1.0, eps=0.01, dt=1e-3, host=None)]
+    if variant == "blocks_and_tree":
+        halo_list[0].update(dt=1.0 / 32, steps=dict(eta=0.025, max_bin=3))
+        halo_list[1].update(tree_alpha=5e-4)
     s, halos, _ = _batch(halo_list, seed_base=40)
     total = s["x"].size
 
