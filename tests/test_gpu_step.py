@@ -83,6 +83,42 @@ def test_step_parity_c1(S, orc, prec):
     assert total_events > 0
 
 
+def test_c1_trajectory_end_to_end(S, orc):
+    """C1 (FP64) over its whole 32 steps, GPU and oracle each stepping from the
+    same initial conditions with no state copied between them: over this span
+    the two trajectories part only by rounding (a 2e-16 perturbation of the
+    initial conditions moves the oracle's state by about 2e-15 and its
+    accelerations by 2e-14), so the events match step for step and positions,
+    velocities, accelerations and kernel sizes stay within 1e-12."""
+    import torch
+    s, halo = _c1()
+    p = _orc_params(orc, halo)
+    ctx, dev = _start(S, orc, s, halo, 0)
+    ref = {k: v.copy() for k, v in s.items()}
+    ref["ax"], ref["ay"], ref["az"], ref["pot"] = orc.gravity(
+        ref["x"], ref["y"], ref["z"], ref["m"], 1.0, halo["eps"])[:4]
+    diag = S.diag_buffer(1)
+    gpu_events, orc_events = [], []
+    for step in range(32):
+        S.sidm_kdk_step(ctx, [halo], dev, step, 0, diag=diag)
+        d = S.read_diag(diag)[0]
+        assert d["status"] == 0
+        gpu_events.append(int(d["n_events"]))
+        orc_events.append(int(orc.kdk_step(ref, p, step).size))
+    torch.cuda.synchronize()
+    out = S.state_to_host(dev)
+    print("events per step", gpu_events, flush=True)
+    assert gpu_events == orc_events
+    assert sum(gpu_events) > 0
+    worst = {}
+    for c in ("x", "y", "z", "vx", "vy", "vz", "ax", "ay", "az"):
+        worst[c] = np.max(np.abs(out[c] - ref[c])) / np.max(np.abs(ref[c]))
+    worst["h"] = np.max(np.abs(out["h"] - ref["h"]) / ref["h"])
+    print("after 32 steps:", {c: f"{e:.2e}" for c, e in worst.items()})
+    for c, e in worst.items():
+        assert e <= 1e-12, (c, e)
+
+
 def test_step_reversible_fp64(S, orc):
     """sigma = 0: 16 steps forward, reverse the velocities, 16 steps back."""
     import torch
