@@ -36,7 +36,7 @@ def _args():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--workload", default="C2", choices=("C2", "C3", "C4", "C5", "BLK", "TREE"),
                     help="C2 (default, the benchmark line): N=2^20 satellite; C3: the same halo "
                          "for --steps steps in one --precision with |dE/E| and central density; "
@@ -110,8 +110,13 @@ def _cpu_baseline(cfg, s, budget_s):
     n = cfg["n"]
     rng = np.random.default_rng(0)
 
-    def per_particle_seconds(m):
-        q = np.sort(rng.choice(n, m, replace=False))
+    order = rng.permutation(n)
+    used = 0
+
+    def sample_seconds(m):
+        nonlocal used
+        q = np.sort(order[used:used + m])
+        used += m
         t = time.perf_counter()
         O.gravity(s["x"], s["y"], s["z"], s["m"], 1.0, cfg["eps"], query=q)
         tg = time.perf_counter() - t
@@ -126,22 +131,54 @@ def _cpu_baseline(cfg, s, budget_s):
         O.find_events(s["x"], s["y"], s["z"], s["vx"], s["vy"], s["vz"], s["m"], s["id"], hh,
                       cfg["sigma_m"], cfg["dt"], 0, 0, qmask=qm)
         ts = time.perf_counter() - t
-        return (tg + tk + ts) / m, (tg, tk, ts)
+        return np.array([tg, tk, ts])
 
-    probe, _ = per_particle_seconds(16)
-    m = int(max(16, min(4096, budget_s / max(probe, 1e-9))))
-    per, parts = per_particle_seconds(m)
+    def sample_until(budget, first=16):
+        # batches of doubling size, all counted, until the next batch would
+        # pass the budget; every particle is drawn once
+        total, m, batch = np.zeros(3), 0, first
+        while True:
+            dt = sample_seconds(batch)
+            total += dt
+            m += batch
+            if total.sum() + 2.0 * dt.sum() > budget or used + 2 * batch > n:
+                return float(total.sum()) / m, total, m
+            batch *= 2
+
+    per, parts, m = sample_until(budget_s)
     step_s = per * n
+    cores = O.num_threads()
+    # the same per-particle work on one thread, on a sample of about a fifth of
+    # the budget, for the oracle's parallel speed-up
+    O.set_threads(1)
+    try:
+        per1, _, m1 = sample_until(0.2 * budget_s, first=4)
+    finally:
+        O.set_threads(cores)
     return {
         "value": n * (n - 1) / step_s,
         "unit": "gravity interactions/s",
-        "cores": O.num_threads(),
+        "cores": cores,
         "kind": "oracle",
         "sample": (f"{m} random particles of the N=2^20 halo: gravity against all N, brute-force "
                    f"kNN and pair tests with probabilities ({parts[0]:.1f} s, {parts[1]:.1f} s, "
                    f"{parts[2]:.1f} s), extrapolated to a full step of N particles"),
         "step_seconds_extrapolated": step_s,
+        "single_thread_value": n * (n - 1) / (per1 * n),
+        "single_thread_sample": m1,
+        "host_cpu": _host_cpu(),
     }
+
+
+def _host_cpu():
+    """Model name and logical CPU count of the host, from /proc/cpuinfo."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            names = [ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")]
+    except OSError:
+        names = []
+    return {"model": names[0] if names else None, "logical_cpus": len(names) or os.cpu_count(),
+            "affinity": len(os.sched_getaffinity(0))}
 
 
 def _traffic(per_launch_flops):

@@ -101,6 +101,8 @@ def _declare(L):
                                C.c_uint32, C.c_void_p, C.c_int64]
     L.orc_kdk_step.restype = C.c_int64
     L.orc_num_threads.restype = C.c_int
+    L.orc_set_threads.argtypes = [C.c_int]
+    L.orc_set_threads.restype = None
 
 
 def _d(a):
@@ -114,6 +116,11 @@ def _f64(a):
 
 def num_threads():
     return int(lib().orc_num_threads())
+
+
+def set_threads(n):
+    """Threads of the oracle's OpenMP loops from here on (for timing)."""
+    lib().orc_set_threads(int(n))
 
 
 # ---------------------------------------------------------------- random

@@ -31,6 +31,15 @@ int orc_num_threads(void)
 #endif
 }
 
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11).  Each round multiplies
  * words 0 and 2 by the two Philox multipliers, and the new block is

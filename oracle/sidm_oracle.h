@@ -240,6 +240,8 @@ int64_t orc_kdk_step(int64_t n, double *x, double *y, double *z,
 
 /* Number of OpenMP threads the oracle uses. */
 int orc_num_threads(void);
+/* Threads of the OpenMP loops that follow (n > 0; timing of the oracle). */
+void orc_set_threads(int n);
 
 #ifdef __cplusplus
 }

@@ -3,16 +3,19 @@
 // neighbours).
 //
 // One wavefront per bucket of 64 Morton-consecutive particles, one particle
-// per lane, all lanes resolved together (each with its own search sphere).  Candidates are read with wave-uniform loads (every lane
-// evaluates the same candidate), and a candidate sub-range is visited only if
+// per lane, all lanes resolved together (each with its own search sphere).
+// Candidates are read with wave-uniform loads (every lane evaluates the same
+// candidate), and a candidate sub-range is visited only if
 // it intersects the search sphere of at least one lane.
 // Selection works on values only, with a private 32-bin histogram per lane
 // (an LDS column, written with LDS atomics that return nothing):
 //   1. a histogram of the distances within a starting radius: 1.15 times the
 //      kernel size the particle had before the call when that is a usable
-//      value (a warm start: the result does not depend on it), otherwise an
-//      estimate from the nearest members of its own sub-range; the radius
-//      grows until the sphere holds k others;
+//      value (a warm start: the result does not depend on it); otherwise the
+//      first member of the particle's compact sub-range is resolved first,
+//      from an estimate out of the nearest members of that sub-range, and
+//      the particle starts from 1.15 times that member's h; the radius grows
+//      until the sphere holds k others;
 //   2. a visit restricted to the shell of the bin that holds the k-th
 //      collects that bin's members (at most 16, kept sorted in registers) or,
 //      if it holds more, records their min..max, whose histogram (step 1 over
@@ -76,7 +79,7 @@ __global__ __launch_bounds__(kBucket) void k_knn(
     double* __restrict__ sh, double* __restrict__ h_out, int* __restrict__ status)
 {
     __shared__ KnnLds L;
-    const int64_t b = blockIdx.x;
+    const int64_t b = xcd_contiguous(blockIdx.x, gridDim.x);
     const int lane = threadIdx.x;
     const BucketInfo B = buckets[b];
     const HaloDev& H = halos[B.halo];
@@ -128,54 +131,9 @@ __global__ __launch_bounds__(kBucket) void k_knn(
         __syncthreads();
     };
 
-    {
-        const bool act = in_bucket;
-
-        // ---- starting radius
-        const bool warm = isfinite(hint) && hint > 0.0 && hint * hint <= diag2;
-        double u2 = kKnnWarm * hint * hint;
-        if (__ballot(act && !warm)) {
-            // the m-th nearest member of the lane's own compact sub-range
-            // (m <= 8), scaled to k neighbours (members of another sub-range
-            // of the bucket can be far away)
-            int go = 0, gc = B.count;
-            for (int g = 0; g < sub_n[b]; ++g) {
-                const SubRange R = sub[kSubMax * b + g];
-                if (lane >= R.off && lane < R.off + R.cnt) {
-                    go = R.off;
-                    gc = R.cnt;
-                }
-            }
-            constexpr int kM = 8;
-            double best[kM];
-#pragma unroll
-            for (int q = 0; q < kM; ++q) best[q] = INFINITY;
-            const int64_t p0 = B.start;
-            for (int j = 0; j < B.count; ++j) {
-                const double4 c = sp4[p0 + j];
-                if (p0 + j == mypos || j < go || j >= go + gc) continue;
-                double v = dist2_exact(xi, yi, zi, c.x, c.y, c.z);
-#pragma unroll
-                for (int q = 0; q < kM; ++q) {
-                    const double lo = fmin(best[q], v);
-                    v = fmax(best[q], v);
-                    best[q] = lo;
-                }
-            }
-            const int m = min(min(kM, k), gc - 1);
-            double rm2 = 0.0;
-#pragma unroll
-            for (int q = 0; q < kM; ++q)
-                if (q == m - 1) rm2 = best[q];
-            if (!warm) {
-                if (m >= 1 && rm2 > 0.0 && rm2 < INFINITY)
-                    u2 = 1.44 * rm2 * pow((double)k / (double)m, 2.0 / 3.0);
-                else
-                    u2 = diag2 / cbrt((double)H.n * (double)H.n);
-                if (!(u2 > 0.0)) u2 = 1.0;
-            }
-        }
-
+    // h^2 of the lanes with act set, from a starting radius^2 u2 (NaN for the
+    // others); a uniform call: every lane of the wave takes part
+    auto resolve = [&](bool act, double u2) {
         // ---- 1. histogram of [0, u2]; grow until the sphere holds k others
         bool need = act, failed = false;
         int grow = 0;
@@ -192,7 +150,7 @@ __global__ __launch_bounds__(kBucket) void k_knn(
                     atomicOr(&status[B.halo], SIDM_DEV_KNN_OVERFLOW);
                 } else {
                     double f = tot > 0 ? 1.44 * pow((double)k / (double)tot, 2.0 / 3.0) : 4.0;
-                    u2 *= fmin(fmax(f, 1.44), 16.0);
+                    u2 *= fmin(fmax(f, 1.44), 4.0);
                 }
             }
         }
@@ -259,11 +217,73 @@ __global__ __launch_bounds__(kBucket) void k_knn(
             }
             if (__ballot(refine)) histogram(refine, a, z, lo, inv);
         }
-        if (act) {
-            const double h = sqrt(d2k);
-            sh[mypos] = h;
-            h_out[perm[mypos]] = h;
+        return act ? d2k : NAN;
+    };
+
+    // ---- starting radius
+    const bool warm = isfinite(hint) && hint > 0.0 && hint * hint <= diag2;
+    double u2 = kKnnWarm * hint * hint;
+    if (__ballot(in_bucket && !warm)) {
+        // the lane's own compact sub-range (members of another sub-range of
+        // the bucket can be far away)
+        int go = 0, gc = B.count;
+        for (int g = 0; g < sub_n[b]; ++g) {
+            const SubRange R = sub[kSubMax * b + g];
+            if (lane >= R.off && lane < R.off + R.cnt) {
+                go = R.off;
+                gc = R.cnt;
+            }
         }
+        // an estimate: the m-th nearest member of that sub-range (m <= 8),
+        // scaled to k neighbours
+        constexpr int kM = 8;
+        double best[kM];
+#pragma unroll
+        for (int q = 0; q < kM; ++q) best[q] = INFINITY;
+        const int64_t p0 = B.start;
+        for (int j = 0; j < B.count; ++j) {
+            const double4 c = sp4[p0 + j];
+            if (p0 + j == mypos || j < go || j >= go + gc) continue;
+            double v = dist2_exact(xi, yi, zi, c.x, c.y, c.z);
+#pragma unroll
+            for (int q = 0; q < kM; ++q) {
+                const double lo = fmin(best[q], v);
+                v = fmax(best[q], v);
+                best[q] = lo;
+            }
+        }
+        const int m = min(min(kM, k), gc - 1);
+        double rm2 = 0.0;
+#pragma unroll
+        for (int q = 0; q < kM; ++q)
+            if (q == m - 1) rm2 = best[q];
+        // With fewer than four members to go by (a sub-range cut off by a
+        // jump of the Morton curve) an estimate can exceed the true radius
+        // many times, and in the dense centre such a sphere holds a large
+        // part of the halo (one wave then streams most of it); those
+        // representatives start instead from the halo's diagonal / N, far
+        // below any neighbour distance, and grow.
+        double e2 = (m >= 4 && rm2 > 0.0 && rm2 < INFINITY)
+                        ? 1.44 * rm2 * pow((double)k / (double)m, 2.0 / 3.0)
+                        : diag2 / ((double)H.n * (double)H.n);
+        if (!(e2 > 0.0)) e2 = 1.0;
+        // The first member of each sub-range is resolved from the estimate
+        // alone; every other member then starts as if warm, from 1.15 times
+        // that representative's h (the kernel size varies slowly across a
+        // compact sub-range).  The estimate errs by a factor of a few in
+        // volume, and taken by all 64 lanes it cost four times the warm
+        // candidate stream; taken by the few representatives it costs one
+        // such stream.
+        const bool rep = in_bucket && lane == go;
+        const double d2r = resolve(rep, warm ? u2 : 0.25 * e2);
+        const double c2 = kKnnWarm * __shfl(d2r, go);
+        if (!warm) u2 = (isfinite(c2) && c2 > 0.0) ? fmin(c2, e2) : e2;
+    }
+    const double d2k = resolve(in_bucket, u2);
+    if (in_bucket) {
+        const double h = sqrt(d2k);
+        sh[mypos] = h;
+        h_out[perm[mypos]] = h;
     }
 }
 

@@ -241,7 +241,7 @@ __global__ __launch_bounds__(64) void k_tree_walk(
     // pending inner nodes as (first child, number of children)
     __shared__ int2 stack[kTreeStack];
 
-    const int64_t g = blockIdx.x;
+    const int64_t g = xcd_chunked<256>(blockIdx.x, gridDim.x);
     const int lane = threadIdx.x;
     const BucketInfo GB = buckets[g];
     const HaloDev& H = halos[GB.halo];

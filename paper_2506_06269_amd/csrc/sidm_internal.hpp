@@ -91,6 +91,34 @@ __device__ inline double rsqrt_pos(double r2)
     const double e = fma(-r2 * y0, y0, 1.0);
     return fma(0.5 * y0, e, y0);
 }
+
+// Work item of workgroup `id` in a launch of n workgroups.  The dispatcher
+// hands workgroups to the eight XCDs in turn (id mod 8), and each XCD has an L2
+// of its own; this numbering gives XCD x one contiguous run of items instead,
+// so that buckets adjacent on the Morton curve, which read the same candidate
+// particles, run under one L2.  A bijection on [0, n) for any n.  It suits
+// passes whose cost per bucket is even along the curve (the kNN search); the
+// pair pass, whose costly buckets crowd into the dense centre, keeps the
+// dispatcher's interleaving, which spreads them over all XCDs.
+__device__ inline int64_t xcd_contiguous(int64_t id, int64_t n)
+{
+    const int64_t q = n >> 3, r = n & 7, x = id & 7;
+    return x * q + (x < r ? x : r) + (id >> 3);
+}
+
+// Between the two: runs of C consecutive items go to the XCDs in turn, so an
+// XCD keeps C neighbouring buckets under its L2 while every XCD still samples
+// the whole curve (the tree walk, whose lists grow towards the centre).  Items
+// past the last whole round of 8 C keep their own number.  A bijection on
+// [0, n).
+template <int64_t C>
+__device__ inline int64_t xcd_chunked(int64_t id, int64_t n)
+{
+    const int64_t full = n / (8 * C) * (8 * C);
+    if (id >= full) return id;
+    const int64_t x = id & 7, j = id >> 3;
+    return (j / C * 8 + x) * C + j % C;
+}
 #endif
 
 }  // namespace sidm

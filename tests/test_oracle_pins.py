@@ -488,6 +488,29 @@ def test_kdk_step_with_scattering_conserves_momentum(orc):
     assert np.array_equal(hk, s["h"])
 
 
+def test_step_independent_of_thread_count(orc):
+    """Every sum of the oracle belongs to one target particle and runs in a
+    fixed order, so a step on one thread equals the step on all threads bit
+    for bit (the CPU timing's single-thread figure times the same arithmetic)."""
+    s0 = W.nfw_halo(1024, seed=4)
+    p = orc.make_params(eps=0.01, sigma_m=200.0, dt=1e-3, k=16, seed=2)
+    out = []
+    cores = orc.num_threads()
+    for threads in (1, cores):
+        orc.set_threads(threads)
+        try:
+            s = {k: v.copy() for k, v in s0.items()}
+            orc.total_accel(s, p)
+            ev = orc.kdk_step(s, p, 0)
+        finally:
+            orc.set_threads(cores)
+        out.append((s, ev))
+    (a, ea), (b, eb) = out
+    assert ea.size > 0 and np.array_equal(ea, eb)
+    for k in ("x", "y", "z", "vx", "vy", "vz", "ax", "ay", "az", "pot", "h"):
+        assert np.array_equal(a[k], b[k]), k
+
+
 def test_diag_two_body(orc):
     vx, vy, vz = np.array([1.0, -1.0]), np.array([0.0, 2.0]), np.zeros(2)
     m = np.array([2.0, 3.0])
