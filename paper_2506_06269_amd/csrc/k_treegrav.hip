@@ -120,6 +120,22 @@ __device__ inline double wave_min(double v)
 }
 
 // ---------------------------------------------------------------- list sums
+// A list entry: position and mass.  The mixed sums take the mass in FP32,
+// so there it is rounded once here and kept in the low half of w, read back
+// by reinterpretation (no conversion per term).
+template <bool MIXED>
+__device__ inline double4 make_entry(double x, double y, double z, double m)
+{
+    if (MIXED)
+        return make_double4(x, y, z, __longlong_as_double((long long)__float_as_uint((float)m)));
+    return make_double4(x, y, z, m);
+}
+
+__device__ inline float entry_mass_f32(const double4& q)
+{
+    return __uint_as_float((uint32_t)__double_as_longlong(q.w));
+}
+
 template <bool MIXED>
 struct TreeAcc;
 
@@ -185,7 +201,7 @@ struct TreeAcc<true> {
             const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
             float rinv = __builtin_amdgcn_rsqf(r2);
             if (DIAG && jj == self) rinv = 0.f;
-            const float mr = (float)q.w * rinv;
+            const float mr = entry_mass_f32(q) * rinv;
             const float mr3 = mr * (rinv * rinv);
             p[0] = fmaf(mr3, dx, p[0]);
             p[1] = fmaf(mr3, dy, p[1]);
@@ -216,10 +232,6 @@ struct TreeAcc<true> {
     }
 };
 
-__device__ inline double4 make_entry(double x, double y, double z, double m)
-{
-    return make_double4(x, y, z, m);
-}
 
 // ---------------------------------------------------------------- walk
 // One block = one wave = one group.  tick > 0: tick of a cycle of block steps
@@ -290,7 +302,7 @@ __global__ __launch_bounds__(64) void k_tree_walk(
         if (len + cnt > kTreeList) flush();
         if (lane < cnt) {
             const int64_t q = start + lane;
-            list[len + lane] = make_entry(sx[q], sy[q], sz[q], sm[q]);
+            list[len + lane] = make_entry<MIXED>(sx[q], sy[q], sz[q], sm[q]);
         }
         if (self) {
             self_lo = len;
@@ -332,7 +344,7 @@ __global__ __launch_bounds__(64) void k_tree_walk(
             if (tree_accept(cb, mm.x, gb, H.G, alpha2, a2min)) {
                 if (mm.x != 0.0) {
                     take = true;
-                    e = make_entry(mm.y / mm.x, mm.z / mm.x, mm.w / mm.x, mm.x);
+                    e = make_entry<MIXED>(mm.y / mm.x, mm.z / mm.x, mm.w / mm.x, mm.x);
                 }
             } else if (cc.nchild > 0) {
                 open_inner = true;

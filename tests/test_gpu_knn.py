@@ -92,6 +92,35 @@ def test_knn_large_sampled(S, orc):
     assert np.all(np.isfinite(h)) and np.all(h > 0)
 
 
+def test_knn_start_does_not_change_h(S):
+    """The starting radius only decides how much work a call does: at the
+    benchmark's N = 2^20, a call without a previous h (each sub-range's first
+    member resolved from an estimate, the rest from it), a warm call from that
+    h, a call from h scaled by 0.5 and by 3 (starts far off, which grow or
+    select within a wide sphere) and from unusable values (NaN, negative,
+    larger than the halo) all give the same h bit for bit."""
+    import torch
+    cfg = W.config("C2")
+    s = W.make_state(cfg)
+    n = cfg["n"]
+    halo = dict(n=n, eps=cfg["eps"], k=cfg["k"])
+    dev = S.state_to_device(s)
+    ctx = S.sidm_create(0, n, 1)
+    S.sidm_knn_h(ctx, [halo], dev)
+    torch.cuda.synchronize()
+    cold = dev["h"].clone()
+    assert torch.all(torch.isfinite(cold)) and torch.all(cold > 0)
+    starts = [lambda h: h, lambda h: 0.5 * h, lambda h: 3.0 * h,
+              lambda h: torch.full_like(h, float("nan")), lambda h: -h,
+              lambda h: torch.full_like(h, 1e6)]
+    for i, f in enumerate(starts):
+        dev["h"].copy_(f(cold))
+        S.sidm_knn_h(ctx, [halo], dev)
+        torch.cuda.synchronize()
+        assert torch.equal(dev["h"], cold), i
+    S.sidm_destroy(ctx)
+
+
 def test_knn_coincident_particles(S, orc):
     """Exact duplicates: zero distances and ties everywhere."""
     base = W.maxwell_box(200, seed=2)
