@@ -51,6 +51,34 @@ def test_philox_matches_torch_header(orc):
         assert orc.philox(ctr, key) == T.block(ctr, key)
 
 
+def test_philox_matches_rocrand_header(orc):
+    import _rocrand_philox as R
+    try:
+        R.load()
+    except Exception as e:  # pragma: no cover
+        pytest.skip(f"cannot compile rocRAND Philox header: {e}")
+    rng = np.random.default_rng(8)
+    for _ in range(200):
+        ctr = [int(v) for v in rng.integers(0, 2 ** 32, 4)]
+        key = [int(v) for v in rng.integers(0, 2 ** 32, 2)]
+        assert orc.philox(ctr, key) == R.block(ctr, key)
+
+
+def test_accept_draws_uniform(orc):
+    """The acceptance draws u(seed, step, a, b) of 40 000 pairs are uniform on
+    [0, 1): chi-square over 50 equal bins, and the mean and variance."""
+    from scipy import stats
+    rng = np.random.default_rng(9)
+    a = rng.integers(0, 2 ** 24, 40000)
+    b = a + 1 + rng.integers(0, 2 ** 20, 40000)
+    u = np.array([orc.accept_u(12345, 7, int(x), int(y)) for x, y in zip(a, b)])
+    assert np.all((u >= 0.0) & (u < 1.0))
+    counts, _ = np.histogram(u, bins=50, range=(0.0, 1.0))
+    assert stats.chisquare(counts).pvalue > 1e-3
+    assert np.mean(u) == pytest.approx(0.5, abs=4 * math.sqrt(1 / 12 / u.size))
+    assert np.var(u) == pytest.approx(1 / 12, rel=0.03)
+
+
 def test_u53_mapping(orc):
     assert orc.u53(0, 0) == 0.0
     assert orc.u53(0, 2048) == 2.0 ** -53
