@@ -48,6 +48,10 @@ def _args():
                     help="TREE: particles (2^20: the C2 set-up; 2^24: the C5 set-up)")
     ap.add_argument("--precision", default="mixed", choices=("mixed", "fp64"),
                     help="precision of the C3 run")
+    ap.add_argument("--log-jsonl", default=None, metavar="PATH",
+                    help="append one JSON line per timed step and halo (energies, momentum, "
+                         "events, rounds, pairs, P > 1, status, pass times); each line reads "
+                         "the diagnostics back, one more wait per step")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="also run one plain device-to-device copy of BYTES bytes (a reference "
                          "dispatch for scaling HBM byte counters)")
@@ -63,6 +67,21 @@ def _halo_of(cfg):
                 k=cfg["k"], seed=cfg["seed"], host=cfg["host"])
 
 
+_LOG = None   # open file of --log-jsonl, or None
+
+
+def _log_step(S, run_label, step, dl, e0, passes):
+    for h, d in enumerate(dl):
+        rec = {"run": run_label, "step": step, "halo": h, "E": _energy(d),
+               "dE_over_E0": (_energy(d) - e0[h]) / abs(e0[h]) if e0[h] else None}
+        rec.update({k: d[k] for k in ("K", "W", "Eext", "px", "py", "pz", "n_events",
+                                      "n_rounds", "n_pairs", "n_p_gt1", "status",
+                                      "n_grav_terms")})
+        rec["pass_ms"] = passes
+        _LOG.write(json.dumps(rec) + "\n")
+    _LOG.flush()
+
+
 def _run(S, torch, halos, s, prec, steps, warmup, timing, progress=False):
     n = s["x"].size
     dev = S.state_to_device(s)
@@ -70,7 +89,9 @@ def _run(S, torch, halos, s, prec, steps, warmup, timing, progress=False):
     diag = S.diag_buffer(len(halos))
     S.sidm_gravity(ctx, halos, dev, prec)
     S.sidm_diagnostics(ctx, halos, dev, diag)
-    e0 = sum(_energy(d) for d in S.read_diag(diag))
+    e0_each = [_energy(d) for d in S.read_diag(diag)]
+    e0 = sum(e0_each)
+    run_label = f"{'fp64' if prec == S.SIDM_PREC_FP64 else 'mixed'} n={n} halos={len(halos)}"
     if progress:
         print("initial forces done", file=sys.stderr, flush=True)
     step = 0
@@ -86,9 +107,11 @@ def _run(S, torch, halos, s, prec, steps, warmup, timing, progress=False):
     for _ in range(steps):
         S.sidm_kdk_step(ctx, halos, dev, step, prec, diag=diag)
         step += 1
-        if timing:
-            for k, v in S.sidm_pass_times(ctx).items():
-                passes[k] = passes.get(k, 0.0) + v
+        pt = S.sidm_pass_times(ctx) if timing else {}
+        for k, v in pt.items():
+            passes[k] = passes.get(k, 0.0) + v
+        if _LOG is not None:
+            _log_step(S, run_label, step - 1, S.read_diag(diag), e0_each, pt)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     dl = S.read_diag(diag)
@@ -241,6 +264,8 @@ def _bench_c3(a, S, torch, W):
     t0 = time.perf_counter()
     for step in range(a.steps):
         S.sidm_kdk_step(ctx, [halo], dev, step, prec, diag=diag)
+        if _LOG is not None:
+            _log_step(S, f"C3 {a.precision}", step, S.read_diag(diag), [e0], {})
         if (step + 1) % 100 == 0 or step + 1 == a.steps:
             d = S.read_diag(diag)[0]
             energy.append(dict(step=step + 1, dE_over_E=abs(_energy(d) - e0) / abs(e0),
@@ -437,6 +462,9 @@ def main():
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for "
               f"--gpus {a.gpus}); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    global _LOG
+    if a.log_jsonl:
+        _LOG = open(a.log_jsonl, "a")
     import torch
     import paper_2506_06269_amd as S
     import workloads as W
