@@ -201,6 +201,10 @@ sidm_status sidm_gravity(sidm_ctx *ctx, const sidm_halo *halos, int32_t n_halos,
  * the kernel size is set by the next N_ngb neighbours), with distances
  * d2 = (dx*dx + dy*dy) + dz*dz evaluated in FP64 without fused multiply-add,
  * ties ordered by id, h = correctly rounded sqrt(d2).  Writes state->h.
+ * The value of state->h on entry, where finite, positive and below the halo's
+ * extent, only sets the starting search radius (the result does not depend on
+ * it): a call after a step, with h a few per cent off, costs about half of a
+ * call without usable values.
  * nbr (nullable, device) receives the k neighbour ids of each particle in
  * (d2, id) order, row-major [n_total][k_max] where k_max is the largest k
  * of the halos (rows of halos with smaller k are filled up to their k). */
