@@ -48,6 +48,10 @@ def _args():
                     help="TREE: particles (2^20: the C2 set-up; 2^24: the C5 set-up)")
     ap.add_argument("--precision", default="mixed", choices=("mixed", "fp64"),
                     help="precision of the C3 run")
+    ap.add_argument("--set", action="append", default=[], metavar="KEY=VALUE",
+                    help="C2 and C3: override a field of the workload (n, eps, dt, sigma_m, k, "
+                         "seed, r_cut); the output's config lists the overrides, and no "
+                         "counter-based traffic figure is reported for an overridden run")
     ap.add_argument("--log-jsonl", default=None, metavar="PATH",
                     help="append one JSON line per timed step and halo (energies, momentum, "
                          "events, rounds, pairs, P > 1, status, pass times); each line reads "
@@ -56,6 +60,23 @@ def _args():
                     help="also run one plain device-to-device copy of BYTES bytes (a reference "
                          "dispatch for scaling HBM byte counters)")
     return ap.parse_args()
+
+
+_OVERRIDABLE = {"n": int, "k": int, "seed": int, "eps": float, "dt": float, "sigma_m": float,
+                "r_cut": float}
+
+
+def _apply_overrides(cfg, sets):
+    """Applies --set KEY=VALUE items to a workload config; returns them."""
+    ov = {}
+    for item in sets:
+        key, sep, val = item.partition("=")
+        if not sep or key not in _OVERRIDABLE:
+            raise SystemExit(f"--set {item!r}: expected KEY=VALUE with KEY one of "
+                             f"{', '.join(sorted(_OVERRIDABLE))}")
+        ov[key] = _OVERRIDABLE[key](val)
+    cfg.update(ov)
+    return ov
 
 
 def _energy(d):
@@ -183,7 +204,7 @@ def _cpu_baseline(cfg, s, budget_s):
         "unit": "gravity interactions/s",
         "cores": cores,
         "kind": "oracle",
-        "sample": (f"{m} random particles of the N=2^20 halo: gravity against all N, brute-force "
+        "sample": (f"{m} random particles of the N={n} halo: gravity against all N, brute-force "
                    f"kNN and pair tests with probabilities ({parts[0]:.1f} s, {parts[1]:.1f} s, "
                    f"{parts[2]:.1f} s), extrapolated to a full step of N particles"),
         "step_seconds_extrapolated": step_s,
@@ -243,6 +264,7 @@ def _bench_c3(a, S, torch, W):
     |dE/E| every 100 steps and the central density within 0.1 r_s of the
     potential minimum (Sec. 3) at the start and every 100 steps."""
     cfg = W.config("C3")
+    overrides = _apply_overrides(cfg, a.set)
     n, radius = cfg["n"], 0.1
     s = W.make_state(cfg)
     halo = _halo_of(cfg)
@@ -286,7 +308,8 @@ def _bench_c3(a, S, torch, W):
                                                          "f64 elsewhere",
            "data": "synthetic NFW halo",
            "config": {"workload": "C3: NFW N=2^20 satellite in the host, eps=0.01, k=64, "
-                                  "sigma/m=10, dt=1e-3", "precision": a.precision},
+                                  "sigma/m=10, dt=1e-3", "precision": a.precision,
+                      **({"overrides": overrides} if overrides else {})},
            "dE_over_E": energy[-1]["dE_over_E"] if energy else None,
            "max_dE_over_E": max((e["dE_over_E"] for e in energy), default=None),
            "energy": energy, "central_density": centers, "radius": radius}
@@ -481,6 +504,7 @@ def main():
     if a.workload == "TREE":
         return _bench_tree(a, S, torch, W)
     cfg = W.config("C2")
+    overrides = _apply_overrides(cfg, a.set)
     n = cfg["n"]
     s = W.make_state(cfg)
     inter = n * (n - 1)
@@ -508,7 +532,7 @@ def main():
     achieved = FLOPS_PER_INTERACTION * inter / tiles_s / 1e12
     roof = {"bound": "alu", "kernel": "k_grav_mixed<4>", "achieved": achieved,
             "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
-            "traffic": _traffic(FLOPS_PER_INTERACTION * inter)}
+            "traffic": None if overrides else _traffic(FLOPS_PER_INTERACTION * inter)}
 
     out = {
         "metric": "gravity interactions/s + SIDM particle-updates/s, mixed vs FP64 at |dE/E|",
@@ -526,7 +550,8 @@ def main():
         "config": {"workload": "NFW N=2^20 satellite on a circular orbit in a static NFW host, "
                                "eps=0.01, k=64, sigma/m=10, dt=1e-3, mixed precision",
                    "n": n, "k": cfg["k"], "sigma_m": cfg["sigma_m"], "dt": cfg["dt"],
-                   "eps": cfg["eps"], "parallelism": "single GPU"},
+                   "eps": cfg["eps"], "parallelism": "single GPU",
+                   **({"overrides": overrides} if overrides else {})},
         "sidm_particle_updates_per_s": n / ms_mixed,
         "dE_over_E": de_mixed,
         "events_last_step": events,
