@@ -482,7 +482,7 @@ def _bench_tree(a, S, torch, W):
 def main():
     a = _args()
     if a.gpus != 1:
-        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for "
+        print(f"bench.py measures one GPU: the library has no multi-GPU path (asked for "
               f"--gpus {a.gpus}); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     global _LOG
