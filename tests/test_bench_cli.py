@@ -1,4 +1,4 @@
-"""Host logic of the benchmark driver and the workload listing (no GPU)."""
+"""Host logic of the benchmark script and the workload listing (no GPU)."""
 import json
 import os
 import subprocess

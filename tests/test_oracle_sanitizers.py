@@ -3,7 +3,7 @@ host code only) runs its step in every mode on a small system without a
 report: fixed steps with direct gravity, the static host with the reflecting
 sphere, block time steps and tree gravity; plus the tree force on its own and
 the event search with an event buffer too small (the capacity path).  The
-driver builds its inputs with a fixed linear congruential generator (inputs
+test program builds its inputs with a fixed linear congruential generator (inputs
 only, no arithmetic of the method)."""
 import os
 import subprocess
