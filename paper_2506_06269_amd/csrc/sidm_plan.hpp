@@ -184,6 +184,16 @@ inline bool alloc_scratch(Scratch& w, int64_t N, int32_t H, int64_t max_events, 
         return false;
     }
     if (!realloc_events(w, max_events, why)) return false;
+    // the counters, per-halo event counts, status words and tree term counts
+    // read by the diagnostics start at zero (a context that has not stepped
+    // yet reports no events and a clean status); the passes reset them later
+    if (hipMemset(w.counters, 0, sizeof(DevCounters)) != hipSuccess ||
+        hipMemset(w.ev_counts, 0, sizeof(*w.ev_counts) * (size_t)(4 * H)) != hipSuccess ||
+        hipMemset(w.status, 0, sizeof(*w.status) * (size_t)H) != hipSuccess ||
+        hipMemset(w.tree_terms, 0, sizeof(*w.tree_terms) * (size_t)H) != hipSuccess) {
+        why = "cannot initialise scratch";
+        return false;
+    }
     // owner slots start free; the scattering pass restores them after use
     std::vector<unsigned long long> ones((size_t)std::min<int64_t>(N, 1 << 20), ~0ull);
     for (int64_t o = 0; o < N; o += (int64_t)ones.size()) {
