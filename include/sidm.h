@@ -271,7 +271,8 @@ sidm_status sidm_kdk_step(sidm_ctx *ctx, const sidm_halo *halos, int32_t n_halos
 /* Energies and momentum of the current state (diag: device, n_halos entries).
  * pot must hold the total potential at x.  The event, pair and status fields
  * are those of the last kNN / scattering pass run on this context with the
- * same halos. */
+ * same halos (zero on a context that has run none); the non-finite bit is
+ * also set from the state given here. */
 sidm_status sidm_diagnostics(sidm_ctx *ctx, const sidm_halo *halos, int32_t n_halos,
                              const sidm_state *state, sidm_diag *diag, void *stream);
 
