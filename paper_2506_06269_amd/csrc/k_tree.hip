@@ -131,28 +131,88 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_count(
     hist[(int64_t)t * nblk + blockIdx.x] = cnt[t];
 }
 
-// Exclusive scan of len counts, in place, by one block of 1024 threads.
-__global__ __launch_bounds__(1024) void k_scan_exclusive(uint32_t* __restrict__ a, int64_t len)
+// Exclusive scan of len counts, in place, in three launches: each of nseg
+// blocks sums its segment of seg entries (a multiple of the tile), one block
+// scans the nseg sums, and each block rescans its segment from its offset in
+// tiles of kScanTile entries, four consecutive ones per thread (coalesced).
+constexpr int kScanThreads = 256;
+constexpr int kScanTile = 4 * kScanThreads;
+
+// Exclusive prefix of v over the block's threads (in thread order); total
+// receives the block's sum.  Every thread of the block must call it.
+__device__ inline uint32_t block_scan_excl(uint32_t v, uint32_t* sw, uint32_t& total)
 {
-    __shared__ uint32_t part[1024];
-    const int t = threadIdx.x;
-    const int64_t chunk = (len + 1023) / 1024;
-    const int64_t b = t * chunk, e = b + chunk < len ? b + chunk : len;
-    uint32_t s = 0;
-    for (int64_t i = b; i < e; ++i) s += a[i];
-    part[t] = s;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    uint32_t inc = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t u = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += u;
+    }
+    if (lane == 63) sw[wv] = inc;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        uint32_t v = t >= off ? part[t - off] : 0u;
+    uint32_t off = 0;
+    total = 0;
+    for (int w = 0; w < kScanThreads / 64; ++w) {
+        const uint32_t s = sw[w];
+        if (w < wv) off += s;
+        total += s;
+    }
+    __syncthreads();   // sw is reused by the next call
+    return off + inc - v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* __restrict__ a,
+                                                              int64_t len, int64_t seg,
+                                                              uint32_t* __restrict__ part)
+{
+    __shared__ uint32_t sw[kScanThreads / 64];
+    const int64_t b0 = (int64_t)blockIdx.x * seg;
+    const int64_t b1 = b0 + seg < len ? b0 + seg : len;
+    uint32_t s = 0;
+    for (int64_t i = b0 + threadIdx.x; i < b1; i += kScanThreads) s += a[i];
+    uint32_t total;
+    (void)block_scan_excl(s, sw, total);
+    if (threadIdx.x == 0) part[blockIdx.x] = total;
+}
+
+// Exclusive scan of n <= kScanMaxSeg segment sums, in place, by one block.
+__global__ __launch_bounds__(kScanMaxSeg) void k_scan_parts(uint32_t* __restrict__ part, int n)
+{
+    __shared__ uint32_t p[kScanMaxSeg];
+    const int t = threadIdx.x;
+    const uint32_t v = t < n ? part[t] : 0u;
+    p[t] = v;
+    __syncthreads();
+    for (int off = 1; off < kScanMaxSeg; off <<= 1) {
+        const uint32_t u = t >= off ? p[t - off] : 0u;
         __syncthreads();
-        part[t] += v;
+        p[t] += u;
         __syncthreads();
     }
-    uint32_t run = part[t] - s;  // exclusive prefix of this chunk
-    for (int64_t i = b; i < e; ++i) {
-        const uint32_t v = a[i];
-        a[i] = run;
-        run += v;
+    if (t < n) part[t] = p[t] - v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(uint32_t* __restrict__ a,
+                                                             int64_t len, int64_t seg,
+                                                             const uint32_t* __restrict__ part)
+{
+    __shared__ uint32_t sw[kScanThreads / 64];
+    const int64_t b0 = (int64_t)blockIdx.x * seg;
+    const int64_t b1 = b0 + seg < len ? b0 + seg : len;
+    uint32_t carry = part[blockIdx.x];
+    for (int64_t t0 = b0; t0 < b1; t0 += kScanTile) {
+        const int64_t i0 = t0 + 4 * (int64_t)threadIdx.x;
+        uint32_t v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = i0 + q < b1 ? a[i0 + q] : 0u;
+        uint32_t total;
+        uint32_t run = carry + block_scan_excl(v[0] + v[1] + v[2] + v[3], sw, total);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (i0 + q < b1) a[i0 + q] = run;
+            run += v[q];
+        }
+        carry += total;
     }
 }
 
@@ -389,6 +449,20 @@ __global__ __launch_bounds__(256) void k_node_hmax(const NodeTask* __restrict__ 
 // ---------------------------------------------------------------- launchers
 static unsigned grid_of(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
+// about four tiles per segment, at most kScanMaxSeg segments
+static void launch_scan(uint32_t* a, int64_t len, uint32_t* part, hipStream_t st)
+{
+    int64_t nseg = (len + 4 * kScanTile - 1) / (4 * kScanTile);
+    nseg = nseg < 1 ? 1 : (nseg > kScanMaxSeg ? kScanMaxSeg : nseg);
+    int64_t seg = (len + nseg - 1) / nseg;
+    seg = (seg + kScanTile - 1) / kScanTile * kScanTile;
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nseg), dim3(kScanThreads), 0, st, a, len, seg,
+                       part);
+    hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(kScanMaxSeg), 0, st, part, (int)nseg);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nseg), dim3(kScanThreads), 0, st, a, len, seg,
+                       part);
+}
+
 hipError_t launch_cell_list(const Plan& P, const sidm_state* s, Scratch& w, hipStream_t st,
                             int tick, int bmax)
 {
@@ -407,8 +481,7 @@ hipError_t launch_cell_list(const Plan& P, const sidm_state* s, Scratch& w, hipS
         const int shift = p * kSortBits;
         hipLaunchKernelGGL(k_sort_count, dim3((unsigned)nblk), dim3(kSortBlock), 0, st,
                            w.keys[cur], n, shift, w.hist, nblk);
-        hipLaunchKernelGGL(k_scan_exclusive, dim3(1), dim3(1024), 0, st, w.hist,
-                           nblk * (1 << kSortBits));
+        launch_scan(w.hist, nblk * (1 << kSortBits), w.scan_part, st);
         hipLaunchKernelGGL(k_sort_scatter, dim3((unsigned)nblk), dim3(kSortBlock), 0, st,
                            w.keys[cur], w.vals[cur], w.keys[cur ^ 1], w.vals[cur ^ 1], n, shift,
                            w.hist, nblk);

@@ -22,6 +22,7 @@ constexpr int kTickSplit = 16;       // j-splits of a block-step tick
 constexpr int kSortBits = 8;         // radix digit width
 constexpr int kSortItems = 16;       // keys per thread per sort block
 constexpr int kSortBlock = 256;
+constexpr int kScanMaxSeg = 1024;   // blocks of the multi-block exclusive scan at most
 
 // Per-halo parameters and derived layout, uploaded once per halo configuration.
 struct HaloDev {

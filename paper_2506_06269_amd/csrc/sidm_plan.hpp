@@ -82,6 +82,7 @@ struct Scratch {
     unsigned long long* keys[2] = {nullptr, nullptr};
     uint32_t* vals[2] = {nullptr, nullptr};
     uint32_t* hist = nullptr;
+    uint32_t* scan_part = nullptr;    // segment sums of the histogram scan
     int64_t hist_cap = 0;
     double *sx = nullptr, *sy = nullptr, *sz = nullptr;
     double4* sp4 = nullptr;       // sorted positions as (x, y, z, 0): one load per candidate
@@ -171,7 +172,7 @@ inline bool alloc_scratch(Scratch& w, int64_t N, int32_t H, int64_t max_events, 
               dalloc(w.tidal, 8 * H) && dalloc(w.bbox, 6 * H) &&
               dalloc(w.xm32, N) &&  dalloc(w.partial, w.partial_rows) && dalloc(w.keys[0], N) &&
               dalloc(w.keys[1], N) && dalloc(w.vals[0], N) && dalloc(w.vals[1], N) &&
-              dalloc(w.hist, w.hist_cap) && dalloc(w.sx, N) && dalloc(w.sy, N) &&
+              dalloc(w.hist, w.hist_cap) && dalloc(w.scan_part, kScanMaxSeg) && dalloc(w.sx, N) && dalloc(w.sy, N) &&
               dalloc(w.sz, N) && dalloc(w.sp4, N) && dalloc(w.svx, N) && dalloc(w.svy, N) && dalloc(w.svz, N) &&
               dalloc(w.sh, N) && dalloc(w.sm, N) && dalloc(w.bin, N) &&
               dalloc(w.mom, w.nodes_cap) && dalloc(w.tree_terms, H) && dalloc(w.sid, N) && dalloc(w.perm, N) &&
@@ -211,7 +212,7 @@ inline void free_scratch(Scratch& w)
 {
     dfree(w.halos); dfree(w.blocks); dfree(w.items); dfree(w.buckets); dfree(w.node_tasks); dfree(w.nodes);
     dfree(w.bsum); dfree(w.cref); dfree(w.radius); dfree(w.center); dfree(w.tidal); dfree(w.bbox); dfree(w.xm32);  dfree(w.partial);
-    dfree(w.keys[0]); dfree(w.keys[1]); dfree(w.vals[0]); dfree(w.vals[1]); dfree(w.hist);
+    dfree(w.keys[0]); dfree(w.keys[1]); dfree(w.vals[0]); dfree(w.vals[1]); dfree(w.hist); dfree(w.scan_part);
     dfree(w.sx); dfree(w.sy); dfree(w.sz); dfree(w.sp4); dfree(w.svx); dfree(w.svy); dfree(w.svz);
     dfree(w.items_tick); dfree(w.partial_tick);
     w.items_tick_cap = w.partial_tick_rows = 0;
