@@ -56,18 +56,21 @@ def test_struct_layouts_match_header():
 #include <stddef.h>
 #include "sidm.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(sidm_halo), sizeof(sidm_state),
-         sizeof(sidm_diag), sizeof(sidm_event), offsetof(sidm_halo, seed),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(sidm_halo),
+         sizeof(sidm_state), sizeof(sidm_diag), sizeof(sidm_event), offsetof(sidm_halo, seed),
          offsetof(sidm_diag, n_events), offsetof(sidm_diag, status), sizeof(sidm_center),
-         offsetof(sidm_center, index), offsetof(sidm_halo, eta), offsetof(sidm_halo, max_bin));
+         offsetof(sidm_center, index), offsetof(sidm_halo, eta), offsetof(sidm_halo, max_bin),
+         offsetof(sidm_halo, tree_alpha), offsetof(sidm_diag, n_grav_terms));
   return 0; }
 '''
     d = tempfile.mkdtemp()
     c, exe = os.path.join(d, "l.c"), os.path.join(d, "l")
     open(c, "w").write(src)
-    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I",
+                    os.path.join(ROOT, "include"), c, "-o", exe], check=True)
     got = [int(v) for v in subprocess.run([exe], capture_output=True, text=True).stdout.split()]
     assert got == [C.sizeof(S.SidmHalo), C.sizeof(S.SidmState), C.sizeof(S.SidmDiag),
                    S.EVENT_BYTES, S.SidmHalo.seed.offset, S.SidmDiag.n_events.offset,
                    S.SidmDiag.status.offset, C.sizeof(S.SidmCenter), S.SidmCenter.index.offset,
-                   S.SidmHalo.eta.offset, S.SidmHalo.max_bin.offset]
+                   S.SidmHalo.eta.offset, S.SidmHalo.max_bin.offset,
+                   S.SidmHalo.tree_alpha.offset, S.SidmDiag.n_grav_terms.offset]
