@@ -22,9 +22,24 @@
  *   - Argument errors are detected on the host before anything is enqueued and
  *     return SIDM_ERR_INVALID (or SIDM_ERR_UNSUPPORTED) with a message in
  *     sidm_last_error().  HIP launch errors return SIDM_ERR_HIP.  Conditions the
- *     device detects (event buffer overflow, kNN search overflow, non-finite
- *     state) are reported in sidm_diag.status and, for synchronous calls, as
- *     SIDM_ERR_CAPACITY.
+ *     device detects (the SIDM_DEV_* bits: event buffer overflow, kNN search
+ *     overflow, unequal masses or repeated ids in a halo that scatters, a stale
+ *     graph replay) are reported in sidm_diag.status, by a synchronous call
+ *     itself, and otherwise by the next call on the context that finds the
+ *     earlier call's kernels finished: that call returns SIDM_ERR_CAPACITY
+ *     (overflows), SIDM_ERR_UNSUPPORTED (unequal masses) or SIDM_ERR_INVALID
+ *     (repeated ids, stale replay) without running, with the conditions in
+ *     sidm_last_error(); they are reported once.  sidm_take_status() waits and
+ *     returns them instead.
+ *   - Graphs: calls may be captured into a HIP graph once a call outside
+ *     capture has used the same halos and the same state pointers (that call
+ *     builds the launch plan).  A replay uses the pointers of the capture.  A
+ *     call outside capture with other halos or state pointers, or a change of
+ *     the context's scratch (sidm_set_event_capacity, the first call with block
+ *     time steps), makes earlier captures stale: their replays set
+ *     SIDM_DEV_STALE_GRAPH (the kernels still run with the captured pointers,
+ *     so free nothing a graph may still use).  Reallocating state buffers
+ *     without any call outside capture in between is not detected.
  *   - Halos are independent systems: particles of different halos neither
  *     attract nor scatter.  Halo ranges must not overlap.
  *   - A context is thread-compatible (one thread at a time), not thread-safe.
@@ -148,6 +163,14 @@ typedef struct {
 #define SIDM_DEV_KNN_OVERFLOW   2   /* a neighbour search needed more refinement
                                        levels than supported (h is NaN there)   */
 #define SIDM_DEV_NONFINITE      4   /* a position or velocity is not finite     */
+#define SIDM_DEV_UNEQUAL_MASS   8   /* sigma_m > 0 but the masses of the halo are
+                                       not all equal: the halo was not scattered */
+#define SIDM_DEV_DUPLICATE_ID  16   /* two particles of the halo share an id: the
+                                       halo was not scattered                    */
+#define SIDM_DEV_STALE_GRAPH   32   /* a captured sequence was replayed after a
+                                       call outside capture changed the halos,
+                                       the state pointers or the context's
+                                       scratch (see Graphs above)                */
 
 /* ---- context ---------------------------------------------------------------
  * Creates a context on HIP device `device` with scratch memory for up to
@@ -234,10 +257,24 @@ sidm_status sidm_knn_h(sidm_ctx *ctx, const sidm_halo *halos, int32_t n_halos,
  * n_events_host (nullable): if given, the call waits for the device and stores
  * the number of events; it returns SIDM_ERR_CAPACITY if the context's event
  * capacity or `cap` was exceeded (then no kick was applied; the decisions are a
- * pure function of the state, so a retry with more capacity reproduces them). */
+ * pure function of the state, so a retry with more capacity reproduces them),
+ * SIDM_ERR_UNSUPPORTED if a halo with sigma_m > 0 has unequal masses, and
+ * SIDM_ERR_INVALID if a halo repeats an id (such halos are not scattered: the
+ * probability takes the mass of the member with the larger id, which is only
+ * symmetric for equal masses -- every run of the paper's Table 1 has one
+ * particle mass -- and ids key the draws and order the kicks). */
 sidm_status sidm_scatter(sidm_ctx *ctx, const sidm_halo *halos, int32_t n_halos,
                          const sidm_state *state, uint32_t step, sidm_event *events,
                          int64_t cap, int64_t *n_events_host, void *stream);
+
+/* Copies the events of the last scattering pass run on the context
+ * (sidm_scatter or sidm_kdk_step) into out (device, cap records), in
+ * unspecified order; nothing when they overflowed the context's buffer.
+ * n_events_host (nullable): if given, the call waits for the device, stores the
+ * number of events found and returns SIDM_ERR_CAPACITY when they exceed the
+ * context's capacity or cap.  For tests and for callers that record events. */
+sidm_status sidm_last_events(sidm_ctx *ctx, sidm_event *out, int64_t cap,
+                             int64_t *n_events_host, void *stream);
 
 /* ---- one step ------------------------------------------------------------------
  * Pre-condition: state a/pot hold the values at the current x (call
@@ -315,6 +352,10 @@ typedef struct {
 } sidm_tidal;
 sidm_status sidm_tidal_radius(sidm_ctx *ctx, const sidm_halo *halos, int32_t n_halos,
                               const sidm_state *state, sidm_tidal *out, void *stream);
+
+/* Waits for the device and returns in *bits the SIDM_DEV_* conditions found
+ * by the context's calls and not yet reported, then clears them. */
+sidm_status sidm_take_status(sidm_ctx *ctx, int32_t *bits);
 
 /* ---- pass timing ---------------------------------------------------------
  * When enabled, sidm_kdk_step records HIP events on its stream around each

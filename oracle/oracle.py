@@ -84,6 +84,11 @@ def _declare(L):
                                    _i64p]
     L.orc_tidal_radius.restype = C.c_int
     L.orc_knn_grid.argtypes = [C.c_int64, _dp, _dp, _dp, _u32p, C.c_int32, _dp]
+    L.orc_knn_tree.argtypes = [C.c_int64, _dp, _dp, _dp, _u32p, C.c_int32, _dp, _u32p]
+    L.orc_find_events_tree.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _u32p,
+                                       _dp, C.c_double, C.c_double, C.c_double, C.c_uint64,
+                                       C.c_uint32, C.c_void_p, C.c_int64, _i64p, _i64p]
+    L.orc_find_events_tree.restype = C.c_int64
     L.orc_find_events_sweep.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _u32p,
                                         _dp, C.c_double, C.c_double, C.c_double, C.c_uint64,
                                         C.c_uint32,
@@ -251,6 +256,18 @@ def knn_grid(x, y, z, ids, k):
     return h
 
 
+def knn_tree(x, y, z, ids, k, want_list=False):
+    """h (and the neighbour lists) of every particle from the k-d tree search
+    (equal to knn's)."""
+    x, y, z = _f64(x), _f64(y), _f64(z)
+    ids = np.ascontiguousarray(ids, dtype=np.uint32)
+    h = np.zeros(x.size)
+    nbr = np.zeros((x.size, k), dtype=np.uint32) if want_list else None
+    lib().orc_knn_tree(x.size, _d(x), _d(y), _d(z), ids.ctypes.data_as(_u32p), int(k), _d(h),
+                       nbr.ctypes.data_as(_u32p) if want_list else None)
+    return (h, nbr) if want_list else h
+
+
 # ---------------------------------------------------------------- scatter
 def sigma(sigma_m, sigma_w, g):
     return lib().orc_sigma(float(sigma_m), float(sigma_w), float(g))
@@ -290,6 +307,26 @@ def find_events_sweep(x, y, z, vx, vy, vz, m, ids, h, sigma_m, dt, seed, step, s
     ev = np.zeros(max(found, 1), dtype=EVENT_DTYPE)
     found2 = lib().orc_find_events_sweep(*args, ev.ctypes.data, found, None, None)
     assert found2 == found
+    return ev[:found], int(npairs.value), int(npgt1.value)
+
+
+def find_events_tree(x, y, z, vx, vy, vz, m, ids, h, sigma_m, dt, seed, step, sigma_w=0.0):
+    """find_events over all pairs, from the k-d tree range search (equal results)."""
+    arrs = [_f64(a) for a in (x, y, z, vx, vy, vz, m)]
+    ids = np.ascontiguousarray(ids, dtype=np.uint32)
+    h = _f64(h)
+    n = arrs[0].size
+    npairs, npgt1 = C.c_int64(0), C.c_int64(0)
+    args = [n] + [_d(a) for a in arrs] + [ids.ctypes.data_as(_u32p), _d(h), float(sigma_m),
+                                          float(sigma_w), float(dt), int(seed), int(step)]
+    cap = max(16, n // 64)
+    ev = np.zeros(cap, dtype=EVENT_DTYPE)
+    found = lib().orc_find_events_tree(*args, ev.ctypes.data, cap, C.byref(npairs),
+                                       C.byref(npgt1))
+    if found > cap:
+        ev = np.zeros(found, dtype=EVENT_DTYPE)
+        found2 = lib().orc_find_events_tree(*args, ev.ctypes.data, found, None, None)
+        assert found2 == found
     return ev[:found], int(npairs.value), int(npgt1.value)
 
 

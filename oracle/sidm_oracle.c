@@ -1101,6 +1101,324 @@ int64_t orc_find_events_sweep(int64_t n, const double *x, const double *y, const
 }
 
 /* ------------------------------------------------------------------------ */
+/* Exact searches over a k-d tree (for full-size runs).  Like the grid and the
+ * sweep they change only the order in which candidates are examined: every
+ * distance, the (d2, id) order and the pair test are the expressions of the
+ * brute-force definitions.  A subtree is skipped only when the squared
+ * distance from the particle to its box (the same expression on the box's
+ * gaps, which rounding cannot make larger than any member's d2) already rules
+ * out every member. */
+
+typedef struct {
+    double lo[3], hi[3];    /* bounding box of the node's particles            */
+    double hmin;            /* smallest h among them (event search; else 0)     */
+    int64_t begin, end;     /* the node's particles: idx[begin .. end)          */
+    int64_t left, right;    /* children, -1 for a leaf                           */
+} kd_node;
+
+typedef struct {
+    const double *p[3];
+    const double *h;
+    int64_t *idx;
+    kd_node *node;
+    int64_t n_node, cap;
+} kd_tree;
+
+enum { KD_LEAF = 16 };
+
+/* i before j along axis a (ties by index, so every key is distinct) */
+static int kd_before(const kd_tree *t, int a, int64_t i, int64_t j)
+{
+    const double u = t->p[a][i], v = t->p[a][j];
+    return u < v || (u == v && i < j);
+}
+
+/* Rearranges idx[lo, hi) so that position k holds the element of rank k - lo
+ * along axis a, smaller ones before it and larger ones after it. */
+static void kd_select(kd_tree *t, int a, int64_t lo, int64_t hi, int64_t k)
+{
+    int64_t *v = t->idx;
+    while (hi - lo > 1) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        int64_t tmp = v[mid]; v[mid] = v[hi - 1]; v[hi - 1] = tmp;
+        const int64_t pv = v[hi - 1];
+        int64_t s = lo;
+        for (int64_t i = lo; i < hi - 1; ++i)
+            if (kd_before(t, a, v[i], pv)) {
+                tmp = v[i]; v[i] = v[s]; v[s] = tmp;
+                ++s;
+            }
+        tmp = v[s]; v[s] = v[hi - 1]; v[hi - 1] = tmp;
+        if (k == s) return;
+        if (k < s) hi = s;
+        else lo = s + 1;
+    }
+}
+
+static int64_t kd_new(kd_tree *t)
+{
+    if (t->n_node == t->cap) {
+        t->cap = t->cap ? 2 * t->cap : 64;
+        t->node = (kd_node *)realloc(t->node, sizeof(kd_node) * (size_t)t->cap);
+    }
+    return t->n_node++;
+}
+
+/* Node over idx[begin, end): its box, then a split at the median of the
+ * longest side while it holds more than KD_LEAF particles. */
+static int64_t kd_build_node(kd_tree *t, int64_t begin, int64_t end)
+{
+    const int64_t nd = kd_new(t);
+    kd_node N;
+    for (int a = 0; a < 3; ++a) {
+        N.lo[a] = INFINITY;
+        N.hi[a] = -INFINITY;
+    }
+    N.hmin = INFINITY;
+    for (int64_t q = begin; q < end; ++q) {
+        const int64_t i = t->idx[q];
+        for (int a = 0; a < 3; ++a) {
+            if (t->p[a][i] < N.lo[a]) N.lo[a] = t->p[a][i];
+            if (t->p[a][i] > N.hi[a]) N.hi[a] = t->p[a][i];
+        }
+        if (t->h && t->h[i] < N.hmin) N.hmin = t->h[i];
+    }
+    if (!t->h) N.hmin = 0.0;
+    N.begin = begin;
+    N.end = end;
+    N.left = N.right = -1;
+    if (end - begin > KD_LEAF) {
+        int a = 0;
+        for (int c = 1; c < 3; ++c)
+            if (N.hi[c] - N.lo[c] > N.hi[a] - N.lo[a]) a = c;
+        const int64_t mid = begin + (end - begin) / 2;
+        kd_select(t, a, begin, end, mid);
+        N.left = kd_build_node(t, begin, mid);
+        N.right = kd_build_node(t, mid, end);
+    }
+    t->node[nd] = N;
+    return nd;
+}
+
+static void kd_build(kd_tree *t, int64_t n, const double *x, const double *y, const double *z,
+                     const double *h)
+{
+    t->p[0] = x;
+    t->p[1] = y;
+    t->p[2] = z;
+    t->h = h;
+    t->idx = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) t->idx[i] = i;
+    t->node = NULL;
+    t->n_node = t->cap = 0;
+    kd_build_node(t, 0, n);
+}
+
+static void kd_free(kd_tree *t)
+{
+    free(t->idx);
+    free(t->node);
+}
+
+/* Squared distance from (x, y, z) to the node's box: the gaps per axis
+ * combined as a candidate's d2 is.  For a member q, |fl(q - x)| is at least
+ * the gap on each axis (rounding is monotone), so this is at most its d2. */
+static double kd_box_d2(const kd_node *N, double x, double y, double z)
+{
+    const double p[3] = {x, y, z};
+    double g[3];
+    for (int a = 0; a < 3; ++a) {
+        const double u = N->lo[a] - p[a], v = p[a] - N->hi[a];
+        const double w = u > v ? u : v;
+        g[a] = w > 0.0 ? w : 0.0;
+    }
+    return (g[0] * g[0] + g[1] * g[1]) + g[2] * g[2];
+}
+
+typedef struct {
+    const uint32_t *id;
+    double *bd;
+    uint32_t *bi;
+    int32_t k, cnt;
+} kd_best;
+
+/* The k best (d2, id) of particle i over the subtree, nearer child first. */
+static void kd_knn_visit(const kd_tree *t, int64_t nd, int64_t i, kd_best *B)
+{
+    const kd_node *N = &t->node[nd];
+    const double *x = t->p[0], *y = t->p[1], *z = t->p[2];
+    const int32_t k = B->k;
+    if (B->cnt == k && kd_box_d2(N, x[i], y[i], z[i]) > B->bd[k - 1]) return;
+    if (N->left < 0) {
+        for (int64_t q = N->begin; q < N->end; ++q) {
+            const int64_t j = t->idx[q];
+            if (j == i) continue;
+            double dx = x[j] - x[i], dy = y[j] - y[i], dz = z[j] - z[i];
+            double d2 = (dx * dx + dy * dy) + dz * dz;
+            if (B->cnt == k && !key_less(d2, B->id[j], B->bd[k - 1], B->bi[k - 1])) continue;
+            int32_t pos = B->cnt < k ? B->cnt : k - 1;
+            while (pos > 0 && key_less(d2, B->id[j], B->bd[pos - 1], B->bi[pos - 1])) {
+                B->bd[pos] = B->bd[pos - 1];
+                B->bi[pos] = B->bi[pos - 1];
+                --pos;
+            }
+            B->bd[pos] = d2;
+            B->bi[pos] = B->id[j];
+            if (B->cnt < k) ++B->cnt;
+        }
+        return;
+    }
+    const double dl = kd_box_d2(&t->node[N->left], x[i], y[i], z[i]);
+    const double dr = kd_box_d2(&t->node[N->right], x[i], y[i], z[i]);
+    if (dl <= dr) {
+        kd_knn_visit(t, N->left, i, B);
+        kd_knn_visit(t, N->right, i, B);
+    } else {
+        kd_knn_visit(t, N->right, i, B);
+        kd_knn_visit(t, N->left, i, B);
+    }
+}
+
+void orc_knn_tree(int64_t n, const double *x, const double *y, const double *z,
+                  const uint32_t *id, int32_t k, double *h, uint32_t *nbr)
+{
+    kd_tree t;
+    kd_build(&t, n, x, y, z, NULL);
+#pragma omp parallel
+    {
+        kd_best B;
+        B.id = id;
+        B.k = k;
+        B.bd = (double *)malloc(sizeof(double) * (size_t)k);
+        B.bi = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)k);
+#pragma omp for schedule(dynamic, 256)
+        for (int64_t i = 0; i < n; ++i) {
+            B.cnt = 0;
+            kd_knn_visit(&t, 0, i, &B);
+            h[i] = sqrt(B.bd[k - 1]);
+            if (nbr) memcpy(nbr + (size_t)i * (size_t)k, B.bi, sizeof(uint32_t) * (size_t)k);
+        }
+        free(B.bd);
+        free(B.bi);
+    }
+    kd_free(&t);
+}
+
+/* Per-thread event collection of the tree search. */
+typedef struct {
+    const double *x, *y, *z, *vx, *vy, *vz, *m, *h;
+    const uint32_t *id;
+    double sigma_m, sigma_w, dt;
+    uint64_t seed;
+    uint32_t step;
+    int64_t pairs, pgt1, n, cap;
+    orc_event *ev;
+} kd_pairs;
+
+/* The pair {i, j} as orc_find_events tests and decides it (indices ordered
+ * for the differences, ids for the roles a and b).  The overlap integral is
+ * evaluated only when the draw lies below an upper bound of P: Lambda is at
+ * most the smaller of the two kernels' central values, 8 / (pi max(h)^3), so
+ * a draw at or above that bound (with a margin far beyond rounding) can be
+ * neither an event nor a pair with P > 1 (the bound is then below 1). */
+static void kd_pair(kd_pairs *C, int64_t i, int64_t j)
+{
+    const int64_t lo_i = i < j ? i : j, hi_i = i < j ? j : i;
+    const double *x = C->x, *y = C->y, *z = C->z, *h = C->h;
+    double dx = x[hi_i] - x[lo_i], dy = y[hi_i] - y[lo_i], dz = z[hi_i] - z[lo_i];
+    double d2 = (dx * dx + dy * dy) + dz * dz;
+    double hs = h[lo_i] + h[hi_i];
+    if (!(d2 < hs * hs)) return;
+    ++C->pairs;
+    const int64_t ia = C->id[lo_i] < C->id[hi_i] ? lo_i : hi_i;
+    const int64_t ib = C->id[lo_i] < C->id[hi_i] ? hi_i : lo_i;
+    const uint32_t a = C->id[ia], b = C->id[ib];
+    const double u = orc_accept_u(C->seed, C->step, a, b);
+    double gx = C->vx[ia] - C->vx[ib], gy = C->vy[ia] - C->vy[ib], gz = C->vz[ia] - C->vz[ib];
+    double gg = sqrt((gx * gx + gy * gy) + gz * gz);
+    const double sg = orc_sigma(C->sigma_m, C->sigma_w, gg);
+    const double hm = h[ia] > h[ib] ? h[ia] : h[ib];
+    const double bound = sg * C->m[ib] * gg * (8.0 / (M_PI * hm * hm * hm)) * C->dt * (1.0 + 1e-6);
+    if (!(u < bound)) return;
+    double lam = orc_lambda(sqrt(d2), h[ia], h[ib]);
+    double P = sg * C->m[ib] * gg * lam * C->dt;
+    if (P > 1.0) ++C->pgt1;
+    if (u < P) {
+        if (C->n == C->cap) {
+            C->cap = C->cap ? 2 * C->cap : 64;
+            C->ev = (orc_event *)realloc(C->ev, sizeof(orc_event) * (size_t)C->cap);
+        }
+        orc_event e = {a, b, ia, ib, u, P};
+        C->ev[C->n++] = e;
+    }
+}
+
+/* A pair with d < h_i + h_j has d < 2 max(h_i, h_j): it is found from its
+ * member with the larger h (the larger index on ties), among the particles
+ * within twice that h. */
+static void kd_pairs_visit(const kd_tree *t, int64_t nd, int64_t i, double R2, kd_pairs *C)
+{
+    const kd_node *N = &t->node[nd];
+    const double *h = C->h;
+    if (N->hmin > h[i] || kd_box_d2(N, C->x[i], C->y[i], C->z[i]) > R2) return;
+    if (N->left < 0) {
+        for (int64_t q = N->begin; q < N->end; ++q) {
+            const int64_t j = t->idx[q];
+            if (j == i) continue;
+            if (!(h[j] < h[i] || (h[j] == h[i] && j < i))) continue;
+            kd_pair(C, i, j);
+        }
+        return;
+    }
+    kd_pairs_visit(t, N->left, i, R2, C);
+    kd_pairs_visit(t, N->right, i, R2, C);
+}
+
+int64_t orc_find_events_tree(int64_t n, const double *x, const double *y, const double *z,
+                             const double *vx, const double *vy, const double *vz,
+                             const double *m, const uint32_t *id, const double *h,
+                             double sigma_m, double sigma_w, double dt, uint64_t seed,
+                             uint32_t step, orc_event *ev, int64_t cap, int64_t *n_pairs,
+                             int64_t *n_p_gt1)
+{
+    kd_tree t;
+    kd_build(&t, n, x, y, z, h);
+    int64_t found = 0, pairs = 0, pgt1 = 0;
+    orc_event *all = NULL;
+    int64_t all_cap = 0;
+#pragma omp parallel
+    {
+        kd_pairs C = {x, y, z, vx, vy, vz, m, h, id, sigma_m, sigma_w, dt, seed, step,
+                      0, 0, 0, 0, NULL};
+#pragma omp for schedule(dynamic, 256)
+        for (int64_t i = 0; i < n; ++i) {
+            const double R = 2.0 * h[i] * (1.0 + 1e-9);
+            kd_pairs_visit(&t, 0, i, R * R, &C);
+        }
+#pragma omp critical
+        {
+            if (found + C.n > all_cap) {
+                all_cap = 2 * (found + C.n) + 64;
+                all = (orc_event *)realloc(all, sizeof(orc_event) * (size_t)all_cap);
+            }
+            if (C.n > 0) memcpy(all + found, C.ev, sizeof(orc_event) * (size_t)C.n);
+            found += C.n;
+            pairs += C.pairs;
+            pgt1 += C.pgt1;
+        }
+        free(C.ev);
+    }
+    kd_free(&t);
+    if (found > 0) qsort(all, (size_t)found, sizeof(orc_event), cmp_event);
+    int64_t stored = found < cap ? found : cap;
+    if (stored > 0 && ev) memcpy(ev, all, sizeof(orc_event) * (size_t)stored);
+    free(all);
+    if (n_pairs) *n_pairs = pairs;
+    if (n_p_gt1) *n_p_gt1 = pgt1;
+    return found;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Central density (Sec. 3: the halo centre is the minimum of the
  * gravitational potential).  Reading: the centre is the particle with the
  * lowest self-potential phi (first index on ties); the density is the mass
@@ -1409,18 +1727,18 @@ int64_t orc_kdk_step(int64_t n, double *x, double *y, double *z,
         vz[i] += az[i] * hdt;
     }
 synchronised:
-    orc_knn_grid(n, x, y, z, id, p->k, h);
+    orc_knn_tree(n, x, y, z, id, p->k, h, NULL);
     if (p->sigma_m == 0.0) return 0;
     int64_t cap = ev_cap > 0 ? ev_cap : 0;
     orc_event *buf = ev;
-    int64_t found = orc_find_events_sweep(n, x, y, z, vx, vy, vz, m, id, h, p->sigma_m,
-                                          p->sigma_w, p->dt, p->seed, step, buf, cap, NULL,
-                                          NULL);
+    int64_t found = orc_find_events_tree(n, x, y, z, vx, vy, vz, m, id, h, p->sigma_m,
+                                         p->sigma_w, p->dt, p->seed, step, buf, cap, NULL,
+                                         NULL);
     if (found > cap) {
         /* not enough room to hold the ordered list: collect it privately */
         buf = (orc_event *)malloc(sizeof(orc_event) * (size_t)found);
-        orc_find_events_sweep(n, x, y, z, vx, vy, vz, m, id, h, p->sigma_m, p->sigma_w, p->dt,
-                              p->seed, step, buf, found, NULL, NULL);
+        orc_find_events_tree(n, x, y, z, vx, vy, vz, m, id, h, p->sigma_m, p->sigma_w, p->dt,
+                             p->seed, step, buf, found, NULL, NULL);
     }
     orc_apply_events(found, buf, m, vx, vy, vz, p->seed, step);
     if (buf != ev) {

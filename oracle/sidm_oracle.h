@@ -132,6 +132,11 @@ void orc_knn(int64_t n, const double *x, const double *y, const double *z,
 void orc_knn_grid(int64_t n, const double *x, const double *y, const double *z,
                   const uint32_t *id, int32_t k, double *h);
 
+/* The same h as orc_knn for every particle, bit for bit, and (nbr nullable)
+ * the same neighbour lists, from a search over a k-d tree. */
+void orc_knn_tree(int64_t n, const double *x, const double *y, const double *z,
+                  const uint32_t *id, int32_t k, double *h, uint32_t *nbr);
+
 /* ---- pairwise scattering (paper Sec. 2 and Sec. 3.5) ---- */
 
 /* Cross-section per unit mass at relative speed g (Sec. 3.8, Eq. vel_dep):
@@ -167,6 +172,16 @@ int64_t orc_find_events_sweep(int64_t n, const double *x, const double *y, const
                               double sigma_m, double sigma_w, double dt, uint64_t seed,
                               uint32_t step, orc_event *ev, int64_t cap, int64_t *n_pairs,
                               int64_t *n_p_gt1);
+
+/* The same events, pair count and P > 1 count as orc_find_events without a
+ * query set, from a range search over a k-d tree (the overlap integral only
+ * where the draw falls below an upper bound of P; see the source). */
+int64_t orc_find_events_tree(int64_t n, const double *x, const double *y, const double *z,
+                             const double *vx, const double *vy, const double *vz,
+                             const double *m, const uint32_t *id, const double *h,
+                             double sigma_m, double sigma_w, double dt, uint64_t seed,
+                             uint32_t step, orc_event *ev, int64_t cap, int64_t *n_pairs,
+                             int64_t *n_p_gt1);
 
 /* Elastic isotropic scattering of one pair in its centre-of-mass frame, using
  * the direction draw at counter (a, b, step, 1).  Updates the two velocities. */
@@ -226,7 +241,7 @@ typedef struct orc_params_s {
 int32_t orc_bin(double dt, double eta, double eps, double dt_min, int32_t max_bin,
                 double ax, double ay, double az);
 
-/* Full-N step for one halo (exact searches: orc_knn_grid, orc_find_events_sweep).
+/* Full-N step for one halo (exact searches: orc_knn_tree, orc_find_events_tree).
  * With eta > 0 the step is one cycle of block time steps (see the source).  On entry a/pot hold the acceleration
  * and potential at x (self + host).  Performs K(dt/2), D(dt), gravity + host,
  * K(dt/2), h from kNN, events, ordered kicks.  Writes h; returns the number of

@@ -34,11 +34,14 @@ SIDM_MAX_K = 128
 SIDM_DEV_EVENT_OVERFLOW = 1
 SIDM_DEV_KNN_OVERFLOW = 2
 SIDM_DEV_NONFINITE = 4
+SIDM_DEV_UNEQUAL_MASS = 8
+SIDM_DEV_DUPLICATE_ID = 16
+SIDM_DEV_STALE_GRAPH = 32
 
 EXPORTED = ("sidm_create", "sidm_destroy", "sidm_set_event_capacity", "sidm_status_string",
             "sidm_last_error", "sidm_gravity", "sidm_knn_h", "sidm_scatter", "sidm_kdk_step",
             "sidm_diagnostics", "sidm_central_density", "sidm_tidal_radius", "sidm_enable_timing",
-            "sidm_pass_times")
+            "sidm_pass_times", "sidm_last_events", "sidm_take_status")
 PASS_NAMES = ("kick_drift", "gravity", "gravity_tiles", "cell_list", "knn", "pairs", "kicks",
               "diag")
 
@@ -121,6 +124,8 @@ def lib():
         L.sidm_tidal_radius.argtypes = [vp, hp, i32, sp, vp, vp]
         L.sidm_enable_timing.argtypes = [vp, C.c_int]
         L.sidm_pass_times.argtypes = [vp, C.POINTER(C.c_double)]
+        L.sidm_last_events.argtypes = [vp, vp, i64, C.POINTER(i64), vp]
+        L.sidm_take_status.argtypes = [vp, C.POINTER(i32)]
         for name in EXPORTED:
             if name not in ("sidm_destroy", "sidm_status_string", "sidm_last_error"):
                 getattr(L, name).restype = C.c_int
@@ -257,6 +262,24 @@ def sidm_scatter(ctx, halos, state, step, events=None, want_count=False, stream=
                                    int(cap), C.byref(cnt) if want_count else None,
                                    _stream(stream)))
     return int(cnt.value) if want_count else None
+
+
+def sidm_last_events(ctx, events, want_count=False, stream=None):
+    """Copies the events of the last scattering pass on the context into
+    `events` (uint8 device tensor of cap*16 bytes).  Returns the number of
+    events if want_count (this waits for the device)."""
+    cnt = C.c_int64(0)
+    cap = events.numel() * events.element_size() // EVENT_BYTES
+    _check(ctx, lib().sidm_last_events(ctx.handle, C.c_void_p(events.data_ptr()), int(cap),
+                                       C.byref(cnt) if want_count else None, _stream(stream)))
+    return int(cnt.value) if want_count else None
+
+
+def sidm_take_status(ctx):
+    """Waits for the device; the SIDM_DEV_* bits not yet reported (cleared)."""
+    bits = C.c_int32(0)
+    _check(ctx, lib().sidm_take_status(ctx.handle, C.byref(bits)))
+    return int(bits.value)
 
 
 def sidm_kdk_step(ctx, halos, state, step, prec=SIDM_PREC_MIXED, diag=None, stream=None):

@@ -28,7 +28,11 @@ namespace sidm {
 
 // ---------------------------------------------------------------- masses, tiles
 // Smallest and largest mass per streaming block, then per halo: cmass[h] is
-// the common mass when all masses of the halo are equal (else 0).
+// the common mass when all masses of the halo are equal (else 0).  With a
+// status array, a halo that scatters (sigma_m > 0) without a common mass is
+// flagged: the probability of a pair takes the mass of one member, which is
+// only symmetric when the masses are equal (each run of the paper's Table 1
+// has one particle mass), so such a halo is not scattered.
 __global__ __launch_bounds__(kStreamBlock) void k_block_mass_range(
     const double* __restrict__ m, const StreamBlock* __restrict__ blocks, double* __restrict__ bsum)
 {
@@ -53,7 +57,8 @@ __global__ __launch_bounds__(kStreamBlock) void k_block_mass_range(
 }
 
 __global__ __launch_bounds__(kStreamBlock) void k_halo_mass(
-    const HaloDev* __restrict__ halos, const double* __restrict__ bsum, double* __restrict__ cmass)
+    const HaloDev* __restrict__ halos, const double* __restrict__ bsum, double* __restrict__ cmass,
+    int* __restrict__ status)
 {
     __shared__ double lo[kStreamBlock], hi[kStreamBlock];
     const HaloDev& H = halos[blockIdx.x];
@@ -74,7 +79,12 @@ __global__ __launch_bounds__(kStreamBlock) void k_halo_mass(
         }
         __syncthreads();
     }
-    if (t == 0) cmass[blockIdx.x] = lo[0] == hi[0] ? lo[0] : 0.0;
+    if (t == 0) {
+        const bool equal = lo[0] == hi[0];
+        cmass[blockIdx.x] = equal ? lo[0] : 0.0;
+        if (status && !equal && H.sigma_m > 0.0)
+            atomicOr(&status[blockIdx.x], SIDM_DEV_UNEQUAL_MASS);
+    }
 }
 
 // Frame of a sorted position: the compact sub-range of its bucket that holds
@@ -280,7 +290,7 @@ __global__ __launch_bounds__(kGravThreads) void k_grav_mixed(
     const int64_t pbase = tick_rows ? H.tick_part_base : H.part_base;
     const double meq = cmass[it.halo];
     if (meq > 0.0)
-        grav_mixed_body<IREG, true>(xm32, sub, sub_n, it, H, (double)(float)meq, partial, tile,
+        grav_mixed_body<IREG, true>(xm32, sub, sub_n, it, H, meq, partial, tile,
                                     pbase);
     else
         grav_mixed_body<IREG, false>(xm32, sub, sub_n, it, H, 1.0, partial, tile, pbase);
@@ -423,6 +433,7 @@ __global__ __launch_bounds__(kStreamBlock) void k_grav_finalize(
     double* __restrict__ svz, int kick, int8_t* __restrict__ bin, int tick, int bmax,
     const double4* __restrict__ partial_tick)
 {
+#pragma clang fp contract(off)
     const StreamBlock B = blocks[blockIdx.x];
     const int t = threadIdx.x;
     if (t >= B.count) return;
@@ -488,6 +499,17 @@ int64_t gravity_slots(int device)
     return (int64_t)cus * per_cu;
 }
 
+// The common mass of each halo (w.cref) and the unequal-mass flag of the
+// halos that scatter (w.status).
+hipError_t launch_mass_check(const Plan& P, Scratch& w, const double* m, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_block_mass_range, dim3((unsigned)P.n_blocks), dim3(kStreamBlock), 0, st,
+                       m, w.blocks, w.bsum);
+    hipLaunchKernelGGL(k_halo_mass, dim3(P.n_halos), dim3(kStreamBlock), 0, st, w.halos, w.bsum,
+                       w.cref, w.status);
+    return hipGetLastError();
+}
+
 // Expects the cell list of the current positions (sorted copies sx, sy, sz, sm
 // and perm) to be in place.  tick > 0: tick of a cycle of 2^bmax block steps
 // (bins in w.bin).
@@ -502,7 +524,7 @@ hipError_t launch_gravity(bool mixed, const Plan& P, Scratch& w, const sidm_stat
     hipLaunchKernelGGL(k_block_mass_range, dim3(nb), dim3(kStreamBlock), 0, st, s->m, w.blocks,
                        w.bsum);
     hipLaunchKernelGGL(k_halo_mass, dim3(P.n_halos), dim3(kStreamBlock), 0, st, w.halos, w.bsum,
-                       w.cref);
+                       w.cref, (int*)nullptr);
     if (P.has_tree) {
         // tree halos: one partial row per particle from the walk
         if (tile_begin) (void)hipEventRecord(tile_begin, st);

@@ -50,6 +50,85 @@ __global__ void k_scatter_reset(DevCounters* __restrict__ counters,
     if (t < n_halos) status[t] = 0;
 }
 
+// ---------------------------------------------------------------- contract checks
+// Keys (halo << 32 | id) of every particle of the call in the compact order:
+// once sorted, equal neighbours are an id repeated within a halo (ids key the
+// random draws and order the kicks, so they must be unique per halo).
+__global__ __launch_bounds__(kStreamBlock) void k_id_keys(
+    const StreamBlock* __restrict__ blocks, const HaloDev* __restrict__ halos,
+    const uint32_t* __restrict__ id, unsigned long long* __restrict__ keys,
+    uint32_t* __restrict__ vals)
+{
+    const StreamBlock B = blocks[blockIdx.x];
+    const int t = threadIdx.x;
+    if (t >= B.count) return;
+    const HaloDev& H = halos[B.halo];
+    const int64_t i = B.start + t;
+    const int64_t pos = H.sbase + (i - H.offset);
+    keys[pos] = ((unsigned long long)(uint32_t)B.halo << 32) | id[i];
+    vals[pos] = (uint32_t)i;
+}
+
+__global__ __launch_bounds__(256) void k_dup_ids(const unsigned long long* __restrict__ keys,
+                                                  int64_t n, int* __restrict__ status)
+{
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p + 1 >= n) return;
+    const unsigned long long a = keys[p];
+    if (a == keys[p + 1]) atomicOr(&status[(int)(a >> 32)], SIDM_DEV_DUPLICATE_ID);
+}
+
+// OR of the halos' status words into the context's sticky word, which keeps
+// them until the host has read it.
+__global__ __launch_bounds__(256) void k_publish_status(const int* __restrict__ status,
+                                                         int n_halos, int* __restrict__ sticky)
+{
+    for (int h = threadIdx.x; h < n_halos; h += 256) {
+        const int v = status[h];
+        if (v) atomicOr(sticky, v);
+    }
+}
+
+// The fingerprint (halos, state pointers, scratch generation) of the last call
+// made outside stream capture.
+__global__ void k_set_fingerprint(unsigned long long* __restrict__ fp_dev,
+                                  unsigned long long fp)
+{
+    if (threadIdx.x == 0) *fp_dev = fp;
+}
+
+// First kernel of a captured call: a replay after a call outside capture
+// changed the fingerprint is flagged in every halo and in the sticky word.
+__global__ __launch_bounds__(256) void k_guard(const unsigned long long* __restrict__ fp_dev,
+                                               unsigned long long fp, int* __restrict__ status,
+                                               int n_halos, int* __restrict__ sticky)
+{
+    if (*fp_dev == fp) return;
+    for (int h = threadIdx.x; h < n_halos; h += 256) atomicOr(&status[h], SIDM_DEV_STALE_GRAPH);
+    if (threadIdx.x == 0) atomicOr(sticky, SIDM_DEV_STALE_GRAPH);
+}
+
+// The events of the last scattering pass as sidm_event records (nothing when
+// they overflowed the context's buffer; at most cap).
+__global__ __launch_bounds__(256) void k_copy_events(const DevCounters* __restrict__ counters,
+                                                     const EventRec* __restrict__ ev,
+                                                     int64_t max_events, int64_t cap,
+                                                     sidm_event* __restrict__ out)
+{
+    const int64_t total = (int64_t)counters->n_events_total;
+    if (total > max_events) return;
+    const int64_t n = total < cap ? total : cap;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * 256) {
+        sidm_event o;
+        o.a = (uint32_t)(ev[e].key >> 32);
+        o.b = (uint32_t)ev[e].key;
+        o.halo = ev[e].halo;
+        o.round = ev[e].round;
+        out[e] = o;
+    }
+}
+
 struct PairSide {
     double x[kBucket], y[kBucket], z[kBucket];
     double vx[kBucket], vy[kBucket], vz[kBucket];
@@ -77,7 +156,8 @@ __global__ __launch_bounds__(kBucket) void k_pairs(
     const double* __restrict__ svy, const double* __restrict__ svz, const double* __restrict__ sh,
     const double* __restrict__ sm, const uint32_t* __restrict__ sid,
     const uint32_t* __restrict__ perm, uint32_t step, DevCounters* __restrict__ counters,
-    EventRec* __restrict__ events, int64_t max_events, unsigned long long* __restrict__ ev_counts)
+    EventRec* __restrict__ events, int64_t max_events, unsigned long long* __restrict__ ev_counts,
+    const int* __restrict__ status)
 {
     __shared__ PairSide I, J;
     __shared__ uint16_t queue[2 * kBucket];
@@ -87,6 +167,8 @@ __global__ __launch_bounds__(kBucket) void k_pairs(
     const BucketInfo B = buckets[b];
     const HaloDev& H = halos[B.halo];
     if (!(H.sigma_m > 0.0)) return;   // uniform over the block
+    // a halo with unequal masses or repeated ids is not scattered (flagged)
+    if (status[B.halo] & (SIDM_DEV_UNEQUAL_MASS | SIDM_DEV_DUPLICATE_ID)) return;
     const bool act = lane < B.count;
     auto load = [&](PairSide& S, int64_t p) {
         S.x[lane] = sx[p]; S.y[lane] = sy[p]; S.z[lane] = sz[p];
@@ -333,15 +415,72 @@ hipError_t launch_reset(const Plan& P, Scratch& w, hipStream_t st)
     return hipGetLastError();
 }
 
+int launch_sort_keys(Scratch& w, int64_t n, int key_bits, hipStream_t st);
+hipError_t launch_mass_check(const Plan& P, Scratch& w, const double* m, hipStream_t st);
+
+// The scattering pass's checks of its contract: a common mass in every halo
+// that scatters, and ids unique within each halo (the id check reuses the
+// cell list's sort buffers, which hold nothing the later passes read).
+hipError_t launch_contract_checks(const Plan& P, const sidm_state* s, Scratch& w, hipStream_t st)
+{
+    if (!P.any_scatter) return hipSuccess;
+    hipError_t e = launch_mass_check(P, w, s->m, st);
+    if (e != hipSuccess) return e;
+    const int64_t n = P.n_sorted;
+    hipLaunchKernelGGL(k_id_keys, dim3((unsigned)P.n_blocks), dim3(kStreamBlock), 0, st, w.blocks,
+                       w.halos, s->id, w.keys[0], w.vals[0]);
+    const int cur = launch_sort_keys(w, n, 32 + P.halo_bits, st);
+    hipLaunchKernelGGL(k_dup_ids, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                       w.keys[cur], n, w.status);
+    return hipGetLastError();
+}
+
+hipError_t launch_publish_status(const Plan& P, Scratch& w, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_publish_status, dim3(1), dim3(256), 0, st, w.status, P.n_halos, w.sticky);
+    return hipGetLastError();
+}
+
+hipError_t launch_fingerprint(const Plan& P, Scratch& w, unsigned long long fp, bool captured,
+                              hipStream_t st)
+{
+    if (captured)
+        hipLaunchKernelGGL(k_guard, dim3(1), dim3(256), 0, st, w.fp_dev, fp, w.status, P.n_halos,
+                           w.sticky);
+    else
+        hipLaunchKernelGGL(k_set_fingerprint, dim3(1), dim3(64), 0, st, w.fp_dev, fp);
+    return hipGetLastError();
+}
+
+__global__ void k_clear_word(int* __restrict__ w)
+{
+    if (threadIdx.x == 0) *w = 0;
+}
+
+hipError_t launch_clear_sticky(Scratch& w, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_clear_word, dim3(1), dim3(64), 0, st, w.sticky);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_events(Scratch& w, sidm_event* out, int64_t cap, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_copy_events, dim3(64), dim3(256), 0, st, w.counters, w.events,
+                       w.max_events, cap, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_scatter(const Plan& P, const sidm_state* s, Scratch& w, uint32_t step,
                           sidm_event* out_events, int64_t out_cap, hipStream_t st,
                           hipEvent_t after_pairs)
 {
+    hipError_t e = launch_contract_checks(P, s, w, st);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_pairs, dim3((unsigned)P.n_buckets), dim3(kBucket), 0, st, w.halos,
                        w.buckets, w.nodes, w.box, w.hmax, w.sub, w.sub_n, P.n_buckets, w.sx,
                        w.sy, w.sz, w.svx,
                        w.svy, w.svz, w.sh, w.sm, w.sid, w.perm, step, w.counters, w.events,
-                       w.max_events, (unsigned long long*)w.ev_counts);
+                       w.max_events, (unsigned long long*)w.ev_counts, w.status);
     if (after_pairs) (void)hipEventRecord(after_pairs, st);
     hipLaunchKernelGGL(k_rounds, dim3(1), dim3(kRoundThreads), 0, st, w.halos, P.n_halos,
                        w.counters, w.events, w.max_events, w.owner, s->vx, s->vy, s->vz, s->m,

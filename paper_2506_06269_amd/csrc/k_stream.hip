@@ -30,6 +30,7 @@ __global__ __launch_bounds__(kStreamBlock) void k_kick_drift(
     double* __restrict__ vx, double* __restrict__ vy, double* __restrict__ vz,
     const double* __restrict__ ax, const double* __restrict__ ay, const double* __restrict__ az)
 {
+#pragma clang fp contract(off)
     const StreamBlock B = blocks[blockIdx.x];
     const int t = threadIdx.x;
     if (t >= B.count) return;
@@ -53,6 +54,7 @@ __global__ __launch_bounds__(kStreamBlock) void k_open_kick(
     const double* __restrict__ ax, const double* __restrict__ ay, const double* __restrict__ az,
     int8_t* __restrict__ bin)
 {
+#pragma clang fp contract(off)
     const StreamBlock B = blocks[blockIdx.x];
     const int t = threadIdx.x;
     if (t >= B.count) return;
@@ -74,6 +76,7 @@ __global__ __launch_bounds__(kStreamBlock) void k_tick_drift(
     double* __restrict__ x, double* __restrict__ y, double* __restrict__ z,
     double* __restrict__ vx, double* __restrict__ vy, double* __restrict__ vz, int tick, int bmax)
 {
+#pragma clang fp contract(off)
     const StreamBlock B = blocks[blockIdx.x];
     const int t = threadIdx.x;
     if (t >= B.count) return;

@@ -463,6 +463,26 @@ static void launch_scan(uint32_t* a, int64_t len, uint32_t* part, hipStream_t st
                        part);
 }
 
+// Stable LSD radix sort of keys[0] (with vals[0]) over their low key_bits
+// bits, n keys; returns the index of the buffer pair that holds the result.
+int launch_sort_keys(Scratch& w, int64_t n, int key_bits, hipStream_t st)
+{
+    int cur = 0;
+    const int passes = (key_bits + kSortBits - 1) / kSortBits;
+    const int64_t nblk = (n + kTile - 1) / kTile;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = p * kSortBits;
+        hipLaunchKernelGGL(k_sort_count, dim3((unsigned)nblk), dim3(kSortBlock), 0, st,
+                           w.keys[cur], n, shift, w.hist, nblk);
+        launch_scan(w.hist, nblk * (1 << kSortBits), w.scan_part, st);
+        hipLaunchKernelGGL(k_sort_scatter, dim3((unsigned)nblk), dim3(kSortBlock), 0, st,
+                           w.keys[cur], w.vals[cur], w.keys[cur ^ 1], w.vals[cur ^ 1], n, shift,
+                           w.hist, nblk);
+        cur ^= 1;
+    }
+    return cur;
+}
+
 hipError_t launch_cell_list(const Plan& P, const sidm_state* s, Scratch& w, hipStream_t st,
                             int tick, int bmax)
 {
@@ -474,19 +494,7 @@ hipError_t launch_cell_list(const Plan& P, const sidm_state* s, Scratch& w, hipS
     hipLaunchKernelGGL(k_morton_keys, dim3((unsigned)P.n_blocks), dim3(kStreamBlock), 0, st, s->x,
                        s->y, s->z, w.blocks, w.halos, w.bbox, w.keys[0], w.vals[0], w.bin,
                        tick, bmax, P.rank_shift);
-    int cur = 0;
-    const int passes = (P.key_bits + kSortBits - 1) / kSortBits;
-    const int64_t nblk = P.sort_blocks;
-    for (int p = 0; p < passes; ++p) {
-        const int shift = p * kSortBits;
-        hipLaunchKernelGGL(k_sort_count, dim3((unsigned)nblk), dim3(kSortBlock), 0, st,
-                           w.keys[cur], n, shift, w.hist, nblk);
-        launch_scan(w.hist, nblk * (1 << kSortBits), w.scan_part, st);
-        hipLaunchKernelGGL(k_sort_scatter, dim3((unsigned)nblk), dim3(kSortBlock), 0, st,
-                           w.keys[cur], w.vals[cur], w.keys[cur ^ 1], w.vals[cur ^ 1], n, shift,
-                           w.hist, nblk);
-        cur ^= 1;
-    }
+    const int cur = launch_sort_keys(w, n, P.key_bits, st);
     hipLaunchKernelGGL(k_permute, dim3(grid_of(n, kStreamBlock)), dim3(kStreamBlock), 0, st, n,
                        w.vals[cur], s->x, s->y, s->z, s->vx, s->vy, s->vz, s->m, s->id, s->h,
                        w.sx, w.sy, w.sz, w.sp4, w.svx, w.svy, w.svz, w.sm, w.sid, w.sh, w.perm);

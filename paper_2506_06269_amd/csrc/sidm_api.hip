@@ -55,6 +55,11 @@ hipError_t launch_tree_terms_reset(Scratch& w, int n_halos, hipStream_t st);
 hipError_t launch_scatter(const Plan& plan, const sidm_state* s, Scratch& w, uint32_t step,
                           sidm_event* out_events, int64_t out_cap, hipStream_t st,
                           hipEvent_t after_pairs);
+hipError_t launch_publish_status(const Plan& P, Scratch& w, hipStream_t st);
+hipError_t launch_fingerprint(const Plan& P, Scratch& w, unsigned long long fp, bool captured,
+                              hipStream_t st);
+hipError_t launch_copy_events(Scratch& w, sidm_event* out, int64_t cap, hipStream_t st);
+hipError_t launch_clear_sticky(Scratch& w, hipStream_t st);
 }  // namespace sidm
 
 using namespace sidm;
@@ -72,6 +77,16 @@ struct sidm_ctx {
     bool timing = false;
     bool timed = false;               // the last step recorded its events
     hipEvent_t ev[SIDM_N_PASSES + 2] = {};
+    // device status not yet reported: the sticky word is copied to pinned host
+    // memory at the end of each call outside capture and read by a later call
+    int* sticky_host = nullptr;
+    hipEvent_t sticky_ev = nullptr;
+    bool sticky_pending = false;
+    // fingerprint of the halos, the state pointers and the scratch memory of
+    // the last call outside capture; scratch_gen changes when scratch moves
+    uint64_t scratch_gen = 1;
+    uint64_t fp_eager = 0;
+    bool fp_valid = false;
 };
 
 namespace {
@@ -241,14 +256,114 @@ sidm_status ensure_plan(sidm_ctx* c, const sidm_halo* halos, int32_t n_halos, hi
         return SIDM_ERR_INVALID;
     }
     std::string why;
+    const GravItem* items_tick = c->w.items_tick;
+    const double4* partial_tick = c->w.partial_tick;
     if (!build_plan(c->plan, c->w, halos, n_halos, why) || !ensure_tick_tables(c->w, c->plan, why)) {
         set_err(c, "%s", why.c_str());
         return SIDM_ERR_CAPACITY;
     }
+    if (items_tick != c->w.items_tick || partial_tick != c->w.partial_tick) ++c->scratch_gen;
     hipError_t e = upload_plan(c->plan, c->w);
     if (e != hipSuccess) return hip_fail(c, e, "uploading the launch plan");
     c->plan_key.assign(halos, halos + n_halos);
     c->plan_valid = true;
+    return SIDM_OK;
+}
+
+bool capturing(hipStream_t st)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+}
+
+// Status code and text for device status bits.
+sidm_status report_bits(sidm_ctx* c, int bits, const char* when)
+{
+    std::string what;
+    if (bits & SIDM_DEV_EVENT_OVERFLOW) what += " event buffer overflow (no kicks applied);";
+    if (bits & SIDM_DEV_KNN_OVERFLOW) what += " kNN refinement overflow (h is NaN there);";
+    if (bits & SIDM_DEV_UNEQUAL_MASS) what += " sigma_m > 0 with unequal masses (not scattered);";
+    if (bits & SIDM_DEV_DUPLICATE_ID) what += " repeated ids within a halo (not scattered);";
+    if (bits & SIDM_DEV_STALE_GRAPH)
+        what += " a captured call was replayed after the halos, state or scratch changed;";
+    set_err(c, "%s:%s", when, what.c_str());
+    if (bits & (SIDM_DEV_EVENT_OVERFLOW | SIDM_DEV_KNN_OVERFLOW)) return SIDM_ERR_CAPACITY;
+    if (bits & (SIDM_DEV_DUPLICATE_ID | SIDM_DEV_STALE_GRAPH)) return SIDM_ERR_INVALID;
+    if (bits & SIDM_DEV_UNEQUAL_MASS) return SIDM_ERR_UNSUPPORTED;
+    return SIDM_OK;
+}
+
+// Conditions a previous call's kernels found, once its copy of the sticky
+// word has arrived (no waiting); they are reported once, and clear.
+sidm_status take_sticky(sidm_ctx* c, hipStream_t st)
+{
+    if (!c->sticky_pending || hipEventQuery(c->sticky_ev) != hipSuccess) return SIDM_OK;
+    c->sticky_pending = false;
+    const int bits = *(volatile int*)c->sticky_host;
+    if (!bits) return SIDM_OK;
+    *(volatile int*)c->sticky_host = 0;
+    (void)launch_clear_sticky(c->w, st);
+    const sidm_status r =
+        report_bits(c, bits, "an earlier call on this context found (this call was not run)");
+    return r == SIDM_OK ? SIDM_ERR_INVALID : r;
+}
+
+// After a call's kernels: the status words (when the call reset and set them)
+// into the sticky word and, outside capture, its copy to the host.
+void publish(sidm_ctx* c, hipStream_t st, bool captured, bool with_status = true)
+{
+    if (with_status) (void)launch_publish_status(c->plan, c->w, st);
+    if (captured) return;
+    if (hipMemcpyAsync(c->sticky_host, c->w.sticky, sizeof(int), hipMemcpyDeviceToHost, st) ==
+            hipSuccess &&
+        hipEventRecord(c->sticky_ev, st) == hipSuccess)
+        c->sticky_pending = true;
+}
+
+uint64_t fingerprint(const sidm_ctx* c, const sidm_halo* halos, int32_t n_halos,
+                     const sidm_state* s)
+{
+    uint64_t h = 1469598103934665603ull;   // FNV-1a, 64 bit
+    auto mix = [&](const void* p, size_t n) {
+        const unsigned char* b = (const unsigned char*)p;
+        for (size_t i = 0; i < n; ++i) {
+            h ^= b[i];
+            h *= 1099511628211ull;
+        }
+    };
+    mix(halos, sizeof(sidm_halo) * (size_t)n_halos);
+    mix(s, sizeof(sidm_state));
+    mix(&c->scratch_gen, sizeof c->scratch_gen);
+    return h;
+}
+
+// Common start of the calls that enqueue kernels (after validation): reports
+// conditions found by earlier calls, builds the launch plan, and records the
+// fingerprint (outside capture) or enqueues its check (inside capture: the
+// last call outside capture must have used the same halos and state).
+sidm_status enter(sidm_ctx* c, const sidm_halo* halos, int32_t n_halos, const sidm_state* s,
+                  hipStream_t st, bool& captured)
+{
+    captured = capturing(st);
+    sidm_status r;
+    if (!captured && (r = take_sticky(c, st)) != SIDM_OK) return r;
+    if ((r = ensure_plan(c, halos, n_halos, st)) != SIDM_OK) return r;
+    const uint64_t fp = fingerprint(c, halos, n_halos, s);
+    if (captured) {
+        if (!c->fp_valid || fp != c->fp_eager) {
+            set_err(c, "the halos or the state pointers differ from the last call outside "
+                       "capture; call once outside capture with them before capturing");
+            return SIDM_ERR_INVALID;
+        }
+    } else if (c->fp_valid && fp == c->fp_eager) {
+        return SIDM_OK;
+    }
+    const hipError_t e = launch_fingerprint(c->plan, c->w, fp, captured, st);
+    if (e != hipSuccess) return hip_fail(c, e, "fingerprint launch");
+    if (!captured) {
+        c->fp_eager = fp;
+        c->fp_valid = true;
+    }
     return SIDM_OK;
 }
 
@@ -300,6 +415,14 @@ sidm_status sidm_create(sidm_ctx** out, int device, int64_t max_particles, int32
         return SIDM_ERR_NOMEM;
     }
     c->w.grav_slots = gravity_slots(device);
+    if (hipHostMalloc((void**)&c->sticky_host, sizeof(int), hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&c->sticky_ev, hipEventDisableTiming) != hipSuccess) {
+        if (c->sticky_host) (void)hipHostFree(c->sticky_host);
+        free_scratch(c->w);
+        delete c;
+        return SIDM_ERR_NOMEM;
+    }
+    *c->sticky_host = 0;
     *out = c;
     return SIDM_OK;
 }
@@ -309,6 +432,8 @@ sidm_status sidm_set_event_capacity(sidm_ctx* c, int64_t max_events)
     if (!c || max_events < 1) return SIDM_ERR_INVALID;
     DeviceGuard g(c->device);
     std::string why;
+    (void)hipDeviceSynchronize();   // the old buffer may still be in use
+    ++c->scratch_gen;                // graphs captured before hold the old buffer
     if (!realloc_events(c->w, max_events, why)) {
         set_err(c, "%s", why.c_str());
         return SIDM_ERR_NOMEM;
@@ -325,6 +450,8 @@ void sidm_destroy(sidm_ctx* c)
         free_scratch(c->w);
         for (auto& ev : c->ev)
             if (ev) (void)hipEventDestroy(ev);
+        if (c->sticky_ev) (void)hipEventDestroy(c->sticky_ev);
+        if (c->sticky_host) (void)hipHostFree(c->sticky_host);
     }
     delete c;
 }
@@ -340,12 +467,14 @@ sidm_status sidm_gravity(sidm_ctx* c, const sidm_halo* halos, int32_t n_halos,
     }
     DeviceGuard g(c->device);
     hipStream_t st = (hipStream_t)stream;
-    if ((r = ensure_plan(c, halos, n_halos, st)) != SIDM_OK) return r;
+    bool cap = false;
+    if ((r = enter(c, halos, n_halos, s, st, cap)) != SIDM_OK) return r;
     hipError_t e = launch_tree_terms_reset(c->w, n_halos, st);
     if (e == hipSuccess) e = launch_cell_list(c->plan, s, c->w, st);
     if (e == hipSuccess)
         e = launch_gravity(prec == SIDM_PREC_MIXED, c->plan, c->w, s, 0, st, nullptr, nullptr);
     if (e != hipSuccess) return hip_fail(c, e, "gravity launch");
+    publish(c, st, cap, false);
     c->err.clear();
     return SIDM_OK;
 }
@@ -357,11 +486,13 @@ sidm_status sidm_knn_h(sidm_ctx* c, const sidm_halo* halos, int32_t n_halos, con
     if (r != SIDM_OK) return r;
     DeviceGuard g(c->device);
     hipStream_t st = (hipStream_t)stream;
-    if ((r = ensure_plan(c, halos, n_halos, st)) != SIDM_OK) return r;
+    bool cap = false;
+    if ((r = enter(c, halos, n_halos, s, st, cap)) != SIDM_OK) return r;
     hipError_t e = launch_reset(c->plan, c->w, st);
     if (e == hipSuccess) e = launch_cell_list(c->plan, s, c->w, st);
     if (e == hipSuccess) e = launch_knn(c->plan, s, c->w, nbr, max_k(halos, n_halos), st);
     if (e != hipSuccess) return hip_fail(c, e, "kNN launch");
+    publish(c, st, cap);
     c->err.clear();
     return SIDM_OK;
 }
@@ -378,13 +509,63 @@ sidm_status sidm_scatter(sidm_ctx* c, const sidm_halo* halos, int32_t n_halos,
     }
     DeviceGuard g(c->device);
     hipStream_t st = (hipStream_t)stream;
-    if ((r = ensure_plan(c, halos, n_halos, st)) != SIDM_OK) return r;
+    bool captured = false;
+    if ((r = enter(c, halos, n_halos, s, st, captured)) != SIDM_OK) return r;
+    if (n_events_host && captured) {
+        set_err(c, "n_events_host waits for the device: not possible during stream capture");
+        return SIDM_ERR_INVALID;
+    }
     hipError_t e = launch_reset(c->plan, c->w, st);
     if (e == hipSuccess) e = launch_cell_list(c->plan, s, c->w, st);
     if (e == hipSuccess) e = launch_tree_hmax(c->plan, c->w, st);
     if (e == hipSuccess)
         e = launch_scatter(c->plan, s, c->w, step, events, events ? cap : 0, st, nullptr);
     if (e != hipSuccess) return hip_fail(c, e, "scatter launch");
+    if (!n_events_host) {
+        publish(c, st, captured);
+        c->err.clear();
+        return SIDM_OK;
+    }
+    // synchronous: the count and the conditions of this pass are reported here
+    unsigned long long cnt = 0;
+    std::vector<int> status((size_t)n_halos, 0);
+    e = hipMemcpyAsync(&cnt, &c->w.counters->n_events_total, sizeof cnt, hipMemcpyDeviceToHost,
+                       st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(status.data(), c->w.status, sizeof(int) * (size_t)n_halos,
+                           hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(c, e, "reading the event count");
+    *n_events_host = (int64_t)cnt;
+    int bits = 0;
+    for (int v : status) bits |= v;
+    if ((int64_t)cnt > c->w.max_events || (events && (int64_t)cnt > cap)) {
+        set_err(c, "%llu events exceed the capacity (context %lld, caller %lld)", cnt,
+                (long long)c->w.max_events, (long long)(events ? cap : -1));
+        return SIDM_ERR_CAPACITY;
+    }
+    if (bits) return report_bits(c, bits, "the scattering pass found");
+    c->err.clear();
+    return SIDM_OK;
+}
+
+sidm_status sidm_last_events(sidm_ctx* c, sidm_event* out, int64_t cap, int64_t* n_events_host,
+                             void* stream)
+{
+    if (!c) return SIDM_ERR_INVALID;
+    if ((cap > 0 && !out) || cap < 0) {
+        set_err(c, "need a device buffer for cap >= 0 events");
+        return SIDM_ERR_INVALID;
+    }
+    DeviceGuard g(c->device);
+    hipStream_t st = (hipStream_t)stream;
+    if (n_events_host && capturing(st)) {
+        set_err(c, "n_events_host waits for the device: not possible during stream capture");
+        return SIDM_ERR_INVALID;
+    }
+    hipError_t e = hipSuccess;
+    if (cap > 0) e = launch_copy_events(c->w, out, cap, st);
+    if (e != hipSuccess) return hip_fail(c, e, "event copy launch");
     if (n_events_host) {
         unsigned long long cnt = 0;
         e = hipMemcpyAsync(&cnt, &c->w.counters->n_events_total, sizeof cnt,
@@ -392,9 +573,9 @@ sidm_status sidm_scatter(sidm_ctx* c, const sidm_halo* halos, int32_t n_halos,
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) return hip_fail(c, e, "reading the event count");
         *n_events_host = (int64_t)cnt;
-        if ((int64_t)cnt > c->w.max_events || (events && (int64_t)cnt > cap)) {
+        if ((int64_t)cnt > c->w.max_events || (int64_t)cnt > cap) {
             set_err(c, "%llu events exceed the capacity (context %lld, caller %lld)", cnt,
-                    (long long)c->w.max_events, (long long)(events ? cap : -1));
+                    (long long)c->w.max_events, (long long)cap);
             return SIDM_ERR_CAPACITY;
         }
     }
@@ -414,13 +595,14 @@ sidm_status sidm_kdk_step(sidm_ctx* c, const sidm_halo* halos, int32_t n_halos,
     }
     DeviceGuard g(c->device);
     hipStream_t st = (hipStream_t)stream;
-    if ((r = ensure_plan(c, halos, n_halos, st)) != SIDM_OK) return r;
+    bool captured = false;
+    if ((r = enter(c, halos, n_halos, s, st, captured)) != SIDM_OK) return r;
     const Plan& P = c->plan;
     // events: 0 start, 1 after kick+drift, 5 after the cell list, 2/3 around
     // the gravity tiles, 4 after gravity, 6 after kNN, 7 after the pair search,
     // 8 after the kicks, 9 after the diagnostics
     hipEvent_t* E = c->ev;
-    const bool tm = c->timing;
+    const bool tm = c->timing && !captured;
     auto mark = [&](int i) {
         if (tm) (void)hipEventRecord(E[i], st);
     };
@@ -471,6 +653,7 @@ sidm_status sidm_kdk_step(sidm_ctx* c, const sidm_halo* halos, int32_t n_halos,
     mark(9);
     c->timed = tm;
     if (e != hipSuccess) return hip_fail(c, e, "step launch");
+    publish(c, st, captured);
     c->err.clear();
     return SIDM_OK;
 }
@@ -486,7 +669,8 @@ sidm_status sidm_diagnostics(sidm_ctx* c, const sidm_halo* halos, int32_t n_halo
     }
     DeviceGuard g(c->device);
     hipStream_t st = (hipStream_t)stream;
-    if ((r = ensure_plan(c, halos, n_halos, st)) != SIDM_OK) return r;
+    bool cap = false;
+    if ((r = enter(c, halos, n_halos, s, st, cap)) != SIDM_OK) return r;
     const Plan& P = c->plan;
     hipError_t e = launch_diag(c->w.blocks, P.n_blocks, c->w.halos, n_halos, s->x, s->y, s->z,
                                s->vx, s->vy, s->vz, s->m, s->pot, c->w.bsum, c->w.ev_counts,
@@ -514,7 +698,8 @@ sidm_status sidm_central_density(sidm_ctx* c, const sidm_halo* halos, int32_t n_
         }
     DeviceGuard g(c->device);
     hipStream_t st = (hipStream_t)stream;
-    if ((r = ensure_plan(c, halos, n_halos, st)) != SIDM_OK) return r;
+    bool cap = false;
+    if ((r = enter(c, halos, n_halos, s, st, cap)) != SIDM_OK) return r;
     const Plan& P = c->plan;
     c->radius.assign(radius, radius + n_halos);
     hipError_t e = hipMemcpyAsync(c->w.radius, c->radius.data(), sizeof(double) * (size_t)n_halos,
@@ -543,12 +728,28 @@ sidm_status sidm_tidal_radius(sidm_ctx* c, const sidm_halo* halos, int32_t n_hal
         }
     DeviceGuard g(c->device);
     hipStream_t st = (hipStream_t)stream;
-    if ((r = ensure_plan(c, halos, n_halos, st)) != SIDM_OK) return r;
+    bool cap = false;
+    if ((r = enter(c, halos, n_halos, s, st, cap)) != SIDM_OK) return r;
     const Plan& P = c->plan;
     hipError_t e = launch_tidal(c->w.blocks, P.n_blocks, c->w.halos, n_halos, s->x, s->y, s->z,
                                 s->m, s->pot, c->w.bsum, c->w.center, c->w.tidal, out, st);
     if (e != hipSuccess) return hip_fail(c, e, "tidal radius launch");
     c->err.clear();
+    return SIDM_OK;
+}
+
+sidm_status sidm_take_status(sidm_ctx* c, int32_t* bits)
+{
+    if (!c || !bits) return SIDM_ERR_INVALID;
+    DeviceGuard g(c->device);
+    int v = 0;
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(&v, c->w.sticky, sizeof v, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && v) e = hipMemset(c->w.sticky, 0, sizeof v);
+    if (e != hipSuccess) return hip_fail(c, e, "reading the status");
+    c->sticky_pending = false;
+    *(volatile int*)c->sticky_host = 0;
+    *bits = v;
     return SIDM_OK;
 }
 

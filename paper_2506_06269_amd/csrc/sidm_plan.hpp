@@ -104,6 +104,8 @@ struct Scratch {
     DevCounters* counters = nullptr;
     long long* ev_counts = nullptr;   // 4 per halo: events, rounds, pairs, P>1
     int* status = nullptr;            // per halo
+    int* sticky = nullptr;            // OR of the status words not yet read by the host
+    unsigned long long* fp_dev = nullptr;   // fingerprint of the last call outside capture
 };
 
 struct Plan {
@@ -114,6 +116,8 @@ struct Plan {
     int key_bits = 48;
     int rank_shift = 48;              // 49 when block steps order active particles first
     bool has_tree = false;            // some halo uses the tree walk
+    bool any_scatter = false;         // some halo has sigma_m > 0
+    int halo_bits = 0;                // bits of a halo index
     int64_t sort_blocks = 0;
     std::vector<HaloDev> halos;
     std::vector<StreamBlock> blocks;
@@ -179,7 +183,7 @@ inline bool alloc_scratch(Scratch& w, int64_t N, int32_t H, int64_t max_events, 
               dalloc(w.box, 6 * w.nodes_cap) && dalloc(w.hmax, w.nodes_cap) &&
               dalloc(w.sub, kSubMax * w.buckets_cap) && dalloc(w.sub_n, w.buckets_cap) &&
               dalloc(w.owner, N) && dalloc(w.counters, 1) && dalloc(w.ev_counts, 4 * H) &&
-              dalloc(w.status, H);
+              dalloc(w.status, H) && dalloc(w.sticky, 1) && dalloc(w.fp_dev, 1);
     if (!ok) {
         why = "device allocation failed";
         return false;
@@ -191,6 +195,8 @@ inline bool alloc_scratch(Scratch& w, int64_t N, int32_t H, int64_t max_events, 
     if (hipMemset(w.counters, 0, sizeof(DevCounters)) != hipSuccess ||
         hipMemset(w.ev_counts, 0, sizeof(*w.ev_counts) * (size_t)(4 * H)) != hipSuccess ||
         hipMemset(w.status, 0, sizeof(*w.status) * (size_t)H) != hipSuccess ||
+        hipMemset(w.sticky, 0, sizeof(*w.sticky)) != hipSuccess ||
+        hipMemset(w.fp_dev, 0, sizeof(*w.fp_dev)) != hipSuccess ||
         hipMemset(w.tree_terms, 0, sizeof(*w.tree_terms) * (size_t)H) != hipSuccess) {
         why = "cannot initialise scratch";
         return false;
@@ -219,6 +225,7 @@ inline void free_scratch(Scratch& w)
     dfree(w.sh); dfree(w.sm); dfree(w.bin); dfree(w.mom); dfree(w.tree_terms); dfree(w.sid); dfree(w.perm); dfree(w.box); dfree(w.hmax);
     dfree(w.sub); dfree(w.sub_n);
     dfree(w.owner); dfree(w.events); dfree(w.counters); dfree(w.ev_counts); dfree(w.status);
+    dfree(w.sticky); dfree(w.fp_dev);
 }
 
 // Number of j-splits for the gravity sum of each halo.  Work items (one
@@ -336,6 +343,7 @@ inline bool build_plan(Plan& P, const Scratch& w, const sidm_halo* halos, int32_
         H.max_bin = S.eta > 0.0 ? S.max_bin : 0;
         H.tree_alpha = S.tree_alpha;
         if (S.tree_alpha > 0.0) P.has_tree = true;
+        if (S.sigma_m > 0.0) P.any_scatter = true;
         H.sbase = sbase[h];
         H.rank = P.rank_of[h];
         // streaming blocks
@@ -453,6 +461,7 @@ inline bool build_plan(Plan& P, const Scratch& w, const sidm_halo* halos, int32_
     for (const auto& H : P.halos)
         if (H.max_bin > 0 && !(H.tree_alpha > 0.0)) P.rank_shift = 49;
     P.key_bits = P.rank_shift + hb;
+    P.halo_bits = hb;
     P.sort_blocks = (P.n_sorted + kSortBlock * kSortItems - 1) / (kSortBlock * kSortItems);
     if (prow > w.partial_rows || P.n_items > w.items_cap || P.n_blocks > w.blocks_cap ||
         P.n_buckets > w.buckets_cap || P.n_nodes > w.nodes_cap ||

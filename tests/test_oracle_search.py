@@ -1,8 +1,9 @@
 """Pins of the oracle's exact accelerated searches and of its central density.
 
-The grid kNN and the x-sorted pair sweep must return exactly what the
-brute-force definitions return (h bit for bit; the same events, pair count and
-P > 1 count) on inputs with ties, duplicates, flat and clustered geometry.
+The grid kNN, the k-d tree kNN, the x-sorted pair sweep and the k-d tree pair
+search must return exactly what the brute-force definitions return (h and
+neighbour lists bit for bit; the same events, pair count and P > 1 count) on
+inputs with ties, duplicates, flat and clustered geometry.
 The central density is checked on configurations whose answer is known by
 construction (Sec. 3: the centre is the potential minimum)."""
 import math
@@ -45,6 +46,46 @@ def test_knn_grid_equals_brute_force(orc, name, make, ks):
 
 
 @pytest.mark.parametrize("name,make,ks", CASES, ids=[c[0] for c in CASES])
+def test_knn_tree_equals_brute_force(orc, name, make, ks):
+    s = make()
+    for k in ks:
+        hb, lb = orc.knn(s["x"], s["y"], s["z"], s["id"], k, want_list=True)
+        ht, lt = orc.knn_tree(s["x"], s["y"], s["z"], s["id"], k, want_list=True)
+        assert np.array_equal(hb, ht), (name, k)
+        assert np.array_equal(lb, lt), (name, k)
+
+
+@pytest.mark.parametrize("name,make,ks", CASES, ids=[c[0] for c in CASES])
+def test_event_tree_equals_brute_force(orc, name, make, ks):
+    """Also with a velocity-dependent cross-section, and at sigma/m large
+    enough for pairs with P > 1 (where the bound that spares the overlap
+    integral exceeds 1 and never applies)."""
+    s = make()
+    k = max(ks)
+    h = orc.knn(s["x"], s["y"], s["z"], s["id"], k)
+    for sigma, w, seed, step in ((1.0, 0.0, 0, 0), (300.0, 0.0, 3, 7), (5e4, 0.0, 9, 2),
+                                 (2e3, 0.3, 4, 5)):
+        ref = orc.find_events(s["x"], s["y"], s["z"], s["vx"], s["vy"], s["vz"], s["m"],
+                              s["id"], h, sigma, 1e-3, seed, step, sigma_w=w)
+        got = orc.find_events_tree(s["x"], s["y"], s["z"], s["vx"], s["vy"], s["vz"], s["m"],
+                                   s["id"], h, sigma, 1e-3, seed, step, sigma_w=w)
+        assert got[1] == ref[1] and got[2] == ref[2], (name, sigma)
+        assert bytes(got[0]) == bytes(ref[0]), (name, sigma)
+
+
+def test_event_tree_counts_p_above_one(orc):
+    """A case where pairs with P > 1 exist, so the P > 1 count is pinned."""
+    s = W.clustered(1500, seed=8)
+    h = orc.knn(s["x"], s["y"], s["z"], s["id"], 16)
+    ref = orc.find_events(s["x"], s["y"], s["z"], s["vx"], s["vy"], s["vz"], s["m"], s["id"], h,
+                          3e6, 1e-2, 2, 3)
+    got = orc.find_events_tree(s["x"], s["y"], s["z"], s["vx"], s["vy"], s["vz"], s["m"],
+                               s["id"], h, 3e6, 1e-2, 2, 3)
+    assert ref[2] > 0
+    assert got[1:] == ref[1:] and bytes(got[0]) == bytes(ref[0])
+
+
+@pytest.mark.parametrize("name,make,ks", CASES, ids=[c[0] for c in CASES])
 def test_event_sweep_equals_brute_force(orc, name, make, ks):
     s = make()
     k = max(ks)
@@ -70,6 +111,9 @@ def test_event_sweep_equal_kernel_sizes(orc):
     d1, d2, d3, d4 = 3 * 8 * 8 * 7, 6 * 8 * 7 * 7, 4 * 7 * 7 * 7, 3 * 8 * 8 * 6
     assert got[1] == ref[1] == d1 + d2 + d3 + d4
     assert bytes(got[0]) == bytes(ref[0])
+    got = orc.find_events_tree(s["x"], s["y"], s["z"], s["vx"], s["vy"], s["vz"], s["m"],
+                               s["id"], h, 2e3, 1e-3, 1, 1)
+    assert got[1] == ref[1] and bytes(got[0]) == bytes(ref[0])
 
 
 def test_central_density_lattice(orc):
