@@ -62,6 +62,9 @@ def _declare(L):
     L.orc_tree_gravity.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp, C.c_double,
                                    C.c_double, C.c_double, C.c_int64, _i64p, _dp, _dp, _dp, _dp,
                                    _i64p]
+    L.orc_octree_gravity.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp,
+                                     C.c_double, C.c_double, C.c_double, C.c_int64, _i64p, _dp,
+                                     _dp, _dp, _dp, _i64p]
     L.orc_host_nfw.argtypes = [C.c_int64, _dp, _dp, _dp, C.c_double, C.c_double,
                                C.c_double, _dp, _dp, _dp, _dp, _dp]
     L.orc_knn.argtypes = [C.c_int64, _dp, _dp, _dp, _u32p, C.c_int32, C.c_int64,
@@ -105,6 +108,9 @@ def _declare(L):
                                _dp, _dp, _dp, _dp, _dp, C.POINTER(OrcParams),
                                C.c_uint32, C.c_void_p, C.c_int64]
     L.orc_kdk_step.restype = C.c_int64
+    L.orc_kick_drift.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp,
+                                 C.POINTER(OrcParams)]
+    L.orc_close_kick.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, C.POINTER(OrcParams)]
     L.orc_num_threads.restype = C.c_int
     L.orc_set_threads.argtypes = [C.c_int]
     L.orc_set_threads.restype = None
@@ -191,6 +197,26 @@ def tree_gravity(x, y, z, m, a_old, G, eps, alpha, query=None):
     lib().orc_tree_gravity(n, _d(x), _d(y), _d(z), _d(m), _d(ox), _d(oy), _d(oz), float(G),
                            float(eps), float(alpha), nq, qp, _d(ax), _d(ay), _d(az), _d(pot),
                            C.byref(terms))
+    return ax, ay, az, pot, int(terms.value)
+
+
+def octree_gravity(x, y, z, m, a_old, G, eps, alpha, query=None):
+    """The paper's tree: a geometric oct-tree walked per particle with the
+    relative opening criterion.  Returns ax, ay, az, pot (per query) and the
+    number of source terms summed."""
+    x, y, z, m = _f64(x), _f64(y), _f64(z), _f64(m)
+    ox, oy, oz = (_f64(v) for v in a_old)
+    n = x.size
+    if query is None:
+        nq, qp = n, None
+    else:
+        query = np.ascontiguousarray(query, dtype=np.int64)
+        nq, qp = query.size, query.ctypes.data_as(_i64p)
+    ax, ay, az, pot = (np.zeros(nq) for _ in range(4))
+    terms = C.c_int64(0)
+    lib().orc_octree_gravity(n, _d(x), _d(y), _d(z), _d(m), _d(ox), _d(oy), _d(oz), float(G),
+                             float(eps), float(alpha), nq, qp, _d(ax), _d(ay), _d(az), _d(pot),
+                             C.byref(terms))
     return ax, ay, az, pot, int(terms.value)
 
 
@@ -422,6 +448,22 @@ def total_accel(s, p):
         ax, ay, az, pot = ax + hx, ay + hy, az + hz, pot + hp
     s["ax"], s["ay"], s["az"], s["pot"] = ax, ay, az, pot
     return s
+
+
+def kick_drift(s, p):
+    """K(dt/2) D(dt) of a fixed step on the dict-of-arrays state s (in place)."""
+    for key in ("x", "y", "z", "vx", "vy", "vz", "ax", "ay", "az"):
+        s[key] = np.array(s[key], dtype=np.float64)
+    lib().orc_kick_drift(s["x"].size, *[_d(s[k]) for k in ("x", "y", "z", "vx", "vy", "vz",
+                                                           "ax", "ay", "az")], C.byref(p))
+
+
+def close_kick(s, p):
+    """The closing K(dt/2) with the state's a (in place)."""
+    for key in ("vx", "vy", "vz", "ax", "ay", "az"):
+        s[key] = np.array(s[key], dtype=np.float64)
+    lib().orc_close_kick(s["x"].size, *[_d(s[k]) for k in ("vx", "vy", "vz", "ax", "ay", "az")],
+                         C.byref(p))
 
 
 def kdk_step(s, p, step, ev_cap=1 << 20):

@@ -1101,6 +1101,178 @@ int64_t orc_find_events_sweep(int64_t n, const double *x, const double *y, const
 }
 
 /* ------------------------------------------------------------------------ */
+/* The paper's tree (Sec. 2): a one-sided oct-tree with the relative opening
+ * criterion, walked per particle (see the header). */
+
+typedef struct {
+    double c[3], half;      /* cube centre and half side                        */
+    double M, cm[3];        /* mass and centre of mass                          */
+    int64_t begin, end;     /* the cell's particles: idx[begin .. end)          */
+    int64_t child[8];       /* -1: no particle in that octant                    */
+    int leaf;
+} oct_cell;
+
+typedef struct {
+    const double *x, *y, *z, *m;
+    int64_t *idx;
+    oct_cell *cell;
+    int64_t n_cell, cap;
+} oct_tree;
+
+enum { OCT_MAX_DEPTH = 60 };
+
+static int64_t oct_build(oct_tree *T, int64_t begin, int64_t end, const double c[3], double half,
+                         int depth)
+{
+    if (T->n_cell == T->cap) {
+        T->cap = T->cap ? 2 * T->cap : 1024;
+        T->cell = (oct_cell *)realloc(T->cell, sizeof(oct_cell) * (size_t)T->cap);
+    }
+    const int64_t id = T->n_cell++;
+    oct_cell C;
+    for (int a = 0; a < 3; ++a) C.c[a] = c[a];
+    C.half = half;
+    C.begin = begin;
+    C.end = end;
+    C.M = 0.0;
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+    for (int64_t q = begin; q < end; ++q) {
+        const int64_t i = T->idx[q];
+        C.M += T->m[i];
+        sx += T->m[i] * T->x[i];
+        sy += T->m[i] * T->y[i];
+        sz += T->m[i] * T->z[i];
+    }
+    C.cm[0] = sx / C.M;
+    C.cm[1] = sy / C.M;
+    C.cm[2] = sz / C.M;
+    for (int o = 0; o < 8; ++o) C.child[o] = -1;
+    C.leaf = (end - begin <= 1 || depth >= OCT_MAX_DEPTH);
+    if (!C.leaf) {
+        /* counting sort of the particles into the octants, in index order */
+        int64_t cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        int *oct = (int *)malloc(sizeof(int) * (size_t)(end - begin));
+        for (int64_t q = begin; q < end; ++q) {
+            const int64_t i = T->idx[q];
+            const int o = (T->x[i] >= c[0] ? 1 : 0) | (T->y[i] >= c[1] ? 2 : 0) |
+                          (T->z[i] >= c[2] ? 4 : 0);
+            oct[q - begin] = o;
+            ++cnt[o];
+        }
+        int64_t start[8], fill[8], acc = begin;
+        for (int o = 0; o < 8; ++o) {
+            start[o] = fill[o] = acc;
+            acc += cnt[o];
+        }
+        int64_t *tmp = (int64_t *)malloc(sizeof(int64_t) * (size_t)(end - begin));
+        for (int64_t q = begin; q < end; ++q) tmp[fill[oct[q - begin]]++ - begin] = T->idx[q];
+        memcpy(T->idx + begin, tmp, sizeof(int64_t) * (size_t)(end - begin));
+        free(tmp);
+        free(oct);
+        for (int o = 0; o < 8; ++o) {
+            if (cnt[o] == 0) continue;
+            const double h2 = 0.5 * half;
+            const double cc[3] = {c[0] + ((o & 1) ? h2 : -h2), c[1] + ((o & 2) ? h2 : -h2),
+                                  c[2] + ((o & 4) ? h2 : -h2)};
+            C.child[o] = oct_build(T, start[o], start[o] + cnt[o], cc, h2, depth + 1);
+        }
+    }
+    T->cell[id] = C;
+    return id;
+}
+
+typedef struct {
+    double ax, ay, az, pot;
+    int64_t terms;
+} oct_acc;
+
+static void oct_term(oct_acc *A, double dx, double dy, double dz, double mj, double eps2)
+{
+    const double r2 = ((dx * dx + dy * dy) + dz * dz) + eps2;
+    const double rinv = 1.0 / sqrt(r2);
+    const double f = mj * rinv * rinv * rinv;
+    A->ax += f * dx;
+    A->ay += f * dy;
+    A->az += f * dz;
+    A->pot -= mj * rinv;
+    ++A->terms;
+}
+
+static void oct_walk(const oct_tree *T, int64_t id, int64_t i, double GMcrit, double eps2,
+                     oct_acc *A)
+{
+    const oct_cell *C = &T->cell[id];
+    const double xi = T->x[i], yi = T->y[i], zi = T->z[i];
+    if (C->leaf) {
+        for (int64_t q = C->begin; q < C->end; ++q) {
+            const int64_t j = T->idx[q];
+            if (j == i) continue;
+            oct_term(A, T->x[j] - xi, T->y[j] - yi, T->z[j] - zi, T->m[j], eps2);
+        }
+        return;
+    }
+    const int inside = fabs(xi - C->c[0]) <= C->half && fabs(yi - C->c[1]) <= C->half &&
+                       fabs(zi - C->c[2]) <= C->half;
+    if (!inside) {
+        const double dx = C->cm[0] - xi, dy = C->cm[1] - yi, dz = C->cm[2] - zi;
+        const double r2 = (dx * dx + dy * dy) + dz * dz;
+        const double l = 2.0 * C->half;
+        /* G M l^2 <= alpha |a_old| r^4; GMcrit = alpha |a_old| / G */
+        if (C->M * l * l <= GMcrit * r2 * r2) {
+            oct_term(A, dx, dy, dz, C->M, eps2);
+            return;
+        }
+    }
+    for (int o = 0; o < 8; ++o)
+        if (C->child[o] >= 0) oct_walk(T, C->child[o], i, GMcrit, eps2, A);
+}
+
+void orc_octree_gravity(int64_t n, const double *x, const double *y, const double *z,
+                        const double *m, const double *ax_old, const double *ay_old,
+                        const double *az_old, double G, double eps, double alpha, int64_t nq,
+                        const int64_t *q, double *ax, double *ay, double *az, double *pot,
+                        int64_t *terms)
+{
+    if (q == NULL) nq = n;
+    oct_tree T = {x, y, z, m, NULL, NULL, 0, 0};
+    T.idx = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    const double *p[3] = {x, y, z};
+    for (int64_t i = 0; i < n; ++i) {
+        T.idx[i] = i;
+        for (int a = 0; a < 3; ++a) {
+            if (p[a][i] < lo[a]) lo[a] = p[a][i];
+            if (p[a][i] > hi[a]) hi[a] = p[a][i];
+        }
+    }
+    double c[3], half = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        c[a] = 0.5 * (lo[a] + hi[a]);
+        if (0.5 * (hi[a] - lo[a]) > half) half = 0.5 * (hi[a] - lo[a]);
+    }
+    half = half > 0.0 ? half * (1.0 + 1e-9) : 1.0;
+    if (n > 0) oct_build(&T, 0, n, c, half, 0);
+    const double eps2 = eps * eps;
+    int64_t total = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : total)
+    for (int64_t t = 0; t < nq; ++t) {
+        const int64_t i = q ? q[t] : t;
+        const double a2 = (ax_old[i] * ax_old[i] + ay_old[i] * ay_old[i]) + az_old[i] * az_old[i];
+        const double GMcrit = G != 0.0 ? alpha * sqrt(a2) / G : 0.0;
+        oct_acc A = {0.0, 0.0, 0.0, 0.0, 0};
+        oct_walk(&T, 0, i, GMcrit, eps2, &A);
+        ax[t] = G * A.ax;
+        ay[t] = G * A.ay;
+        az[t] = G * A.az;
+        pot[t] = G * A.pot;
+        total += A.terms;
+    }
+    if (terms) *terms = total;
+    free(T.idx);
+    free(T.cell);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Exact searches over a k-d tree (for full-size runs).  Like the grid and the
  * sweep they change only the order in which candidates are examined: every
  * distance, the (d2, id) order and the pair test are the expressions of the
@@ -1120,6 +1292,8 @@ typedef struct {
     const double *p[3];
     const double *h;
     int64_t *idx;
+    double *q[3];           /* the positions in tree order: q[a][s] = p[a][idx[s]] */
+    double *qh;             /* h in tree order (event search)                      */
     kd_node *node;
     int64_t n_node, cap;
 } kd_tree;
@@ -1212,12 +1386,23 @@ static void kd_build(kd_tree *t, int64_t n, const double *x, const double *y, co
     t->node = NULL;
     t->n_node = t->cap = 0;
     kd_build_node(t, 0, n);
+    /* copies in tree order, so that a leaf is read from consecutive memory */
+    const size_t nn = (size_t)(n > 0 ? n : 1);
+    for (int a = 0; a < 3; ++a) t->q[a] = (double *)malloc(sizeof(double) * nn);
+    t->qh = h ? (double *)malloc(sizeof(double) * nn) : NULL;
+    for (int64_t q = 0; q < n; ++q) {
+        const int64_t i = t->idx[q];
+        for (int a = 0; a < 3; ++a) t->q[a][q] = t->p[a][i];
+        if (h) t->qh[q] = h[i];
+    }
 }
 
 static void kd_free(kd_tree *t)
 {
     free(t->idx);
     free(t->node);
+    for (int a = 0; a < 3; ++a) free(t->q[a]);
+    free(t->qh);
 }
 
 /* Squared distance from (x, y, z) to the node's box: the gaps per axis
@@ -1250,10 +1435,11 @@ static void kd_knn_visit(const kd_tree *t, int64_t nd, int64_t i, kd_best *B)
     const int32_t k = B->k;
     if (B->cnt == k && kd_box_d2(N, x[i], y[i], z[i]) > B->bd[k - 1]) return;
     if (N->left < 0) {
+        const double *qx = t->q[0], *qy = t->q[1], *qz = t->q[2];
         for (int64_t q = N->begin; q < N->end; ++q) {
             const int64_t j = t->idx[q];
             if (j == i) continue;
-            double dx = x[j] - x[i], dy = y[j] - y[i], dz = z[j] - z[i];
+            double dx = qx[q] - x[i], dy = qy[q] - y[i], dz = qz[q] - z[i];
             double d2 = (dx * dx + dy * dy) + dz * dz;
             if (B->cnt == k && !key_less(d2, B->id[j], B->bd[k - 1], B->bi[k - 1])) continue;
             int32_t pos = B->cnt < k ? B->cnt : k - 1;
@@ -1292,7 +1478,8 @@ void orc_knn_tree(int64_t n, const double *x, const double *y, const double *z,
         B.bd = (double *)malloc(sizeof(double) * (size_t)k);
         B.bi = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)k);
 #pragma omp for schedule(dynamic, 256)
-        for (int64_t i = 0; i < n; ++i) {
+        for (int64_t s = 0; s < n; ++s) {
+            const int64_t i = t.idx[s];   /* in tree order: neighbours share the walk */
             B.cnt = 0;
             kd_knn_visit(&t, 0, i, &B);
             h[i] = sqrt(B.bd[k - 1]);
@@ -1362,10 +1549,12 @@ static void kd_pairs_visit(const kd_tree *t, int64_t nd, int64_t i, double R2, k
     const double *h = C->h;
     if (N->hmin > h[i] || kd_box_d2(N, C->x[i], C->y[i], C->z[i]) > R2) return;
     if (N->left < 0) {
+        const double hi = h[i];
         for (int64_t q = N->begin; q < N->end; ++q) {
+            const double hj = t->qh[q];
+            if (!(hj <= hi)) continue;
             const int64_t j = t->idx[q];
-            if (j == i) continue;
-            if (!(h[j] < h[i] || (h[j] == h[i] && j < i))) continue;
+            if (j == i || (hj == hi && j > i)) continue;
             kd_pair(C, i, j);
         }
         return;
@@ -1391,7 +1580,8 @@ int64_t orc_find_events_tree(int64_t n, const double *x, const double *y, const 
         kd_pairs C = {x, y, z, vx, vy, vz, m, h, id, sigma_m, sigma_w, dt, seed, step,
                       0, 0, 0, 0, NULL};
 #pragma omp for schedule(dynamic, 256)
-        for (int64_t i = 0; i < n; ++i) {
+        for (int64_t s = 0; s < n; ++s) {
+            const int64_t i = t.idx[s];
             const double R = 2.0 * h[i] * (1.0 + 1e-9);
             kd_pairs_visit(&t, 0, i, R * R, &C);
         }
@@ -1694,21 +1884,13 @@ static void block_cycle(int64_t n, double *x, double *y, double *z, double *vx, 
     free(w);
 }
 
-/* One step: K(dt/2) D(dt) [forces] K(dt/2), then the SIDM pass at the
- * synchronised point (reading: the paper does not state where scattering sits
- * inside the step; placing it after the closing kick keeps x fixed during the
- * pass, so the pass conserves energy exactly and sigma = 0 is plain KDK). */
-int64_t orc_kdk_step(int64_t n, double *x, double *y, double *z,
-                     double *vx, double *vy, double *vz, const double *m,
-                     const uint32_t *id, double *ax, double *ay, double *az,
-                     double *pot, double *h, const orc_params *p, uint32_t step,
-                     orc_event *ev, int64_t ev_cap)
+/* Opening half kick and drift of a fixed step: v += a dt/2, x += v dt, then
+ * the reflecting sphere. */
+void orc_kick_drift(int64_t n, double *x, double *y, double *z, double *vx, double *vy,
+                    double *vz, const double *ax, const double *ay, const double *az,
+                    const orc_params *p)
 {
-    double hdt = 0.5 * p->dt;
-    if (p->eta > 0.0) {
-        block_cycle(n, x, y, z, vx, vy, vz, m, ax, ay, az, pot, p);
-        goto synchronised;
-    }
+    const double hdt = 0.5 * p->dt;
     for (int64_t i = 0; i < n; ++i) {
         vx[i] += ax[i] * hdt;
         vy[i] += ay[i] * hdt;
@@ -1720,12 +1902,37 @@ int64_t orc_kdk_step(int64_t n, double *x, double *y, double *z,
         z[i] += vz[i] * p->dt;
     }
     reflect(n, x, y, z, vx, vy, vz, p);
-    accel_total(n, x, y, z, m, p, ax, ay, az, pot);
+}
+
+/* Closing half kick of a fixed step: v += a dt/2. */
+void orc_close_kick(int64_t n, double *vx, double *vy, double *vz, const double *ax,
+                    const double *ay, const double *az, const orc_params *p)
+{
+    const double hdt = 0.5 * p->dt;
     for (int64_t i = 0; i < n; ++i) {
         vx[i] += ax[i] * hdt;
         vy[i] += ay[i] * hdt;
         vz[i] += az[i] * hdt;
     }
+}
+
+/* One step: K(dt/2) D(dt) [forces] K(dt/2), then the SIDM pass at the
+ * synchronised point (reading: the paper does not state where scattering sits
+ * inside the step; placing it after the closing kick keeps x fixed during the
+ * pass, so the pass conserves energy exactly and sigma = 0 is plain KDK). */
+int64_t orc_kdk_step(int64_t n, double *x, double *y, double *z,
+                     double *vx, double *vy, double *vz, const double *m,
+                     const uint32_t *id, double *ax, double *ay, double *az,
+                     double *pot, double *h, const orc_params *p, uint32_t step,
+                     orc_event *ev, int64_t ev_cap)
+{
+    if (p->eta > 0.0) {
+        block_cycle(n, x, y, z, vx, vy, vz, m, ax, ay, az, pot, p);
+        goto synchronised;
+    }
+    orc_kick_drift(n, x, y, z, vx, vy, vz, ax, ay, az, p);
+    accel_total(n, x, y, z, m, p, ax, ay, az, pot);
+    orc_close_kick(n, vx, vy, vz, ax, ay, az, p);
 synchronised:
     orc_knn_tree(n, x, y, z, id, p->k, h, NULL);
     if (p->sigma_m == 0.0) return 0;

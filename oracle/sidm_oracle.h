@@ -90,6 +90,28 @@ void orc_tree_gravity(int64_t n, const double *x, const double *y, const double 
                       const int64_t *q, double *ax, double *ay, double *az, double *pot,
                       int64_t *terms);
 
+/* Tree gravity as the paper states it (Sec. 2: a one-sided oct-tree opened
+ * with the relative criterion of Springel 2005, eq. 18), the accuracy
+ * reference for the tree option.  The tree: a cube around all particles,
+ * split into eight octants (a particle on a midplane goes to the upper side)
+ * until a cell holds one particle (or at depth 60, where the rest stay
+ * together); each cell holds its particles' mass M and centre of mass.  Each
+ * particle i walks it from the root on its own: a cell is accepted as one
+ * Plummer-softened monopole at its centre of mass when G M l^2 <= alpha
+ * |a_old,i| r^4 (l the cube's side, r the distance from x_i to the centre of
+ * mass) and x_i lies outside the cube (reading: a cell that holds the
+ * particle is always opened, as the criterion assumes a distant cell);
+ * otherwise it is opened, and a leaf contributes its particles (self
+ * excluded).  a_old = 0 opens every cell: the direct sum.  Plain double sums
+ * in walk order.  q == NULL: all n particles; otherwise the nq particles q[k]
+ * at index k.  `terms` (nullable): source terms summed over the queried
+ * particles.  OpenMP over the queried particles. */
+void orc_octree_gravity(int64_t n, const double *x, const double *y, const double *z,
+                        const double *m, const double *ax_old, const double *ay_old,
+                        const double *az_old, double G, double eps, double alpha, int64_t nq,
+                        const int64_t *q, double *ax, double *ay, double *az, double *pot,
+                        int64_t *terms);
+
 /* Static NFW host (paper Sec. 4.1, Eq. nfw_potential) centred at c:
  * Phi(r) = -4 pi G rho_s r_s^3 ln(1 + r/r_s) / r and a = -grad Phi.
  * Writes (not adds) the host acceleration and potential for n particles. */
@@ -240,6 +262,14 @@ typedef struct orc_params_s {
  * max_bin), then decreased while dt / 2^b < dt_min. */
 int32_t orc_bin(double dt, double eta, double eps, double dt_min, int32_t max_bin,
                 double ax, double ay, double az);
+
+/* The parts of a fixed step around the forces: K(dt/2) D(dt) with the
+ * reflecting sphere, and the closing K(dt/2) (orc_kdk_step calls both). */
+void orc_kick_drift(int64_t n, double *x, double *y, double *z, double *vx, double *vy,
+                    double *vz, const double *ax, const double *ay, const double *az,
+                    const orc_params *p);
+void orc_close_kick(int64_t n, double *vx, double *vy, double *vz, const double *ax,
+                    const double *ay, const double *az, const orc_params *p);
 
 /* Full-N step for one halo (exact searches: orc_knn_tree, orc_find_events_tree).
  * With eta > 0 the step is one cycle of block time steps (see the source).  On entry a/pot hold the acceleration

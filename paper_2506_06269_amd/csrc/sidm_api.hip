@@ -120,8 +120,6 @@ struct DeviceGuard {
     }
 };
 
-enum Need { NEED_GRAV = 1, NEED_KNN = 2, NEED_SCATTER = 4, NEED_STEP = 8 };
-
 sidm_status validate(sidm_ctx* c, const sidm_halo* halos, int32_t n_halos, const sidm_state* s,
                      int need)
 {
@@ -159,73 +157,11 @@ sidm_status validate(sidm_ctx* c, const sidm_halo* halos, int32_t n_halos, const
     int64_t total = 0;
     for (int32_t h = 0; h < n_halos; ++h) {
         const sidm_halo& H = halos[h];
-        if (H.offset < 0 || H.n < 2 || H.n > (int64_t(1) << 24)) {
-            set_err(c, "halo %d: need offset >= 0 and 2 <= n <= 2^24 (offset=%lld n=%lld)", h,
-                    (long long)H.offset, (long long)H.n);
-            return SIDM_ERR_INVALID;
-        }
-        if (!(H.eps > 0.0) || !std::isfinite(H.eps) || !std::isfinite(H.G)) {
-            set_err(c, "halo %d: softening eps must be finite and > 0 (eps=%g)", h, H.eps);
-            return SIDM_ERR_INVALID;
-        }
-        if ((need & (NEED_SCATTER | NEED_STEP)) && (!(H.dt > 0.0) || !std::isfinite(H.dt))) {
-            set_err(c, "halo %d: dt must be finite and > 0 (dt=%g)", h, H.dt);
-            return SIDM_ERR_INVALID;
-        }
-        if ((need & (NEED_SCATTER | NEED_STEP)) &&
-            (!(H.sigma_w >= 0.0) || !std::isfinite(H.sigma_w))) {
-            set_err(c, "halo %d: sigma_w must be finite and >= 0", h);
-            return SIDM_ERR_INVALID;
-        }
-        if ((need & (NEED_SCATTER | NEED_STEP)) && (!(H.sigma_m >= 0.0) || !std::isfinite(H.sigma_m))) {
-            set_err(c, "halo %d: sigma_m must be finite and >= 0", h);
-            return SIDM_ERR_INVALID;
-        }
-        if ((need & (NEED_KNN | NEED_STEP)) &&
-            (H.k < 1 || H.k > SIDM_MAX_K || (int64_t)H.k > H.n - 1)) {
-            set_err(c, "halo %d: need 1 <= k <= min(n-1, %d) (k=%d n=%lld)", h, SIDM_MAX_K, H.k,
-                    (long long)H.n);
-            return SIDM_ERR_INVALID;
-        }
-        if (H.host_kind < 0 || H.host_kind > 2) {
-            set_err(c, "halo %d: host_kind must be 0, 1 or 2", h);
-            return SIDM_ERR_UNSUPPORTED;
-        }
-        if (H.host_kind != 0 && (!(H.host_r_s > 0.0) || !std::isfinite(H.host_r_s) ||
-                                 !std::isfinite(H.host_rho_s))) {
-            set_err(c, "halo %d: host needs r_s > 0 and finite rho_s", h);
-            return SIDM_ERR_INVALID;
-        }
-        if (H.host_kind == 2) {
-            if (!std::isfinite(H.host_hern_M) ||
-                (H.host_hern_M != 0.0 && !(H.host_hern_a > 0.0 && std::isfinite(H.host_hern_a)))) {
-                set_err(c, "halo %d: the Hernquist bulge needs a finite mass and a > 0", h);
-                return SIDM_ERR_INVALID;
-            }
-            for (int d = 0; d < 4; ++d) {
-                const double* D = H.host_disk[d];
-                if (!std::isfinite(D[0]) ||
-                    (D[0] != 0.0 && !(D[1] >= 0.0 && D[2] >= 0.0 && D[1] + D[2] > 0.0 &&
-                                      std::isfinite(D[1]) && std::isfinite(D[2])))) {
-                    set_err(c, "halo %d: disc %d needs a finite mass, a, b >= 0, a + b > 0", h, d);
-                    return SIDM_ERR_INVALID;
-                }
-            }
-        }
-        if (!(H.boundary_r >= 0.0) || !std::isfinite(H.boundary_r)) {
-            set_err(c, "halo %d: boundary_r must be finite and >= 0", h);
-            return SIDM_ERR_INVALID;
-        }
-        if (!(H.tree_alpha >= 0.0) || !std::isfinite(H.tree_alpha)) {
-            set_err(c, "halo %d: tree_alpha must be finite and >= 0", h);
-            return SIDM_ERR_INVALID;
-        }
-        if (!(H.eta >= 0.0) || !std::isfinite(H.eta) || !(H.dt_min >= 0.0) ||
-            !std::isfinite(H.dt_min) || H.max_bin < 0 || H.max_bin > SIDM_MAX_BIN ||
-            (H.eta == 0.0 && H.max_bin != 0)) {
-            set_err(c, "halo %d: block steps need finite eta >= 0, dt_min >= 0 and "
-                       "0 <= max_bin <= %d (max_bin = 0 when eta = 0)", h, SIDM_MAX_BIN);
-            return SIDM_ERR_INVALID;
+        char msg[256];
+        const sidm_status r = check_halo(H, need, msg, sizeof msg);
+        if (r != SIDM_OK) {
+            set_err(c, "halo %d: %s", h, msg);
+            return r;
         }
         ranges.push_back({H.offset, H.offset + H.n});
         total = std::max(total, H.offset + H.n);
@@ -355,16 +291,23 @@ sidm_status enter(sidm_ctx* c, const sidm_halo* halos, int32_t n_halos, const si
                        "capture; call once outside capture with them before capturing");
             return SIDM_ERR_INVALID;
         }
-    } else if (c->fp_valid && fp == c->fp_eager) {
-        return SIDM_OK;
+        return SIDM_OK;   // the check is enqueued by guard(), after the status reset
     }
-    const hipError_t e = launch_fingerprint(c->plan, c->w, fp, captured, st);
+    if (c->fp_valid && fp == c->fp_eager) return SIDM_OK;
+    const hipError_t e = launch_fingerprint(c->plan, c->w, fp, false, st);
     if (e != hipSuccess) return hip_fail(c, e, "fingerprint launch");
-    if (!captured) {
-        c->fp_eager = fp;
-        c->fp_valid = true;
-    }
+    c->fp_eager = fp;
+    c->fp_valid = true;
     return SIDM_OK;
+}
+
+// Inside capture: the kernel that flags a replay whose fingerprint is no
+// longer the device's (placed after the call's reset of the status words).
+sidm_status guard(sidm_ctx* c, hipStream_t st, bool captured)
+{
+    if (!captured) return SIDM_OK;
+    const hipError_t e = launch_fingerprint(c->plan, c->w, c->fp_eager, true, st);
+    return e == hipSuccess ? SIDM_OK : hip_fail(c, e, "guard launch");
 }
 
 int max_k(const sidm_halo* halos, int32_t n)
@@ -469,6 +412,7 @@ sidm_status sidm_gravity(sidm_ctx* c, const sidm_halo* halos, int32_t n_halos,
     hipStream_t st = (hipStream_t)stream;
     bool cap = false;
     if ((r = enter(c, halos, n_halos, s, st, cap)) != SIDM_OK) return r;
+    if ((r = guard(c, st, cap)) != SIDM_OK) return r;
     hipError_t e = launch_tree_terms_reset(c->w, n_halos, st);
     if (e == hipSuccess) e = launch_cell_list(c->plan, s, c->w, st);
     if (e == hipSuccess)
@@ -489,6 +433,7 @@ sidm_status sidm_knn_h(sidm_ctx* c, const sidm_halo* halos, int32_t n_halos, con
     bool cap = false;
     if ((r = enter(c, halos, n_halos, s, st, cap)) != SIDM_OK) return r;
     hipError_t e = launch_reset(c->plan, c->w, st);
+    if (e == hipSuccess && (r = guard(c, st, cap)) != SIDM_OK) return r;
     if (e == hipSuccess) e = launch_cell_list(c->plan, s, c->w, st);
     if (e == hipSuccess) e = launch_knn(c->plan, s, c->w, nbr, max_k(halos, n_halos), st);
     if (e != hipSuccess) return hip_fail(c, e, "kNN launch");
@@ -516,6 +461,7 @@ sidm_status sidm_scatter(sidm_ctx* c, const sidm_halo* halos, int32_t n_halos,
         return SIDM_ERR_INVALID;
     }
     hipError_t e = launch_reset(c->plan, c->w, st);
+    if (e == hipSuccess && (r = guard(c, st, captured)) != SIDM_OK) return r;
     if (e == hipSuccess) e = launch_cell_list(c->plan, s, c->w, st);
     if (e == hipSuccess) e = launch_tree_hmax(c->plan, c->w, st);
     if (e == hipSuccess)
@@ -612,6 +558,7 @@ sidm_status sidm_kdk_step(sidm_ctx* c, const sidm_halo* halos, int32_t n_halos,
         if (halos[h].eta > 0.0) bmax = std::max(bmax, (int)halos[h].max_bin);
     mark(0);
     hipError_t e = launch_reset(P, c->w, st);
+    if (e == hipSuccess && (r = guard(c, st, captured)) != SIDM_OK) return r;
     if (e == hipSuccess) e = launch_tree_terms_reset(c->w, n_halos, st);
     if (bmax < 0) {
         if (e == hipSuccess)
@@ -671,6 +618,7 @@ sidm_status sidm_diagnostics(sidm_ctx* c, const sidm_halo* halos, int32_t n_halo
     hipStream_t st = (hipStream_t)stream;
     bool cap = false;
     if ((r = enter(c, halos, n_halos, s, st, cap)) != SIDM_OK) return r;
+    if ((r = guard(c, st, cap)) != SIDM_OK) return r;
     const Plan& P = c->plan;
     hipError_t e = launch_diag(c->w.blocks, P.n_blocks, c->w.halos, n_halos, s->x, s->y, s->z,
                                s->vx, s->vy, s->vz, s->m, s->pot, c->w.bsum, c->w.ev_counts,
@@ -700,6 +648,7 @@ sidm_status sidm_central_density(sidm_ctx* c, const sidm_halo* halos, int32_t n_
     hipStream_t st = (hipStream_t)stream;
     bool cap = false;
     if ((r = enter(c, halos, n_halos, s, st, cap)) != SIDM_OK) return r;
+    if ((r = guard(c, st, cap)) != SIDM_OK) return r;
     const Plan& P = c->plan;
     c->radius.assign(radius, radius + n_halos);
     hipError_t e = hipMemcpyAsync(c->w.radius, c->radius.data(), sizeof(double) * (size_t)n_halos,
@@ -730,6 +679,7 @@ sidm_status sidm_tidal_radius(sidm_ctx* c, const sidm_halo* halos, int32_t n_hal
     hipStream_t st = (hipStream_t)stream;
     bool cap = false;
     if ((r = enter(c, halos, n_halos, s, st, cap)) != SIDM_OK) return r;
+    if ((r = guard(c, st, cap)) != SIDM_OK) return r;
     const Plan& P = c->plan;
     hipError_t e = launch_tidal(c->w.blocks, P.n_blocks, c->w.halos, n_halos, s->x, s->y, s->z,
                                 s->m, s->pot, c->w.bsum, c->w.center, c->w.tidal, out, st);

@@ -4,6 +4,7 @@
 #pragma once
 
 #include <algorithm>
+#include <cstdio>
 #include <functional>
 #include <string>
 #include <vector>
@@ -127,7 +128,7 @@ struct Plan {
     std::vector<BucketInfo> buckets;
     std::vector<NodeTask> node_tasks;
     std::vector<NodeChild> nodes;
-    std::vector<int64_t> level_task_off;  // tasks of level l: [off[l-1], off[l])
+    int64_t level_task_off[kMaxLevels + 1] = {};   // tasks of level l: [off[l-1], off[l])
     std::vector<int> rank_of;
 };
 
@@ -228,6 +229,116 @@ inline void free_scratch(Scratch& w)
     dfree(w.sticky); dfree(w.fp_dev);
 }
 
+// The physical parameters of a halo (the layout fields stay zero).
+inline void fill_halo_params(HaloDev& H, const sidm_halo& S)
+{
+    std::memset(&H, 0, sizeof H);
+    H.offset = S.offset;
+    H.n = S.n;
+    H.G = S.G;
+    H.eps = S.eps;
+    H.eps2 = S.eps * S.eps;
+    H.sigma_m = S.sigma_m;
+    H.sigma_w = S.sigma_w;
+    H.dt = S.dt;
+    H.k = S.k;
+    H.host_kind = S.host_kind;
+    H.seed = S.seed;
+    H.host_r_s = S.host_r_s > 0 ? S.host_r_s : 1.0;
+    H.host_K = 4.0 * M_PI * S.G * S.host_rho_s * H.host_r_s * H.host_r_s * H.host_r_s;
+    for (int c = 0; c < 3; ++c) H.host_c[c] = S.host_center[c];
+    if (S.host_kind == 2) {
+        H.hern_GM = S.G * S.host_hern_M;
+        H.hern_a = S.host_hern_a;
+        for (int d = 0; d < 4; ++d) {
+            H.disk_GM[d] = S.G * S.host_disk[d][0];
+            H.disk_a[d] = S.host_disk[d][1];
+            H.disk_b[d] = S.host_disk[d][2];
+        }
+    }
+    H.bnd_r = S.boundary_r;
+    for (int c = 0; c < 3; ++c) H.bnd_c[c] = S.boundary_center[c];
+    H.eta = S.eta;
+    H.dt_min = S.dt_min;
+    H.max_bin = S.eta > 0.0 ? S.max_bin : 0;
+    H.tree_alpha = S.tree_alpha;
+}
+
+// Checks of one halo's parameters that do not depend on a context (need: the
+// NEED_* bits of the call).  Writes a message into msg and returns a status.
+enum Need { NEED_GRAV = 1, NEED_KNN = 2, NEED_SCATTER = 4, NEED_STEP = 8 };
+inline sidm_status check_halo(const sidm_halo& H, int need, char* msg, size_t cap)
+{
+    if (H.offset < 0 || H.n < 2 || H.n > (int64_t(1) << 24)) {
+        snprintf(msg, cap, "need offset >= 0 and 2 <= n <= 2^24 (offset=%lld n=%lld)",
+                 (long long)H.offset, (long long)H.n);
+        return SIDM_ERR_INVALID;
+    }
+    if (!(H.eps > 0.0) || !std::isfinite(H.eps) || !std::isfinite(H.G)) {
+        snprintf(msg, cap, "softening eps must be finite and > 0 (eps=%g)", H.eps);
+        return SIDM_ERR_INVALID;
+    }
+    if ((need & (NEED_SCATTER | NEED_STEP)) && (!(H.dt > 0.0) || !std::isfinite(H.dt))) {
+        snprintf(msg, cap, "dt must be finite and > 0 (dt=%g)", H.dt);
+        return SIDM_ERR_INVALID;
+    }
+    if ((need & (NEED_SCATTER | NEED_STEP)) && (!(H.sigma_w >= 0.0) || !std::isfinite(H.sigma_w))) {
+        snprintf(msg, cap, "sigma_w must be finite and >= 0");
+        return SIDM_ERR_INVALID;
+    }
+    if ((need & (NEED_SCATTER | NEED_STEP)) && (!(H.sigma_m >= 0.0) || !std::isfinite(H.sigma_m))) {
+        snprintf(msg, cap, "sigma_m must be finite and >= 0");
+        return SIDM_ERR_INVALID;
+    }
+    if ((need & (NEED_KNN | NEED_STEP)) &&
+        (H.k < 1 || H.k > SIDM_MAX_K || (int64_t)H.k > H.n - 1)) {
+        snprintf(msg, cap, "need 1 <= k <= min(n-1, %d) (k=%d n=%lld)", SIDM_MAX_K, H.k,
+                 (long long)H.n);
+        return SIDM_ERR_INVALID;
+    }
+    if (H.host_kind < 0 || H.host_kind > 2) {
+        snprintf(msg, cap, "host_kind must be 0, 1 or 2");
+        return SIDM_ERR_UNSUPPORTED;
+    }
+    if (H.host_kind != 0 && (!(H.host_r_s > 0.0) || !std::isfinite(H.host_r_s) ||
+                             !std::isfinite(H.host_rho_s))) {
+        snprintf(msg, cap, "host needs r_s > 0 and finite rho_s");
+        return SIDM_ERR_INVALID;
+    }
+    if (H.host_kind == 2) {
+        if (!std::isfinite(H.host_hern_M) ||
+            (H.host_hern_M != 0.0 && !(H.host_hern_a > 0.0 && std::isfinite(H.host_hern_a)))) {
+            snprintf(msg, cap, "the Hernquist bulge needs a finite mass and a > 0");
+            return SIDM_ERR_INVALID;
+        }
+        for (int d = 0; d < 4; ++d) {
+            const double* D = H.host_disk[d];
+            if (!std::isfinite(D[0]) ||
+                (D[0] != 0.0 && !(D[1] >= 0.0 && D[2] >= 0.0 && D[1] + D[2] > 0.0 &&
+                                  std::isfinite(D[1]) && std::isfinite(D[2])))) {
+                snprintf(msg, cap, "disc %d needs a finite mass, a, b >= 0, a + b > 0", d);
+                return SIDM_ERR_INVALID;
+            }
+        }
+    }
+    if (!(H.boundary_r >= 0.0) || !std::isfinite(H.boundary_r)) {
+        snprintf(msg, cap, "boundary_r must be finite and >= 0");
+        return SIDM_ERR_INVALID;
+    }
+    if (!(H.tree_alpha >= 0.0) || !std::isfinite(H.tree_alpha)) {
+        snprintf(msg, cap, "tree_alpha must be finite and >= 0");
+        return SIDM_ERR_INVALID;
+    }
+    if (!(H.eta >= 0.0) || !std::isfinite(H.eta) || !(H.dt_min >= 0.0) ||
+        !std::isfinite(H.dt_min) || H.max_bin < 0 || H.max_bin > SIDM_MAX_BIN ||
+        (H.eta == 0.0 && H.max_bin != 0)) {
+        snprintf(msg, cap, "block steps need finite eta >= 0, dt_min >= 0 and "
+                           "0 <= max_bin <= %d (max_bin = 0 when eta = 0)", SIDM_MAX_BIN);
+        return SIDM_ERR_INVALID;
+    }
+    return SIDM_OK;
+}
+
 // Number of j-splits for the gravity sum of each halo.  Work items (one
 // block of kGravThreads * 4 i-particles against one j-range) are started
 // largest first on `slots` resident blocks; the split whose simulated
@@ -312,36 +423,7 @@ inline bool build_plan(Plan& P, const Scratch& w, const sidm_halo* halos, int32_
     for (int h = 0; h < n_halos; ++h) {
         const sidm_halo& S = halos[h];
         HaloDev& H = P.halos[h];
-        std::memset(&H, 0, sizeof H);
-        H.offset = S.offset;
-        H.n = S.n;
-        H.G = S.G;
-        H.eps = S.eps;
-        H.eps2 = S.eps * S.eps;
-        H.sigma_m = S.sigma_m;
-        H.sigma_w = S.sigma_w;
-        H.dt = S.dt;
-        H.k = S.k;
-        H.host_kind = S.host_kind;
-        H.seed = S.seed;
-        H.host_r_s = S.host_r_s > 0 ? S.host_r_s : 1.0;
-        H.host_K = 4.0 * M_PI * S.G * S.host_rho_s * H.host_r_s * H.host_r_s * H.host_r_s;
-        for (int c = 0; c < 3; ++c) H.host_c[c] = S.host_center[c];
-        if (S.host_kind == 2) {
-            H.hern_GM = S.G * S.host_hern_M;
-            H.hern_a = S.host_hern_a;
-            for (int d = 0; d < 4; ++d) {
-                H.disk_GM[d] = S.G * S.host_disk[d][0];
-                H.disk_a[d] = S.host_disk[d][1];
-                H.disk_b[d] = S.host_disk[d][2];
-            }
-        }
-        H.bnd_r = S.boundary_r;
-        for (int c = 0; c < 3; ++c) H.bnd_c[c] = S.boundary_center[c];
-        H.eta = S.eta;
-        H.dt_min = S.dt_min;
-        H.max_bin = S.eta > 0.0 ? S.max_bin : 0;
-        H.tree_alpha = S.tree_alpha;
+        fill_halo_params(H, S);
         if (S.tree_alpha > 0.0) P.has_tree = true;
         if (S.sigma_m > 0.0) P.any_scatter = true;
         H.sbase = sbase[h];
@@ -398,10 +480,10 @@ inline bool build_plan(Plan& P, const Scratch& w, const sidm_halo* halos, int32_
         for (auto& t : per_level[l])
             P.nodes[(size_t)t.node] =
                 NodeChild{t.child0, P.nodes[(size_t)(t.child0 + t.nchild - 1)].last, t.nchild, 0};
-    P.level_task_off.push_back(0);
+    P.level_task_off[0] = 0;
     for (int l = 1; l < P.n_levels; ++l) {
         for (auto& t : per_level[l]) P.node_tasks.push_back(t);
-        P.level_task_off.push_back((int64_t)P.node_tasks.size());
+        P.level_task_off[l] = (int64_t)P.node_tasks.size();
     }
     // gravity work items
     choose_splits(P.halos, w.partial_rows, w.grav_slots);

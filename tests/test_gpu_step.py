@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 import workloads as W
+from tests._parity import event_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -41,36 +42,6 @@ def _start(S, orc, s, halo, prec):
     S.sidm_gravity(ctx, [halo], dev, prec)
     torch.cuda.synchronize()
     return ctx, dev
-
-
-def _event_parity(orc, got, pre, halo, step, marginal_tol):
-    """GPU events `got` (a, b pairs) against the oracle's decisions on the
-    pre-scatter state `pre`: equal sets, except pairs whose draw lies within
-    marginal_tol * P of the oracle's P (counted and returned)."""
-    ref, _, _ = orc.find_events(pre["x"], pre["y"], pre["z"], pre["vx"], pre["vy"], pre["vz"],
-                                pre["m"], pre["id"], pre["h"], halo["sigma_m"], halo["dt"],
-                                halo.get("seed", 0), step)
-    rset = {(int(a), int(b)): (u, P) for a, b, u, P in zip(ref["a"], ref["b"], ref["u"], ref["P"])}
-    gset = {(int(a), int(b)) for a, b in zip(got["a"], got["b"])}
-    assert len(gset) == len(got), "an event appears twice"
-    idx_of = {int(v): i for i, v in enumerate(pre["id"])}
-    marginal = 0
-    for pair in gset ^ set(rset):
-        if pair in rset:
-            u, P = rset[pair]
-        else:
-            ia, ib = idx_of[pair[0]], idx_of[pair[1]]
-            d = np.sqrt((pre["x"][ia] - pre["x"][ib]) ** 2 + (pre["y"][ia] - pre["y"][ib]) ** 2 +
-                        (pre["z"][ia] - pre["z"][ib]) ** 2)
-            g = np.sqrt((pre["vx"][ia] - pre["vx"][ib]) ** 2 +
-                        (pre["vy"][ia] - pre["vy"][ib]) ** 2 +
-                        (pre["vz"][ia] - pre["vz"][ib]) ** 2)
-            u = orc.accept_u(halo.get("seed", 0), step, *pair)
-            P = halo["sigma_m"] * pre["m"][ib] * g * orc.lam(d, pre["h"][ia], pre["h"][ib]) * \
-                halo["dt"]
-        assert abs(u - P) <= marginal_tol * P, (pair, u, P)
-        marginal += 1
-    return ref, marginal
 
 
 @pytest.mark.parametrize("prec", [0, 1])
@@ -112,7 +83,7 @@ def test_step_parity_c1(S, orc, prec):
                      (out["az"] - ref["az"]) ** 2) / an
         assert ea.max() < tol_a, ea.max()
         assert np.array_equal(out["x"], ref["x"]) and np.array_equal(out["z"], ref["z"])
-        ev, m = _event_parity(orc, got, ref, halo, step, tol_u)
+        ev, m = event_parity(orc, got, ref, halo, step, tol_u)
         marginal += m
         print(f"step {step}: events gpu {cnt} oracle {ev.size} rounds {d['n_rounds']} "
               f"marginal {m}", flush=True)

@@ -516,6 +516,28 @@ def test_kdk_step_with_scattering_conserves_momentum(orc):
     assert np.array_equal(hk, s["h"])
 
 
+def test_step_parts_compose_to_the_step(orc):
+    """The parts the full-size GPU tests call (kick + drift, forces, closing
+    kick, the k-d tree kNN and pair search, the ordered kicks) make exactly
+    orc.kdk_step, bit for bit, for a satellite in the host."""
+    s0 = W.place_on_orbit(W.nfw_halo(3000, seed=9))
+    p = orc.make_params(eps=0.01, sigma_m=300.0, dt=1e-3, k=24, seed=6, host=W.host_params())
+    orc.total_accel(s0, p)
+    a = {k: v.copy() for k, v in s0.items()}
+    ev = orc.kdk_step(a, p, 4)
+    b = {k: v.copy() for k, v in s0.items()}
+    orc.kick_drift(b, p)
+    orc.total_accel(b, p)
+    orc.close_kick(b, p)
+    b["h"] = orc.knn_tree(b["x"], b["y"], b["z"], b["id"], 24)
+    ev2, _, _ = orc.find_events_tree(b["x"], b["y"], b["z"], b["vx"], b["vy"], b["vz"], b["m"],
+                                     b["id"], b["h"], 300.0, 1e-3, 6, 4)
+    orc.apply_events(ev2, b["m"], b["vx"], b["vy"], b["vz"], 6, 4)
+    assert ev.size > 0 and bytes(ev) == bytes(ev2)
+    for k in ("x", "y", "z", "vx", "vy", "vz", "ax", "ay", "az", "pot", "h"):
+        assert np.array_equal(a[k], b[k]), k
+
+
 def test_step_independent_of_thread_count(orc):
     """Every sum of the oracle belongs to one target particle and runs in a
     fixed order, so a step on one thread equals the step on all threads bit
