@@ -189,7 +189,8 @@ void sidm_destroy(sidm_ctx *ctx);
 const char *sidm_status_string(sidm_status s);
 
 /* Detail text of the last error on this context ("" if none).  The pointer is
- * valid until the next call on the context. */
+ * valid until the next call on the context.  With ctx = NULL: the text of the
+ * last sidm_gravity_static call on the calling thread. */
 const char *sidm_last_error(const sidm_ctx *ctx);
 
 /* ---- gravity -----------------------------------------------------------------
@@ -218,6 +219,27 @@ const char *sidm_last_error(const sidm_ctx *ctx);
  * source terms summed is reported in sidm_diag.n_grav_terms. */
 sidm_status sidm_gravity(sidm_ctx *ctx, const sidm_halo *halos, int32_t n_halos,
                          const sidm_state *state, sidm_precision prec, void *stream);
+
+/* ---- gravity without allocation ---------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the pass of
+ * sidm_gravity (direct sum, either precision, host included) for ONE halo of
+ * at most SIDM_STATIC_MAX_N particles, without a context.  Every scratch
+ * buffer of the pass (cell list, sort keys, FP32 frames, partial rows, launch
+ * tables) lies in one fixed array of SIDM_STATIC_BYTES in the library, one per
+ * GPU, held until the process ends; the launch tables are written there by a
+ * kernel from the halo's parameters.  The call allocates nothing and enqueues
+ * on `stream` of the current device.  Every call on a GPU uses that GPU's
+ * array, which keeps the last call's contents: calls that overlap on one GPU
+ * (other streams, other threads) race and must be ordered by the caller.
+ * Results equal sidm_gravity's for the same halo and state.  Errors:
+ * SIDM_ERR_CAPACITY when n > SIDM_STATIC_MAX_N, SIDM_ERR_UNSUPPORTED when
+ * tree_alpha > 0, SIDM_ERR_INVALID for the argument errors of sidm_gravity;
+ * the text is sidm_last_error(NULL) on the calling thread. */
+#define SIDM_STATIC_MAX_N 65536
+#define SIDM_STATIC_BYTES (17u << 20)
+sidm_status sidm_gravity_static(const sidm_halo *halo, const sidm_state *state,
+                                sidm_precision prec, void *stream);
 
 /* ---- kernel size -----------------------------------------------------------
  * h_i = distance to the k-th nearest other particle of the same halo (Sec. 2:

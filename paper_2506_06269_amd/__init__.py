@@ -41,7 +41,8 @@ SIDM_DEV_STALE_GRAPH = 32
 EXPORTED = ("sidm_create", "sidm_destroy", "sidm_set_event_capacity", "sidm_status_string",
             "sidm_last_error", "sidm_gravity", "sidm_knn_h", "sidm_scatter", "sidm_kdk_step",
             "sidm_diagnostics", "sidm_central_density", "sidm_tidal_radius", "sidm_enable_timing",
-            "sidm_pass_times", "sidm_last_events", "sidm_take_status")
+            "sidm_pass_times", "sidm_last_events", "sidm_take_status", "sidm_gravity_static")
+SIDM_STATIC_MAX_N = 65536
 PASS_NAMES = ("kick_drift", "gravity", "gravity_tiles", "cell_list", "knn", "pairs", "kicks",
               "diag")
 
@@ -126,6 +127,7 @@ def lib():
         L.sidm_pass_times.argtypes = [vp, C.POINTER(C.c_double)]
         L.sidm_last_events.argtypes = [vp, vp, i64, C.POINTER(i64), vp]
         L.sidm_take_status.argtypes = [vp, C.POINTER(i32)]
+        L.sidm_gravity_static.argtypes = [hp, sp, C.c_int, vp]
         for name in EXPORTED:
             if name not in ("sidm_destroy", "sidm_status_string", "sidm_last_error"):
                 getattr(L, name).restype = C.c_int
@@ -240,6 +242,14 @@ def sidm_gravity(ctx, halos, state, prec=SIDM_PREC_MIXED, stream=None):
     S = make_state(state)
     _check(ctx, lib().sidm_gravity(ctx.handle, H, len(halos), C.byref(S), int(prec),
                                    _stream(stream)))
+
+
+def sidm_gravity_static(halo, state, prec=SIDM_PREC_MIXED, stream=None):
+    """The gravity pass for one halo (n <= SIDM_STATIC_MAX_N) without a context
+    and without any allocation (the library's fixed scratch array)."""
+    H = make_halos([halo])
+    S = make_state(state)
+    _check(None, lib().sidm_gravity_static(H, C.byref(S), int(prec), _stream(stream)))
 
 
 def sidm_knn_h(ctx, halos, state, nbr=None, stream=None):

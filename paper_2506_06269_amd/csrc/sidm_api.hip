@@ -64,6 +64,8 @@ hipError_t launch_clear_sticky(Scratch& w, hipStream_t st);
 
 using namespace sidm;
 
+const char* sidm_static_error_text();
+
 struct sidm_ctx {
     int device = 0;
     int64_t max_particles = 0;
@@ -334,7 +336,7 @@ const char* sidm_status_string(sidm_status s)
     return "unknown status";
 }
 
-const char* sidm_last_error(const sidm_ctx* c) { return c ? c->err.c_str() : "null context"; }
+const char* sidm_last_error(const sidm_ctx* c) { return c ? c->err.c_str() : sidm_static_error_text(); }
 
 sidm_status sidm_create(sidm_ctx** out, int device, int64_t max_particles, int32_t max_halos)
 {
