@@ -379,6 +379,43 @@ sidm_status sidm_tidal_radius(sidm_ctx *ctx, const sidm_halo *halos, int32_t n_h
  * by the context's calls and not yet reported, then clears them. */
 sidm_status sidm_take_status(sidm_ctx *ctx, int32_t *bits);
 
+/* ---- launch shape of the gravity tiles ------------------------------------
+ * The direct-sum tiles run in one of several launch shapes: ireg i-particles
+ * per thread (2, 4 or 8) and threads per block, which is also the j-tile
+ * staged in LDS (128, 256 or 512), in a plain launch (one block per work
+ * item) or a persistent one (as many blocks as the device holds, each taking
+ * work items from an atomic ticket until none is left).  The j-splits follow
+ * from the shape (a simulation of the items on the resident blocks).  The
+ * results of the shapes agree to rounding; the default is 4 x 256, plain.
+ * Cycles of block time steps run their ticks in the default shape. */
+sidm_status sidm_set_launch_shape(sidm_ctx *ctx, int32_t ireg, int32_t threads,
+                                  int32_t persistent);
+
+/* Chooses the shape for these halos and precision on this device: when
+ * cache_path names a file that holds an entry for the key (device
+ * architecture, compute units, precision, and the call's direct-sum size
+ * class: log2 of its direct-sum particles and of its halos, rounded), that
+ * entry; otherwise every shape is timed on the caller's state (the gravity
+ * pass, best of a few runs; about 2 x 9 x 4 gravity passes) and the fastest is
+ * kept and written to the cache (a JSON object, one entry per key; the file
+ * is created or rewritten).  Then runs sidm_gravity with the chosen shape, so
+ * a and pot are those of the shape (the timing runs also write them).  The
+ * shape stays on the context.  Waits for the device; not during capture. */
+#define SIDM_TUNE_FORCE 1       /* time the shapes even if the cache has the key   */
+#define SIDM_TUNE_QUICK 2       /* one timed run per shape instead of three        */
+typedef struct {
+    int32_t ireg, threads, persistent;   /* the chosen shape                         */
+    int32_t from_cache;                  /* 1: read from the cache, not timed        */
+    int32_t n_tried;                     /* shapes timed                             */
+    int32_t reserved;
+    double ms;                           /* the chosen shape's gravity pass (timed)  */
+    double ms_default;                   /* the default shape's                      */
+    char key[96];                        /* the cache key                            */
+} sidm_tune_result;
+sidm_status sidm_autotune(sidm_ctx *ctx, const sidm_halo *halos, int32_t n_halos,
+                          const sidm_state *state, sidm_precision prec, const char *cache_path,
+                          int32_t flags, sidm_tune_result *out, void *stream);
+
 /* ---- pass timing ---------------------------------------------------------
  * When enabled, sidm_kdk_step records HIP events on its stream around each
  * pass (not usable while the stream is being captured into a graph).

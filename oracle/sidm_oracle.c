@@ -276,6 +276,8 @@ typedef struct {
     int32_t nchild, pad;
     double box[6];              /* lo xyz, hi xyz                              */
     double M, Mx, My, Mz;       /* mass and first moments                      */
+    double S[6];                /* second moments about the centre of mass:
+                                   xx, yy, zz, xy, xz, yz                      */
 } tree_node;
 
 typedef struct {
@@ -352,7 +354,7 @@ static void tree_visit(tree_walk *W, int64_t node)
         W->ly[W->len] = nd->My / nd->M;
         W->lz[W->len] = nd->Mz / nd->M;
         W->lm[W->len] = nd->M;
-        W->lidx[W->len] = -1;
+        W->lidx[W->len] = -2 - node;    /* an accepted node */
         W->len++;
         return;
     }
@@ -471,6 +473,38 @@ void orc_tree_gravity(int64_t n, const double *x, const double *y, const double 
         cnt = nn;
     }
     const int64_t root = top - 1;
+    /* second moments about each node's centre of mass: a bucket's from its
+     * particles in order, a node's from its children (parallel axes) */
+    for (int64_t t = 0; t < top; ++t) {
+        tree_node *nd = &nodes[t];
+        for (int k = 0; k < 6; ++k) nd->S[k] = 0.0;
+        if (nd->M == 0.0) continue;
+        const double cx = nd->Mx / nd->M, cy = nd->My / nd->M, cz = nd->Mz / nd->M;
+        if (nd->child0 < 0) {
+            for (int64_t p = nd->first; p < nd->first + nd->count; ++p) {
+                const double u = sx[p] - cx, v = sy[p] - cy, w = sz[p] - cz;
+                nd->S[0] += sm[p] * u * u;
+                nd->S[1] += sm[p] * v * v;
+                nd->S[2] += sm[p] * w * w;
+                nd->S[3] += sm[p] * u * v;
+                nd->S[4] += sm[p] * u * w;
+                nd->S[5] += sm[p] * v * w;
+            }
+            continue;
+        }
+        for (int32_t k = 0; k < nd->nchild; ++k) {
+            const tree_node *ch = &nodes[nd->child0 + k];
+            if (ch->M == 0.0) continue;
+            const double u = ch->Mx / ch->M - cx, v = ch->My / ch->M - cy,
+                         w = ch->Mz / ch->M - cz;
+            nd->S[0] += ch->S[0] + ch->M * u * u;
+            nd->S[1] += ch->S[1] + ch->M * v * v;
+            nd->S[2] += ch->S[2] + ch->M * w * w;
+            nd->S[3] += ch->S[3] + ch->M * u * v;
+            nd->S[4] += ch->S[4] + ch->M * u * w;
+            nd->S[5] += ch->S[5] + ch->M * v * w;
+        }
+    }
     /* the groups that hold a queried particle (all of them without q) */
     const int64_t nqq = q ? nq : n;
     int64_t *pos = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
@@ -531,6 +565,27 @@ void orc_tree_gravity(int64_t n, const double *x, const double *y, const double 
                     neum_add(&gy, w * dy);
                     neum_add(&gz, w * dz);
                     neum_add(&gp, -W.lm[t] * rinv);
+                    if (W.lidx[t] <= -2) {
+                        /* an accepted node's quadrupole: the second-order term
+                         * of the softened potential -G sum m / sqrt(|d - s|^2
+                         * + eps^2) expanded about its centre of mass (s: a
+                         * particle's offset from it, d: from it to the member,
+                         * rho^2 = |d|^2 + eps^2, S the second moments, T
+                         * their trace): phi_Q = -G (3 d.S.d - rho^2 T) /
+                         * (2 rho^5), a_Q = -grad phi_Q */
+                        const double *S = nodes[-2 - W.lidx[t]].S;
+                        const double d0 = -dx, d1 = -dy, d2 = -dz;
+                        const double ri2 = rinv * rinv, ri5 = rinv * ri2 * ri2, ri7 = ri5 * ri2;
+                        const double Sd0 = (S[0] * d0 + S[3] * d1) + S[4] * d2;
+                        const double Sd1 = (S[3] * d0 + S[1] * d1) + S[5] * d2;
+                        const double Sd2 = (S[4] * d0 + S[5] * d1) + S[2] * d2;
+                        const double T = (S[0] + S[1]) + S[2];
+                        const double br = 3.0 * ((d0 * Sd0 + d1 * Sd1) + d2 * Sd2) - r2 * T;
+                        neum_add(&gx, (3.0 * Sd0 - T * d0) * ri5 - 2.5 * br * d0 * ri7);
+                        neum_add(&gy, (3.0 * Sd1 - T * d1) * ri5 - 2.5 * br * d1 * ri7);
+                        neum_add(&gz, (3.0 * Sd2 - T * d2) * ri5 - 2.5 * br * d2 * ri7);
+                        neum_add(&gp, -0.5 * br * ri5);
+                    }
                 }
                 ax[out] = G * neum_get(&gx);
                 ay[out] = G * neum_get(&gy);

@@ -76,8 +76,10 @@ void orc_gravity(int64_t n, const double *x, const double *y, const double *z,
  * squared, for every member and every particle of the node: a node's centre
  * of mass can lie far from some of its particles).  Otherwise the
  * node is opened; an opened bucket contributes its particles.  Forces and
- * potentials: Plummer-softened pair terms with the accepted nodes' monopoles
- * and the contributed particles (self excluded), Neumaier sums.  alpha = 0
+ * potentials: Plummer-softened pair terms with the contributed particles (self
+ * excluded) and, for an accepted node, its monopole plus its quadrupole (the
+ * second-order term of the softened potential about the node's centre of
+ * mass, from the node's second moments), Neumaier sums.  alpha = 0
  * opens every node: the direct sum.  q == NULL: writes ax, ay, az, pot of all
  * n particles in the caller's order; otherwise of the nq particles q[k] at
  * index k (the whole tree is built, only the groups holding them walk).

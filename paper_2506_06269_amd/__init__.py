@@ -41,7 +41,12 @@ SIDM_DEV_STALE_GRAPH = 32
 EXPORTED = ("sidm_create", "sidm_destroy", "sidm_set_event_capacity", "sidm_status_string",
             "sidm_last_error", "sidm_gravity", "sidm_knn_h", "sidm_scatter", "sidm_kdk_step",
             "sidm_diagnostics", "sidm_central_density", "sidm_tidal_radius", "sidm_enable_timing",
-            "sidm_pass_times", "sidm_last_events", "sidm_take_status", "sidm_gravity_static")
+            "sidm_pass_times", "sidm_last_events", "sidm_take_status", "sidm_gravity_static",
+            "sidm_set_launch_shape", "sidm_autotune")
+SIDM_TUNE_FORCE = 1
+SIDM_TUNE_QUICK = 2
+# launch shapes of the gravity tiles: (i-particles per thread, threads per block)
+SHAPES = [(i, t) for t in (128, 256, 512) for i in (2, 4, 8)]
 SIDM_STATIC_MAX_N = 65536
 PASS_NAMES = ("kick_drift", "gravity", "gravity_tiles", "cell_list", "knn", "pairs", "kicks",
               "diag")
@@ -70,6 +75,12 @@ class SidmDiag(C.Structure):
                 ("n_events", C.c_int64), ("n_rounds", C.c_int64), ("n_pairs", C.c_int64),
                 ("n_p_gt1", C.c_int64), ("status", C.c_int32), ("reserved", C.c_int32),
                 ("n_grav_terms", C.c_int64)]
+
+
+class SidmTuneResult(C.Structure):
+    _fields_ = [("ireg", C.c_int32), ("threads", C.c_int32), ("persistent", C.c_int32),
+                ("from_cache", C.c_int32), ("n_tried", C.c_int32), ("reserved", C.c_int32),
+                ("ms", C.c_double), ("ms_default", C.c_double), ("key", C.c_char * 96)]
 
 
 class SidmCenter(C.Structure):
@@ -128,6 +139,9 @@ def lib():
         L.sidm_last_events.argtypes = [vp, vp, i64, C.POINTER(i64), vp]
         L.sidm_take_status.argtypes = [vp, C.POINTER(i32)]
         L.sidm_gravity_static.argtypes = [hp, sp, C.c_int, vp]
+        L.sidm_set_launch_shape.argtypes = [vp, i32, i32, i32]
+        L.sidm_autotune.argtypes = [vp, hp, i32, sp, C.c_int, C.c_char_p, i32,
+                                    C.POINTER(SidmTuneResult), vp]
         for name in EXPORTED:
             if name not in ("sidm_destroy", "sidm_status_string", "sidm_last_error"):
                 getattr(L, name).restype = C.c_int
@@ -250,6 +264,28 @@ def sidm_gravity_static(halo, state, prec=SIDM_PREC_MIXED, stream=None):
     H = make_halos([halo])
     S = make_state(state)
     _check(None, lib().sidm_gravity_static(H, C.byref(S), int(prec), _stream(stream)))
+
+
+def sidm_set_launch_shape(ctx, ireg, threads, persistent=False):
+    """Launch shape of the direct-sum gravity tiles (see SHAPES)."""
+    _check(ctx, lib().sidm_set_launch_shape(ctx.handle, int(ireg), int(threads),
+                                            1 if persistent else 0))
+
+
+def sidm_autotune(ctx, halos, state, prec=SIDM_PREC_MIXED, cache_path=None, flags=0,
+                  stream=None):
+    """Chooses the launch shape for these halos (from the cache or by timing
+    every shape), leaves it on the context and computes the gravity with it.
+    Returns the result as a dict."""
+    H = make_halos(halos)
+    S = make_state(state)
+    res = SidmTuneResult()
+    path = None if cache_path is None else os.fsencode(cache_path)
+    _check(ctx, lib().sidm_autotune(ctx.handle, H, len(halos), C.byref(S), int(prec), path,
+                                    int(flags), C.byref(res), _stream(stream)))
+    out = {f: getattr(res, f) for f, _ in SidmTuneResult._fields_ if f != "reserved"}
+    out["key"] = res.key.decode()
+    return out
 
 
 def sidm_knn_h(ctx, halos, state, nbr=None, stream=None):

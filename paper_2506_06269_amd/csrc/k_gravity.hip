@@ -127,7 +127,7 @@ __global__ __launch_bounds__(kStreamBlock) void k_pack_frames(
 // masses of the halo equal) the mass is factored out of the sums and applied
 // once per partial row: one multiply fewer per interaction.  DIAG tiles hold
 // some of the block's own i and skip j == i exactly.
-template <int IREG, bool EQM, bool DIAG>
+template <int IREG, int NT, bool EQM, bool DIAG>
 __device__ inline void tile_f32(const float4* __restrict__ tile, int ja, int jb, const float* xi,
                                 const float* yi, const float* zi, float eps2, int64_t j0, int64_t i0,
                                 int t, float* px, float* py, float* pz, float* pp)
@@ -142,7 +142,7 @@ __device__ inline void tile_f32(const float4* __restrict__ tile, int ja, int jb,
             const float dz = q.z - zi[r];
             const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
             float rinv = __builtin_amdgcn_rsqf(r2);
-            if (DIAG && j0 + jj == i0 + (int64_t)r * kGravThreads + t) rinv = 0.f;
+            if (DIAG && j0 + jj == i0 + (int64_t)r * NT + t) rinv = 0.f;
             if (EQM) {
                 const float rinv3 = rinv * (rinv * rinv);
                 px[r] = fmaf(rinv3, dx, px[r]);
@@ -161,7 +161,7 @@ __device__ inline void tile_f32(const float4* __restrict__ tile, int ja, int jb,
     }
 }
 
-template <int IREG, bool EQM>
+template <int IREG, int NT, bool EQM>
 __device__ inline void grav_mixed_body(const float4* __restrict__ xm32,
                                        const SubRange* __restrict__ sub,
                                        const int* __restrict__ sub_n, const GravItem& it,
@@ -178,7 +178,7 @@ __device__ inline void grav_mixed_body(const float4* __restrict__ xm32,
     float cx[IREG], cy[IREG], cz[IREG], cp[IREG];     // Kahan compensations
 #pragma unroll
     for (int r = 0; r < IREG; ++r) {
-        const int64_t li = il0 + (int64_t)r * kGravThreads + t;
+        const int64_t li = il0 + (int64_t)r * NT + t;
         float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
         cix[r] = ciy[r] = ciz[r] = 0.0;
         if (li < H.n) {
@@ -192,7 +192,7 @@ __device__ inline void grav_mixed_body(const float4* __restrict__ xm32,
         cx[r] = cy[r] = cz[r] = cp[r] = 0.f;
     }
     const int64_t last_bucket = H.level_off[0] + H.level_n[0] - 1;
-    for (int64_t j0 = it.j0; j0 < it.j1; j0 += kGravTileJ) {
+    for (int64_t j0 = it.j0; j0 < it.j1; j0 += NT) {
         const int64_t lj0 = j0 - H.offset;
         float4 pj = make_float4(0.f, 0.f, 0.f, 0.f);
         if (j0 + t < it.j1) pj = xm32[H.sbase + lj0 + t];
@@ -202,10 +202,10 @@ __device__ inline void grav_mixed_body(const float4* __restrict__ xm32,
         float px[IREG], py[IREG], pz[IREG], pp[IREG];
 #pragma unroll
         for (int r = 0; r < IREG; ++r) px[r] = py[r] = pz[r] = pp[r] = 0.f;
-        const bool diag = j0 < it.i0 + (int64_t)IREG * kGravThreads && j0 + kGravTileJ > it.i0;
+        const bool diag = j0 < it.i0 + (int64_t)IREG * NT && j0 + NT > it.i0;
         // the tile's buckets and their compact sub-ranges are the frames
         const int64_t b0 = H.level_off[0] + lj0 / kBucket;
-        for (int64_t b = b0; b < b0 + kGravTileJ / kBucket && b <= last_bucket; ++b) {
+        for (int64_t b = b0; b < b0 + NT / kBucket && b <= last_bucket; ++b) {
             const int ns = sub_n[b];
             const int base = (int)((b - b0) * kBucket);
             for (int f = 0; f < ns; ++f) {
@@ -223,10 +223,10 @@ __device__ inline void grav_mixed_body(const float4* __restrict__ xm32,
                 }
                 const int ja = base + R.off, jb = base + R.off + R.cnt;
                 if (diag)
-                    tile_f32<IREG, EQM, true>(tile, ja, jb, qx, qy, qz, eps2, j0, it.i0, t, px, py,
+                    tile_f32<IREG, NT, EQM, true>(tile, ja, jb, qx, qy, qz, eps2, j0, it.i0, t, px, py,
                                               pz, pp);
                 else
-                    tile_f32<IREG, EQM, false>(tile, ja, jb, qx, qy, qz, eps2, j0, it.i0, t, px,
+                    tile_f32<IREG, NT, EQM, false>(tile, ja, jb, qx, qy, qz, eps2, j0, it.i0, t, px,
                                                py, pz, pp);
             }
         }
@@ -241,7 +241,7 @@ __device__ inline void grav_mixed_body(const float4* __restrict__ xm32,
     }
 #pragma unroll
     for (int r = 0; r < IREG; ++r) {
-        const int64_t li = il0 + (int64_t)r * kGravThreads + t;
+        const int64_t li = il0 + (int64_t)r * NT + t;
         if (li >= H.n) continue;
         const int64_t row = pbase + (int64_t)it.slot * H.n + li;
         // the compensation holds the negated lost low part
@@ -254,7 +254,7 @@ __device__ inline void grav_mixed_body(const float4* __restrict__ xm32,
 
 // Block time steps: whether any i-particle of the item is active at this tick
 // (tick 0: not a cycle, every item runs).  Uniform over the block.
-template <int IREG>
+template <int IREG, int NT>
 __device__ inline bool item_active(const GravItem& it, const HaloDev& H,
                                    const int8_t* __restrict__ bin,
                                    const uint32_t* __restrict__ perm, int tick, int bmax)
@@ -266,45 +266,63 @@ __device__ inline bool item_active(const GravItem& it, const HaloDev& H,
         const int64_t il0 = it.i0 - H.offset;
 #pragma unroll
         for (int r = 0; r < IREG; ++r) {
-            const int64_t li = il0 + (int64_t)r * kGravThreads + threadIdx.x;
+            const int64_t li = il0 + (int64_t)r * NT + threadIdx.x;
             if (li < H.n && bin_active(H, bin[perm[H.sbase + li]], kl)) any = 1;
         }
     }
     return __syncthreads_or(any) != 0;
 }
 
-template <int IREG>
-__global__ __launch_bounds__(kGravThreads) void k_grav_mixed(
+// Work items in a plain launch take item blockIdx.x; a persistent launch
+// (PERSIST) runs as many blocks as the device holds at once, and each takes
+// items from a ticket counter until none is left (every block leaves the loop
+// when the counter passes n_items; no block waits on another).
+template <int IREG, int NT, bool PERSIST>
+__global__ __launch_bounds__(NT) void k_grav_mixed(
     const float4* __restrict__ xm32, const SubRange* __restrict__ sub,
-    const int* __restrict__ sub_n, const GravItem* __restrict__ items,
-    const HaloDev* __restrict__ halos,
+    const int* __restrict__ sub_n, const GravItem* __restrict__ items, int64_t n_items,
+    unsigned long long* __restrict__ ticket, const HaloDev* __restrict__ halos,
     const double* __restrict__ cmass, double4* __restrict__ partial,
     const int8_t* __restrict__ bin, const uint32_t* __restrict__ perm, int tick, int bmax,
     int tick_rows)
 {
-    __shared__ float4 tile[kGravTileJ];
-    const GravItem it = items[blockIdx.x];
-    const HaloDev& H = halos[it.halo];
-    if (!item_active<IREG>(it, H, bin, perm, tick, bmax)) return;
-    // the items of a block-step tick (tick_rows) write their own partial rows
-    const int64_t pbase = tick_rows ? H.tick_part_base : H.part_base;
-    const double meq = cmass[it.halo];
-    if (meq > 0.0)
-        grav_mixed_body<IREG, true>(xm32, sub, sub_n, it, H, meq, partial, tile,
-                                    pbase);
-    else
-        grav_mixed_body<IREG, false>(xm32, sub, sub_n, it, H, 1.0, partial, tile, pbase);
+    __shared__ float4 tile[NT];
+    __shared__ int64_t next;
+    int64_t k = blockIdx.x;
+    for (;;) {
+        if (PERSIST) {
+            __syncthreads();   // every thread has read the previous `next`
+            if (threadIdx.x == 0) next = (int64_t)atomicAdd(ticket, 1ull);
+            __syncthreads();
+            k = next;
+            if (k >= n_items) return;
+        }
+        const GravItem it = items[k];
+        const HaloDev& H = halos[it.halo];
+        if (item_active<IREG, NT>(it, H, bin, perm, tick, bmax)) {
+            // the items of a block-step tick (tick_rows) write their own partial rows
+            const int64_t pbase = tick_rows ? H.tick_part_base : H.part_base;
+            const double meq = cmass[it.halo];
+            if (meq > 0.0)
+                grav_mixed_body<IREG, NT, true>(xm32, sub, sub_n, it, H, meq, partial, tile,
+                                                pbase);
+            else
+                grav_mixed_body<IREG, NT, false>(xm32, sub, sub_n, it, H, 1.0, partial, tile,
+                                                 pbase);
+        }
+        if (!PERSIST) return;
+    }
 }
 
 // ---------------------------------------------------------------- FP64 tiles
 // Pair terms of one LDS tile for IREG i-particles in FP64 (see tile_f32).
-template <int IREG, bool EQM, bool DIAG>
+template <int IREG, int NT, bool EQM, bool DIAG>
 __device__ inline void tile_f64(const double4* __restrict__ tile, const double* xi,
                                 const double* yi, const double* zi, double eps2, int64_t j0,
                                 int64_t i0, int t, double* px, double* py, double* pz, double* pp)
 {
 #pragma unroll 2
-    for (int jj = 0; jj < kGravTileJ; ++jj) {
+    for (int jj = 0; jj < NT; ++jj) {
         const double4 q = tile[jj];
 #pragma unroll
         for (int r = 0; r < IREG; ++r) {
@@ -313,7 +331,7 @@ __device__ inline void tile_f64(const double4* __restrict__ tile, const double* 
             const double dz = q.z - zi[r];
             const double r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
             double rinv = rsqrt_pos(r2);
-            if (DIAG && j0 + jj == i0 + (int64_t)r * kGravThreads + t) rinv = 0.0;
+            if (DIAG && j0 + jj == i0 + (int64_t)r * NT + t) rinv = 0.0;
             if (EQM) {
                 const double rinv3 = rinv * (rinv * rinv);
                 px[r] = fma(rinv3, dx, px[r]);
@@ -332,7 +350,7 @@ __device__ inline void tile_f64(const double4* __restrict__ tile, const double* 
     }
 }
 
-template <int IREG, bool EQM>
+template <int IREG, int NT, bool EQM>
 __device__ inline void grav_fp64_body(const double* __restrict__ x, const double* __restrict__ y,
                                       const double* __restrict__ z, const double* __restrict__ m,
                                       const GravItem& it, const HaloDev& H, double mscale,
@@ -347,7 +365,7 @@ __device__ inline void grav_fp64_body(const double* __restrict__ x, const double
     double cx[IREG], cy[IREG], cz[IREG], cp[IREG];
 #pragma unroll
     for (int r = 0; r < IREG; ++r) {
-        const int64_t li = il0 + (int64_t)r * kGravThreads + t;
+        const int64_t li = il0 + (int64_t)r * NT + t;
         xi[r] = yi[r] = zi[r] = 0.0;
         if (li < H.n) {
             const int64_t p = H.sbase + li;
@@ -356,7 +374,7 @@ __device__ inline void grav_fp64_body(const double* __restrict__ x, const double
         sx[r] = sy[r] = sz[r] = sp[r] = 0.0;
         cx[r] = cy[r] = cz[r] = cp[r] = 0.0;
     }
-    for (int64_t j0 = it.j0; j0 < it.j1; j0 += kGravTileJ) {
+    for (int64_t j0 = it.j0; j0 < it.j1; j0 += NT) {
         // padding: r2 ~ 1e300 stays finite, r^-3 underflows to 0 and r^-1 ~ 1e-150
         // cannot change a potential sum
         double4 pj = make_double4(1.0e150, 1.0e150, 1.0e150, 0.0);
@@ -370,11 +388,11 @@ __device__ inline void grav_fp64_body(const double* __restrict__ x, const double
         double px[IREG], py[IREG], pz[IREG], pp[IREG];
 #pragma unroll
         for (int r = 0; r < IREG; ++r) px[r] = py[r] = pz[r] = pp[r] = 0.0;
-        const bool diag = j0 < it.i0 + (int64_t)IREG * kGravThreads && j0 + kGravTileJ > it.i0;
+        const bool diag = j0 < it.i0 + (int64_t)IREG * NT && j0 + NT > it.i0;
         if (diag)
-            tile_f64<IREG, EQM, true>(tile, xi, yi, zi, eps2, j0, it.i0, t, px, py, pz, pp);
+            tile_f64<IREG, NT, EQM, true>(tile, xi, yi, zi, eps2, j0, it.i0, t, px, py, pz, pp);
         else
-            tile_f64<IREG, EQM, false>(tile, xi, yi, zi, eps2, j0, it.i0, t, px, py, pz, pp);
+            tile_f64<IREG, NT, EQM, false>(tile, xi, yi, zi, eps2, j0, it.i0, t, px, py, pz, pp);
 #pragma unroll
         for (int r = 0; r < IREG; ++r) {
             double yk, tk;
@@ -386,7 +404,7 @@ __device__ inline void grav_fp64_body(const double* __restrict__ x, const double
     }
 #pragma unroll
     for (int r = 0; r < IREG; ++r) {
-        const int64_t li = il0 + (int64_t)r * kGravThreads + t;
+        const int64_t li = il0 + (int64_t)r * NT + t;
         if (li >= H.n) continue;
         const int64_t row = pbase + (int64_t)it.slot * H.n + li;
         partial[row] = make_double4(mscale * (sx[r] - cx[r]), mscale * (sy[r] - cy[r]),
@@ -394,25 +412,38 @@ __device__ inline void grav_fp64_body(const double* __restrict__ x, const double
     }
 }
 
-template <int IREG>
-__global__ __launch_bounds__(kGravThreads) void k_grav_fp64(
+template <int IREG, int NT, bool PERSIST>
+__global__ __launch_bounds__(NT) void k_grav_fp64(
     const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
-    const double* __restrict__ m, const GravItem* __restrict__ items,
-    const HaloDev* __restrict__ halos, const double* __restrict__ cmass,
-    double4* __restrict__ partial, const int8_t* __restrict__ bin,
-    const uint32_t* __restrict__ perm, int tick, int bmax, int tick_rows)
+    const double* __restrict__ m, const GravItem* __restrict__ items, int64_t n_items,
+    unsigned long long* __restrict__ ticket, const HaloDev* __restrict__ halos,
+    const double* __restrict__ cmass, double4* __restrict__ partial,
+    const int8_t* __restrict__ bin, const uint32_t* __restrict__ perm, int tick, int bmax,
+    int tick_rows)
 {
-    __shared__ double4 tile[kGravTileJ];
-    const GravItem it = items[blockIdx.x];
-    const HaloDev& H = halos[it.halo];
-    if (!item_active<IREG>(it, H, bin, perm, tick, bmax)) return;
-    // the items of a block-step tick (tick_rows) write their own partial rows
-    const int64_t pbase = tick_rows ? H.tick_part_base : H.part_base;
-    const double meq = cmass[it.halo];
-    if (meq > 0.0)
-        grav_fp64_body<IREG, true>(x, y, z, m, it, H, meq, partial, tile, pbase);
-    else
-        grav_fp64_body<IREG, false>(x, y, z, m, it, H, 1.0, partial, tile, pbase);
+    __shared__ double4 tile[NT];
+    __shared__ int64_t next;
+    int64_t k = blockIdx.x;
+    for (;;) {
+        if (PERSIST) {
+            __syncthreads();
+            if (threadIdx.x == 0) next = (int64_t)atomicAdd(ticket, 1ull);
+            __syncthreads();
+            k = next;
+            if (k >= n_items) return;
+        }
+        const GravItem it = items[k];
+        const HaloDev& H = halos[it.halo];
+        if (item_active<IREG, NT>(it, H, bin, perm, tick, bmax)) {
+            const int64_t pbase = tick_rows ? H.tick_part_base : H.part_base;
+            const double meq = cmass[it.halo];
+            if (meq > 0.0)
+                grav_fp64_body<IREG, NT, true>(x, y, z, m, it, H, meq, partial, tile, pbase);
+            else
+                grav_fp64_body<IREG, NT, false>(x, y, z, m, it, H, 1.0, partial, tile, pbase);
+        }
+        if (!PERSIST) return;
+    }
 }
 
 // ---------------------------------------------------------------- host + finalize
@@ -486,17 +517,46 @@ __global__ __launch_bounds__(kStreamBlock) void k_grav_finalize(
 }
 
 // ---------------------------------------------------------------- launchers
-// Blocks of the mixed-precision tiles that the device holds at once (compute
-// units times resident blocks per unit), or 0 if unknown.
-int64_t gravity_slots(int device)
+// The kernel instantiation of a launch shape: f(kernel pointer, threads) for
+// the mixed (MIXED) or the FP64 tiles of shape (ireg, nt), plain or
+// persistent.  False for a shape without an instantiation.
+template <bool MIXED, bool PERSIST, class F>
+static bool with_shape(int ireg, int nt, F f)
+{
+#define SIDM_SHAPE(I, T)                                                                      \
+    if (ireg == I && nt == T) {                                                               \
+        if constexpr (MIXED) f(k_grav_mixed<I, T, PERSIST>, T);                               \
+        else f(k_grav_fp64<I, T, PERSIST>, T);                                                \
+        return true;                                                                          \
+    }
+    SIDM_SHAPE(2, 128) SIDM_SHAPE(4, 128) SIDM_SHAPE(8, 128)
+    SIDM_SHAPE(2, 256) SIDM_SHAPE(4, 256) SIDM_SHAPE(8, 256)
+    SIDM_SHAPE(2, 512) SIDM_SHAPE(4, 512) SIDM_SHAPE(8, 512)
+#undef SIDM_SHAPE
+    return false;
+}
+
+// Blocks of the tiles of a launch shape that the device holds at once
+// (compute units times resident blocks per unit), or 0 if unknown.
+int64_t gravity_slots(int device, const GravShape& shape, bool mixed)
 {
     int cus = 0, per_cu = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
         return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_grav_mixed<4>, kGravThreads, 0) !=
-        hipSuccess)
-        return 0;
-    return (int64_t)cus * per_cu;
+    hipError_t e = hipErrorInvalidValue;
+    auto query = [&](auto kern, int threads) {
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, 0);
+    };
+    if (mixed) with_shape<true, true>(shape.ireg, shape.nt, query);
+    else with_shape<false, true>(shape.ireg, shape.nt, query);
+    return e == hipSuccess ? (int64_t)cus * per_cu : 0;
+}
+
+int64_t gravity_slots(int device) { return gravity_slots(device, GravShape{}, true); }
+
+__global__ void k_ticket_reset(DevCounters* __restrict__ c)
+{
+    if (threadIdx.x == 0) c->ticket = 0ull;
 }
 
 // The common mass of each halo (w.cref) and the unequal-mass flag of the
@@ -540,19 +600,37 @@ hipError_t launch_gravity(bool mixed, const Plan& P, Scratch& w, const sidm_stat
     double4* rows = tk ? w.partial_tick : w.partial;
     if (n_items == 0) {
         // no direct-sum halo
-    } else if (mixed) {
-        hipLaunchKernelGGL(k_pack_frames, dim3(nb), dim3(kStreamBlock), 0, st, w.sx, w.sy, w.sz,
-                           w.sm, w.blocks, w.halos, w.sub, w.sub_n, w.xm32);
-        if (tile_begin) (void)hipEventRecord(tile_begin, st);
-        hipLaunchKernelGGL((k_grav_mixed<4>), dim3((unsigned)n_items), dim3(kGravThreads), 0,
-                           st, w.xm32, w.sub, w.sub_n, items, w.halos, w.cref, rows, w.bin,
-                           w.perm, tick, bmax, tk ? 1 : 0);
-        if (tile_end) (void)hipEventRecord(tile_end, st);
     } else {
+        // ticks of block steps use the default shape their items were cut for
+        const GravShape shape = tk ? GravShape{} : P.shape;
+        const bool persist = shape.persist != 0;
+        const int64_t slots = persist ? (mixed ? w.slots_mixed : w.slots_fp64) : 0;
+        if (persist && slots <= 0) return hipErrorInvalidValue;
+        const unsigned grid = (unsigned)(persist ? std::min<int64_t>(slots, n_items) : n_items);
+        if (mixed)
+            hipLaunchKernelGGL(k_pack_frames, dim3(nb), dim3(kStreamBlock), 0, st, w.sx, w.sy,
+                               w.sz, w.sm, w.blocks, w.halos, w.sub, w.sub_n, w.xm32);
+        if (persist) hipLaunchKernelGGL(k_ticket_reset, dim3(1), dim3(64), 0, st, w.counters);
         if (tile_begin) (void)hipEventRecord(tile_begin, st);
-        hipLaunchKernelGGL((k_grav_fp64<4>), dim3((unsigned)n_items), dim3(kGravThreads), 0, st,
-                           w.sx, w.sy, w.sz, w.sm, items, w.halos, w.cref, rows, w.bin,
-                           w.perm, tick, bmax, tk ? 1 : 0);
+        unsigned long long* ticket = &w.counters->ticket;
+        auto launch_mixed = [&](auto kern, int threads) {
+            hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), 0, st, w.xm32, w.sub, w.sub_n,
+                               items, n_items, ticket, w.halos, w.cref, rows, w.bin, w.perm,
+                               tick, bmax, tk ? 1 : 0);
+        };
+        auto launch_fp64 = [&](auto kern, int threads) {
+            hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), 0, st, w.sx, w.sy, w.sz, w.sm,
+                               items, n_items, ticket, w.halos, w.cref, rows, w.bin, w.perm,
+                               tick, bmax, tk ? 1 : 0);
+        };
+        bool ok;
+        if (mixed)
+            ok = persist ? with_shape<true, true>(shape.ireg, shape.nt, launch_mixed)
+                         : with_shape<true, false>(shape.ireg, shape.nt, launch_mixed);
+        else
+            ok = persist ? with_shape<false, true>(shape.ireg, shape.nt, launch_fp64)
+                         : with_shape<false, false>(shape.ireg, shape.nt, launch_fp64);
+        if (!ok) return hipErrorInvalidValue;
         if (tile_end) (void)hipEventRecord(tile_end, st);
     }
     hipLaunchKernelGGL(k_grav_finalize, dim3(nb), dim3(kStreamBlock), 0, st, w.blocks, w.halos,

@@ -7,7 +7,9 @@
 // to one root, each node with its particles' bounding box.  This pass adds the
 // mass and first moments of every node (bucket sums in particle order, then
 // child sums in child order, no fused multiply-adds, so the centres of mass
-// are reproducible to the bit).
+// are reproducible to the bit), and the second moments about each node's
+// centre of mass (a bucket's from its particles, a node's from its children
+// by parallel axes).
 //
 // A group is a bucket: one wave of 64 lanes, one member per lane, walks the
 // tree once for all members.  A node is accepted when its box and the group's
@@ -16,12 +18,14 @@
 // members and r the distance between the two boxes: the paper's criterion
 // G M l^2 <= alpha |a_old| r^4, squared (no square root in the decision) and
 // made to hold for every member and every particle of the node.  An accepted
-// node contributes its monopole; an opened bucket its particles.  Sources are
-// staged in an LDS list (the children of a popped node are tested by lanes
-// 0..7 at once, accepted ones appended by a ballot prefix); a full list is
-// summed by all lanes, each for its own member, with the self pair skipped in
-// the group's own bucket, and the list sums are folded into compensated
-// accumulators.  The result is one partial row per particle, finished by the
+// node contributes its monopole and quadrupole (the second-order term of the
+// softened potential about its centre of mass, from its second moments); an
+// opened bucket contributes its particles.  Sources are staged in two LDS
+// lists, particles and accepted nodes (the children of a popped node are
+// tested by lanes 0..7 at once, accepted ones appended by a ballot prefix);
+// full lists are summed by all lanes, each for its own member, with the self
+// pair skipped in the group's own bucket, and the list sums are folded into
+// compensated accumulators.  The result is one partial row per particle, finished by the
 // gravity finalize pass (G, host, kicks).
 //
 // FP64 form: positions and arithmetic in FP64.  Mixed form: the list holds
@@ -37,6 +41,14 @@
 namespace sidm {
 
 constexpr int kTreeList = 128;                    // source list entries per group
+constexpr int kTreeNodes = 64;                    // accepted-node list entries per group
+
+// An accepted node: centre of mass, mass and second moments about the centre
+// (xx, yy, zz, xy, xz, yz).
+struct NodeEntry {
+    double x, y, z, m;
+    double S[6];
+};
 // Popping kFanout nodes per round and pushing at most kFanout^2 children, the
 // stack holds at most (kFanout^2 - kFanout) nodes per level plus one round's
 // pushes: 56 * kMaxLevels + 64 = 624 for ten levels.
@@ -46,7 +58,7 @@ constexpr int kTreeStack = (kFanout * kFanout - kFanout) * kMaxLevels + kFanout 
 __global__ __launch_bounds__(256) void k_tree_mom_bucket(
     const BucketInfo* __restrict__ buckets, int64_t nb, const double* __restrict__ sx,
     const double* __restrict__ sy, const double* __restrict__ sz, const double* __restrict__ sm,
-    double4* __restrict__ mom)
+    double4* __restrict__ mom, double* __restrict__ mom2)
 {
 #pragma clang fp contract(off)
     const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -62,10 +74,27 @@ __global__ __launch_bounds__(256) void k_tree_mom_bucket(
         Z += m * sz[p];
     }
     mom[b] = make_double4(M, X, Y, Z);
+    double S[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (M != 0.0) {
+        const double cx = X / M, cy = Y / M, cz = Z / M;
+        for (int q = 0; q < B.count; ++q) {
+            const int64_t p = B.start + q;
+            const double m = sm[p];
+            const double u = sx[p] - cx, v = sy[p] - cy, w = sz[p] - cz;
+            S[0] += m * u * u;
+            S[1] += m * v * v;
+            S[2] += m * w * w;
+            S[3] += m * u * v;
+            S[4] += m * u * w;
+            S[5] += m * v * w;
+        }
+    }
+    for (int k = 0; k < 6; ++k) mom2[6 * b + k] = S[k];
 }
 
 __global__ __launch_bounds__(256) void k_tree_mom_node(const NodeTask* __restrict__ tasks,
-                                                       int64_t nt, double4* __restrict__ mom)
+                                                       int64_t nt, double4* __restrict__ mom,
+                                                       double* __restrict__ mom2)
 {
 #pragma clang fp contract(off)
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -80,6 +109,24 @@ __global__ __launch_bounds__(256) void k_tree_mom_node(const NodeTask* __restric
         Z += q.w;
     }
     mom[T.node] = make_double4(M, X, Y, Z);
+    double S[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (M != 0.0) {
+        const double cx = X / M, cy = Y / M, cz = Z / M;
+        for (int c = 0; c < T.nchild; ++c) {
+            const int64_t ch = T.child0 + c;
+            const double4 q = mom[ch];
+            if (q.x == 0.0) continue;
+            const double u = q.y / q.x - cx, v = q.z / q.x - cy, w = q.w / q.x - cz;
+            const double* Sc = mom2 + 6 * ch;
+            S[0] += Sc[0] + q.x * u * u;
+            S[1] += Sc[1] + q.x * v * v;
+            S[2] += Sc[2] + q.x * w * w;
+            S[3] += Sc[3] + q.x * u * v;
+            S[4] += Sc[4] + q.x * u * w;
+            S[5] += Sc[5] + q.x * v * w;
+        }
+    }
+    for (int k = 0; k < 6; ++k) mom2[6 * T.node + k] = S[k];
 }
 
 // Zeroes the per-halo count of source terms.
@@ -178,6 +225,40 @@ struct TreeAcc<false> {
         y = p[2] - cz; t = sz + y; cz = (t - sz) - y; sz = t;
         y = p[3] - cp; t = sp + y; cp = (t - sp) - y; sp = t;
     }
+    // Accepted nodes: monopole plus quadrupole.  With d from the node's centre
+    // of mass to the member, rho^2 = |d|^2 + eps^2, S the second moments and T
+    // their trace, the second-order term of -G sum m / sqrt(|d - s|^2 + eps^2)
+    // is phi_Q = -G (3 d.S.d - rho^2 T) / (2 rho^5); a_Q = -grad phi_Q.
+    __device__ inline void sum_nodes(const NodeEntry* L, int len)
+    {
+        double p[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int jj = 0; jj < len; ++jj) {
+            const NodeEntry& q = L[jj];
+            const double dx = q.x - xi, dy = q.y - yi, dz = q.z - zi;
+            const double r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
+            const double rinv = rsqrt_pos(r2);
+            const double mr = q.m * rinv;
+            const double ri2 = rinv * rinv;
+            const double mr3 = mr * ri2;
+            const double ri5 = rinv * ri2 * ri2, ri7 = ri5 * ri2;
+            const double d0 = -dx, d1 = -dy, d2 = -dz;
+            const double Sd0 = fma(q.S[0], d0, fma(q.S[3], d1, q.S[4] * d2));
+            const double Sd1 = fma(q.S[3], d0, fma(q.S[1], d1, q.S[5] * d2));
+            const double Sd2 = fma(q.S[4], d0, fma(q.S[5], d1, q.S[2] * d2));
+            const double T = q.S[0] + q.S[1] + q.S[2];
+            const double br = 3.0 * fma(d0, Sd0, fma(d1, Sd1, d2 * Sd2)) - r2 * T;
+            const double c5 = 2.5 * br * ri7;
+            p[0] += fma(mr3, dx, (3.0 * Sd0 - T * d0) * ri5 - c5 * d0);
+            p[1] += fma(mr3, dy, (3.0 * Sd1 - T * d1) * ri5 - c5 * d1);
+            p[2] += fma(mr3, dz, (3.0 * Sd2 - T * d2) * ri5 - c5 * d2);
+            p[3] += mr + 0.5 * br * ri5;
+        }
+        double y, t;
+        y = p[0] - cx; t = sx + y; cx = (t - sx) - y; sx = t;
+        y = p[1] - cy; t = sy + y; cy = (t - sy) - y; sy = t;
+        y = p[2] - cz; t = sz + y; cz = (t - sz) - y; sz = t;
+        y = p[3] - cp; t = sp + y; cp = (t - sp) - y; sp = t;
+    }
     __device__ inline double4 result() const
     {
         return make_double4(sx - cx, sy - cy, sz - cz, sp - cp);
@@ -225,6 +306,39 @@ struct TreeAcc<true> {
         y = p[2] - cz; t = sz + y; cz = (t - sz) - y; sz = t;
         y = p[3] - cp; t = sp + y; cp = (t - sp) - y; sp = t;
     }
+    // Accepted nodes (see the FP64 form): separations from FP64, the rest FP32.
+    __device__ inline void sum_nodes(const NodeEntry* L, int len)
+    {
+        float p[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int jj = 0; jj < len; ++jj) {
+            const NodeEntry& q = L[jj];
+            const float dx = (float)(q.x - xi), dy = (float)(q.y - yi), dz = (float)(q.z - zi);
+            const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
+            const float rinv = __builtin_amdgcn_rsqf(r2);
+            const float mr = (float)q.m * rinv;
+            const float ri2 = rinv * rinv;
+            const float mr3 = mr * ri2;
+            const float ri5 = rinv * ri2 * ri2, ri7 = ri5 * ri2;
+            const float S0 = (float)q.S[0], S1 = (float)q.S[1], S2 = (float)q.S[2];
+            const float S3 = (float)q.S[3], S4 = (float)q.S[4], S5 = (float)q.S[5];
+            const float d0 = -dx, d1 = -dy, d2 = -dz;
+            const float Sd0 = fmaf(S0, d0, fmaf(S3, d1, S4 * d2));
+            const float Sd1 = fmaf(S3, d0, fmaf(S1, d1, S5 * d2));
+            const float Sd2 = fmaf(S4, d0, fmaf(S5, d1, S2 * d2));
+            const float T = S0 + S1 + S2;
+            const float br = 3.f * fmaf(d0, Sd0, fmaf(d1, Sd1, d2 * Sd2)) - r2 * T;
+            const float c5 = 2.5f * br * ri7;
+            p[0] += fmaf(mr3, dx, (3.f * Sd0 - T * d0) * ri5 - c5 * d0);
+            p[1] += fmaf(mr3, dy, (3.f * Sd1 - T * d1) * ri5 - c5 * d1);
+            p[2] += fmaf(mr3, dz, (3.f * Sd2 - T * d2) * ri5 - c5 * d2);
+            p[3] += mr + 0.5f * br * ri5;
+        }
+        float y, t;
+        y = p[0] - cx; t = sx + y; cx = (t - sx) - y; sx = t;
+        y = p[1] - cy; t = sy + y; cy = (t - sy) - y; sy = t;
+        y = p[2] - cz; t = sz + y; cz = (t - sz) - y; sz = t;
+        y = p[3] - cp; t = sp + y; cp = (t - sp) - y; sp = t;
+    }
     __device__ inline double4 result() const
     {
         return make_double4((double)sx - (double)cx, (double)sy - (double)cy,
@@ -240,7 +354,7 @@ template <bool MIXED>
 __global__ __launch_bounds__(64) void k_tree_walk(
     const BucketInfo* __restrict__ buckets, const NodeChild* __restrict__ nodes,
     const double* __restrict__ box, const double4* __restrict__ mom,
-    const HaloDev* __restrict__ halos, const double* __restrict__ sx,
+    const double* __restrict__ mom2, const HaloDev* __restrict__ halos, const double* __restrict__ sx,
     const double* __restrict__ sy, const double* __restrict__ sz, const double* __restrict__ sm,
     const uint32_t* __restrict__ perm, const double* __restrict__ ax_old,
     const double* __restrict__ ay_old, const double* __restrict__ az_old,
@@ -250,6 +364,7 @@ __global__ __launch_bounds__(64) void k_tree_walk(
     using Acc = TreeAcc<MIXED>;
     using Entry = typename Acc::Entry;
     __shared__ Entry list[kTreeList];
+    __shared__ NodeEntry nlist[kTreeNodes];
     // pending inner nodes as (first child, number of children)
     __shared__ int2 stack[kTreeStack];
 
@@ -286,14 +401,16 @@ __global__ __launch_bounds__(64) void k_tree_walk(
     }
 
     const int64_t root = H.level_off[H.n_levels - 1];
-    int sp = 0, len = 0, self_lo = -1, self_n = 0;
+    int sp = 0, len = 0, nlen = 0, self_lo = -1, self_n = 0;
     unsigned long long total = 0;
 
     auto flush = [&]() {
         __syncthreads();
         if (len > 0) acc.sum(list, len, self_lo, self_n, lane);
-        total += (unsigned long long)len;
+        if (nlen > 0) acc.sum_nodes(nlist, nlen);
+        total += (unsigned long long)(len + nlen);
         len = 0;
+        nlen = 0;
         self_lo = -1;
         __syncthreads();
     };
@@ -331,7 +448,7 @@ __global__ __launch_bounds__(64) void k_tree_walk(
         if (slot < npop) nd = stack[sp - 1 - slot];
         sp -= npop;
         bool take = false, open_inner = false, open_bucket = false, self = false;
-        Entry e{};
+        NodeEntry e{};
         int2 push = make_int2(0, 0);
         int64_t bstart = 0;
         int bcnt = 0;
@@ -344,7 +461,11 @@ __global__ __launch_bounds__(64) void k_tree_walk(
             if (tree_accept(cb, mm.x, gb, H.G, alpha2, a2min)) {
                 if (mm.x != 0.0) {
                     take = true;
-                    e = make_entry<MIXED>(mm.y / mm.x, mm.z / mm.x, mm.w / mm.x, mm.x);
+                    e.x = mm.y / mm.x;
+                    e.y = mm.z / mm.x;
+                    e.z = mm.w / mm.x;
+                    e.m = mm.x;
+                    for (int k = 0; k < 6; ++k) e.S[k] = mom2[6 * c + k];
                 }
             } else if (cc.nchild > 0) {
                 open_inner = true;
@@ -361,9 +482,9 @@ __global__ __launch_bounds__(64) void k_tree_walk(
         const unsigned long long below = (1ull << lane) - 1ull;
         const unsigned long long tm = __ballot(take);
         const int nt = __popcll(tm);
-        if (len + nt > kTreeList) flush();
-        if (take) list[len + __popcll(tm & below)] = e;
-        len += nt;
+        if (nlen + nt > kTreeNodes) flush();
+        if (take) nlist[nlen + __popcll(tm & below)] = e;
+        nlen += nt;
         const unsigned long long om = __ballot(open_inner);
         if (open_inner) stack[sp + __popcll(om & below)] = push;
         sp += __popcll(om);
@@ -392,21 +513,23 @@ hipError_t launch_tree_gravity(bool mixed, const Plan& P, Scratch& w, const sidm
                                int tick, int bmax, hipStream_t st)
 {
     hipLaunchKernelGGL(k_tree_mom_bucket, dim3(grid_of(P.n_buckets, 256)), dim3(256), 0, st,
-                       w.buckets, P.n_buckets, w.sx, w.sy, w.sz, w.sm, w.mom);
+                       w.buckets, P.n_buckets, w.sx, w.sy, w.sz, w.sm, w.mom, w.mom2);
     for (int l = 1; l < P.n_levels; ++l) {
         const int64_t t0 = P.level_task_off[l - 1], nt = P.level_task_off[l] - t0;
         if (nt > 0)
             hipLaunchKernelGGL(k_tree_mom_node, dim3(grid_of(nt, 256)), dim3(256), 0, st,
-                               w.node_tasks + t0, nt, w.mom);
+                               w.node_tasks + t0, nt, w.mom, w.mom2);
     }
     if (mixed)
         hipLaunchKernelGGL(k_tree_walk<true>, dim3((unsigned)P.n_buckets), dim3(64), 0, st,
-                           w.buckets, w.nodes, w.box, w.mom, w.halos, w.sx, w.sy, w.sz, w.sm,
+                           w.buckets, w.nodes, w.box, w.mom, w.mom2, w.halos, w.sx, w.sy, w.sz,
+                           w.sm,
                            w.perm, s->ax, s->ay, s->az, w.bin, tick, bmax, w.partial,
                            w.tree_terms);
     else
         hipLaunchKernelGGL(k_tree_walk<false>, dim3((unsigned)P.n_buckets), dim3(64), 0, st,
-                           w.buckets, w.nodes, w.box, w.mom, w.halos, w.sx, w.sy, w.sz, w.sm,
+                           w.buckets, w.nodes, w.box, w.mom, w.mom2, w.halos, w.sx, w.sy, w.sz,
+                           w.sm,
                            w.perm, s->ax, s->ay, s->az, w.bin, tick, bmax, w.partial,
                            w.tree_terms);
     return hipGetLastError();

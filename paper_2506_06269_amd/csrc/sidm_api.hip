@@ -45,6 +45,7 @@ hipError_t launch_gravity(bool mixed, const Plan& P, Scratch& w, const sidm_stat
                           hipStream_t st, hipEvent_t tile_begin, hipEvent_t tile_end, int tick = 0,
                           int bmax = 0);
 int64_t gravity_slots(int device);
+int64_t gravity_slots(int device, const GravShape& shape, bool mixed);
 hipError_t launch_cell_list(const Plan& plan, const sidm_state* s, Scratch& w, hipStream_t st,
                             int tick = 0, int bmax = 0);
 hipError_t launch_knn(const Plan& plan, const sidm_state* s, Scratch& w, uint32_t* nbr, int k_max,
@@ -89,6 +90,7 @@ struct sidm_ctx {
     uint64_t scratch_gen = 1;
     uint64_t fp_eager = 0;
     bool fp_valid = false;
+    GravShape shape;                  // launch shape of the direct-sum tiles
 };
 
 namespace {
@@ -196,7 +198,10 @@ sidm_status ensure_plan(sidm_ctx* c, const sidm_halo* halos, int32_t n_halos, hi
     std::string why;
     const GravItem* items_tick = c->w.items_tick;
     const double4* partial_tick = c->w.partial_tick;
-    if (!build_plan(c->plan, c->w, halos, n_halos, why) || !ensure_tick_tables(c->w, c->plan, why)) {
+    c->w.slots_mixed = gravity_slots(c->device, c->shape, true);
+    c->w.slots_fp64 = gravity_slots(c->device, c->shape, false);
+    if (!build_plan(c->plan, c->w, halos, n_halos, c->shape, c->w.slots_mixed, why) ||
+        !ensure_tick_tables(c->w, c->plan, why)) {
         set_err(c, "%s", why.c_str());
         return SIDM_ERR_CAPACITY;
     }
@@ -735,6 +740,229 @@ sidm_status sidm_pass_times(sidm_ctx* c, double ms[SIDM_N_PASSES])
         ms[p] = t;
     }
     return SIDM_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- launch shapes
+namespace {
+
+bool shape_supported(int ireg, int nt)
+{
+    for (int k = 0; k < kNumShapes; ++k)
+        if (kShapeIreg[k] == ireg && kShapeNt[k] == nt) return true;
+    return false;
+}
+
+// Key of a tuning-cache entry: device architecture and compute units,
+// precision, and the call's direct-sum size class (log2 of the particles in
+// direct-sum halos, and of the number of halos, both rounded to nearest).
+std::string tune_key(int device, const sidm_halo* halos, int32_t n_halos, sidm_precision prec)
+{
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    int cus = 0;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+        arch = prop.gcnArchName;
+        const size_t colon = arch.find(':');
+        if (colon != std::string::npos) arch.resize(colon);
+        cus = prop.multiProcessorCount;
+    }
+    double ndir = 0.0;
+    int nh = 0;
+    for (int32_t h = 0; h < n_halos; ++h)
+        if (!(halos[h].tree_alpha > 0.0)) {
+            ndir += (double)halos[h].n;
+            ++nh;
+        }
+    const int ln = ndir > 0.0 ? (int)std::lround(std::log2(ndir)) : 0;
+    const int lh = nh > 0 ? (int)std::lround(std::log2((double)nh)) : 0;
+    char buf[160];
+    snprintf(buf, sizeof buf, "%s:%dcu:%s:n2^%d:h2^%d", arch.c_str(), cus,
+             prec == SIDM_PREC_MIXED ? "mixed" : "fp64", ln, lh);
+    return buf;
+}
+
+// The cache file: one JSON object, one entry per line,
+//   "key": {"ireg": I, "threads": T, "persistent": P, "ms": X, "ms_default": Y},
+// read back line by line (the file is only ever written by tune_write).
+bool tune_read(const char* path, const std::string& key, GravShape& shape)
+{
+    FILE* f = fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    const std::string want = "\"" + key + "\":";
+    bool found = false;
+    while (fgets(line, sizeof line, f)) {
+        const char* p = strstr(line, want.c_str());
+        if (!p) continue;
+        int ireg = 0, nt = 0, persist = 0;
+        if (sscanf(p + want.size(), " {\"ireg\": %d, \"threads\": %d, \"persistent\": %d", &ireg,
+                   &nt, &persist) == 3 && shape_supported(ireg, nt)) {
+            shape.ireg = ireg;
+            shape.nt = nt;
+            shape.persist = persist ? 1 : 0;
+            found = true;
+        }
+        break;
+    }
+    fclose(f);
+    return found;
+}
+
+bool tune_write(const char* path, const std::string& key, const GravShape& s, double ms,
+                double ms_default)
+{
+    std::vector<std::string> lines;
+    if (FILE* f = fopen(path, "r")) {
+        char line[512];
+        const std::string want = "\"" + key + "\":";
+        while (fgets(line, sizeof line, f)) {
+            std::string l(line);
+            while (!l.empty() && (l.back() == '\n' || l.back() == ',' || l.back() == ' '))
+                l.pop_back();
+            if (l.find("\": {\"ireg\"") == std::string::npos) continue;   // braces, junk
+            if (l.find(want) != std::string::npos) continue;              // replaced below
+            size_t a = l.find('"');
+            lines.push_back(a == std::string::npos ? l : l.substr(a));
+        }
+        fclose(f);
+    }
+    char buf[320];
+    snprintf(buf, sizeof buf,
+             "\"%s\": {\"ireg\": %d, \"threads\": %d, \"persistent\": %d, \"ms\": %.4f, "
+             "\"ms_default\": %.4f}",
+             key.c_str(), s.ireg, s.nt, s.persist, ms, ms_default);
+    lines.push_back(buf);
+    std::sort(lines.begin(), lines.end());
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = fopen(tmp.c_str(), "w");
+    if (!f) return false;
+    fputs("{\n", f);
+    for (size_t i = 0; i < lines.size(); ++i)
+        fprintf(f, "  %s%s\n", lines[i].c_str(), i + 1 < lines.size() ? "," : "");
+    fputs("}\n", f);
+    const bool ok = fclose(f) == 0;
+    return ok && rename(tmp.c_str(), path) == 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+sidm_status sidm_set_launch_shape(sidm_ctx* c, int32_t ireg, int32_t threads, int32_t persistent)
+{
+    if (!c) return SIDM_ERR_INVALID;
+    if (!shape_supported(ireg, threads)) {
+        set_err(c, "no gravity tiles of shape ireg=%d threads=%d", ireg, threads);
+        return SIDM_ERR_UNSUPPORTED;
+    }
+    DeviceGuard g(c->device);
+    GravShape s;
+    s.ireg = ireg;
+    s.nt = threads;
+    s.persist = persistent ? 1 : 0;
+    if (s.persist && gravity_slots(c->device, s, true) <= 0) {
+        set_err(c, "no resident blocks known for the persistent launch of this shape");
+        return SIDM_ERR_UNSUPPORTED;
+    }
+    if (s.ireg != c->shape.ireg || s.nt != c->shape.nt || s.persist != c->shape.persist) {
+        c->shape = s;
+        c->plan_valid = false;   // the work items follow the shape
+    }
+    c->err.clear();
+    return SIDM_OK;
+}
+
+sidm_status sidm_autotune(sidm_ctx* c, const sidm_halo* halos, int32_t n_halos,
+                          const sidm_state* s, sidm_precision prec, const char* cache_path,
+                          int32_t flags, sidm_tune_result* out, void* stream)
+{
+    sidm_status r = validate(c, halos, n_halos, s, NEED_GRAV);
+    if (r != SIDM_OK) return r;
+    if (prec != SIDM_PREC_FP64 && prec != SIDM_PREC_MIXED) {
+        set_err(c, "unknown precision %d", (int)prec);
+        return SIDM_ERR_INVALID;
+    }
+    DeviceGuard g(c->device);
+    hipStream_t st = (hipStream_t)stream;
+    if (capturing(st)) {
+        set_err(c, "the tuner times launches: not possible during stream capture");
+        return SIDM_ERR_INVALID;
+    }
+    const std::string key = tune_key(c->device, halos, n_halos, prec);
+    sidm_tune_result res;
+    std::memset(&res, 0, sizeof res);
+    snprintf(res.key, sizeof res.key, "%s", key.c_str());
+    GravShape best;
+    bool have = false;
+    if (cache_path && !(flags & SIDM_TUNE_FORCE)) have = tune_read(cache_path, key, best);
+    const GravShape saved = c->shape;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipSuccess;
+    if (!have) {
+        // time every shape on the caller's halos: the cell list once, then the
+        // gravity pass (all its kernels) per shape, the best of a few runs
+        if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess)
+            return hip_fail(c, e, "tuner events");
+        bool cap = false;
+        double best_ms = 1e300, default_ms = 0.0;
+        for (int k = 0; k < 2 * kNumShapes && e == hipSuccess; ++k) {
+            GravShape cand;
+            cand.ireg = kShapeIreg[k % kNumShapes];
+            cand.nt = kShapeNt[k % kNumShapes];
+            cand.persist = k >= kNumShapes ? 1 : 0;
+            if (gravity_slots(c->device, cand, prec == SIDM_PREC_MIXED) <= 0) continue;
+            c->shape = cand;
+            c->plan_valid = false;
+            if ((r = enter(c, halos, n_halos, s, st, cap)) != SIDM_OK) break;
+            e = launch_cell_list(c->plan, s, c->w, st);
+            double ms = 1e300;
+            const int runs = (flags & SIDM_TUNE_QUICK) ? 2 : 4;
+            for (int rep = 0; rep < runs && e == hipSuccess; ++rep) {
+                (void)hipEventRecord(e0, st);
+                e = launch_gravity(prec == SIDM_PREC_MIXED, c->plan, c->w, s, 0, st, nullptr,
+                                   nullptr);
+                (void)hipEventRecord(e1, st);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float t = 0.f;
+                if (e == hipSuccess && rep > 0 && hipEventElapsedTime(&t, e0, e1) == hipSuccess)
+                    ms = std::min(ms, (double)t);
+            }
+            if (cand.ireg == 4 && cand.nt == 256 && !cand.persist) default_ms = ms;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = cand;
+            }
+            ++res.n_tried;
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (r != SIDM_OK || e != hipSuccess) {
+            c->shape = saved;
+            c->plan_valid = false;
+            return r != SIDM_OK ? r : hip_fail(c, e, "tuner launch");
+        }
+        res.ms = best_ms;
+        res.ms_default = default_ms;
+        if (cache_path && !tune_write(cache_path, key, best, best_ms, default_ms)) {
+            set_err(c, "cannot write the tuning cache %s", cache_path);
+            c->shape = best;
+            c->plan_valid = false;
+            return SIDM_ERR_INVALID;
+        }
+    } else {
+        res.from_cache = 1;
+    }
+    // the chosen shape, and a and pot as sidm_gravity computes them with it
+    c->shape = best;
+    c->plan_valid = false;
+    res.ireg = best.ireg;
+    res.threads = best.nt;
+    res.persistent = best.persist;
+    if (out) *out = res;
+    c->err.clear();
+    return sidm_gravity(c, halos, n_halos, s, prec, stream);
 }
 
 }  // extern "C"

@@ -24,6 +24,21 @@ constexpr int kSortItems = 16;       // keys per thread per sort block
 constexpr int kSortBlock = 256;
 constexpr int kScanMaxSeg = 1024;   // blocks of the multi-block exclusive scan at most
 
+// Shape of the direct-sum gravity launch: i-particles per thread, threads per
+// block (also the j-particles of one LDS tile), and whether the blocks are
+// persistent (as many as the device holds, taking work items from a ticket).
+// A work item's i-block holds ireg * nt particles; j-ranges are cut at
+// multiples of nt.  The tuner chooses among kShapes.
+struct GravShape {
+    int32_t ireg = 4;
+    int32_t nt = 256;
+    int32_t persist = 0;
+    int32_t pad = 0;
+};
+constexpr int kNumShapes = 9;
+constexpr int kShapeIreg[kNumShapes] = {2, 4, 8, 2, 4, 8, 2, 4, 8};
+constexpr int kShapeNt[kNumShapes] = {128, 128, 128, 256, 256, 256, 512, 512, 512};
+
 // Per-halo parameters and derived layout, uploaded once per halo configuration.
 struct HaloDev {
     int64_t offset, n;
@@ -78,7 +93,7 @@ struct BucketInfo {
 // Device-side error bits live in a per-halo status word.
 struct DevCounters {
     unsigned long long n_events_total;    // events found (may exceed capacity)
-    unsigned long long ticket;            // persistent-kernel work counter
+    unsigned long long ticket;            // next work item of a persistent gravity launch
 };
 
 #ifdef __HIPCC__

@@ -79,6 +79,7 @@ struct Scratch {
     double4* partial_tick = nullptr;
     int64_t partial_tick_rows = 0;
     int64_t grav_slots = 0;       // resident blocks of the gravity tiles on the whole device
+    int64_t slots_mixed = 0, slots_fp64 = 0;   // of the plan's shape, per precision
     // cell list
     unsigned long long* keys[2] = {nullptr, nullptr};
     uint32_t* vals[2] = {nullptr, nullptr};
@@ -91,6 +92,7 @@ struct Scratch {
     double *sh = nullptr, *sm = nullptr;
     int8_t* bin = nullptr;        // block time-step bin per particle (caller's order)
     double4* mom = nullptr;       // per node: mass and first moments (tree gravity)
+    double* mom2 = nullptr;       // per node: 6 second moments about its centre of mass
     unsigned long long* tree_terms = nullptr;   // per halo: source terms of the tree walk
     uint32_t* sid = nullptr;
     uint32_t* perm = nullptr;
@@ -118,6 +120,7 @@ struct Plan {
     int rank_shift = 48;              // 49 when block steps order active particles first
     bool has_tree = false;            // some halo uses the tree walk
     bool any_scatter = false;         // some halo has sigma_m > 0
+    GravShape shape;                  // launch shape of the direct-sum tiles
     int halo_bits = 0;                // bits of a halo index
     int64_t sort_blocks = 0;
     std::vector<HaloDev> halos;
@@ -180,7 +183,7 @@ inline bool alloc_scratch(Scratch& w, int64_t N, int32_t H, int64_t max_events, 
               dalloc(w.hist, w.hist_cap) && dalloc(w.scan_part, kScanMaxSeg) && dalloc(w.sx, N) && dalloc(w.sy, N) &&
               dalloc(w.sz, N) && dalloc(w.sp4, N) && dalloc(w.svx, N) && dalloc(w.svy, N) && dalloc(w.svz, N) &&
               dalloc(w.sh, N) && dalloc(w.sm, N) && dalloc(w.bin, N) &&
-              dalloc(w.mom, w.nodes_cap) && dalloc(w.tree_terms, H) && dalloc(w.sid, N) && dalloc(w.perm, N) &&
+              dalloc(w.mom, w.nodes_cap) && dalloc(w.mom2, 6 * w.nodes_cap) && dalloc(w.tree_terms, H) && dalloc(w.sid, N) && dalloc(w.perm, N) &&
               dalloc(w.box, 6 * w.nodes_cap) && dalloc(w.hmax, w.nodes_cap) &&
               dalloc(w.sub, kSubMax * w.buckets_cap) && dalloc(w.sub_n, w.buckets_cap) &&
               dalloc(w.owner, N) && dalloc(w.counters, 1) && dalloc(w.ev_counts, 4 * H) &&
@@ -223,7 +226,7 @@ inline void free_scratch(Scratch& w)
     dfree(w.sx); dfree(w.sy); dfree(w.sz); dfree(w.sp4); dfree(w.svx); dfree(w.svy); dfree(w.svz);
     dfree(w.items_tick); dfree(w.partial_tick);
     w.items_tick_cap = w.partial_tick_rows = 0;
-    dfree(w.sh); dfree(w.sm); dfree(w.bin); dfree(w.mom); dfree(w.tree_terms); dfree(w.sid); dfree(w.perm); dfree(w.box); dfree(w.hmax);
+    dfree(w.sh); dfree(w.sm); dfree(w.bin); dfree(w.mom); dfree(w.mom2); dfree(w.tree_terms); dfree(w.sid); dfree(w.perm); dfree(w.box); dfree(w.hmax);
     dfree(w.sub); dfree(w.sub_n);
     dfree(w.owner); dfree(w.events); dfree(w.counters); dfree(w.ev_counts); dfree(w.status);
     dfree(w.sticky); dfree(w.fp_dev);
@@ -344,9 +347,10 @@ inline sidm_status check_halo(const sidm_halo& H, int need, char* msg, size_t ca
 // largest first on `slots` resident blocks; the split whose simulated
 // finishing time is smallest wins (ties go to fewer splits, which write fewer
 // partial rows).  Without an occupancy figure, enough items to fill the chip.
-inline void choose_splits(std::vector<HaloDev>& hd, int64_t partial_rows, int64_t slots)
+inline void choose_splits(std::vector<HaloDev>& hd, int64_t partial_rows, int64_t slots,
+                          const GravShape& shape)
 {
-    const int64_t kIBlock = kGravThreads * 4;
+    const int64_t kIBlock = (int64_t)shape.ireg * shape.nt, kGravTileJ = shape.nt;
     int64_t iblocks = 0, ntot = 0;
     for (auto& H : hd) {
         if (H.tree_alpha > 0.0) continue;
@@ -400,9 +404,10 @@ inline void choose_splits(std::vector<HaloDev>& hd, int64_t partial_rows, int64_
 }
 
 inline bool build_plan(Plan& P, const Scratch& w, const sidm_halo* halos, int32_t n_halos,
-                       std::string& why)
+                       const GravShape& shape, int64_t slots, std::string& why)
 {
     P = Plan();
+    P.shape = shape;
     P.n_halos = n_halos;
     P.halos.resize(n_halos);
     // halos ordered by offset define the sorted (compact) index space
@@ -485,10 +490,11 @@ inline bool build_plan(Plan& P, const Scratch& w, const sidm_halo* halos, int32_
         for (auto& t : per_level[l]) P.node_tasks.push_back(t);
         P.level_task_off[l] = (int64_t)P.node_tasks.size();
     }
-    // gravity work items
-    choose_splits(P.halos, w.partial_rows, w.grav_slots);
+    // gravity work items (i-blocks and tiles of the launch shape)
+    choose_splits(P.halos, w.partial_rows, slots, shape);
     int64_t prow = 0;
-    const int64_t kIBlock = kGravThreads * 4;
+    {
+    const int64_t kIBlock = (int64_t)shape.ireg * shape.nt, kGravTileJ = shape.nt;
     for (int h = 0; h < n_halos; ++h) {
         HaloDev& H = P.halos[h];
         H.part_base = prow;
@@ -503,13 +509,15 @@ inline bool build_plan(Plan& P, const Scratch& w, const sidm_halo* halos, int32_
                 P.items.push_back({H.offset + i0, j0, j1, h, s});
         }
     }
-    // Block-step ticks: a tick may hold only a few active i-blocks (they come
+    }
+    // Block-step ticks (the default launch shape): a tick may hold only a few active i-blocks (they come
     // first in the tick's order), so its items cut j finer, into up to
     // kTickSplit ranges, to keep the device busy; their partial rows are their own.
     bool blocks = false;
     for (const auto& H : P.halos)
         if (H.max_bin > 0 && !(H.tree_alpha > 0.0)) blocks = true;
     if (blocks) {
+        const int64_t kIBlock = kGravThreads * 4;
         int64_t trow = 0;
         for (int h = 0; h < n_halos; ++h) {
             HaloDev& H = P.halos[h];

@@ -130,3 +130,94 @@ def test_query_form_equals_the_full_form(orc):
     for c in range(4):
         assert np.array_equal(part[c], full[c][q])
     assert 0 < part[4] < full[4]
+
+
+def _rod_and_probes(R, seed=87):
+    """An elongated cluster (Gaussian, sigma = (4, 1, 0.5)) of unit mass centred
+    at (R, 0, 0), and 50 massless probes within 1 of the origin."""
+    rng = np.random.default_rng(seed)
+    n = 3000
+    rod = np.stack([rng.normal(0, 4.0, n) + R, rng.normal(0, 1.0, n), rng.normal(0, 0.5, n)])
+    probes = rng.uniform(-1.0, 1.0, (3, 50))
+    x, y, z = (np.concatenate([probes[c], rod[c]]) for c in range(3))
+    m = np.concatenate([np.zeros(50), np.full(n, 1.0 / n)])
+    return x, y, z, m
+
+
+def test_far_nodes_carry_their_quadrupole(orc):
+    """Every node of the elongated cluster disjoint from the probes' group is
+    accepted (a_old huge): with monopoles alone the error of the far field
+    would fall as (l/R)^2, with the quadrupole term it falls as (l/R)^3 --
+    doubling R divides it by about 8 -- and is far below the monopole's
+    (l/R)^2 level.  The direct sum is the reference."""
+    errs = []
+    for R in (150.0, 300.0):
+        x, y, z, m = _rod_and_probes(R)
+        d = orc.gravity(x, y, z, m, 1.0, 1e-3)
+        big = [np.full(x.size, 1e30)] * 3
+        q = np.arange(50)
+        t = orc.tree_gravity(x, y, z, m, big, 1.0, 1e-3, 1.0, query=q)
+        e = _rel_err([t[c] for c in range(3)], [d[c][:50] for c in range(3)])
+        errs.append(e.max())
+        assert e.max() < 0.05 * (4.0 / R) ** 2, (R, e.max())
+    assert 5.0 < errs[0] / errs[1] < 12.0, errs
+
+
+@pytest.mark.parametrize("n", [2, 100, 2000])
+def test_octree_without_a_old_is_the_direct_sum(orc, n):
+    """a_old = 0 opens every cell of the paper-style oct-tree: each particle
+    sums every other one (n(n-1) terms), the direct sum to rounding."""
+    s = W.nfw_halo(max(n, 2), seed=88)
+    x, y, z, m = (s[k][:n] for k in ("x", "y", "z", "m"))
+    d = orc.gravity(x, y, z, m, 1.3, 0.02, want_norm=True)
+    zero = [np.zeros(n)] * 3
+    t = orc.octree_gravity(x, y, z, m, zero, 1.3, 0.02, 5e-4)
+    assert t[4] == n * (n - 1)
+    e = np.sqrt((t[0] - d[0]) ** 2 + (t[1] - d[1]) ** 2 + (t[2] - d[2]) ** 2) / d[4]
+    assert e.max() < 1e-13
+    assert np.max(np.abs(t[3] - d[3]) / np.abs(d[3])) < 1e-13
+
+
+def test_octree_distant_cluster_is_one_monopole(orc):
+    """Massless probes near the origin and a Plummer cluster (mass 2, a = 1)
+    1000 away: with the per-particle criterion at alpha = 5e-4 the far
+    cluster is taken as one cell or a few, so the probes feel
+    G M (c - x) / |c - x|^3 (c its centre of mass) to order (a/R)^2."""
+    b = W.plummer(3000, seed=86, a=1.0, M=2.0)
+    rng = np.random.default_rng(4)
+    pr = rng.uniform(-1.0, 1.0, (3, 40))
+    x = np.concatenate([pr[0], b["x"] + 1000.0])
+    y = np.concatenate([pr[1], b["y"]])
+    z = np.concatenate([pr[2], b["z"]])
+    m = np.concatenate([np.zeros(40), b["m"]])
+    d = orc.gravity(x, y, z, m, 1.0, 0.01)
+    q = np.arange(40)
+    t = orc.octree_gravity(x, y, z, m, d[:3], 1.0, 0.01, 5e-4, query=q)
+    assert t[4] < 40 * 100      # a few cells per probe, not the 3000 particles
+    Mb = np.sum(b["m"])
+    cm = [np.sum(b["m"] * (b["x"] + 1000.0)) / Mb, np.sum(b["m"] * b["y"]) / Mb,
+          np.sum(b["m"] * b["z"]) / Mb]
+    dx, dy, dz = cm[0] - pr[0], cm[1] - pr[1], cm[2] - pr[2]
+    r3 = (dx * dx + dy * dy + dz * dz + 1e-4) ** 1.5
+    far = (Mb * dx / r3, Mb * dy / r3, Mb * dz / r3)
+    for c in range(3):
+        assert np.max(np.abs(t[c] - far[c])) < 1e-5 * np.max(np.abs(far[0]))
+
+
+def test_octree_error_and_work_follow_alpha(orc):
+    """On an NFW halo with a_old from the direct sum: the terms summed fall and
+    the error against the direct sum grows as alpha grows, and at alpha =
+    5e-4 the median error stays within a few alpha of |a| (normwise)."""
+    s = W.nfw_halo(6000, seed=89)
+    d = orc.gravity(s["x"], s["y"], s["z"], s["m"], 1.0, 0.01, want_norm=True)
+    q = np.arange(0, 6000, 7)
+    meds, terms = [], []
+    for alpha in (1e-4, 5e-4, 2.5e-3):
+        t = orc.octree_gravity(s["x"], s["y"], s["z"], s["m"], d[:3], 1.0, 0.01, alpha, query=q)
+        e = np.sqrt((t[0] - d[0][q]) ** 2 + (t[1] - d[1][q]) ** 2 + (t[2] - d[2][q]) ** 2)
+        e /= np.sqrt(d[0][q] ** 2 + d[1][q] ** 2 + d[2][q] ** 2)
+        meds.append(np.median(e))
+        terms.append(t[4])
+    assert terms[0] > terms[1] > terms[2]
+    assert meds[0] < meds[1] < meds[2]
+    assert meds[1] < 10 * 5e-4
