@@ -14,14 +14,17 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 _SRC = r'''
 #include "sidm_plan.hpp"
-extern "C" int plan_split(int nh, const long long* n, long long slots, long long partial_rows) {
+extern "C" int plan_split(int nh, const long long* n, long long slots, long long partial_rows,
+                          int ireg, int nt) {
     std::vector<sidm::HaloDev> hd(nh);
     for (int h = 0; h < nh; ++h) { std::memset(&hd[h], 0, sizeof(hd[h])); hd[h].n = n[h]; }
-    sidm::choose_splits(hd, partial_rows, slots);
+    sidm::GravShape shape;
+    shape.ireg = ireg;
+    shape.nt = nt;
+    sidm::choose_splits(hd, partial_rows, slots, shape);
     return hd[0].grav_split;
 }
 '''
-IBLOCK, TILE = 1024, 256
 
 
 @pytest.fixture(scope="module")
@@ -39,12 +42,13 @@ def L():
     return C.CDLL(so)
 
 
-def _split(L, ns, slots):
+def _split(L, ns, slots, ireg=4, nt=256):
     a = (C.c_longlong * len(ns))(*ns)
-    return L.plan_split(len(ns), a, slots, 4 * sum(ns))
+    return L.plan_split(len(ns), a, slots, 4 * sum(ns), ireg, nt)
 
 
-def _makespan(ns, s, slots):
+def _makespan(ns, s, slots, ireg=4, nt=256):
+    IBLOCK, TILE = ireg * nt, nt
     cost = []
     for n in ns:
         tiles = -(-n // TILE)
@@ -66,10 +70,12 @@ def _makespan(ns, s, slots):
 @pytest.mark.parametrize("ns,slots", [([1 << 20], 768), ([1 << 20], 512), ([1 << 24], 768),
                                       ([1000], 768), ([8192], 768), ([3000, 5000], 768),
                                       ([4096 * (b + 1) for b in range(20)], 1024)])
-def test_split_minimises_finishing_time(L, ns, slots):
-    s = _split(L, ns, slots)
+@pytest.mark.parametrize("ireg,nt", [(4, 256), (2, 128), (8, 512), (2, 256)])
+def test_split_minimises_finishing_time(L, ns, slots, ireg, nt):
+    """In every launch shape (i-block ireg * nt, j-tiles of nt)."""
+    s = _split(L, ns, slots, ireg, nt)
     assert 1 <= s <= 4
-    times = {q: _makespan(ns, q, slots) for q in range(1, 5)}
+    times = {q: _makespan(ns, q, slots, ireg, nt) for q in range(1, 5)}
     best = min(times.values())
     assert times[s] <= best * (1 + 5e-3) + 1e-9, (s, times)
 
