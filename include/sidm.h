@@ -156,6 +156,9 @@ typedef struct {
                                    particles of opened buckets) summed over the
                                    groups by the tree walks since the step (or the
                                    sidm_gravity call) began; 0 for direct sums      */
+    int64_t n_candidates;       /* tested pairs whose draw fell below the cheap
+                                   bound 8 (sigma/m) m g dt / (pi max(h)^3) of P,
+                                   so that the overlap integral was evaluated    */
 } sidm_diag;
 
 #define SIDM_DEV_EVENT_OVERFLOW 1   /* more events than the context can hold: no
@@ -175,11 +178,15 @@ typedef struct {
 /* ---- context ---------------------------------------------------------------
  * Creates a context on HIP device `device` with scratch memory for up to
  * `max_particles` particles in total and `max_halos` halos per call, and room
- * for max(4096, max_particles / 8) scattering events per call.  Allocates
+ * for max(4096, max_particles / 8) scattering events per call (and four times
+ * as many candidates: pairs whose draw falls below the cheap bound of P and
+ * whose decision needs the overlap integral; when they are more, a second
+ * pair pass decides them all, with the same result).  Allocates
  * device memory (SIDM_ERR_NOMEM on failure).  *out is NULL on error. */
 sidm_status sidm_create(sidm_ctx **out, int device, int64_t max_particles, int32_t max_halos);
 
-/* Sets the per-call event capacity (reallocates; call outside graph capture). */
+/* Sets the per-call event capacity, and the candidate capacity to four times
+ * it (reallocates; call outside graph capture). */
 sidm_status sidm_set_event_capacity(sidm_ctx *ctx, int64_t max_events);
 
 /* Releases the context and its scratch memory (waits for the device). */
@@ -403,6 +410,7 @@ sidm_status sidm_set_launch_shape(sidm_ctx *ctx, int32_t ireg, int32_t threads,
  * shape stays on the context.  Waits for the device; not during capture. */
 #define SIDM_TUNE_FORCE 1       /* time the shapes even if the cache has the key   */
 #define SIDM_TUNE_QUICK 2       /* one timed run per shape instead of three        */
+#define SIDM_TUNE_CACHE_ONLY 4  /* without a cache entry keep the current shape     */
 typedef struct {
     int32_t ireg, threads, persistent;   /* the chosen shape                         */
     int32_t from_cache;                  /* 1: read from the cache, not timed        */

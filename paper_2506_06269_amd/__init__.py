@@ -45,6 +45,8 @@ EXPORTED = ("sidm_create", "sidm_destroy", "sidm_set_event_capacity", "sidm_stat
             "sidm_set_launch_shape", "sidm_autotune")
 SIDM_TUNE_FORCE = 1
 SIDM_TUNE_QUICK = 2
+SIDM_TUNE_CACHE_ONLY = 4
+TILES_CACHE = os.path.join(HERE, "tiles.json")   # tuned launch shapes (MI355X entries)
 # launch shapes of the gravity tiles: (i-particles per thread, threads per block)
 SHAPES = [(i, t) for t in (128, 256, 512) for i in (2, 4, 8)]
 SIDM_STATIC_MAX_N = 65536
@@ -74,7 +76,7 @@ class SidmDiag(C.Structure):
                 ("px", C.c_double), ("py", C.c_double), ("pz", C.c_double),
                 ("n_events", C.c_int64), ("n_rounds", C.c_int64), ("n_pairs", C.c_int64),
                 ("n_p_gt1", C.c_int64), ("status", C.c_int32), ("reserved", C.c_int32),
-                ("n_grav_terms", C.c_int64)]
+                ("n_grav_terms", C.c_int64), ("n_candidates", C.c_int64)]
 
 
 class SidmTuneResult(C.Structure):

@@ -71,12 +71,14 @@ __device__ inline void insert_sorted(double (&best)[kKnnSurv], double v)
     }
 }
 
+template <bool LIST>
 __global__ __launch_bounds__(kBucket) void k_knn(
     const HaloDev* __restrict__ halos, const BucketInfo* __restrict__ buckets,
     const NodeChild* __restrict__ nodes, const double* __restrict__ box,
     const SubRange* __restrict__ sub, const int* __restrict__ sub_n, int64_t n_buckets,
     const double4* __restrict__ sp4, const uint32_t* __restrict__ perm,
-    double* __restrict__ sh, double* __restrict__ h_out, int* __restrict__ status)
+    double* __restrict__ sh, double* __restrict__ h_out, int* __restrict__ status,
+    const uint32_t* __restrict__ sid, uint32_t* __restrict__ nbr, int k_max)
 {
     __shared__ KnnLds L;
     const int64_t b = xcd_contiguous(blockIdx.x, gridDim.x);
@@ -285,14 +287,48 @@ __global__ __launch_bounds__(kBucket) void k_knn(
         sh[mypos] = h;
         h_out[perm[mypos]] = h;
     }
+    if (!LIST) return;
+
+    // Neighbour lists: the members of the sphere of the k-th distance, as
+    // sorted positions in the particle's row (k_knn_list_order puts them in
+    // (d2, id) order and turns them into ids): first every candidate strictly
+    // closer than the k-th (fewer than k), then the candidates at exactly that
+    // distance, keeping the smallest ids when they are more than the rest.
+    uint32_t* row = nbr + (int64_t)(in_bucket ? perm[mypos] : 0) * k_max;
+    const bool on = in_bucket && isfinite(d2k);
+    int cnt = 0;
+    visit(d2k * (1.0 + 1e-9), !on, [&](int64_t p, const double4& c) {
+        const double d2 = dist2_exact(xi, yi, zi, c.x, c.y, c.z);
+        if (on && p != mypos && d2 < d2k && cnt < k) row[cnt++] = (uint32_t)p;
+    });
+    const int need = k - cnt;
+    int nt = 0;
+    visit(d2k * (1.0 + 1e-9), !on, [&](int64_t p, const double4& c) {
+        const double d2 = dist2_exact(xi, yi, zi, c.x, c.y, c.z);
+        if (!(on && p != mypos && d2 == d2k && need > 0)) return;
+        if (nt < need) {
+            row[cnt + nt++] = (uint32_t)p;
+            return;
+        }
+        int worst = 0;
+        uint32_t wid = 0;
+        for (int q = 0; q < need; ++q) {
+            const uint32_t iq = sid[row[cnt + q]];
+            if (iq >= wid) {
+                wid = iq;
+                worst = q;
+            }
+        }
+        if (sid[p] < wid) row[cnt + worst] = (uint32_t)p;
+    });
 }
 
-// Neighbour lists for verification: brute force over the halo, one thread per
-// particle, the best k (d2, id) kept in order in a scratch row.
-__global__ __launch_bounds__(kStreamBlock) void k_knn_list(
+// The rows k_knn collected, in (d2, id) order, as ids: one thread per
+// particle, the distances recomputed with the same expression.
+__global__ __launch_bounds__(kStreamBlock) void k_knn_list_order(
     const StreamBlock* __restrict__ blocks, const HaloDev* __restrict__ halos,
     const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
-    const uint32_t* __restrict__ id, int k_max, double* __restrict__ rowd2,
+    const double4* __restrict__ sp4, const uint32_t* __restrict__ sid, int k_max,
     uint32_t* __restrict__ nbr)
 {
     const StreamBlock B = blocks[blockIdx.x];
@@ -301,45 +337,42 @@ __global__ __launch_bounds__(kStreamBlock) void k_knn_list(
     const HaloDev& H = halos[B.halo];
     const int64_t i = B.start + t;
     const int k = H.k;
-    double* rd = rowd2 + i * (int64_t)k_max;
-    uint32_t* ri = nbr + i * (int64_t)k_max;
+    uint32_t* row = nbr + i * (int64_t)k_max;
     const double xi = x[i], yi = y[i], zi = z[i];
-    int cnt = 0;
-    for (int64_t j = H.offset; j < H.offset + H.n; ++j) {
-        if (j == i) continue;
-        const double d2 = dist2_exact(xi, yi, zi, x[j], y[j], z[j]);
-        const uint32_t idj = id[j];
-        if (cnt == k && !(d2 < rd[k - 1] || (d2 == rd[k - 1] && idj < ri[k - 1]))) continue;
-        int pos = cnt < k ? cnt : k - 1;
-        while (pos > 0 && (d2 < rd[pos - 1] || (d2 == rd[pos - 1] && idj < ri[pos - 1]))) {
-            rd[pos] = rd[pos - 1];
-            ri[pos] = ri[pos - 1];
+    double d[SIDM_MAX_K];
+    uint32_t id[SIDM_MAX_K];
+    for (int q = 0; q < k; ++q) {
+        const uint32_t p = row[q];
+        const double4 c = sp4[p];
+        const double d2 = dist2_exact(xi, yi, zi, c.x, c.y, c.z);
+        const uint32_t iq = sid[p];
+        int pos = q;
+        while (pos > 0 && (d2 < d[pos - 1] || (d2 == d[pos - 1] && iq < id[pos - 1]))) {
+            d[pos] = d[pos - 1];
+            id[pos] = id[pos - 1];
             --pos;
         }
-        rd[pos] = d2;
-        ri[pos] = idj;
-        if (cnt < k) ++cnt;
+        d[pos] = d2;
+        id[pos] = iq;
     }
+    for (int q = 0; q < k; ++q) row[q] = id[q];
 }
 
 hipError_t launch_knn(const Plan& P, const sidm_state* s, Scratch& w, uint32_t* nbr, int k_max,
                       hipStream_t st)
 {
-    hipLaunchKernelGGL(k_knn, dim3((unsigned)P.n_buckets), dim3(kBucket), 0, st, w.halos,
+    if (!nbr) {
+        hipLaunchKernelGGL(k_knn<false>, dim3((unsigned)P.n_buckets), dim3(kBucket), 0, st,
+                           w.halos, w.buckets, w.nodes, w.box, w.sub, w.sub_n, P.n_buckets,
+                           w.sp4, w.perm, w.sh, s->h, w.status, w.sid, nbr, k_max);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_knn<true>, dim3((unsigned)P.n_buckets), dim3(kBucket), 0, st, w.halos,
                        w.buckets, w.nodes, w.box, w.sub, w.sub_n, P.n_buckets, w.sp4, w.perm,
-                       w.sh, s->h, w.status);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !nbr) return e;
-    double* rowd2 = nullptr;
-    int64_t total = 0;
-    for (const auto& H : P.halos) total = std::max(total, H.offset + H.n);
-    e = hipMallocAsync((void**)&rowd2, sizeof(double) * (size_t)(total * k_max), st);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_knn_list, dim3((unsigned)P.n_blocks), dim3(kStreamBlock), 0, st, w.blocks,
-                       w.halos, s->x, s->y, s->z, s->id, k_max, rowd2, nbr);
-    e = hipGetLastError();
-    hipError_t f = hipFreeAsync(rowd2, st);
-    return e != hipSuccess ? e : f;
+                       w.sh, s->h, w.status, w.sid, nbr, k_max);
+    hipLaunchKernelGGL(k_knn_list_order, dim3((unsigned)P.n_blocks), dim3(kStreamBlock), 0,
+                           st, w.blocks, w.halos, s->x, s->y, s->z, w.sp4, w.sid, k_max, nbr);
+    return hipGetLastError();
 }
 
 }  // namespace sidm

@@ -10,7 +10,10 @@
 // when d2 < (h_i + h_j)^2; accepted pairs are compacted through an LDS queue
 // (ballot + prefix count) so that the expensive per-pair work -- Philox4x32-10,
 // |dv|, and Lambda when the draw falls below a cheap upper bound of P -- runs
-// on full wavefronts.  Events (u < P) are appended to a global buffer.
+// on full wavefronts.  A pair whose draw falls below the bound is appended to
+// a candidate buffer; k_decide evaluates Lambda for those and appends the
+// events (u < P) to the event buffer (when the candidate buffer is full, the
+// pair pass decides the rest itself).
 //
 // k_rounds: the events of a step are applied in (a, b) order as elastic,
 // isotropic kicks in the pair's centre-of-mass frame.  Events that share no
@@ -44,9 +47,10 @@ __global__ void k_scatter_reset(DevCounters* __restrict__ counters,
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t == 0) {
         counters->n_events_total = 0ull;
+        counters->n_cands = 0ull;
         counters->ticket = 0ull;
     }
-    if (t < 4 * n_halos) ev_counts[t] = 0ull;
+    if (t < kEvCounts * n_halos) ev_counts[t] = 0ull;
     if (t < n_halos) status[t] = 0;
 }
 
@@ -129,11 +133,43 @@ __global__ __launch_bounds__(256) void k_copy_events(const DevCounters* __restri
     }
 }
 
-struct PairSide {
-    double x[kBucket], y[kBucket], z[kBucket];
+// The exact decision of a candidate: P = (sigma/m) m_b g Lambda dt with the
+// overlap integral, an event iff u < P (and a count of P > 1).  One function
+// for both callers, so that a decision never depends on which kernel took it.
+__device__ __forceinline__ void decide_pair(const CandRec& r, double dt,
+                                         DevCounters* __restrict__ counters,
+                                         EventRec* __restrict__ events, int64_t max_events,
+                                         unsigned long long* __restrict__ ev_counts)
+{
+    const double lam = kernel_overlap(r.d, r.ha, r.hb);
+    const double P = r.sg * r.mb * r.g * lam * dt;
+    if (P > 1.0) atomicAdd(&ev_counts[kEvCounts * r.halo + 3], 1ull);
+    if (r.u < P) {
+        const unsigned long long slot = atomicAdd(&counters->n_events_total, 1ull);
+        if ((int64_t)slot < max_events) {
+            EventRec e;
+            e.key = ((unsigned long long)r.a << 32) | r.b;
+            e.ia = r.ia;
+            e.ib = r.ib;
+            e.halo = r.halo;
+            e.round = 0u;
+            events[slot] = e;
+        }
+    }
+}
+
+// LDS copies of the bucket's own particles (I: what the per-pair work reads)
+// and of the candidate range (J: also the positions of the pair test).  The
+// rest (positions of I, original indices) is read from memory for the rare
+// candidates, and the mass is the halo's common one.
+struct PairI {
+    double vx[kBucket], vy[kBucket], vz[kBucket], h[kBucket];
+    uint32_t id[kBucket];
+};
+struct PairJ {
+    double x[kBucket], y[kBucket], z[kBucket], h[kBucket];
     double vx[kBucket], vy[kBucket], vz[kBucket];
-    double h[kBucket], m[kBucket];
-    uint32_t id[kBucket], orig[kBucket];
+    uint32_t id[kBucket];
 };
 
 // Cross-section per unit mass at relative speed g: sigma_m, or with a velocity
@@ -147,6 +183,11 @@ __device__ inline double sigma_at(const HaloDev& H, double g)
     return H.sigma_m / (q * q);
 }
 
+// INLINE: the pass after an overflow of the candidate buffer.  It runs only
+// then (it returns at once otherwise), repeats the search and decides every
+// candidate itself; k_decide then decides none, and the counts of pairs and
+// candidates are those of the first pass.
+template <bool INLINE>
 __global__ __launch_bounds__(kBucket) void k_pairs(
     const HaloDev* __restrict__ halos, const BucketInfo* __restrict__ buckets,
     const NodeChild* __restrict__ nodes, const double* __restrict__ box,
@@ -154,33 +195,36 @@ __global__ __launch_bounds__(kBucket) void k_pairs(
     const int* __restrict__ sub_n, int64_t n_buckets, const double* __restrict__ sx,
     const double* __restrict__ sy, const double* __restrict__ sz, const double* __restrict__ svx,
     const double* __restrict__ svy, const double* __restrict__ svz, const double* __restrict__ sh,
-    const double* __restrict__ sm, const uint32_t* __restrict__ sid,
+    const double* __restrict__ cmass, const uint32_t* __restrict__ sid,
     const uint32_t* __restrict__ perm, uint32_t step, DevCounters* __restrict__ counters,
-    EventRec* __restrict__ events, int64_t max_events, unsigned long long* __restrict__ ev_counts,
-    const int* __restrict__ status)
+    CandRec* __restrict__ cands, int64_t max_cands, EventRec* __restrict__ events,
+    int64_t max_events, unsigned long long* __restrict__ ev_counts, const int* __restrict__ status)
 {
-    __shared__ PairSide I, J;
+    __shared__ PairI I;
+    __shared__ PairJ J;
     __shared__ uint16_t queue[2 * kBucket];
     __shared__ int64_t stack[kStackMax];
     const int64_t b = blockIdx.x;
     const int lane = threadIdx.x;
+    if (INLINE && (int64_t)counters->n_cands <= max_cands) return;
     const BucketInfo B = buckets[b];
     const HaloDev& H = halos[B.halo];
     if (!(H.sigma_m > 0.0)) return;   // uniform over the block
     // a halo with unequal masses or repeated ids is not scattered (flagged)
     if (status[B.halo] & (SIDM_DEV_UNEQUAL_MASS | SIDM_DEV_DUPLICATE_ID)) return;
     const bool act = lane < B.count;
-    auto load = [&](PairSide& S, int64_t p) {
-        S.x[lane] = sx[p]; S.y[lane] = sy[p]; S.z[lane] = sz[p];
-        S.vx[lane] = svx[p]; S.vy[lane] = svy[p]; S.vz[lane] = svz[p];
-        S.h[lane] = sh[p]; S.m[lane] = sm[p];
-        S.id[lane] = sid[p]; S.orig[lane] = perm[p];
-    };
-    if (act) load(I, B.start + lane);
+    const double mb = cmass[B.halo];   // the masses of a halo that scatters are equal
+    int64_t jbase = 0;                  // first sorted position of the range in J
+    if (act) {
+        const int64_t p = B.start + lane;
+        I.vx[lane] = svx[p]; I.vy[lane] = svy[p]; I.vz[lane] = svz[p];
+        I.h[lane] = sh[p];
+        I.id[lane] = sid[p];
+    }
     const uint32_t k0 = (uint32_t)(H.seed & 0xffffffffull), k1 = (uint32_t)(H.seed >> 32);
     const double kInvPi8 = 8.0 / 3.14159265358979323846;
     const unsigned long long lt = (1ull << lane) - 1ull;
-    long long my_pairs = 0;
+    long long my_pairs = 0, my_cands = 0;
     int qn = 0;
 
     // per-pair work for queue entries [0, cnt): lane l takes entry l
@@ -197,27 +241,35 @@ __global__ __launch_bounds__(kBucket) void k_pairs(
             const double g = norm3(I.vx[il] - J.vx[jl], I.vy[il] - J.vy[jl], I.vz[il] - J.vz[jl]);
             const double ha = I.h[il], hbb = J.h[jl];
             const double hm = fmax(ha, hbb);
-            const double mb = iswap ? I.m[il] : J.m[jl];
+
             // Lambda <= min(W_a(0), W_b(0)) = 8 / (pi max(h)^3)
             const double sg = sigma_at(H, g);
             const double pub = sg * mb * g * (kInvPi8 / (hm * hm * hm)) * H.dt;
             if (u < pub) {
-                const double d =
-                    sqrt(dist2_pair(I.x[il], I.y[il], I.z[il], J.x[jl], J.y[jl], J.z[jl]));
-                const double lam = iswap ? kernel_overlap(d, hbb, ha) : kernel_overlap(d, ha, hbb);
-                const double P = sg * mb * g * lam * H.dt;
-                if (P > 1.0) atomicAdd(&ev_counts[4 * B.halo + 3], 1ull);
-                if (u < P) {
-                    const unsigned long long slot = atomicAdd(&counters->n_events_total, 1ull);
-                    if ((int64_t)slot < max_events) {
-                        EventRec r;
-                        r.key = ((unsigned long long)a << 32) | bb;
-                        r.ia = iswap ? J.orig[jl] : I.orig[il];
-                        r.ib = iswap ? I.orig[il] : J.orig[jl];
-                        r.halo = B.halo;
-                        r.round = 0u;
-                        events[slot] = r;
-                    }
+                // the exact decision needs Lambda: k_decide takes it from here
+                // (after an overflow of its buffer, the INLINE pass)
+                ++my_cands;
+                CandRec r;
+                r.sg = sg;
+                r.mb = mb;
+                r.g = g;
+                const int64_t pi = B.start + il;
+                r.d = sqrt(dist2_pair(sx[pi], sy[pi], sz[pi], J.x[jl], J.y[jl], J.z[jl]));
+                r.ha = iswap ? hbb : ha;
+                r.hb = iswap ? ha : hbb;
+                r.u = u;
+                r.a = a;
+                r.b = bb;
+                const uint32_t oi = perm[pi], oj = perm[jbase + jl];
+                r.ia = iswap ? oj : oi;
+                r.ib = iswap ? oi : oj;
+                r.halo = B.halo;
+                r.pad = 0;
+                if (INLINE) {
+                    decide_pair(r, H.dt, counters, events, max_events, ev_counts);
+                } else {
+                    const unsigned long long slot = atomicAdd(&counters->n_cands, 1ull);
+                    if ((int64_t)slot < max_cands) cands[slot] = r;
                 }
             }
         }
@@ -228,7 +280,8 @@ __global__ __launch_bounds__(kBucket) void k_pairs(
     // h_i + max h over c; pairs between two buckets are handled by the lower
     // bucket index, pairs inside a bucket by the smaller id
     const double hi_l = act ? I.h[lane] : 0.0;
-    const double xl = I.x[act ? lane : 0], yl = I.y[act ? lane : 0], zl = I.z[act ? lane : 0];
+    const int64_t pl = B.start + (act ? lane : 0);
+    const double xl = sx[pl], yl = sy[pl], zl = sz[pl];
     tree_visit(H, nodes, n_buckets, stack,
                [&](int64_t c) {
                    const double r = hi_l + hmax[c];
@@ -245,7 +298,14 @@ __global__ __launch_bounds__(kBucket) void k_pairs(
             if (!__ballot(act && point_box_dist2(xl, yl, zl, R.box) < rr * rr * (1.0 + 1e-9)))
                 continue;
             __syncthreads();
-            if (lane < R.cnt) load(J, C.start + R.off + lane);
+            jbase = C.start + R.off;
+            if (lane < R.cnt) {
+                const int64_t p = jbase + lane;
+                J.x[lane] = sx[p]; J.y[lane] = sy[p]; J.z[lane] = sz[p];
+                J.h[lane] = sh[p];
+                J.vx[lane] = svx[p]; J.vy[lane] = svy[p]; J.vz[lane] = svz[p];
+                J.id[lane] = sid[p];
+            }
             __syncthreads();
             const double xi = xl, yi = yl, zi = zl, hi = hi_l;
             const uint32_t idi = I.id[act ? lane : 0];
@@ -277,10 +337,33 @@ __global__ __launch_bounds__(kBucket) void k_pairs(
             }
         }
     });
-    // pairs tested by this bucket
-    long long v = my_pairs;
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    if (lane == 0 && v > 0) atomicAdd(&ev_counts[4 * B.halo + 2], (unsigned long long)v);
+    // pairs tested and candidates of the exact decision found by this bucket
+    if (INLINE) return;
+    long long v = my_pairs, vc = my_cands;
+    for (int o = 32; o > 0; o >>= 1) {
+        v += __shfl_xor(v, o, 64);
+        vc += __shfl_xor(vc, o, 64);
+    }
+    if (lane == 0 && v > 0) atomicAdd(&ev_counts[kEvCounts * B.halo + 2], (unsigned long long)v);
+    if (lane == 0 && vc > 0) atomicAdd(&ev_counts[kEvCounts * B.halo + 4], (unsigned long long)vc);
+}
+
+// The exact decisions of the candidates the pair pass stored; none after an
+// overflow of their buffer (the INLINE pair pass decides them all).
+__global__ __launch_bounds__(256) void k_decide(const HaloDev* __restrict__ halos,
+                                                const CandRec* __restrict__ cands,
+                                                int64_t max_cands,
+                                                DevCounters* __restrict__ counters,
+                                                EventRec* __restrict__ events, int64_t max_events,
+                                                unsigned long long* __restrict__ ev_counts)
+{
+    const int64_t total = (int64_t)counters->n_cands;
+    if (total > max_cands) return;
+    for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < total;
+         c += (int64_t)gridDim.x * 256) {
+        const CandRec r = cands[c];
+        decide_pair(r, halos[r.halo].dt, counters, events, max_events, ev_counts);
+    }
 }
 
 // Elastic isotropic scattering in the centre-of-mass frame: the relative speed
@@ -382,8 +465,8 @@ __global__ __launch_bounds__(kRoundThreads) void k_rounds(
                           va, vb);
                 vx[E.ia] = va[0]; vy[E.ia] = va[1]; vz[E.ia] = va[2];
                 vx[E.ib] = vb[0]; vy[E.ib] = vb[1]; vz[E.ib] = vb[2];
-                atomicAdd(&ev_counts[4 * E.halo + 0], 1ull);
-                atomicMax(&ev_counts[4 * E.halo + 1], (unsigned long long)r);
+                atomicAdd(&ev_counts[kEvCounts * E.halo + 0], 1ull);
+                atomicMax(&ev_counts[kEvCounts * E.halo + 1], (unsigned long long)r);
             } else if (E.round == 0u) {
                 ++mine;
             }
@@ -409,7 +492,7 @@ __global__ __launch_bounds__(kRoundThreads) void k_rounds(
 
 hipError_t launch_reset(const Plan& P, Scratch& w, hipStream_t st)
 {
-    const int nt = 4 * P.n_halos + 1;
+    const int nt = kEvCounts * P.n_halos + 1;
     hipLaunchKernelGGL(k_scatter_reset, dim3((nt + 255) / 256), dim3(256), 0, st, w.counters,
                        (unsigned long long*)w.ev_counts, w.status, P.n_halos);
     return hipGetLastError();
@@ -476,11 +559,17 @@ hipError_t launch_scatter(const Plan& P, const sidm_state* s, Scratch& w, uint32
 {
     hipError_t e = launch_contract_checks(P, s, w, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_pairs, dim3((unsigned)P.n_buckets), dim3(kBucket), 0, st, w.halos,
-                       w.buckets, w.nodes, w.box, w.hmax, w.sub, w.sub_n, P.n_buckets, w.sx,
-                       w.sy, w.sz, w.svx,
-                       w.svy, w.svz, w.sh, w.sm, w.sid, w.perm, step, w.counters, w.events,
-                       w.max_events, (unsigned long long*)w.ev_counts, w.status);
+    auto pairs = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3((unsigned)P.n_buckets), dim3(kBucket), 0, st, w.halos,
+                           w.buckets, w.nodes, w.box, w.hmax, w.sub, w.sub_n, P.n_buckets, w.sx,
+                           w.sy, w.sz, w.svx, w.svy, w.svz, w.sh, w.cref, w.sid, w.perm, step,
+                           w.counters, w.cands, w.max_cands, w.events, w.max_events,
+                           (unsigned long long*)w.ev_counts, w.status);
+    };
+    pairs(k_pairs<false>);
+    hipLaunchKernelGGL(k_decide, dim3(256), dim3(256), 0, st, w.halos, w.cands, w.max_cands,
+                       w.counters, w.events, w.max_events, (unsigned long long*)w.ev_counts);
+    pairs(k_pairs<true>);
     if (after_pairs) (void)hipEventRecord(after_pairs, st);
     hipLaunchKernelGGL(k_rounds, dim3(1), dim3(kRoundThreads), 0, st, w.halos, P.n_halos,
                        w.counters, w.events, w.max_events, w.owner, s->vx, s->vy, s->vz, s->m,

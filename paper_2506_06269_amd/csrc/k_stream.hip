@@ -153,10 +153,11 @@ __global__ __launch_bounds__(kStreamBlock) void k_diag_halo(
         d.K = red[0][0]; d.W = red[1][0]; d.Eext = red[2][0];
         d.px = red[3][0]; d.py = red[4][0]; d.pz = red[5][0];
         const int h = blockIdx.x;
-        d.n_events = ev_counts ? ev_counts[4 * h + 0] : 0;
-        d.n_rounds = ev_counts ? ev_counts[4 * h + 1] : 0;
-        d.n_pairs = ev_counts ? ev_counts[4 * h + 2] : 0;
-        d.n_p_gt1 = ev_counts ? ev_counts[4 * h + 3] : 0;
+        d.n_events = ev_counts ? ev_counts[kEvCounts * h + 0] : 0;
+        d.n_rounds = ev_counts ? ev_counts[kEvCounts * h + 1] : 0;
+        d.n_pairs = ev_counts ? ev_counts[kEvCounts * h + 2] : 0;
+        d.n_p_gt1 = ev_counts ? ev_counts[kEvCounts * h + 3] : 0;
+        d.n_candidates = ev_counts ? ev_counts[kEvCounts * h + 4] : 0;
         d.status = (status ? status[h] : 0) | (red[6][0] > 0.0 ? SIDM_DEV_NONFINITE : 0);
         d.reserved = 0;
         d.n_grav_terms = tree_terms ? (int64_t)tree_terms[h] : 0;

@@ -897,6 +897,15 @@ sidm_status sidm_autotune(sidm_ctx* c, const sidm_halo* halos, int32_t n_halos,
     GravShape best;
     bool have = false;
     if (cache_path && !(flags & SIDM_TUNE_FORCE)) have = tune_read(cache_path, key, best);
+    if (!have && (flags & SIDM_TUNE_CACHE_ONLY)) {
+        best = c->shape;   // no entry: the current shape stays, nothing is timed
+        res.ireg = best.ireg;
+        res.threads = best.nt;
+        res.persistent = best.persist;
+        if (out) *out = res;
+        c->err.clear();
+        return sidm_gravity(c, halos, n_halos, s, prec, stream);
+    }
     const GravShape saved = c->shape;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipSuccess;

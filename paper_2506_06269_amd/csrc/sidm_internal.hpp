@@ -90,9 +90,14 @@ struct BucketInfo {
     int32_t halo;
 };
 
+// Per-halo counters of a scattering pass: events, rounds, pairs tested, pairs
+// with P > 1 and candidates of the exact decision.
+constexpr int kEvCounts = 5;
+
 // Device-side error bits live in a per-halo status word.
 struct DevCounters {
     unsigned long long n_events_total;    // events found (may exceed capacity)
+    unsigned long long n_cands;           // pairs whose draw fell below the P bound
     unsigned long long ticket;            // next work item of a persistent gravity launch
 };
 

@@ -21,6 +21,17 @@ struct EventRec {
     uint32_t round;
 };
 
+// A pair whose accept draw fell below the cheap upper bound of P: the exact
+// probability needs the overlap integral, which a second kernel evaluates.
+struct CandRec {
+    double sg, mb, g;         // cross-section, mass of b and relative speed
+    double d, ha, hb;         // separation and the kernel sizes of a and b
+    double u;                 // the accept draw
+    uint32_t a, b;            // ids
+    uint32_t ia, ib;          // original particle indices
+    int32_t halo, pad;
+};
+
 // A tree node of level >= 1 and the range of its children (global indices).
 struct NodeTask {
     int64_t node;
@@ -104,8 +115,10 @@ struct Scratch {
     // scattering
     unsigned long long* owner = nullptr;
     EventRec* events = nullptr;
+    CandRec* cands = nullptr;         // candidates of the exact decision
+    int64_t max_cands = 0;
     DevCounters* counters = nullptr;
-    long long* ev_counts = nullptr;   // 4 per halo: events, rounds, pairs, P>1
+    long long* ev_counts = nullptr;   // kEvCounts per halo
     int* status = nullptr;            // per halo
     int* sticky = nullptr;            // OR of the status words not yet read by the host
     unsigned long long* fp_dev = nullptr;   // fingerprint of the last call outside capture
@@ -150,13 +163,18 @@ inline void dfree(T*& p)
     p = nullptr;
 }
 
+// Events and the candidates of the exact decision (four per event slot: a
+// pair's draw falls below the bound some ten times as often as below P, and
+// the event buffer holds N/8 by default).
 inline bool realloc_events(Scratch& w, int64_t max_events, std::string& why)
 {
     dfree(w.events);
+    dfree(w.cands);
     w.max_events = max_events;
-    if (!dalloc(w.events, max_events)) {
-        why = "cannot allocate the event buffer";
-        w.max_events = 0;
+    w.max_cands = 4 * max_events;
+    if (!dalloc(w.events, max_events) || !dalloc(w.cands, w.max_cands)) {
+        why = "cannot allocate the event buffers";
+        w.max_events = w.max_cands = 0;
         return false;
     }
     return true;
@@ -186,7 +204,7 @@ inline bool alloc_scratch(Scratch& w, int64_t N, int32_t H, int64_t max_events, 
               dalloc(w.mom, w.nodes_cap) && dalloc(w.mom2, 6 * w.nodes_cap) && dalloc(w.tree_terms, H) && dalloc(w.sid, N) && dalloc(w.perm, N) &&
               dalloc(w.box, 6 * w.nodes_cap) && dalloc(w.hmax, w.nodes_cap) &&
               dalloc(w.sub, kSubMax * w.buckets_cap) && dalloc(w.sub_n, w.buckets_cap) &&
-              dalloc(w.owner, N) && dalloc(w.counters, 1) && dalloc(w.ev_counts, 4 * H) &&
+              dalloc(w.owner, N) && dalloc(w.counters, 1) && dalloc(w.ev_counts, kEvCounts * H) &&
               dalloc(w.status, H) && dalloc(w.sticky, 1) && dalloc(w.fp_dev, 1);
     if (!ok) {
         why = "device allocation failed";
@@ -197,7 +215,7 @@ inline bool alloc_scratch(Scratch& w, int64_t N, int32_t H, int64_t max_events, 
     // read by the diagnostics start at zero (a context that has not stepped
     // yet reports no events and a clean status); the passes reset them later
     if (hipMemset(w.counters, 0, sizeof(DevCounters)) != hipSuccess ||
-        hipMemset(w.ev_counts, 0, sizeof(*w.ev_counts) * (size_t)(4 * H)) != hipSuccess ||
+        hipMemset(w.ev_counts, 0, sizeof(*w.ev_counts) * (size_t)(kEvCounts * H)) != hipSuccess ||
         hipMemset(w.status, 0, sizeof(*w.status) * (size_t)H) != hipSuccess ||
         hipMemset(w.sticky, 0, sizeof(*w.sticky)) != hipSuccess ||
         hipMemset(w.fp_dev, 0, sizeof(*w.fp_dev)) != hipSuccess ||
@@ -228,7 +246,7 @@ inline void free_scratch(Scratch& w)
     w.items_tick_cap = w.partial_tick_rows = 0;
     dfree(w.sh); dfree(w.sm); dfree(w.bin); dfree(w.mom); dfree(w.mom2); dfree(w.tree_terms); dfree(w.sid); dfree(w.perm); dfree(w.box); dfree(w.hmax);
     dfree(w.sub); dfree(w.sub_n);
-    dfree(w.owner); dfree(w.events); dfree(w.counters); dfree(w.ev_counts); dfree(w.status);
+    dfree(w.owner); dfree(w.events); dfree(w.cands); dfree(w.counters); dfree(w.ev_counts); dfree(w.status);
     dfree(w.sticky); dfree(w.fp_dev);
 }
 

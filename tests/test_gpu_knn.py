@@ -72,23 +72,26 @@ def test_knn_batched_mixed_k(S, orc):
         for f in ("x", "y", "z", "vx", "vy", "vz", "m", "id"):
             s[f][o:o + n] = p[f]
         halos.append(dict(n=n, offset=o, eps=0.01, k=k))
-    h, _ = _gpu_knn(S, halos, s)
+    h, lists = _gpu_knn(S, halos, s, want_list=True)
     for p, hh in zip(parts, halos):
-        ref = orc.knn(p["x"], p["y"], p["z"], p["id"], hh["k"])
-        got = h[hh["offset"]:hh["offset"] + hh["n"]]
-        assert np.array_equal(got, ref), hh
+        ref, lref = orc.knn(p["x"], p["y"], p["z"], p["id"], hh["k"], want_list=True)
+        sl = slice(hh["offset"], hh["offset"] + hh["n"])
+        assert np.array_equal(h[sl], ref), hh
+        assert np.array_equal(lists[sl, :hh["k"]], lref), hh
 
 
 def test_knn_large_sampled(S, orc):
-    """N = 2^20 halo in the host (the benchmark's workload), k = 64: h of 512
-    sampled particles against the oracle's brute force over all N."""
+    """N = 2^20 halo in the host (the benchmark's workload), k = 64: h and the
+    neighbour lists of 512 sampled particles against the oracle's brute force
+    over all N."""
     cfg = W.config("C2")
     s = W.make_state(cfg)
     halo = dict(n=cfg["n"], eps=cfg["eps"], k=cfg["k"])
-    h, _ = _gpu_knn(S, [halo], s)
+    h, lists = _gpu_knn(S, [halo], s, want_list=True)
     q = np.random.default_rng(1).choice(cfg["n"], 512, replace=False)
-    ref = orc.knn(s["x"], s["y"], s["z"], s["id"], cfg["k"], query=q)
+    ref, lref = orc.knn(s["x"], s["y"], s["z"], s["id"], cfg["k"], query=q, want_list=True)
     assert np.array_equal(h[q], ref)
+    assert np.array_equal(lists[q], lref)
     assert np.all(np.isfinite(h)) and np.all(h > 0)
 
 

@@ -118,6 +118,8 @@ def test_scatter_pair_count_and_diag(S, orc):
     assert d["n_events"] == ref.size == cnt
     assert d["n_p_gt1"] == npgt1
     assert d["status"] == 0
+    # every event and every P > 1 pair passed the cheap bound first
+    assert max(d["n_events"], d["n_p_gt1"]) <= d["n_candidates"] <= d["n_pairs"]
     out = S.state_to_host(dev)
     od = orc.diag(out["vx"], out["vy"], out["vz"], out["m"], out["pot"])
     for f in ("K", "W", "px", "py", "pz"):
@@ -145,6 +147,42 @@ def test_scatter_capacity_retry(S, orc):
     ref, _, _ = orc.find_events(s["x"], s["y"], s["z"], s["vx"], s["vy"], s["vz"], s["m"],
                                 s["id"], s["h"], 500.0, 1e-3, 1, 0)
     assert cnt == ref.size > 4
+
+
+def test_scatter_candidate_overflow(S, orc):
+    """Room for every event but not for the candidates of the exact decision
+    (four per event slot): a second pair pass decides them all itself, and the
+    events, their count, the pair and P > 1 counts and the kicks equal those of
+    a call with room (and the events the oracle's)."""
+    import torch
+    n, k = 2000, 32
+    s = _prepare(orc, W.nfw_halo(n, seed=5), k)
+    halo = dict(n=n, eps=0.01, k=k, sigma_m=500.0, dt=1e-3, seed=1)
+    ref, npairs, npgt1 = orc.find_events(s["x"], s["y"], s["z"], s["vx"], s["vy"], s["vz"],
+                                         s["m"], s["id"], s["h"], 500.0, 1e-3, 1, 0)
+    runs = []
+    for cap in (None, ref.size):
+        dev = S.state_to_device(s)
+        ctx = S.sidm_create(0, n, 1)
+        if cap is not None:
+            S.sidm_set_event_capacity(ctx, cap)
+        ev = S.event_buffer(ref.size)
+        cnt = S.sidm_scatter(ctx, [halo], dev, 0, events=ev, want_count=True)
+        diag = S.diag_buffer(1)
+        S.sidm_diagnostics(ctx, [halo], dev, diag)
+        torch.cuda.synchronize()
+        d = S.read_diag(diag)[0]
+        runs.append((cnt, S.read_events(ev, cnt), d, dev["vx"].cpu().numpy().copy()))
+        S.sidm_destroy(ctx)
+    (c0, e0, d0, v0), (c1, e1, d1, v1) = runs
+    assert d1["n_candidates"] > 4 * ref.size    # the buffer did overflow
+    assert c0 == c1 == ref.size
+    key = lambda e: sorted(zip(e["a"].tolist(), e["b"].tolist()))
+    assert key(e0) == key(e1) == sorted(zip(ref["a"].tolist(), ref["b"].tolist()))
+    assert d0["n_pairs"] == d1["n_pairs"] == npairs
+    assert d0["n_p_gt1"] == d1["n_p_gt1"] == npgt1
+    assert d0["n_candidates"] == d1["n_candidates"]
+    assert np.array_equal(v0, v1)
 
 
 def test_scatter_deterministic(S, orc):
