@@ -37,7 +37,14 @@ def _args():
     ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
-    ap.add_argument("--workload", default="C2", choices=("C2", "C3", "C4", "C5", "BLK", "TREE"),
+    ap.add_argument("--tune", action="store_true",
+                    help="time every launch shape of the gravity tiles for the workload and "
+                         "store the fastest in the tiles cache (default: read the cache only)")
+    ap.add_argument("--shape", default=None, metavar="IxT[p]",
+                    help="force a launch shape of the gravity tiles, e.g. 4x256 or 2x128p "
+                         "(p: persistent)")
+    ap.add_argument("--workload", default="C2",
+                    choices=("C1", "C2", "C3", "C4", "C5", "BLK", "TREE"),
                     help="C2 (default, the benchmark line): N=2^20 satellite; C3: the same halo "
                          "for --steps steps in one --precision with |dE/E| and central density; "
                          "C4: 64-halo batch; C5: N=2^24 satellite, one step, per-pass rooflines; "
@@ -83,6 +90,33 @@ def _energy(d):
     return d["K"] + d["W"] + d["Eext"]
 
 
+def _internal_energy(d, mass):
+    """K relative to the halo's centre-of-mass motion plus W: the halo's own
+    energy, without its orbit in the host (which dominates E for a satellite)."""
+    p2 = d["px"] ** 2 + d["py"] ** 2 + d["pz"] ** 2
+    return d["K"] - 0.5 * p2 / mass + d["W"]
+
+
+_TUNE = {"mode": "cache", "shape": None}   # set from the command line
+
+
+def _tiles(S, ctx, halos, dev, prec):
+    """Launch shape of the gravity tiles for this run: forced, timed (--tune,
+    stored in the cache) or read from the cache (default; without an entry the
+    default shape).  Computes the initial forces.  Returns the tuner's record."""
+    if _TUNE["shape"]:
+        spec = _TUNE["shape"]
+        i, t = spec.rstrip("p").split("x")
+        S.sidm_set_launch_shape(ctx, int(i), int(t), spec.endswith("p"))
+        S.sidm_gravity(ctx, halos, dev, prec)
+        return {"ireg": int(i), "threads": int(t), "persistent": int(spec.endswith("p")),
+                "source": "forced"}
+    flags = 0 if _TUNE["mode"] == "tune" else S.SIDM_TUNE_CACHE_ONLY
+    r = S.sidm_autotune(ctx, halos, dev, prec, S.TILES_CACHE, flags)
+    r["source"] = "timed" if r["n_tried"] else ("cache" if r["from_cache"] else "default")
+    return r
+
+
 def _halo_of(cfg):
     return dict(n=cfg["n"], eps=cfg["eps"], G=1.0, sigma_m=cfg["sigma_m"], dt=cfg["dt"],
                 k=cfg["k"], seed=cfg["seed"], host=cfg["host"])
@@ -108,10 +142,14 @@ def _run(S, torch, halos, s, prec, steps, warmup, timing, progress=False):
     dev = S.state_to_device(s)
     ctx = S.sidm_create(0, n, len(halos))
     diag = S.diag_buffer(len(halos))
-    S.sidm_gravity(ctx, halos, dev, prec)
+    tiles = _tiles(S, ctx, halos, dev, prec)
+    _run.tiles = tiles
     S.sidm_diagnostics(ctx, halos, dev, diag)
-    e0_each = [_energy(d) for d in S.read_diag(diag)]
+    d0 = S.read_diag(diag)
+    e0_each = [_energy(d) for d in d0]
     e0 = sum(e0_each)
+    mass0 = float(s["m"][halos[0].get("offset", 0):halos[0].get("offset", 0) + halos[0]["n"]].sum())
+    ei0 = _internal_energy(d0[0], mass0)
     run_label = f"{'fp64' if prec == S.SIDM_PREC_FP64 else 'mixed'} n={n} halos={len(halos)}"
     if progress:
         print("initial forces done", file=sys.stderr, flush=True)
@@ -139,6 +177,7 @@ def _run(S, torch, halos, s, prec, steps, warmup, timing, progress=False):
     d = dl[0]
     events = sum(x["n_events"] for x in dl)
     rel_e = abs(sum(_energy(x) for x in dl) - e0) / abs(e0)
+    _run.rel_e_internal = abs(_internal_energy(d, mass0) - ei0) / abs(ei0)
     for k in passes:
         passes[k] /= steps
     S.sidm_destroy(ctx)
@@ -272,9 +311,12 @@ def _bench_c3(a, S, torch, W):
     dev = S.state_to_device(s)
     ctx = S.sidm_create(0, n, 1)
     diag = S.diag_buffer(1)
-    S.sidm_gravity(ctx, [halo], dev, prec)
+    tiles = _tiles(S, ctx, [halo], dev, prec)
     S.sidm_diagnostics(ctx, [halo], dev, diag)
-    e0 = _energy(S.read_diag(diag)[0])
+    d0 = S.read_diag(diag)[0]
+    e0 = _energy(d0)
+    mass = float(s["m"].sum())
+    ei0 = _internal_energy(d0, mass)
     vol = 4.0 / 3.0 * math.pi * radius ** 3
 
     def center(step):
@@ -291,9 +333,11 @@ def _bench_c3(a, S, torch, W):
         if (step + 1) % 100 == 0 or step + 1 == a.steps:
             d = S.read_diag(diag)[0]
             energy.append(dict(step=step + 1, dE_over_E=abs(_energy(d) - e0) / abs(e0),
+                               dEint_over_Eint=abs(_internal_energy(d, mass) - ei0) / abs(ei0),
                                events=d["n_events"], status=d["status"]))
             centers.append(center(step + 1))
             print(f"C3 {a.precision} step {step + 1}: |dE/E| {energy[-1]['dE_over_E']:.3e} "
+                  f"internal {energy[-1]['dEint_over_Eint']:.3e} "
                   f"rho(<{radius}) {centers[-1]['rho']:.4g} ({centers[-1]['count']}) "
                   f"{time.perf_counter() - t0:.0f} s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
@@ -311,8 +355,61 @@ def _bench_c3(a, S, torch, W):
                                   "sigma/m=10, dt=1e-3", "precision": a.precision,
                       **({"overrides": overrides} if overrides else {})},
            "dE_over_E": energy[-1]["dE_over_E"] if energy else None,
+           "dEint_over_Eint": energy[-1]["dEint_over_Eint"] if energy else None,
+           "tiles": tiles,
            "max_dE_over_E": max((e["dE_over_E"] for e in energy), default=None),
            "energy": energy, "central_density": centers, "radius": radius}
+    print(json.dumps(out), flush=True)
+
+
+def _bench_c1(a, S, torch, W):
+    """C1 (N = 8192, FP64, isolated, k = 32, sigma/m = 1, dt = 1e-3): the
+    latency of one step, eager (one call per step) and replayed from a HIP
+    graph captured from one call, over its 32 steps."""
+    cfg = W.config("C1")
+    n = cfg["n"]
+    s = W.nfw_halo(n, seed=0)
+    halo = dict(n=n, eps=cfg["eps"], G=1.0, sigma_m=cfg["sigma_m"], dt=cfg["dt"], k=cfg["k"],
+                seed=0)
+    steps = 32
+    dev = S.state_to_device(s)
+    ctx = S.sidm_create(0, n, 1)
+    diag = S.diag_buffer(1)
+    tiles = _tiles(S, ctx, [halo], dev, S.SIDM_PREC_FP64)
+    for st in range(3):
+        S.sidm_kdk_step(ctx, [halo], dev, st, S.SIDM_PREC_FP64, diag=diag)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for st in range(steps):
+        S.sidm_kdk_step(ctx, [halo], dev, st, S.SIDM_PREC_FP64, diag=diag)
+    torch.cuda.synchronize()
+    eager = (time.perf_counter() - t0) / steps
+    stream = torch.cuda.Stream()
+    graph = torch.cuda.CUDAGraph()
+    S.sidm_diagnostics(ctx, [halo], dev, diag)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        graph.capture_begin()
+        S.sidm_kdk_step(ctx, [halo], dev, 0, S.SIDM_PREC_FP64, diag=diag)
+        graph.capture_end()
+    for _ in range(3):
+        graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    replay = (time.perf_counter() - t0) / steps
+    S.sidm_destroy(ctx)
+    inter = n * (n - 1)
+    out = {"metric": "per-step latency of the C1 step (FP64)", "value": eager * 1e3,
+           "unit": "ms/step", "n_gpus": 1, "steps": steps, "warmup": 3,
+           "ms_per_step": eager * 1e3, "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic NFW halo",
+           "config": {"workload": "C1: isolated NFW N=8192, eps=0.01, k=32, sigma/m=1, "
+                                  "dt=1e-3, FP64", "n": n},
+           "graph_replay_ms_per_step": replay * 1e3,
+           "interactions_per_s_eager": inter / eager, "tiles": tiles}
     print(json.dumps(out), flush=True)
 
 
@@ -342,7 +439,7 @@ def _bench_c4(a, S, torch, W):
                                                                   "sigma/m {1,10,50}, k {16..128}",
                                                      "n_total": total, "halos": 64},
            "sidm_particle_updates_per_s": total / ms, "dE_over_E": de, "events_last_step": events,
-           "pass_ms": passes}
+           "pass_ms": passes, "tiles": _run.tiles}
     print(json.dumps(out), flush=True)
 
 
@@ -493,6 +590,10 @@ def main():
     import workloads as W
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
+    _TUNE["mode"] = "tune" if a.tune else "cache"
+    _TUNE["shape"] = a.shape
+    if a.workload == "C1":
+        return _bench_c1(a, S, torch, W)
     if a.workload == "C3":
         return _bench_c3(a, S, torch, W)
     if a.workload == "C4":
@@ -519,10 +620,12 @@ def main():
 
     ms_mixed, de_mixed, passes, dlast, events = _run(S, torch, halos, s, S.SIDM_PREC_MIXED,
                                                      a.steps, a.warmup, True)
+    de_int_mixed, tiles_mixed = _run.rel_e_internal, _run.tiles
     fp64 = None
     if a.fp64_steps > 0:
         ms64, de64, p64, _, _ = _run(S, torch, halos, s, S.SIDM_PREC_FP64, a.fp64_steps, 1, True)
         fp64 = {"interactions_per_s": inter / ms64, "ms_per_step": ms64 * 1e3, "dE_over_E": de64,
+                "dEint_over_Eint": _run.rel_e_internal, "tiles": _run.tiles,
                 "gravity_tiles_ms": p64.get("gravity_tiles"),
                 "gravity_tiles_frac_fp64_peak":
                     FLOPS_PER_INTERACTION * inter / (p64["gravity_tiles"] * 1e-3) / 1e12
@@ -530,7 +633,9 @@ def main():
 
     tiles_s = passes["gravity_tiles"] * 1e-3
     achieved = FLOPS_PER_INTERACTION * inter / tiles_s / 1e12
-    roof = {"bound": "alu", "kernel": "k_grav_mixed<4>", "achieved": achieved,
+    shape = tiles_mixed
+    kname = f"k_grav_mixed<{shape['ireg']},{shape['threads']},{bool(shape['persistent'])}>"
+    roof = {"bound": "alu", "kernel": kname, "achieved": achieved,
             "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
             "traffic": None if overrides else _traffic(FLOPS_PER_INTERACTION * inter)}
 
@@ -554,6 +659,8 @@ def main():
                    **({"overrides": overrides} if overrides else {})},
         "sidm_particle_updates_per_s": n / ms_mixed,
         "dE_over_E": de_mixed,
+        "dEint_over_Eint": de_int_mixed,
+        "tiles": tiles_mixed,
         "events_last_step": events,
         "pass_ms": passes,
         "fp64": fp64,
