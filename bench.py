@@ -27,6 +27,10 @@ sys.path.insert(0, ROOT)
 FP32_PEAK_TFLOPS = 157.3      # MI355X vector FP32 (datasheet)
 FP64_PEAK_TFLOPS = 78.6       # MI355X vector FP64 (datasheet)
 FLOPS_PER_INTERACTION = 20    # 3 sub, 3 fma (r^2+eps^2), rsqrt, 4 mul/add, 3 fma
+# the symmetric tiles evaluate an unordered pair once for both members: 3 sub,
+# 3 fma, rsqrt, 2 mul, 3 fma + 1 add for each side = 26 flops, 13 per interaction
+SYM_FLOPS_PER_INTERACTION = 13
+SYM_MIN_N = 131072            # the library's default threshold of the symmetric tiles
 
 
 def _args():
@@ -40,6 +44,9 @@ def _args():
     ap.add_argument("--tune", action="store_true",
                     help="time every launch shape of the gravity tiles for the workload and "
                          "store the fastest in the tiles cache (default: read the cache only)")
+    ap.add_argument("--symmetric-min-n", type=int, default=None, metavar="N",
+                    help="halos of at least N particles take the symmetric tiles in mixed "
+                         "precision (0: none; default: the library's 131072)")
     ap.add_argument("--shape", default=None, metavar="IxT[p]",
                     help="force a launch shape of the gravity tiles, e.g. 4x256 or 2x128p "
                          "(p: persistent)")
@@ -97,13 +104,15 @@ def _internal_energy(d, mass):
     return d["K"] - 0.5 * p2 / mass + d["W"]
 
 
-_TUNE = {"mode": "cache", "shape": None}   # set from the command line
+_TUNE = {"mode": "cache", "shape": None, "sym_min_n": None}   # set from the command line
 
 
 def _tiles(S, ctx, halos, dev, prec):
     """Launch shape of the gravity tiles for this run: forced, timed (--tune,
     stored in the cache) or read from the cache (default; without an entry the
     default shape).  Computes the initial forces.  Returns the tuner's record."""
+    if _TUNE["sym_min_n"] is not None:
+        S.sidm_set_symmetric(ctx, _TUNE["sym_min_n"])
     if _TUNE["shape"]:
         spec = _TUNE["shape"]
         i, t = spec.rstrip("p").split("x")
@@ -130,7 +139,7 @@ def _log_step(S, run_label, step, dl, e0, passes):
         rec = {"run": run_label, "step": step, "halo": h, "E": _energy(d),
                "dE_over_E0": (_energy(d) - e0[h]) / abs(e0[h]) if e0[h] else None}
         rec.update({k: d[k] for k in ("K", "W", "Eext", "px", "py", "pz", "n_events",
-                                      "n_rounds", "n_pairs", "n_p_gt1", "status",
+                                      "n_rounds", "n_pairs", "n_p_gt1", "n_candidates", "status",
                                       "n_grav_terms")})
         rec["pass_ms"] = passes
         _LOG.write(json.dumps(rec) + "\n")
@@ -178,6 +187,7 @@ def _run(S, torch, halos, s, prec, steps, warmup, timing, progress=False):
     events = sum(x["n_events"] for x in dl)
     rel_e = abs(sum(_energy(x) for x in dl) - e0) / abs(e0)
     _run.rel_e_internal = abs(_internal_energy(d, mass0) - ei0) / abs(ei0)
+    _run.last = {k: sum(x[k] for x in dl) for k in ("n_pairs", "n_candidates", "n_p_gt1")}
     for k in passes:
         passes[k] /= steps
     S.sidm_destroy(ctx)
@@ -592,6 +602,7 @@ def main():
 
     _TUNE["mode"] = "tune" if a.tune else "cache"
     _TUNE["shape"] = a.shape
+    _TUNE["sym_min_n"] = a.symmetric_min_n
     if a.workload == "C1":
         return _bench_c1(a, S, torch, W)
     if a.workload == "C3":
@@ -620,7 +631,7 @@ def main():
 
     ms_mixed, de_mixed, passes, dlast, events = _run(S, torch, halos, s, S.SIDM_PREC_MIXED,
                                                      a.steps, a.warmup, True)
-    de_int_mixed, tiles_mixed = _run.rel_e_internal, _run.tiles
+    de_int_mixed, tiles_mixed, last_counts = _run.rel_e_internal, _run.tiles, _run.last
     fp64 = None
     if a.fp64_steps > 0:
         ms64, de64, p64, _, _ = _run(S, torch, halos, s, S.SIDM_PREC_FP64, a.fp64_steps, 1, True)
@@ -634,9 +645,20 @@ def main():
     tiles_s = passes["gravity_tiles"] * 1e-3
     achieved = FLOPS_PER_INTERACTION * inter / tiles_s / 1e12
     shape = tiles_mixed
-    kname = f"k_grav_mixed<{shape['ireg']},{shape['threads']},{bool(shape['persistent'])}>"
+    sym_min = SYM_MIN_N if _TUNE["sym_min_n"] is None else _TUNE["sym_min_n"]
+    sym = sym_min > 0 and n >= sym_min
+    if sym:
+        # each unordered pair once: 26 flops of which 13 per interaction are executed
+        jg = 1 if shape["ireg"] >= 8 else 8 // shape["ireg"]
+        kname = f"k_grav_sym<{shape['ireg']},{shape['threads']},{jg}>"
+    else:
+        kname = f"k_grav_mixed<{shape['ireg']},{shape['threads']},{bool(shape['persistent'])}>"
+    executed = (SYM_FLOPS_PER_INTERACTION if sym else FLOPS_PER_INTERACTION) * inter / tiles_s / 1e12
     roof = {"bound": "alu", "kernel": kname, "achieved": achieved,
             "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
+            "executed_flops_per_interaction": SYM_FLOPS_PER_INTERACTION if sym
+            else FLOPS_PER_INTERACTION,
+            "executed_frac": executed / FP32_PEAK_TFLOPS,
             "traffic": None if overrides else _traffic(FLOPS_PER_INTERACTION * inter)}
 
     out = {
@@ -662,6 +684,8 @@ def main():
         "dEint_over_Eint": de_int_mixed,
         "tiles": tiles_mixed,
         "events_last_step": events,
+        "pairs_last_step": last_counts["n_pairs"],
+        "candidates_last_step": last_counts["n_candidates"],
         "pass_ms": passes,
         "fp64": fp64,
         "roofline": roof,

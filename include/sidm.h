@@ -394,14 +394,31 @@ sidm_status sidm_take_status(sidm_ctx *ctx, int32_t *bits);
  * work items from an atomic ticket until none is left).  The j-splits follow
  * from the shape (a simulation of the items on the resident blocks).  The
  * results of the shapes agree to rounding; the default is 4 x 256, plain.
- * Cycles of block time steps run their ticks in the default shape. */
+ * Cycles of block time steps run their ticks in the default shape.  The
+ * symmetric tiles (sidm_set_symmetric) run in the same shape, always
+ * persistent. */
 sidm_status sidm_set_launch_shape(sidm_ctx *ctx, int32_t ireg, int32_t threads,
                                   int32_t persistent);
+
+/* Symmetric tiles.  The softened pair force of the direct sum (Sec. 2) is
+ * antisymmetric: the force of j on i is minus that of i on j.  In mixed precision
+ * the direct sum of a halo of at least min_n particles evaluates each
+ * unordered pair once and applies it to both members; the reactions are
+ * summed in 64-bit fixed point with integer atomics, so the result is
+ * deterministic: it does not depend on the order in which the work items
+ * finish.  The results agree with the one-sided tiles to FP32 rounding.
+ * Halos need a softening eps > 0.  min_n = 0 turns them off; the default is
+ * 131072.  FP64, tree halos and the ticks of a cycle of block time steps
+ * (when some direct-sum halo has max_bin > 0) use the one-sided sums.
+ * Changing it invalidates graphs captured before.  SIDM_ERR_INVALID for
+ * min_n < 0. */
+sidm_status sidm_set_symmetric(sidm_ctx *ctx, int64_t min_n);
 
 /* Chooses the shape for these halos and precision on this device: when
  * cache_path names a file that holds an entry for the key (device
  * architecture, compute units, precision, and the call's direct-sum size
- * class: log2 of its direct-sum particles and of its halos, rounded), that
+ * class: log2 of its direct-sum particles and of its halos, rounded; a mixed
+ * call with a halo that takes the symmetric tiles is keyed apart), that
  * entry; otherwise every shape is timed on the caller's state (the gravity
  * pass, best of a few runs; about 2 x 9 x 4 gravity passes) and the fastest is
  * kept and written to the cache (a JSON object, one entry per key; the file

@@ -42,7 +42,7 @@ EXPORTED = ("sidm_create", "sidm_destroy", "sidm_set_event_capacity", "sidm_stat
             "sidm_last_error", "sidm_gravity", "sidm_knn_h", "sidm_scatter", "sidm_kdk_step",
             "sidm_diagnostics", "sidm_central_density", "sidm_tidal_radius", "sidm_enable_timing",
             "sidm_pass_times", "sidm_last_events", "sidm_take_status", "sidm_gravity_static",
-            "sidm_set_launch_shape", "sidm_autotune")
+            "sidm_set_launch_shape", "sidm_autotune", "sidm_set_symmetric")
 SIDM_TUNE_FORCE = 1
 SIDM_TUNE_QUICK = 2
 SIDM_TUNE_CACHE_ONLY = 4
@@ -142,6 +142,7 @@ def lib():
         L.sidm_take_status.argtypes = [vp, C.POINTER(i32)]
         L.sidm_gravity_static.argtypes = [hp, sp, C.c_int, vp]
         L.sidm_set_launch_shape.argtypes = [vp, i32, i32, i32]
+        L.sidm_set_symmetric.argtypes = [vp, i64]
         L.sidm_autotune.argtypes = [vp, hp, i32, sp, C.c_int, C.c_char_p, i32,
                                     C.POINTER(SidmTuneResult), vp]
         for name in EXPORTED:
@@ -272,6 +273,12 @@ def sidm_set_launch_shape(ctx, ireg, threads, persistent=False):
     """Launch shape of the direct-sum gravity tiles (see SHAPES)."""
     _check(ctx, lib().sidm_set_launch_shape(ctx.handle, int(ireg), int(threads),
                                             1 if persistent else 0))
+
+
+def sidm_set_symmetric(ctx, min_n):
+    """Mixed-precision direct sums of halos with at least min_n particles use
+    the symmetric tiles (0: never)."""
+    _check(ctx, lib().sidm_set_symmetric(ctx.handle, int(min_n)))
 
 
 def sidm_autotune(ctx, halos, state, prec=SIDM_PREC_MIXED, cache_path=None, flags=0,

@@ -46,6 +46,7 @@ hipError_t launch_gravity(bool mixed, const Plan& P, Scratch& w, const sidm_stat
                           int bmax = 0);
 int64_t gravity_slots(int device);
 int64_t gravity_slots(int device, const GravShape& shape, bool mixed);
+int64_t gravity_sym_slots(int device, const GravShape& shape);
 hipError_t launch_cell_list(const Plan& plan, const sidm_state* s, Scratch& w, hipStream_t st,
                             int tick = 0, int bmax = 0);
 hipError_t launch_knn(const Plan& plan, const sidm_state* s, Scratch& w, uint32_t* nbr, int k_max,
@@ -91,6 +92,7 @@ struct sidm_ctx {
     uint64_t fp_eager = 0;
     bool fp_valid = false;
     GravShape shape;                  // launch shape of the direct-sum tiles
+    int64_t sym_min_n = kSymMinN;     // smallest halo of the symmetric tiles (0: none)
 };
 
 namespace {
@@ -198,14 +200,21 @@ sidm_status ensure_plan(sidm_ctx* c, const sidm_halo* halos, int32_t n_halos, hi
     std::string why;
     const GravItem* items_tick = c->w.items_tick;
     const double4* partial_tick = c->w.partial_tick;
+    const SymItem* sym_items = c->w.sym_items;
+    const unsigned long long* symacc = c->w.symacc;
     c->w.slots_mixed = gravity_slots(c->device, c->shape, true);
     c->w.slots_fp64 = gravity_slots(c->device, c->shape, false);
-    if (!build_plan(c->plan, c->w, halos, n_halos, c->shape, c->w.slots_mixed, why) ||
-        !ensure_tick_tables(c->w, c->plan, why)) {
+    c->w.slots_sym = c->sym_min_n > 0 ? gravity_sym_slots(c->device, c->shape) : 0;
+    if (!build_plan(c->plan, c->w, halos, n_halos, c->shape, c->w.slots_mixed, why, c->sym_min_n,
+                    c->w.slots_sym) ||
+        !ensure_tick_tables(c->w, c->plan, why) || !ensure_sym_tables(c->w, c->plan, why)) {
+        c->plan_valid = false;
         set_err(c, "%s", why.c_str());
         return SIDM_ERR_CAPACITY;
     }
-    if (items_tick != c->w.items_tick || partial_tick != c->w.partial_tick) ++c->scratch_gen;
+    if (items_tick != c->w.items_tick || partial_tick != c->w.partial_tick ||
+        sym_items != c->w.sym_items || symacc != c->w.symacc)
+        ++c->scratch_gen;
     hipError_t e = upload_plan(c->plan, c->w);
     if (e != hipSuccess) return hip_fail(c, e, "uploading the launch plan");
     c->plan_key.assign(halos, halos + n_halos);
@@ -757,7 +766,10 @@ bool shape_supported(int ireg, int nt)
 // Key of a tuning-cache entry: device architecture and compute units,
 // precision, and the call's direct-sum size class (log2 of the particles in
 // direct-sum halos, and of the number of halos, both rounded to nearest).
-std::string tune_key(int device, const sidm_halo* halos, int32_t n_halos, sidm_precision prec)
+// sym_min_n: the context's threshold of the symmetric tiles; a mixed call
+// with a halo that takes them is keyed apart (":sym"), as it times them.
+std::string tune_key(int device, const sidm_halo* halos, int32_t n_halos, sidm_precision prec,
+                     int64_t sym_min_n)
 {
     hipDeviceProp_t prop;
     std::string arch = "unknown";
@@ -770,16 +782,21 @@ std::string tune_key(int device, const sidm_halo* halos, int32_t n_halos, sidm_p
     }
     double ndir = 0.0;
     int nh = 0;
+    bool sym = false;
     for (int32_t h = 0; h < n_halos; ++h)
         if (!(halos[h].tree_alpha > 0.0)) {
             ndir += (double)halos[h].n;
             ++nh;
+            if (sym_min_n > 0 && halos[h].n >= std::max<int64_t>(sym_min_n, 2) &&
+                halos[h].eps > 0.0)
+                sym = true;
         }
     const int ln = ndir > 0.0 ? (int)std::lround(std::log2(ndir)) : 0;
     const int lh = nh > 0 ? (int)std::lround(std::log2((double)nh)) : 0;
     char buf[160];
-    snprintf(buf, sizeof buf, "%s:%dcu:%s:n2^%d:h2^%d", arch.c_str(), cus,
-             prec == SIDM_PREC_MIXED ? "mixed" : "fp64", ln, lh);
+    snprintf(buf, sizeof buf, "%s:%dcu:%s:n2^%d:h2^%d%s", arch.c_str(), cus,
+             prec == SIDM_PREC_MIXED ? "mixed" : "fp64", ln, lh,
+             prec == SIDM_PREC_MIXED && sym ? ":sym" : "");
     return buf;
 }
 
@@ -869,6 +886,23 @@ sidm_status sidm_set_launch_shape(sidm_ctx* c, int32_t ireg, int32_t threads, in
     if (s.ireg != c->shape.ireg || s.nt != c->shape.nt || s.persist != c->shape.persist) {
         c->shape = s;
         c->plan_valid = false;   // the work items follow the shape
+        ++c->scratch_gen;        // graphs captured before launch the old shape
+    }
+    c->err.clear();
+    return SIDM_OK;
+}
+
+sidm_status sidm_set_symmetric(sidm_ctx* c, int64_t min_n)
+{
+    if (!c) return SIDM_ERR_INVALID;
+    if (min_n < 0) {
+        set_err(c, "min_n must be >= 0");
+        return SIDM_ERR_INVALID;
+    }
+    if (min_n != c->sym_min_n) {
+        c->sym_min_n = min_n;
+        c->plan_valid = false;
+        ++c->scratch_gen;
     }
     c->err.clear();
     return SIDM_OK;
@@ -890,7 +924,7 @@ sidm_status sidm_autotune(sidm_ctx* c, const sidm_halo* halos, int32_t n_halos,
         set_err(c, "the tuner times launches: not possible during stream capture");
         return SIDM_ERR_INVALID;
     }
-    const std::string key = tune_key(c->device, halos, n_halos, prec);
+    const std::string key = tune_key(c->device, halos, n_halos, prec, c->sym_min_n);
     sidm_tune_result res;
     std::memset(&res, 0, sizeof res);
     snprintf(res.key, sizeof res.key, "%s", key.c_str());

@@ -39,6 +39,12 @@ constexpr int kNumShapes = 9;
 constexpr int kShapeIreg[kNumShapes] = {2, 4, 8, 2, 4, 8, 2, 4, 8};
 constexpr int kShapeNt[kNumShapes] = {128, 128, 128, 256, 256, 256, 512, 512, 512};
 
+// Symmetric tiles (the mixed direct sums of large halos, each unordered pair
+// evaluated once) run in the launch shape of the one-sided tiles; by default
+// halos of at least kSymMinN particles take them.
+constexpr int64_t kSymMinN = 131072;
+constexpr int kSymFold = 2;           // j-tiles per flush of the i-side sums
+
 // Per-halo parameters and derived layout, uploaded once per halo configuration.
 struct HaloDev {
     int64_t offset, n;
@@ -64,7 +70,7 @@ struct HaloDev {
     int64_t stream_block0;                // first streaming block of this halo
     int64_t sbase;                        // first position in the sorted (compact) order
     int32_t rank;                         // halo rank by offset (high bits of the sort key)
-    int32_t pad0;
+    int32_t grav_sym;                     // mixed direct sums run the symmetric tiles
     int32_t win_lo, win_hi;               // kNN bound window, in buckets around b
     int32_t pad;
 };
@@ -82,6 +88,16 @@ struct GravItem {
     int64_t j0, j1;                       // j range (global indices), tile aligned
     int32_t halo;
     int32_t slot;                         // which partial row set
+};
+
+// One work item of the symmetric tiles: the i-block [i0, i0 + ireg * nt) of one
+// halo against the j-range [j0, j1) with j0 >= i0 (global indices, tile
+// aligned); its tiles inside the i-block are summed one-sided.
+struct SymItem {
+    int64_t i0;
+    int64_t j0, j1;
+    int32_t halo;
+    int32_t pad;
 };
 
 struct BucketInfo {

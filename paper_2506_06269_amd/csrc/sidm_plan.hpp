@@ -91,6 +91,13 @@ struct Scratch {
     int64_t partial_tick_rows = 0;
     int64_t grav_slots = 0;       // resident blocks of the gravity tiles on the whole device
     int64_t slots_mixed = 0, slots_fp64 = 0;   // of the plan's shape, per precision
+    // symmetric tiles: work items, fixed-point totals (4 per sorted particle),
+    // resident blocks
+    SymItem* sym_items = nullptr;
+    int64_t sym_items_cap = 0;
+    unsigned long long* symacc = nullptr;
+    int64_t symacc_n = 0;
+    int64_t slots_sym = 0;
     // cell list
     unsigned long long* keys[2] = {nullptr, nullptr};
     uint32_t* vals[2] = {nullptr, nullptr};
@@ -138,7 +145,10 @@ struct Plan {
     int64_t sort_blocks = 0;
     std::vector<HaloDev> halos;
     std::vector<StreamBlock> blocks;
-    std::vector<GravItem> items;
+    std::vector<GravItem> items;          // one-sided: the halos without symmetric tiles first
+    int64_t n_items_nosym = 0;            // items of the halos without symmetric tiles
+    std::vector<SymItem> sym_items;       // symmetric tiles (mixed precision)
+    int64_t n_sym_items = 0;
     std::vector<GravItem> items_tick;     // block-step ticks (empty without block steps)
     int64_t tick_rows = 0;                // partial rows the tick items need
     std::vector<BucketInfo> buckets;
@@ -248,6 +258,8 @@ inline void free_scratch(Scratch& w)
     dfree(w.sub); dfree(w.sub_n);
     dfree(w.owner); dfree(w.events); dfree(w.cands); dfree(w.counters); dfree(w.ev_counts); dfree(w.status);
     dfree(w.sticky); dfree(w.fp_dev);
+    dfree(w.sym_items); dfree(w.symacc);
+    w.sym_items_cap = w.symacc_n = 0;
 }
 
 // The physical parameters of a halo (the layout fields stay zero).
@@ -421,8 +433,46 @@ inline void choose_splits(std::vector<HaloDev>& hd, int64_t partial_rows, int64_
     }
 }
 
+// Symmetric tiles: marks the halos large enough for them (softened, direct
+// sum, at least sym_min_n particles; none for sym_min_n = 0) and cuts their
+// work: each i-block of ireg * nt against the j from its own start to the
+// halo's end, in ranges of L (a multiple of nt, at least four i-blocks),
+// about 32 items per resident block over all such halos, largest first.
+inline void make_sym_items(std::vector<HaloDev>& halos, const GravShape& shape,
+                           int64_t sym_min_n, int64_t sym_slots, std::vector<SymItem>& items)
+{
+    items.clear();
+    if (sym_min_n <= 0 || sym_slots <= 0) return;
+    const int64_t sym_i = (int64_t)shape.ireg * shape.nt;
+    double pairs = 0.0;
+    for (auto& H : halos)
+        if (!(H.tree_alpha > 0.0) && H.n >= std::max<int64_t>(sym_min_n, 2) && H.eps > 0.0) {
+            H.grav_sym = 1;
+            pairs += 0.5 * (double)H.n * (double)H.n;
+        }
+    const double target = pairs / (32.0 * (double)sym_slots * (double)sym_i);
+    for (int h = 0; h < (int)halos.size(); ++h) {
+        const HaloDev& H = halos[h];
+        if (!H.grav_sym) continue;
+        int64_t L = (int64_t)std::min<double>(target, (double)H.n);
+        L = std::max<int64_t>(L, 4 * sym_i);
+        L = (L + shape.nt - 1) / shape.nt * shape.nt;
+        for (int64_t i0 = 0; i0 < H.n; i0 += sym_i)
+            for (int64_t j0 = i0; j0 < H.n; j0 += L)
+                items.push_back({H.offset + i0, H.offset + j0,
+                                 H.offset + std::min<int64_t>(H.n, j0 + L), h, 0});
+    }
+    std::stable_sort(items.begin(), items.end(), [](const SymItem& a, const SymItem& b) {
+        return (a.j1 - a.j0) > (b.j1 - b.j0);
+    });
+}
+
+// sym_min_n: direct-sum halos of at least that many particles take the
+// symmetric tiles in mixed precision (0: none); sym_slots: resident blocks of
+// those tiles, which sets how finely their j-ranges are cut.
 inline bool build_plan(Plan& P, const Scratch& w, const sidm_halo* halos, int32_t n_halos,
-                       const GravShape& shape, int64_t slots, std::string& why)
+                       const GravShape& shape, int64_t slots, std::string& why,
+                       int64_t sym_min_n = 0, int64_t sym_slots = 0)
 {
     P = Plan();
     P.shape = shape;
@@ -554,11 +604,19 @@ inline bool build_plan(Plan& P, const Scratch& w, const sidm_halo* halos, int32_
         }
         P.tick_rows = trow;
     }
-    // largest items first so that the uneven tail is short; a tick's active
-    // i-blocks come first, so its items are ordered by i-block within a j size
-    std::stable_sort(P.items.begin(), P.items.end(), [](const GravItem& a, const GravItem& b) {
+    make_sym_items(P.halos, shape, sym_min_n, sym_slots, P.sym_items);
+    P.n_sym_items = (int64_t)P.sym_items.size();
+    // largest items first so that the uneven tail is short, those of the halos
+    // without symmetric tiles ahead of the others; a tick's active i-blocks
+    // come first, so its items are ordered by i-block within a j size
+    std::stable_sort(P.items.begin(), P.items.end(), [&](const GravItem& a, const GravItem& b) {
+        const int sa = P.halos[a.halo].grav_sym, sb = P.halos[b.halo].grav_sym;
+        if (sa != sb) return sa < sb;
         return (a.j1 - a.j0) > (b.j1 - b.j0);
     });
+    P.n_items_nosym = 0;
+    for (const auto& it : P.items)
+        if (!P.halos[it.halo].grav_sym) ++P.n_items_nosym;
     std::stable_sort(P.items_tick.begin(), P.items_tick.end(),
                      [](const GravItem& a, const GravItem& b) { return a.i0 < b.i0; });
     P.n_items = (int64_t)P.items.size();
@@ -604,6 +662,31 @@ inline bool ensure_tick_tables(Scratch& w, const Plan& P, std::string& why)
     return true;
 }
 
+// Tables of the symmetric tiles, sized on the first plan that needs them.
+inline bool ensure_sym_tables(Scratch& w, const Plan& P, std::string& why)
+{
+    if (P.n_sym_items == 0) return true;
+    if (P.n_sym_items > w.sym_items_cap) {
+        dfree(w.sym_items);
+        w.sym_items_cap = 0;
+        if (!dalloc(w.sym_items, P.n_sym_items)) {
+            why = "out of device memory for the symmetric work items";
+            return false;
+        }
+        w.sym_items_cap = P.n_sym_items;
+    }
+    if (P.n_sorted > w.symacc_n) {
+        dfree(w.symacc);
+        w.symacc_n = 0;
+        if (!dalloc(w.symacc, 4 * P.n_sorted)) {
+            why = "out of device memory for the symmetric tiles' totals";
+            return false;
+        }
+        w.symacc_n = P.n_sorted;
+    }
+    return true;
+}
+
 inline hipError_t upload_plan(const Plan& P, const Scratch& w)
 {
     hipError_t e = hipMemcpy(w.halos, P.halos.data(), sizeof(HaloDev) * P.halos.size(),
@@ -619,6 +702,9 @@ inline hipError_t upload_plan(const Plan& P, const Scratch& w)
                       hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(w.nodes, P.nodes.data(), sizeof(NodeChild) * P.nodes.size(),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess && !P.sym_items.empty())
+        e = hipMemcpy(w.sym_items, P.sym_items.data(), sizeof(SymItem) * P.sym_items.size(),
                       hipMemcpyHostToDevice);
     if (e == hipSuccess && !P.items_tick.empty())
         e = hipMemcpy(w.items_tick, P.items_tick.data(), sizeof(GravItem) * P.items_tick.size(),

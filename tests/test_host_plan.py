@@ -3,6 +3,8 @@ with g++): the number of j-splits of the gravity sums is the one whose work
 items, started largest first on the device's resident blocks, finish
 soonest; checked against an independent list-scheduling simulation."""
 import ctypes as C
+
+import numpy as np
 import heapq
 import os
 import subprocess
@@ -23,6 +25,26 @@ extern "C" int plan_split(int nh, const long long* n, long long slots, long long
     shape.nt = nt;
     sidm::choose_splits(hd, partial_rows, slots, shape);
     return hd[0].grav_split;
+}
+extern "C" long long plan_sym(int nh, const long long* n, const long long* off, const double* eps,
+                              const double* alpha, long long min_n, long long slots, int ireg,
+                              int nt, long long* out, long long cap, int* flags) {
+    std::vector<sidm::HaloDev> hd(nh);
+    for (int h = 0; h < nh; ++h) {
+        std::memset(&hd[h], 0, sizeof(hd[h]));
+        hd[h].n = n[h]; hd[h].offset = off[h]; hd[h].eps = eps[h]; hd[h].tree_alpha = alpha[h];
+    }
+    sidm::GravShape shape;
+    shape.ireg = ireg;
+    shape.nt = nt;
+    std::vector<sidm::SymItem> items;
+    sidm::make_sym_items(hd, shape, min_n, slots, items);
+    for (int h = 0; h < nh; ++h) flags[h] = hd[h].grav_sym;
+    for (size_t k = 0; k < items.size() && (long long)k < cap; ++k) {
+        out[4 * k + 0] = items[k].i0; out[4 * k + 1] = items[k].j0;
+        out[4 * k + 2] = items[k].j1; out[4 * k + 3] = items[k].halo;
+    }
+    return (long long)items.size();
 }
 '''
 
@@ -89,3 +111,61 @@ def test_split_known_cases(L):
     assert _split(L, [1 << 20], 512) == 1
     # without an occupancy figure: enough items to fill the chip
     assert _split(L, [1 << 20], 0) == 2
+
+
+def _sym(L, ns, offs, eps, alpha, min_n, slots, ireg, nt):
+    nh = len(ns)
+    A = lambda t, v: (t * nh)(*v)
+    cap = 1 << 20
+    out = (C.c_longlong * (4 * cap))()
+    flags = (C.c_int * nh)()
+    L.plan_sym.restype = C.c_longlong
+    cnt = L.plan_sym(nh, A(C.c_longlong, ns), A(C.c_longlong, offs), A(C.c_double, eps),
+                     A(C.c_double, alpha), min_n, slots, ireg, nt, out, cap, flags)
+    items = [tuple(out[4 * k:4 * k + 4]) for k in range(cnt)]
+    return items, list(flags)
+
+
+@pytest.mark.parametrize("ireg,nt", [(2, 128), (4, 256), (8, 512)])
+def test_symmetric_items_cover_every_pair_once(L, ireg, nt):
+    """Each unordered pair of a halo that takes the symmetric tiles falls in
+    exactly one item: a pair of different i-blocks in the item of the lower
+    block whose j-range holds the other, a pair inside one i-block in that
+    block's own first tiles (summed one-sided there).  Items start at tile
+    boundaries, never before their i-block, and come largest first; halos below
+    the threshold, with a tree or without softening take none."""
+    S = ireg * nt
+    ns = [3 * S + 17, 5 * S, S - 3, 7000, 900, 2 * S + 1]
+    offs, o = [], 0
+    for n in ns:
+        offs.append(o)
+        o += n + 5
+    eps = [0.01, 0.01, 0.01, 0.0, 0.01, 0.01]
+    alpha = [0.0, 0.0, 0.0, 0.0, 0.0, 5e-4]
+    items, flags = _sym(L, ns, offs, eps, alpha, 1000, 40, ireg, nt)
+    expect = [1 if (n >= 1000 and e > 0 and a == 0) else 0 for n, e, a in zip(ns, eps, alpha)]
+    assert flags == expect
+    lengths = [j1 - j0 for (_, j0, j1, _) in items]
+    assert lengths == sorted(lengths, reverse=True)
+    for h, (n, off) in enumerate(zip(ns, offs)):
+        mine = [it for it in items if it[3] == h]
+        if not flags[h]:
+            assert not mine
+            continue
+        nb = -(-n // S)
+        cover = np.zeros((nb, n), dtype=np.int32)   # i-block x j
+        for i0, j0, j1, _ in mine:
+            bi = (i0 - off) // S
+            assert (i0 - off) % S == 0 and j0 >= i0 and j1 <= off + n
+            assert (j0 - off) % nt == 0 and ((j1 - off) % nt == 0 or j1 == off + n)
+            cover[bi, j0 - off:j1 - off] += 1
+        for bi in range(nb):
+            assert np.all(cover[bi, :bi * S] == 0)       # pairs with earlier blocks: theirs
+            assert np.all(cover[bi, bi * S:] == 1)       # own block and every later j, once
+
+
+def test_symmetric_items_off(L):
+    items, flags = _sym(L, [5000, 8000], [0, 5000], [0.01, 0.01], [0.0, 0.0], 0, 64, 4, 256)
+    assert items == [] and flags == [0, 0]
+    items, flags = _sym(L, [5000, 8000], [0, 5000], [0.01, 0.01], [0.0, 0.0], 6000, 64, 4, 256)
+    assert flags == [0, 1] and all(it[3] == 1 for it in items)
