@@ -173,9 +173,10 @@ inline void dfree(T*& p)
     p = nullptr;
 }
 
-// Events and the candidates of the exact decision (four per event slot: a
-// pair's draw falls below the bound some ten times as often as below P, and
-// the event buffer holds N/8 by default).
+// Events and the candidates of the exact decision (four per event slot: at the
+// benchmark's density a pair's draw falls below the bound some 70 times as
+// often as below P, and the default event buffer, N/8, holds about 50 times
+// a step's events; an overflow only costs a second pair pass).
 inline bool realloc_events(Scratch& w, int64_t max_events, std::string& why)
 {
     dfree(w.events);
