@@ -120,7 +120,7 @@ def _tiles(S, ctx, halos, dev, prec):
         S.sidm_gravity(ctx, halos, dev, prec)
         return {"ireg": int(i), "threads": int(t), "persistent": int(spec.endswith("p")),
                 "source": "forced"}
-    flags = 0 if _TUNE["mode"] == "tune" else S.SIDM_TUNE_CACHE_ONLY
+    flags = S.SIDM_TUNE_FORCE if _TUNE["mode"] == "tune" else S.SIDM_TUNE_CACHE_ONLY
     r = S.sidm_autotune(ctx, halos, dev, prec, S.TILES_CACHE, flags)
     r["source"] = "timed" if r["n_tried"] else ("cache" if r["from_cache"] else "default")
     return r

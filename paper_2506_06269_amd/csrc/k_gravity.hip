@@ -454,6 +454,71 @@ __device__ inline void tile_sym(const float4* __restrict__ tile, int ja, int jb,
     }
 }
 
+// The same with one j per wave sum, software-pipelined: the wave sum of the
+// previous j's reaction is formed while the pairs of the next j are evaluated
+// (the two are independent, so their instructions interleave).
+template <int IREG, bool EQM>
+__device__ inline void tile_sym1(const float4* __restrict__ tile, int ja, int jb, const float* qx,
+                                 const float* qy, const float* qz, const float* mi, float eps2,
+                                 float* px, float* py, float* pz, float* pp, float (*jp)[4],
+                                 int lane)
+{
+    if (ja >= jb) return;
+    const int rl = lane & 15, comp = sym_row_comp(lane >> 4);
+    auto pairs = [&](int j, float (&v)[4]) {
+        const float4 p = tile[j];
+        float rx = 0.f, ry = 0.f, rz = 0.f, rp = 0.f;
+#pragma unroll
+        for (int r = 0; r < IREG; ++r) {
+            const float dx = p.x - qx[r];
+            const float dy = p.y - qy[r];
+            const float dz = p.z - qz[r];
+            const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
+            const float rinv = __builtin_amdgcn_rsqf(r2);
+            const float w = rinv * (rinv * rinv);
+            if (EQM) {
+                px[r] = fmaf(w, dx, px[r]);
+                py[r] = fmaf(w, dy, py[r]);
+                pz[r] = fmaf(w, dz, pz[r]);
+                pp[r] += rinv;
+                rx = fmaf(w, dx, rx);
+                ry = fmaf(w, dy, ry);
+                rz = fmaf(w, dz, rz);
+                rp += rinv;
+            } else {
+                const float wj = p.w * w, wi = mi[r] * w;
+                px[r] = fmaf(wj, dx, px[r]);
+                py[r] = fmaf(wj, dy, py[r]);
+                pz[r] = fmaf(wj, dz, pz[r]);
+                pp[r] = fmaf(p.w, rinv, pp[r]);
+                rx = fmaf(wi, dx, rx);
+                ry = fmaf(wi, dy, ry);
+                rz = fmaf(wi, dz, rz);
+                rp = fmaf(mi[r], rinv, rp);
+            }
+        }
+        v[0] = rx;
+        v[1] = ry;
+        v[2] = rz;
+        v[3] = rp;
+    };
+    auto finish = [&](int j, const float (&v)[4]) {
+        float x[1];
+        wave_sum<1>(v, x);
+        if (rl == 0) jp[j][comp] = x[0];
+    };
+    float prev[4];
+    pairs(ja, prev);
+    for (int j = ja + 1; j < jb; ++j) {
+        float cur[4];
+        pairs(j, cur);
+        finish(j - 1, prev);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) prev[c] = cur[c];
+    }
+    finish(jb - 1, prev);
+}
+
 template <int IREG, int NT>
 struct SymLds {
     float4 tile[NT];
@@ -542,6 +607,9 @@ __device__ inline void grav_sym_body(const float4* __restrict__ xm32,
                 if (diag)
                     tile_f32<IREG, NT, EQM, true, 1>(L.tile, ja, jb, qx, qy, qz, eps2, j0, it.i0,
                                                      t, px, py, pz, pp);
+                else if (JG == 1)
+                    tile_sym1<IREG, EQM>(L.tile, ja, jb, qx, qy, qz, mi, eps2, px, py, pz, pp,
+                                         L.jpart[wave], lane);
                 else
                     tile_sym<IREG, JG, EQM>(L.tile, ja, jb, qx, qy, qz, mi, eps2, px, py, pz, pp,
                                             L.jpart[wave], lane);
@@ -592,9 +660,12 @@ __device__ inline void grav_sym_body(const float4* __restrict__ xm32,
 // ticket counter until none is left.  The fixed-point totals (4 per sorted
 // particle) start at zero.  EQM: the items of halos with one common mass
 // (masses factored out); the other instantiation takes the rest.  Both run,
-// each skipping the other's items.
+// each skipping the other's items.  At least kSymWaves waves per SIMD: the
+// compiler keeps 128 registers and moves the values used once per frame
+// (positions, frame indices) to scratch, which left the pair loop intact and
+// was faster than fewer waves with everything in registers.
 template <int IREG, int NT, int JG, bool EQM>
-__global__ __launch_bounds__(NT) void k_grav_sym(
+__global__ __launch_bounds__(NT, kSymWaves) void k_grav_sym(
     const float4* __restrict__ xm32, const SubRange* __restrict__ sub,
     const int* __restrict__ sub_n, const SymItem* __restrict__ items, int64_t n_items,
     unsigned long long* __restrict__ ticket, const HaloDev* __restrict__ halos,

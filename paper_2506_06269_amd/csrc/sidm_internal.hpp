@@ -44,6 +44,7 @@ constexpr int kShapeNt[kNumShapes] = {128, 128, 128, 256, 256, 256, 512, 512, 51
 // halos of at least kSymMinN particles take them.
 constexpr int64_t kSymMinN = 131072;
 constexpr int kSymFold = 2;           // j-tiles per flush of the i-side sums
+constexpr int kSymWaves = 4;          // waves per SIMD the symmetric tiles are compiled for
 
 // Per-halo parameters and derived layout, uploaded once per halo configuration.
 struct HaloDev {
