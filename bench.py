@@ -274,16 +274,24 @@ def _host_cpu():
             "affinity": len(os.sched_getaffinity(0))}
 
 
+def _kernel_source_sha():
+    """SHA-256 of the gravity kernels' sources: the kernels, the constants they
+    are compiled with and the planner that cuts their work items."""
+    h = hashlib.sha256()
+    for name in ("k_gravity.hip", "sidm_internal.hpp", "sidm_plan.hpp"):
+        with open(os.path.join(ROOT, "paper_2506_06269_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def _traffic(per_launch_flops):
     """HBM bytes per launch of the gravity tiles from committed rocprofv3
     counter runs, if taken on the current kernel source."""
     path = os.path.join(ROOT, "profiles", "traffic_grav_mixed_c2.json")
-    src = os.path.join(ROOT, "paper_2506_06269_amd", "csrc", "k_gravity.hip")
     try:
         with open(path) as f:
             rec = json.load(f)
-        with open(src, "rb") as f:
-            h = hashlib.sha256(f.read()).hexdigest()
+        h = _kernel_source_sha()
         if rec.get("kernel_source_sha256") != h:
             return None
         return rec.get("bytes_per_launch")

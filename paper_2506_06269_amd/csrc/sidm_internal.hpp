@@ -43,7 +43,7 @@ constexpr int kShapeNt[kNumShapes] = {128, 128, 128, 256, 256, 256, 512, 512, 51
 // evaluated once) run in the launch shape of the one-sided tiles; by default
 // halos of at least kSymMinN particles take them.
 constexpr int64_t kSymMinN = 131072;
-constexpr int kSymFold = 2;           // j-tiles per flush of the i-side sums
+constexpr int kSymFold = 4;           // j-tiles per flush of the i-side sums
 constexpr int kSymWaves = 4;          // waves per SIMD the symmetric tiles are compiled for
 
 // Per-halo parameters and derived layout, uploaded once per halo configuration.
