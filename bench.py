@@ -30,7 +30,7 @@ FLOPS_PER_INTERACTION = 20    # 3 sub, 3 fma (r^2+eps^2), rsqrt, 4 mul/add, 3 fm
 # the symmetric tiles evaluate an unordered pair once for both members: 3 sub,
 # 3 fma, rsqrt, 2 mul, 3 fma + 1 add for each side = 26 flops, 13 per interaction
 SYM_FLOPS_PER_INTERACTION = 13
-SYM_MIN_N = 131072            # the library's default threshold of the symmetric tiles
+SYM_MIN_N = 4096              # the library's default threshold of the symmetric tiles
 
 
 def _args():
@@ -46,7 +46,7 @@ def _args():
                          "store the fastest in the tiles cache (default: read the cache only)")
     ap.add_argument("--symmetric-min-n", type=int, default=None, metavar="N",
                     help="halos of at least N particles take the symmetric tiles in mixed "
-                         "precision (0: none; default: the library's 131072)")
+                         "precision (0: none; default: the library's 4096)")
     ap.add_argument("--shape", default=None, metavar="IxT[p]",
                     help="force a launch shape of the gravity tiles, e.g. 4x256 or 2x128p "
                          "(p: persistent)")

@@ -408,7 +408,7 @@ sidm_status sidm_set_launch_shape(sidm_ctx *ctx, int32_t ireg, int32_t threads,
  * deterministic: it does not depend on the order in which the work items
  * finish.  The results agree with the one-sided tiles to FP32 rounding.
  * Halos need a softening eps > 0.  min_n = 0 turns them off; the default is
- * 131072.  FP64, tree halos and the ticks of a cycle of block time steps
+ * 4096.  FP64, tree halos and the ticks of a cycle of block time steps
  * (when some direct-sum halo has max_bin > 0) use the one-sided sums.
  * Changing it invalidates graphs captured before.  SIDM_ERR_INVALID for
  * min_n < 0. */

@@ -42,7 +42,7 @@ constexpr int kShapeNt[kNumShapes] = {128, 128, 128, 256, 256, 256, 512, 512, 51
 // Symmetric tiles (the mixed direct sums of large halos, each unordered pair
 // evaluated once) run in the launch shape of the one-sided tiles; by default
 // halos of at least kSymMinN particles take them.
-constexpr int64_t kSymMinN = 131072;
+constexpr int64_t kSymMinN = 4096;
 constexpr int kSymFold = 4;           // j-tiles per flush of the i-side sums
 constexpr int kSymWaves = 4;          // waves per SIMD the symmetric tiles are compiled for
 
