@@ -7,20 +7,29 @@
 // Candidates are read with wave-uniform loads (every lane evaluates the same
 // candidate), and a candidate sub-range is visited only if
 // it intersects the search sphere of at least one lane.
-// Selection works on values only, with a private 32-bin histogram per lane
-// (an LDS column, written with LDS atomics that return nothing):
-//   1. a histogram of the distances within a starting radius: 1.15 times the
-//      kernel size the particle had before the call when that is a usable
-//      value (a warm start: the result does not depend on it); otherwise the
-//      first member of the particle's compact sub-range is resolved first,
-//      from an estimate out of the nearest members of that sub-range, and
-//      the particle starts from 1.15 times that member's h; the radius grows
-//      until the sphere holds k others;
+// Selection works on values only.  When the particle's kernel size before
+// the call is a usable value h0 (a warm start: the result does not depend on
+// it), one visit of the sphere of radius (1 + d) h0 counts the candidates
+// closer than (1 - d) h0 and keeps the distances in between (the band: its
+// kKnnBand smallest values, in an LDS column of the lane); if the k-th
+// distance lies in the band and among the kept values, it is read off them.
+// In a step h changes by a few tenths of a per cent (a few per cent at the
+// tail), so almost every lane ends here.  The other lanes, and lanes without
+// a usable h0, take the general search, with a private 32-bin histogram per
+// lane (an LDS column, written with LDS atomics that return nothing):
+//   1. a histogram of the distances within a starting radius: 1.15 times h0
+//      when it is usable; otherwise the first member of the particle's
+//      compact sub-range is resolved first, from an estimate out of the
+//      nearest members of that sub-range, and the particle starts from 1.15
+//      times that member's h; the radius grows until the sphere holds k
+//      others;
 //   2. a visit restricted to the shell of the bin that holds the k-th
 //      collects that bin's members (at most 16, kept sorted in registers) or,
 //      if it holds more, records their min..max, whose histogram (step 1 over
 //      that range) refines the choice; equal values end the refinement.
-// Typical cost: two visits of the candidates around the bucket.
+// Typical cost: one visit of the candidates around the bucket when warm; two
+// visits for the general search, restricted to the sub-ranges that its
+// lanes' spheres reach.
 // Distances d2 = (dx*dx + dy*dy) + dz*dz are evaluated in FP64 without fused
 // multiply-add, the same expression the oracle uses, so h matches bit for bit.
 #include "sidm_tree.hpp"
@@ -32,11 +41,29 @@ constexpr int kKnnSurv = 16;
 constexpr int kKnnLevels = 4;
 constexpr int kKnnGrow = 80;
 constexpr double kKnnWarm = 1.15 * 1.15;   // squared margin on the previous kernel size
+constexpr int kKnnBand = 16;               // band distances kept per lane
 
+// The band pass and the general search never run at once: the band's values
+// live in the histogram columns, value q of a lane in words 2q (low half) and
+// 2q + 1 (high half) of its column (a barrier separates the two uses).
+static_assert(2 * kKnnBand <= kKnnBins, "band values fit the histogram columns");
 struct KnnLds {
     uint32_t hist[kKnnBins][kBucket];
     int64_t stack[kStackMax];
 };
+
+__device__ inline double band_get(const KnnLds& L, int q, int lane)
+{
+    const uint64_t lo = L.hist[2 * q][lane], hi = L.hist[2 * q + 1][lane];
+    return __longlong_as_double((long long)((hi << 32) | lo));
+}
+
+__device__ inline void band_put(KnnLds& L, int q, int lane, double v)
+{
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    L.hist[2 * q][lane] = (uint32_t)u;
+    L.hist[2 * q + 1][lane] = (uint32_t)(u >> 32);
+}
 
 __device__ inline double dist2_exact(double ax, double ay, double az, double bx, double by,
                                      double bz)
@@ -60,11 +87,12 @@ __device__ inline int bin_of(double d2, double lo, double inv)
     return t >= (double)(kKnnBins - 1) ? kKnnBins - 1 : (t > 0.0 ? (int)t : 0);
 }
 
-// Insertion of v into the ascending list best[0..kKnnSurv) (registers).
-__device__ inline void insert_sorted(double (&best)[kKnnSurv], double v)
+// Insertion of v into the ascending list best[0..M) (registers).
+template <int M>
+__device__ inline void insert_sorted(double (&best)[M], double v)
 {
 #pragma unroll
-    for (int q = 0; q < kKnnSurv; ++q) {
+    for (int q = 0; q < M; ++q) {
         const double lo = fmin(best[q], v);
         v = fmax(best[q], v);
         best[q] = lo;
@@ -222,6 +250,56 @@ __global__ __launch_bounds__(kBucket) void k_knn(
         return act ? d2k : NAN;
     };
 
+    // h^2 of the lanes with act set from one visit of the band around their
+    // previous kernel size h0 (NaN for lanes whose k-th distance is not
+    // among the kept band values); a uniform call
+    auto band_pass = [&](bool act, double h0) {
+        // half-width relative to h0: about 12 band members expected (a
+        // spherical shell of relative width 2d holds about 6 d k
+        // neighbours), at least 1 %, at most 6 %
+        const double d = fmin(fmax(2.0 / (double)k, 0.01), 0.06);
+        const double rlo = h0 * (1.0 - d), rhi = h0 * (1.0 + d);
+        const double blo = rlo * rlo, bhi = rhi * rhi;
+        // below the band; kept band values (the band's smallest when it holds
+        // more than kKnnBand); the slot of the largest kept value when full
+        int nlo = 0, kept = 0, imax = 0;
+        auto find_max = [&]() {
+            imax = 0;
+            for (int q = 1; q < kKnnBand; ++q)
+                if (band_get(L, q, lane) > band_get(L, imax, lane)) imax = q;
+        };
+        visit(bhi * (1.0 + 1e-9), !act, [&](int64_t p, const double4& c) {
+            const double d2 = dist2_exact(xi, yi, zi, c.x, c.y, c.z);
+            if (!act || p == mypos || d2 > bhi) return;
+            if (d2 < blo) {
+                ++nlo;
+            } else if (kept < kKnnBand) {
+                band_put(L, kept, lane, d2);
+                if (++kept == kKnnBand) find_max();
+            } else if (d2 < band_get(L, imax, lane)) {
+                band_put(L, imax, lane, d2);
+                find_max();
+            }
+        });
+        // the k-th distance has rank r (0-based) in the band; it is a kept
+        // value iff 0 <= r < kept
+        const int r = k - nlo - 1;
+        if (!act || r < 0 || r >= kept) kept = 0;
+        double d2k = NAN;
+        for (int q = 0; q < kept; ++q) {   // the kept value with r below it and r + 1 up to it
+            const double v = band_get(L, q, lane);
+            int less = 0, upto = 0;
+            for (int t = 0; t < kept; ++t) {
+                const double w = band_get(L, t, lane);
+                less += w < v;
+                upto += w <= v;
+            }
+            if (less <= r && r < upto) d2k = v;
+        }
+        __syncthreads();   // the band columns are read before the histograms reuse them
+        return d2k;
+    };
+
     // ---- starting radius
     const bool warm = isfinite(hint) && hint > 0.0 && hint * hint <= diag2;
     double u2 = kKnnWarm * hint * hint;
@@ -281,7 +359,14 @@ __global__ __launch_bounds__(kBucket) void k_knn(
         const double c2 = kKnnWarm * __shfl(d2r, go);
         if (!warm) u2 = (isfinite(c2) && c2 > 0.0) ? fmin(c2, e2) : e2;
     }
-    const double d2k = resolve(in_bucket, u2);
+    double d2k = NAN;
+    bool todo = in_bucket;
+    if (__ballot(in_bucket && warm)) {
+        d2k = band_pass(in_bucket && warm, hint);
+        todo = in_bucket && !(d2k >= 0.0);
+    }
+    const double d2g = resolve(todo, u2);
+    if (todo) d2k = d2g;
     if (in_bucket) {
         const double h = sqrt(d2k);
         sh[mypos] = h;
