@@ -223,8 +223,13 @@ __global__ __launch_bounds__(kBucket) void k_pairs(
     }
     const uint32_t k0 = (uint32_t)(H.seed & 0xffffffffull), k1 = (uint32_t)(H.seed >> 32);
     const double kInvPi8 = 8.0 / 3.14159265358979323846;
+    const double cbound = H.sigma_m * mb * kInvPi8 * H.dt;
+    const double cbound2 = cbound * cbound * (1.0 + 1e-12);
+    const bool sw = H.sigma_w > 0.0;
+    const double inv_w2 = sw ? 1.0 / (H.sigma_w * H.sigma_w) : 0.0;
     const unsigned long long lt = (1ull << lane) - 1ull;
-    long long my_pairs = 0, my_cands = 0;
+    long long my_cands = 0;
+    unsigned long long wave_pairs = 0;   // wave-uniform: the ballots' counts
     int qn = 0;
 
     // per-pair work for queue entries [0, cnt): lane l takes entry l
@@ -238,19 +243,30 @@ __global__ __launch_bounds__(kBucket) void k_pairs(
             const uint32_t a = iswap ? J.id[jl] : I.id[il], bb = iswap ? I.id[il] : J.id[jl];
             const Philox4 w = philox4x32_10(a, bb, step, 0u, k0, k1);
             const double u = unit53(w.w[0], w.w[1]);
-            const double g = norm3(I.vx[il] - J.vx[jl], I.vy[il] - J.vy[jl], I.vz[il] - J.vz[jl]);
+            const double dvx = I.vx[il] - J.vx[jl], dvy = I.vy[il] - J.vy[jl],
+                         dvz = I.vz[il] - J.vz[jl];
+            const double g2 = (dvx * dvx + dvy * dvy) + dvz * dvz;
             const double ha = I.h[il], hbb = J.h[jl];
             const double hm = fmax(ha, hbb);
 
-            // Lambda <= min(W_a(0), W_b(0)) = 8 / (pi max(h)^3)
-            const double sg = sigma_at(H, g);
-            const double pub = sg * mb * g * (kInvPi8 / (hm * hm * hm)) * H.dt;
-            if (u < pub) {
+            // Lambda <= min(W_a(0), W_b(0)) = 8 / (pi max(h)^3) bounds P by
+            // sigma(g) m g 8 / (pi max(h)^3) dt.  The test u < bound, with
+            // sigma(g) = sigma_m / q^2, reads u max(h)^3 q^2 < cbound g;
+            // both sides are non-negative, so it is taken squared (no square
+            // root, no division), with a relative slack of 1e-12 so that the
+            // candidates include every pair whose rounded P exceeds u.
+            double lhs = u * (hm * hm * hm);
+            if (sw) {
+                const double q = 1.0 + g2 * inv_w2;
+                lhs *= q * q;
+            }
+            if (lhs * lhs < cbound2 * g2) {
                 // the exact decision needs Lambda: k_decide takes it from here
                 // (after an overflow of its buffer, the INLINE pass)
                 ++my_cands;
+                const double g = norm3(dvx, dvy, dvz);
                 CandRec r;
-                r.sg = sg;
+                r.sg = sigma_at(H, g);
                 r.mb = mb;
                 r.g = g;
                 const int64_t pi = B.start + il;
@@ -320,7 +336,7 @@ __global__ __launch_bounds__(kBucket) void k_pairs(
                 const unsigned long long mask = __ballot(pair);
                 if (pair) queue[qn + __popcll(mask & lt)] = (uint16_t)(lane | (jj << 8));
                 qn += __popcll(mask);
-                my_pairs += pair ? 1 : 0;
+                wave_pairs += (unsigned long long)__popcll(mask);
                 if (qn >= kBucket) {
                     process(kBucket);
                     const int rest = qn - kBucket;
@@ -339,12 +355,9 @@ __global__ __launch_bounds__(kBucket) void k_pairs(
     });
     // pairs tested and candidates of the exact decision found by this bucket
     if (INLINE) return;
-    long long v = my_pairs, vc = my_cands;
-    for (int o = 32; o > 0; o >>= 1) {
-        v += __shfl_xor(v, o, 64);
-        vc += __shfl_xor(vc, o, 64);
-    }
-    if (lane == 0 && v > 0) atomicAdd(&ev_counts[kEvCounts * B.halo + 2], (unsigned long long)v);
+    long long vc = my_cands;
+    for (int o = 32; o > 0; o >>= 1) vc += __shfl_xor(vc, o, 64);
+    if (lane == 0 && wave_pairs > 0) atomicAdd(&ev_counts[kEvCounts * B.halo + 2], wave_pairs);
     if (lane == 0 && vc > 0) atomicAdd(&ev_counts[kEvCounts * B.halo + 4], (unsigned long long)vc);
 }
 
