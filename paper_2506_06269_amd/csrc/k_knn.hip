@@ -103,7 +103,8 @@ template <bool LIST>
 __global__ __launch_bounds__(kBucket) void k_knn(
     const HaloDev* __restrict__ halos, const BucketInfo* __restrict__ buckets,
     const NodeChild* __restrict__ nodes, const double* __restrict__ box,
-    const SubRange* __restrict__ sub, const int* __restrict__ sub_n, int64_t n_buckets,
+    const SubRange* __restrict__ sub, const int* __restrict__ sub_n,
+    const double* __restrict__ cbox, int64_t n_buckets,
     const double4* __restrict__ sp4, const uint32_t* __restrict__ perm,
     double* __restrict__ sh, double* __restrict__ h_out, int* __restrict__ status,
     const uint32_t* __restrict__ sid, uint32_t* __restrict__ nbr, int k_max)
@@ -125,7 +126,7 @@ __global__ __launch_bounds__(kBucket) void k_knn(
     // every candidate of the sub-ranges within reach of a lane's sphere
     // (radius^2 r2 of the lane, ignored when `off` is true for the lane);
     // body(p, c) runs on every lane for candidate p at c = (x, y, z, .)
-    auto visit = [&](double r2, bool off, auto body) {
+    auto visit = [&](double r2, bool off, auto body) __attribute__((always_inline)) {
         tree_visit(H, nodes, n_buckets, L.stack,
                    [&](int64_t c) { return !off && point_box_dist2(xi, yi, zi, box + 6 * c) <= r2; },
                    all_nodes, [&](int64_t c) {
@@ -134,23 +135,36 @@ __global__ __launch_bounds__(kBucket) void k_knn(
                        for (int q = 0; q < ns; ++q) {
                            const SubRange& R = sub[kSubMax * c + q];
                            if (!__ballot(!off && point_box_dist2(xi, yi, zi, R.box) <= r2)) continue;
-                           const int64_t p0 = c0 + R.off;
-                           const int cnt = R.cnt;
-                           // four candidates' loads in flight before the first use
-                           int j = 0;
-                           for (; j + 4 <= cnt; j += 4) {
-                               double4 c[4];
+                           // a long sub-range is taken by chunks, those that
+                           // some sphere reaches
+                           const int j1 = R.off + R.cnt;
+                           const bool chunked = R.cnt > kChunk;
+                           for (int a0 = R.off; a0 < j1;) {
+                               const int g = a0 / kChunk;
+                               const int a1 = chunked ? min(j1, (g + 1) * kChunk) : j1;
+                               const bool reach =
+                                   !chunked ||
+                                   __ballot(!off && point_box_dist2(xi, yi, zi,
+                                                                    cbox + 6 * (kChunks * c + g)) <= r2);
+                               // candidates [a0, a1), four loads in flight
+                               // before the first use
+                               int j = reach ? a0 : a1;
+                               for (; j + 4 <= a1; j += 4) {
+                                   double4 v[4];
 #pragma unroll
-                               for (int u = 0; u < 4; ++u) c[u] = sp4[p0 + j + u];
+                                   for (int u = 0; u < 4; ++u) v[u] = sp4[c0 + j + u];
 #pragma unroll
-                               for (int u = 0; u < 4; ++u) body(p0 + j + u, c[u]);
+                                   for (int u = 0; u < 4; ++u) body(c0 + j + u, v[u]);
+                               }
+                               for (; j < a1; ++j) body(c0 + j, sp4[c0 + j]);
+                               a0 = a1;
                            }
-                           for (; j < cnt; ++j) body(p0 + j, sp4[p0 + j]);
                        }
                    });
     };
     // histogram of the distances in [a, z] over kKnnBins bins from lo
-    auto histogram = [&](bool on, double a, double z, double lo, double inv) {
+    auto histogram = [&](bool on, double a, double z, double lo, double inv)
+        __attribute__((always_inline)) {
         if (on)
             for (int q = 0; q < kKnnBins; ++q) L.hist[q][lane] = 0u;
         visit(z * (1.0 + 1e-9), !on, [&](int64_t p, const double4& c) {
@@ -163,7 +177,7 @@ __global__ __launch_bounds__(kBucket) void k_knn(
 
     // h^2 of the lanes with act set, from a starting radius^2 u2 (NaN for the
     // others); a uniform call: every lane of the wave takes part
-    auto resolve = [&](bool act, double u2) {
+    auto resolve = [&](bool act, double u2) __attribute__((always_inline)) {
         // ---- 1. histogram of [0, u2]; grow until the sphere holds k others
         bool need = act, failed = false;
         int grow = 0;
@@ -253,7 +267,7 @@ __global__ __launch_bounds__(kBucket) void k_knn(
     // h^2 of the lanes with act set from one visit of the band around their
     // previous kernel size h0 (NaN for lanes whose k-th distance is not
     // among the kept band values); a uniform call
-    auto band_pass = [&](bool act, double h0) {
+    auto band_pass = [&](bool act, double h0) __attribute__((always_inline)) {
         // half-width relative to h0: about 12 band members expected (a
         // spherical shell of relative width 2d holds about 6 d k
         // neighbours), at least 1 %, at most 6 %
@@ -448,12 +462,12 @@ hipError_t launch_knn(const Plan& P, const sidm_state* s, Scratch& w, uint32_t* 
 {
     if (!nbr) {
         hipLaunchKernelGGL(k_knn<false>, dim3((unsigned)P.n_buckets), dim3(kBucket), 0, st,
-                           w.halos, w.buckets, w.nodes, w.box, w.sub, w.sub_n, P.n_buckets,
+                           w.halos, w.buckets, w.nodes, w.box, w.sub, w.sub_n, w.cbox, P.n_buckets,
                            w.sp4, w.perm, w.sh, s->h, w.status, w.sid, nbr, k_max);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_knn<true>, dim3((unsigned)P.n_buckets), dim3(kBucket), 0, st, w.halos,
-                       w.buckets, w.nodes, w.box, w.sub, w.sub_n, P.n_buckets, w.sp4, w.perm,
+                       w.buckets, w.nodes, w.box, w.sub, w.sub_n, w.cbox, P.n_buckets, w.sp4, w.perm,
                        w.sh, s->h, w.status, w.sid, nbr, k_max);
     hipLaunchKernelGGL(k_knn_list_order, dim3((unsigned)P.n_blocks), dim3(kStreamBlock), 0,
                            st, w.blocks, w.halos, s->x, s->y, s->z, w.sp4, w.sid, k_max, nbr);

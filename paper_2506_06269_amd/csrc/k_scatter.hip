@@ -192,7 +192,8 @@ __global__ __launch_bounds__(kBucket) void k_pairs(
     const HaloDev* __restrict__ halos, const BucketInfo* __restrict__ buckets,
     const NodeChild* __restrict__ nodes, const double* __restrict__ box,
     const double* __restrict__ hmax, const SubRange* __restrict__ sub,
-    const int* __restrict__ sub_n, int64_t n_buckets, const double* __restrict__ sx,
+    const int* __restrict__ sub_n, const double* __restrict__ cbox, int64_t n_buckets,
+    const double* __restrict__ sx,
     const double* __restrict__ sy, const double* __restrict__ sz, const double* __restrict__ svx,
     const double* __restrict__ svy, const double* __restrict__ svz, const double* __restrict__ sh,
     const double* __restrict__ cmass, const uint32_t* __restrict__ sid,
@@ -326,7 +327,19 @@ __global__ __launch_bounds__(kBucket) void k_pairs(
             const double xi = xl, yi = yl, zi = zl, hi = hi_l;
             const uint32_t idi = I.id[act ? lane : 0];
             const bool same = c == b;
-            for (int jj = 0; jj < R.cnt; ++jj) {
+            // a long sub-range is tested by chunks, those within reach of
+            // some lane
+            const bool chunked = R.cnt > kChunk;
+            for (int jj = 0; jj < R.cnt;) {
+            const int g = (R.off + jj) / kChunk;
+            const int je = chunked ? min(R.cnt, (g + 1) * kChunk - R.off) : R.cnt;
+            if (chunked &&
+                !__ballot(act && point_box_dist2(xl, yl, zl, cbox + 6 * (kChunks * c + g)) <
+                                     rr * rr * (1.0 + 1e-9))) {
+                jj = je;
+                continue;
+            }
+            for (; jj < je; ++jj) {
                 bool pair = false;
                 if (act && (!same || idi < J.id[jj])) {
                     const double d2 = dist2_pair(xi, yi, zi, J.x[jj], J.y[jj], J.z[jj]);
@@ -346,6 +359,7 @@ __global__ __launch_bounds__(kBucket) void k_pairs(
                     qn = rest;
                     __syncthreads();
                 }
+            }
             }
             if (qn > 0) {
                 process(qn);   // entries refer to this candidate range: flush now
@@ -574,7 +588,7 @@ hipError_t launch_scatter(const Plan& P, const sidm_state* s, Scratch& w, uint32
     if (e != hipSuccess) return e;
     auto pairs = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3((unsigned)P.n_buckets), dim3(kBucket), 0, st, w.halos,
-                           w.buckets, w.nodes, w.box, w.hmax, w.sub, w.sub_n, P.n_buckets, w.sx,
+                           w.buckets, w.nodes, w.box, w.hmax, w.sub, w.sub_n, w.cbox, P.n_buckets, w.sx,
                            w.sy, w.sz, w.svx, w.svy, w.svz, w.sh, w.cref, w.sid, w.perm, step,
                            w.counters, w.cands, w.max_cands, w.events, w.max_events,
                            (unsigned long long*)w.ev_counts, w.status);

@@ -348,12 +348,14 @@ __device__ inline int split_range(int lo, int hi, int lane, unsigned long long k
     return after < 0.5 * before ? s : -1;
 }
 
-// One wave per bucket: the box, and up to kSubMax compact sub-ranges.
+// One wave per bucket: the box, up to kSubMax compact sub-ranges, and (when
+// cbox is given) the boxes of its chunks of kChunk particles (an empty
+// chunk gets the empty box [+inf, -inf], which no distance test passes).
 __global__ __launch_bounds__(256) void k_bucket_boxes(
     const BucketInfo* __restrict__ buckets, int64_t nb, const double* __restrict__ sx,
     const double* __restrict__ sy, const double* __restrict__ sz,
     const unsigned long long* __restrict__ skeys, double* __restrict__ box,
-    SubRange* __restrict__ sub, int* __restrict__ sub_n)
+    SubRange* __restrict__ sub, int* __restrict__ sub_n, double* __restrict__ cbox)
 {
     const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (b >= nb) return;
@@ -366,6 +368,13 @@ __global__ __launch_bounds__(256) void k_bucket_boxes(
     range_box(0, B.count, lane, px, py, pz, full);
     if (lane == 0)
         for (int q = 0; q < 6; ++q) box[6 * b + q] = full[q];
+    if (cbox)
+        for (int g = 0; g < kChunks; ++g) {
+            double cb[6];
+            range_box(g * kChunk, min(B.count, (g + 1) * kChunk), lane, px, py, pz, cb);
+            if (lane == 0)
+                for (int q = 0; q < 6; ++q) cbox[6 * (kChunks * b + g) + q] = cb[q];
+        }
     // up to two levels of splits
     int lo[kSubMax], hi[kSubMax];
     double bx[kSubMax][6];
@@ -500,7 +509,7 @@ hipError_t launch_cell_list(const Plan& P, const sidm_state* s, Scratch& w, hipS
                        w.sx, w.sy, w.sz, w.sp4, w.svx, w.svy, w.svz, w.sm, w.sid, w.sh, w.perm);
     w.skeys = w.keys[cur];
     hipLaunchKernelGGL(k_bucket_boxes, dim3(grid_of(P.n_buckets, 4)), dim3(256), 0, st, w.buckets,
-                       P.n_buckets, w.sx, w.sy, w.sz, w.skeys, w.box, w.sub, w.sub_n);
+                       P.n_buckets, w.sx, w.sy, w.sz, w.skeys, w.box, w.sub, w.sub_n, w.cbox);
     for (int l = 1; l < P.n_levels; ++l) {
         const int64_t t0 = P.level_task_off[l - 1], nt = P.level_task_off[l] - t0;
         if (nt > 0)
