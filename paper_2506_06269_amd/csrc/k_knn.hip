@@ -42,6 +42,7 @@ constexpr int kKnnLevels = 4;
 constexpr int kKnnGrow = 80;
 constexpr double kKnnWarm = 1.15 * 1.15;   // squared margin on the previous kernel size
 constexpr int kKnnBand = 16;               // band distances kept per lane
+constexpr int kKnnSplitMax = 16;           // waves per bucket for calls with few buckets
 
 // The band pass and the general search never run at once: the band's values
 // live in the histogram columns, value q of a lane in words 2q (low half) and
@@ -107,15 +108,20 @@ __global__ __launch_bounds__(kBucket) void k_knn(
     const double* __restrict__ cbox, int64_t n_buckets,
     const double4* __restrict__ sp4, const uint32_t* __restrict__ perm,
     double* __restrict__ sh, double* __restrict__ h_out, int* __restrict__ status,
-    const uint32_t* __restrict__ sid, uint32_t* __restrict__ nbr, int k_max)
+    const uint32_t* __restrict__ sid, uint32_t* __restrict__ nbr, int k_max, int split)
 {
     __shared__ KnnLds L;
-    const int64_t b = xcd_contiguous(blockIdx.x, gridDim.x);
+    // split waves per bucket: wave `part` resolves the bucket's lanes
+    // [part, part + 1) * 64 / split (a call with few buckets still fills the
+    // device, and each wave's candidates are those of its own lanes' spheres)
+    const int64_t bw = xcd_contiguous(blockIdx.x, gridDim.x);
+    const int64_t b = bw / split;
+    const int part = (int)(bw % split);
     const int lane = threadIdx.x;
     const BucketInfo B = buckets[b];
     const HaloDev& H = halos[B.halo];
     const int k = H.k;
-    const bool in_bucket = lane < B.count;
+    const bool in_bucket = lane < B.count && lane / (kBucket / split) == part;
     const int64_t mypos = B.start + (in_bucket ? lane : 0);
     const double4 me = sp4[mypos];
     const double xi = me.x, yi = me.y, zi = me.z;
@@ -460,15 +466,17 @@ __global__ __launch_bounds__(kStreamBlock) void k_knn_list_order(
 hipError_t launch_knn(const Plan& P, const sidm_state* s, Scratch& w, uint32_t* nbr, int k_max,
                       hipStream_t st)
 {
+    const int split = search_split(P.n_buckets, kKnnSplitMax);
+    const dim3 grid((unsigned)(P.n_buckets * split));
     if (!nbr) {
-        hipLaunchKernelGGL(k_knn<false>, dim3((unsigned)P.n_buckets), dim3(kBucket), 0, st,
+        hipLaunchKernelGGL(k_knn<false>, grid, dim3(kBucket), 0, st,
                            w.halos, w.buckets, w.nodes, w.box, w.sub, w.sub_n, w.cbox, P.n_buckets,
-                           w.sp4, w.perm, w.sh, s->h, w.status, w.sid, nbr, k_max);
+                           w.sp4, w.perm, w.sh, s->h, w.status, w.sid, nbr, k_max, split);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(k_knn<true>, dim3((unsigned)P.n_buckets), dim3(kBucket), 0, st, w.halos,
+    hipLaunchKernelGGL(k_knn<true>, grid, dim3(kBucket), 0, st, w.halos,
                        w.buckets, w.nodes, w.box, w.sub, w.sub_n, w.cbox, P.n_buckets, w.sp4, w.perm,
-                       w.sh, s->h, w.status, w.sid, nbr, k_max);
+                       w.sh, s->h, w.status, w.sid, nbr, k_max, split);
     hipLaunchKernelGGL(k_knn_list_order, dim3((unsigned)P.n_blocks), dim3(kStreamBlock), 0,
                            st, w.blocks, w.halos, s->x, s->y, s->z, w.sp4, w.sid, k_max, nbr);
     return hipGetLastError();

@@ -199,13 +199,18 @@ __global__ __launch_bounds__(kBucket) void k_pairs(
     const double* __restrict__ cmass, const uint32_t* __restrict__ sid,
     const uint32_t* __restrict__ perm, uint32_t step, DevCounters* __restrict__ counters,
     CandRec* __restrict__ cands, int64_t max_cands, EventRec* __restrict__ events,
-    int64_t max_events, unsigned long long* __restrict__ ev_counts, const int* __restrict__ status)
+    int64_t max_events, unsigned long long* __restrict__ ev_counts, const int* __restrict__ status,
+    int split)
 {
     __shared__ PairI I;
     __shared__ PairJ J;
     __shared__ uint16_t queue[2 * kBucket];
     __shared__ int64_t stack[kStackMax];
-    const int64_t b = blockIdx.x;
+    // split waves per bucket: wave `part` takes every split-th candidate
+    // bucket of the bucket's visit (a call with few buckets still fills the
+    // device; every pair is still tested by exactly one wave)
+    const int64_t b = blockIdx.x / split;
+    const int part = (int)(blockIdx.x % split);
     const int lane = threadIdx.x;
     if (INLINE && (int64_t)counters->n_cands <= max_cands) return;
     const BucketInfo B = buckets[b];
@@ -299,6 +304,7 @@ __global__ __launch_bounds__(kBucket) void k_pairs(
     const double hi_l = act ? I.h[lane] : 0.0;
     const int64_t pl = B.start + (act ? lane : 0);
     const double xl = sx[pl], yl = sy[pl], zl = sz[pl];
+    int visit_no = 0;   // candidate buckets visited so far (wave-uniform)
     tree_visit(H, nodes, n_buckets, stack,
                [&](int64_t c) {
                    const double r = hi_l + hmax[c];
@@ -306,6 +312,7 @@ __global__ __launch_bounds__(kBucket) void k_pairs(
                },
                [&](int64_t c) { return nodes[c].last >= b; },
                [&](int64_t c) {
+        if (split > 1 && (visit_no++ % split) != part) return;
         const BucketInfo C = buckets[c];
         const double hc = hmax[c];
         const int nsub = sub_n[c];
@@ -586,12 +593,13 @@ hipError_t launch_scatter(const Plan& P, const sidm_state* s, Scratch& w, uint32
 {
     hipError_t e = launch_contract_checks(P, s, w, st);
     if (e != hipSuccess) return e;
+    const int split = search_split(P.n_buckets, kPairSplitMax);
     auto pairs = [&](auto kern) {
-        hipLaunchKernelGGL(kern, dim3((unsigned)P.n_buckets), dim3(kBucket), 0, st, w.halos,
+        hipLaunchKernelGGL(kern, dim3((unsigned)(P.n_buckets * split)), dim3(kBucket), 0, st, w.halos,
                            w.buckets, w.nodes, w.box, w.hmax, w.sub, w.sub_n, w.cbox, P.n_buckets, w.sx,
                            w.sy, w.sz, w.svx, w.svy, w.svz, w.sh, w.cref, w.sid, w.perm, step,
                            w.counters, w.cands, w.max_cands, w.events, w.max_events,
-                           (unsigned long long*)w.ev_counts, w.status);
+                           (unsigned long long*)w.ev_counts, w.status, split);
     };
     pairs(k_pairs<false>);
     hipLaunchKernelGGL(k_decide, dim3(256), dim3(256), 0, st, w.halos, w.cands, w.max_cands,

@@ -54,6 +54,8 @@ struct NodeChild {
 // consecutive particles that straddles a coarse cell boundary is otherwise
 // spread over a large region.
 constexpr int kSubMax = 4;
+// At most this many j-ranges per halo for the one-sided gravity tiles.
+constexpr int64_t kMaxGravSplit = 32;
 // The searches also skip chunks of kChunk consecutive particles of a bucket
 // (aligned to the bucket start) that no lane's sphere reaches.
 constexpr int kChunk = 16;
@@ -202,7 +204,12 @@ inline bool alloc_scratch(Scratch& w, int64_t N, int32_t H, int64_t max_events, 
     w.max_halos = H;
     const int64_t nb = N / kStreamBlock + H + 1;
     w.blocks_cap = nb;
-    w.items_cap = (N / (kGravThreads * 4) + H + 1) * 64;
+    // gravity items: i-blocks of the smallest launch shape (2 x 128) times the
+    // j-ranges choose_splits may give them (more for small calls)
+    const int64_t split_cap =
+        std::min<int64_t>(kMaxGravSplit, std::max<int64_t>(4, (1 << 18) / std::max<int64_t>(N, 1)));
+    w.items_cap = std::max<int64_t>((N / (kGravThreads * 4) + H + 1) * 64,
+                                    (N / 256 + H + 1) * split_cap);
     w.partial_rows = std::max<int64_t>(4 * N, 1 << 18);
     w.buckets_cap = N / kBucket + H + 1;
     w.nodes_cap = w.buckets_cap * 2 + (int64_t)H * (kMaxLevels + 1);
@@ -395,7 +402,11 @@ inline void choose_splits(std::vector<HaloDev>& hd, int64_t partial_rows, int64_
         ntot += H.n;
     }
     iblocks = std::max<int64_t>(iblocks, 1);
-    const int64_t smax = std::min<int64_t>(4, std::max<int64_t>(1, partial_rows / std::max<int64_t>(ntot, 1)));
+    // at most kMaxGravSplit j-ranges per halo, and as many as the partial rows
+    // hold (four for calls of 2^16 particles and more; small calls get more
+    // j-ranges to fill the device)
+    const int64_t smax = std::min<int64_t>(
+        kMaxGravSplit, std::max<int64_t>(1, partial_rows / std::max<int64_t>(ntot, 1)));
     int64_t best = 1;
     if (slots <= 0) {
         best = std::min<int64_t>(smax, std::max<int64_t>(1, (2048 + iblocks - 1) / iblocks));
