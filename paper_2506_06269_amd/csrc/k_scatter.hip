@@ -55,31 +55,47 @@ __global__ void k_scatter_reset(DevCounters* __restrict__ counters,
 }
 
 // ---------------------------------------------------------------- contract checks
-// Keys (halo << 32 | id) of every particle of the call in the compact order:
-// once sorted, equal neighbours are an id repeated within a halo (ids key the
-// random draws and order the kicks, so they must be unique per halo).
-__global__ __launch_bounds__(kStreamBlock) void k_id_keys(
-    const StreamBlock* __restrict__ blocks, const HaloDev* __restrict__ halos,
-    const uint32_t* __restrict__ id, unsigned long long* __restrict__ keys,
-    uint32_t* __restrict__ vals)
+// Ids key the random draws and order the kicks, so they must be unique per
+// halo.  Every particle inserts its key (halo << 32 | id) into an open-
+// addressing hash table of cap >= 2 n slots (linear probing, the empty slot
+// ~0, which no key equals: halo indices stay below 2^31); finding its own key
+// already there flags the halo.  A table at most half full always has an
+// empty slot, so every probe sequence ends.
+constexpr unsigned long long kEmptySlot = ~0ull;
+
+__global__ __launch_bounds__(256) void k_fill_u64(unsigned long long* __restrict__ a, int64_t n,
+                                                   unsigned long long v)
+{
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += (int64_t)gridDim.x * 256)
+        a[p] = v;
+}
+
+__device__ inline unsigned long long mix64(unsigned long long z)
+{
+    // the finaliser of SplitMix64 (Steele, Lea and Flood 2014)
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(kStreamBlock) void k_id_insert(
+    const StreamBlock* __restrict__ blocks, const uint32_t* __restrict__ id,
+    unsigned long long* __restrict__ table, unsigned long long cap, int* __restrict__ status)
 {
     const StreamBlock B = blocks[blockIdx.x];
     const int t = threadIdx.x;
     if (t >= B.count) return;
-    const HaloDev& H = halos[B.halo];
-    const int64_t i = B.start + t;
-    const int64_t pos = H.sbase + (i - H.offset);
-    keys[pos] = ((unsigned long long)(uint32_t)B.halo << 32) | id[i];
-    vals[pos] = (uint32_t)i;
-}
-
-__global__ __launch_bounds__(256) void k_dup_ids(const unsigned long long* __restrict__ keys,
-                                                  int64_t n, int* __restrict__ status)
-{
-    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (p + 1 >= n) return;
-    const unsigned long long a = keys[p];
-    if (a == keys[p + 1]) atomicOr(&status[(int)(a >> 32)], SIDM_DEV_DUPLICATE_ID);
+    const unsigned long long key = ((unsigned long long)(uint32_t)B.halo << 32) | id[B.start + t];
+    unsigned long long slot = __umul64hi(mix64(key), cap);
+    for (unsigned long long probe = 0; probe < cap; ++probe) {
+        const unsigned long long prev = atomicCAS(&table[slot], kEmptySlot, key);
+        if (prev == kEmptySlot) return;
+        if (prev == key) {
+            atomicOr(&status[B.halo], SIDM_DEV_DUPLICATE_ID);
+            return;
+        }
+        slot = slot + 1 == cap ? 0 : slot + 1;
+    }
 }
 
 // OR of the halos' status words into the context's sticky word, which keeps
@@ -543,12 +559,13 @@ hipError_t launch_contract_checks(const Plan& P, const sidm_state* s, Scratch& w
     if (!P.any_scatter) return hipSuccess;
     hipError_t e = launch_mass_check(P, w, s->m, st);
     if (e != hipSuccess) return e;
-    const int64_t n = P.n_sorted;
-    hipLaunchKernelGGL(k_id_keys, dim3((unsigned)P.n_blocks), dim3(kStreamBlock), 0, st, w.blocks,
-                       w.halos, s->id, w.keys[0], w.vals[0]);
-    const int cur = launch_sort_keys(w, n, 32 + P.halo_bits, st);
-    hipLaunchKernelGGL(k_dup_ids, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
-                       w.keys[cur], n, w.status);
+    // the hash table: the radix sort's two key buffers, 2 max_particles words
+    const unsigned long long cap = 2ull * (unsigned long long)w.max_particles;
+    if ((int64_t)cap < 2 * P.n_sorted) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_fill_u64, dim3(1024), dim3(256), 0, st, w.keys[0], (int64_t)cap,
+                       kEmptySlot);
+    hipLaunchKernelGGL(k_id_insert, dim3((unsigned)P.n_blocks), dim3(kStreamBlock), 0, st,
+                       w.blocks, s->id, w.keys[0], cap, w.status);
     return hipGetLastError();
 }
 

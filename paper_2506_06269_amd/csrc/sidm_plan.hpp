@@ -219,8 +219,8 @@ inline bool alloc_scratch(Scratch& w, int64_t N, int32_t H, int64_t max_events, 
               dalloc(w.buckets, w.buckets_cap) && dalloc(w.node_tasks, w.nodes_cap) && dalloc(w.nodes, w.nodes_cap) &&
               dalloc(w.bsum, 7 * nb) && dalloc(w.cref, 4 * H) && dalloc(w.radius, H) && dalloc(w.center, H) &&
               dalloc(w.tidal, 8 * H) && dalloc(w.bbox, 6 * H) &&
-              dalloc(w.xm32, N) &&  dalloc(w.partial, w.partial_rows) && dalloc(w.keys[0], N) &&
-              dalloc(w.keys[1], N) && dalloc(w.vals[0], N) && dalloc(w.vals[1], N) &&
+              dalloc(w.xm32, N) &&  dalloc(w.partial, w.partial_rows) && dalloc(w.keys[0], 2 * N) &&
+              dalloc(w.vals[0], N) && dalloc(w.vals[1], N) &&
               dalloc(w.hist, w.hist_cap) && dalloc(w.scan_part, kScanMaxSeg) && dalloc(w.sx, N) && dalloc(w.sy, N) &&
               dalloc(w.sz, N) && dalloc(w.sp4, N) && dalloc(w.svx, N) && dalloc(w.svy, N) && dalloc(w.svz, N) &&
               dalloc(w.sh, N) && dalloc(w.sm, N) && dalloc(w.bin, N) &&
@@ -234,6 +234,9 @@ inline bool alloc_scratch(Scratch& w, int64_t N, int32_t H, int64_t max_events, 
         why = "device allocation failed";
         return false;
     }
+    // the two key buffers of the radix sort are one allocation: outside the
+    // sort its 2 N words serve as the hash table of the id check
+    w.keys[1] = w.keys[0] + N;
     if (!realloc_events(w, max_events, why)) return false;
     // the counters, per-halo event counts, status words and tree term counts
     // read by the diagnostics start at zero (a context that has not stepped
@@ -264,7 +267,7 @@ inline void free_scratch(Scratch& w)
 {
     dfree(w.halos); dfree(w.blocks); dfree(w.items); dfree(w.buckets); dfree(w.node_tasks); dfree(w.nodes);
     dfree(w.bsum); dfree(w.cref); dfree(w.radius); dfree(w.center); dfree(w.tidal); dfree(w.bbox); dfree(w.xm32);  dfree(w.partial);
-    dfree(w.keys[0]); dfree(w.keys[1]); dfree(w.vals[0]); dfree(w.vals[1]); dfree(w.hist); dfree(w.scan_part);
+    dfree(w.keys[0]); w.keys[1] = nullptr; dfree(w.vals[0]); dfree(w.vals[1]); dfree(w.hist); dfree(w.scan_part);
     dfree(w.sx); dfree(w.sy); dfree(w.sz); dfree(w.sp4); dfree(w.svx); dfree(w.svy); dfree(w.svz);
     dfree(w.items_tick); dfree(w.partial_tick);
     w.items_tick_cap = w.partial_tick_rows = 0;
