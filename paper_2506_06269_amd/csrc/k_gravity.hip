@@ -1038,7 +1038,11 @@ hipError_t launch_gravity(bool mixed, const Plan& P, Scratch& w, const sidm_stat
     // them and the one-sided tiles for the rest (their items come first in the
     // item table).  Without tick items no direct-sum halo has block steps, so
     // all of their particles are active at every tick.
-    const bool tk = tick > 0 && !P.items_tick.empty();
+    // The last tick of a cycle steps every particle of every halo: it runs the
+    // whole evaluation (the symmetric tiles where they apply) instead of the
+    // tick items.
+    const bool full_tick = tick > 0 && tick == (1 << bmax);
+    const bool tk = tick > 0 && !full_tick && !P.items_tick.empty();
     const bool sym = mixed && !tk && P.n_sym_items > 0;
     const GravItem* items = tk ? w.items_tick : w.items;
     const int64_t n_items =
