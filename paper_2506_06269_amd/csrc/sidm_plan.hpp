@@ -198,19 +198,43 @@ inline bool realloc_events(Scratch& w, int64_t max_events, std::string& why)
     return true;
 }
 
+// Waves per bucket for the searches of a call with few buckets: the smallest
+// power of two (at most max_split) that gives kSearchWaves waves in all.
+constexpr int64_t kSearchWaves = 2048;
+constexpr int kPairSplitMax = 16;
+inline int search_split(int64_t n_buckets, int max_split)
+{
+    int s = 1;
+    while (s < max_split && n_buckets * s < kSearchWaves) s *= 2;
+    return s;
+}
+
+// Partial rows of the one-sided gravity tiles for a context of N particles:
+// four per particle, and at least 2^18 (small calls take more j-ranges).
+inline int64_t gravity_partial_rows(int64_t N)
+{
+    return std::max<int64_t>(4 * N, 1 << 18);
+}
+
+// Gravity work items a context of N particles in H halos can need: the
+// i-blocks of the smallest launch shape (2 x 128) times the j-ranges
+// choose_splits may give them (at most kMaxGravSplit, and as many as the
+// partial rows hold).
+inline int64_t gravity_items_cap(int64_t N, int32_t H)
+{
+    const int64_t split_cap = std::min<int64_t>(
+        kMaxGravSplit, std::max<int64_t>(1, gravity_partial_rows(N) / std::max<int64_t>(N, 1)));
+    return std::max<int64_t>((N / (kGravThreads * 4) + H + 1) * 64, (N / 256 + H + 1) * split_cap);
+}
+
 inline bool alloc_scratch(Scratch& w, int64_t N, int32_t H, int64_t max_events, std::string& why)
 {
     w.max_particles = N;
     w.max_halos = H;
     const int64_t nb = N / kStreamBlock + H + 1;
     w.blocks_cap = nb;
-    // gravity items: i-blocks of the smallest launch shape (2 x 128) times the
-    // j-ranges choose_splits may give them (more for small calls)
-    const int64_t split_cap =
-        std::min<int64_t>(kMaxGravSplit, std::max<int64_t>(4, (1 << 18) / std::max<int64_t>(N, 1)));
-    w.items_cap = std::max<int64_t>((N / (kGravThreads * 4) + H + 1) * 64,
-                                    (N / 256 + H + 1) * split_cap);
-    w.partial_rows = std::max<int64_t>(4 * N, 1 << 18);
+    w.items_cap = gravity_items_cap(N, H);
+    w.partial_rows = gravity_partial_rows(N);
     w.buckets_cap = N / kBucket + H + 1;
     w.nodes_cap = w.buckets_cap * 2 + (int64_t)H * (kMaxLevels + 1);
     const int64_t sort_blocks = N / (kSortBlock * kSortItems) + 1;

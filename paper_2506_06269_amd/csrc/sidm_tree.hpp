@@ -7,17 +7,6 @@ namespace sidm {
 
 constexpr int kStackMax = 96;
 
-// Waves per bucket for the searches of a call with few buckets: the smallest
-// power of two (at most max_split) that gives kSearchWaves waves in all.
-constexpr int64_t kSearchWaves = 2048;
-constexpr int kPairSplitMax = 16;
-inline int search_split(int64_t n_buckets, int max_split)
-{
-    int s = 1;
-    while (s < max_split && n_buckets * s < kSearchWaves) s *= 2;
-    return s;
-}
-
 // A value every lane of the wave holds, moved to a scalar register so that the
 // loads it addresses are issued once per wave.
 __device__ inline int64_t wave_uniform(int64_t v)

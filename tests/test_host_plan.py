@@ -1,7 +1,9 @@
 """CPU checks of the launch planner (csrc/sidm_plan.hpp, compiled for the host
 with g++): the number of j-splits of the gravity sums is the one whose work
 items, started largest first on the device's resident blocks, finish
-soonest; checked against an independent list-scheduling simulation."""
+soonest; checked against an independent list-scheduling simulation.  The
+work items of any plan fit the context's item table, and the searches of a
+call with few buckets get enough waves."""
 import ctypes as C
 
 import numpy as np
@@ -16,6 +18,23 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 _SRC = r'''
 #include "sidm_plan.hpp"
+extern "C" long long plan_items(int nh, const long long* n, long long slots, int ireg, int nt,
+                                long long* cap, int* split) {
+    std::vector<sidm::HaloDev> hd(nh);
+    long long tot = 0;
+    for (int h = 0; h < nh; ++h) { std::memset(&hd[h], 0, sizeof(hd[h])); hd[h].n = n[h]; tot += n[h]; }
+    sidm::GravShape shape;
+    shape.ireg = ireg;
+    shape.nt = nt;
+    sidm::choose_splits(hd, sidm::gravity_partial_rows(tot), slots, shape);
+    long long items = 0;
+    const long long ib = (long long)ireg * nt;
+    for (int h = 0; h < nh; ++h) items += (n[h] + ib - 1) / ib * hd[h].grav_split;
+    *cap = sidm::gravity_items_cap(tot, nh);
+    *split = hd[0].grav_split;
+    return items;
+}
+extern "C" int search_split(long long nb, int max_split) { return sidm::search_split(nb, max_split); }
 extern "C" int plan_split(int nh, const long long* n, long long slots, long long partial_rows,
                           int ireg, int nt) {
     std::vector<sidm::HaloDev> hd(nh);
@@ -169,3 +188,54 @@ def test_symmetric_items_off(L):
     assert items == [] and flags == [0, 0]
     items, flags = _sym(L, [5000, 8000], [0, 5000], [0.01, 0.01], [0.0, 0.0], 6000, 64, 4, 256)
     assert flags == [0, 1] and all(it[3] == 1 for it in items)
+
+
+SHAPES = [(i, t) for i in (2, 4, 8) for t in (128, 256, 512)]
+
+
+@pytest.mark.parametrize("ns", [[64], [1000], [4096], [8192], [65536], [100000], [1 << 20],
+                                [4096 * (b + 1) for b in range(20)], [300] * 64])
+def test_items_fit_the_table(L, ns):
+    """For every launch shape and occupancy the planned one-sided items fit
+    the item table the context allocates for that many particles and halos,
+    and the split stays within what the partial rows hold."""
+    a = (C.c_longlong * len(ns))(*ns)
+    cap, split = C.c_longlong(0), C.c_int(0)
+    L.plan_items.restype = C.c_longlong
+    for ireg, nt in SHAPES:
+        for slots in (0, 64, 512, 4096):
+            items = L.plan_items(len(ns), a, slots, ireg, nt, C.byref(cap), C.byref(split))
+            assert items <= cap.value, (ireg, nt, slots, items, cap.value)
+            rows = max(4 * sum(ns), 1 << 18)
+            assert 1 <= split.value <= min(32, rows // sum(ns))
+
+
+@pytest.mark.parametrize("ireg,nt", [(2, 128), (2, 256), (4, 256)])
+def test_small_call_split_minimises_finishing_time(L, ireg, nt):
+    """A call of 8192 particles may take up to 32 j-ranges (2^18 partial
+    rows); the chosen number finishes soonest among 1..32."""
+    ns, slots = [8192], 1024
+    a = (C.c_longlong * 1)(*ns)
+    cap, split = C.c_longlong(0), C.c_int(0)
+    L.plan_items(1, a, slots, ireg, nt, C.byref(cap), C.byref(split))
+    s = split.value
+    times = {q: _makespan(ns, q, slots, ireg, nt) for q in range(1, 33)}
+    best = min(times.values())
+    assert s > 4
+    assert times[s] <= best * (1 + 5e-3) + 1e-9, (s, times)
+
+
+def test_search_split(L):
+    """Waves per bucket: 1 from 2048 buckets on, else the smallest power of
+    two that reaches 2048 waves, at most the given maximum."""
+    assert L.search_split(16384, 16) == 1
+    assert L.search_split(2048, 16) == 1
+    assert L.search_split(2047, 16) == 2
+    assert L.search_split(128, 16) == 16
+    assert L.search_split(128, 4) == 4
+    assert L.search_split(1, 16) == 16
+    for nb in range(1, 3000, 7):
+        s = L.search_split(nb, 16)
+        assert s in (1, 2, 4, 8, 16)
+        assert nb * s >= 2048 or s == 16
+        assert s == 1 or nb * (s // 2) < 2048
