@@ -56,6 +56,42 @@ def test_knn_bit_exact(S, orc, kind, n, k):
         assert np.array_equal(lists[:, :k], lref)
 
 
+@pytest.mark.parametrize("kind,n,k", [("nfw", 8192, 32), ("clustered", 3000, 128),
+                                      ("lattice", 1000, 16), ("lattice", 512, 6),
+                                      ("nfw", 4100, 64), ("random", 1000, 16)])
+def test_knn_warm_starts_bit_exact(S, orc, kind, n, k):
+    """Warm starts from the exact kernel size and from sizes a little off
+    (the band around the previous h holds the k-th distance, off its centre,
+    or it does not and the general search takes over) give the oracle's h bit
+    for bit and its lists; lattices put many equal distances into the band."""
+    import torch
+    if kind == "nfw":
+        s = W.nfw_halo(n, seed=13)
+    elif kind == "random":
+        s = W.maxwell_box(n, seed=15)
+    elif kind == "clustered":
+        s = W.clustered(n, seed=18, width=0.005)
+    else:
+        s = W.lattice(round(n ** (1 / 3)), seed=14)
+        n = s["x"].size
+    href, lref = orc.knn(s["x"], s["y"], s["z"], s["id"], k, want_list=True)
+    halo = dict(n=n, eps=0.01, k=k)
+    dev = S.state_to_device(s)
+    ctx = S.sidm_create(0, n, 1)
+    nbr = torch.zeros(n * k, dtype=torch.int32, device="cuda")
+    hr = torch.from_numpy(href).to("cuda")
+    for f in (1.0, 0.995, 1.01, 0.97, 1.05, 0.8, 1.3):
+        dev["h"].copy_(hr * f)
+        S.sidm_knn_h(ctx, [halo], dev, nbr=nbr)
+        torch.cuda.synchronize()
+        h = dev["h"].cpu().numpy()
+        bad = np.flatnonzero(h != href)
+        assert bad.size == 0, (f, bad[:5], h[bad[:5]], href[bad[:5]])
+        lists = nbr.cpu().numpy().view(np.uint32).reshape(n, k)
+        assert np.array_equal(lists, lref), f
+    S.sidm_destroy(ctx)
+
+
 def test_knn_batched_mixed_k(S, orc):
     """Four halos (k = 16, 32, 64, 128) in one call, offsets not in order."""
     sizes = [4096, 5000, 6144, 4500]
