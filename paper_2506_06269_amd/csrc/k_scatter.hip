@@ -457,46 +457,69 @@ __device__ inline void owner_free(unsigned long long* p)
 }
 
 constexpr int kRoundThreads = 1024;
+// Halos are independent: workgroup g of kRoundGroups takes the events of the
+// halos h with h % groups == g, listed (as event indices) in its own segment
+// of max_events words of the candidate buffer, which holds nothing once the
+// pair decisions are taken.
+constexpr int kRoundGroups = 64;
+static_assert(4 * sizeof(CandRec) >= kRoundGroups * sizeof(uint32_t),
+              "the candidate buffer holds every workgroup's event list");
 
-// One workgroup applies all events of the step; every wave leaves the loop in
-// the same round (the pending count is reduced through LDS).
+// Each workgroup applies the events of its halos; all of its waves leave the
+// loop in the same round (the pending count is reduced through LDS).
 __global__ __launch_bounds__(kRoundThreads) void k_rounds(
     const HaloDev* __restrict__ halos, int n_halos, const DevCounters* __restrict__ counters,
     EventRec* __restrict__ ev, int64_t max_events, unsigned long long* __restrict__ owner,
     double* __restrict__ vx, double* __restrict__ vy, double* __restrict__ vz,
     const double* __restrict__ m, unsigned long long* __restrict__ ev_counts,
-    int* __restrict__ status, uint32_t step, int64_t out_cap, sidm_event* __restrict__ out)
+    int* __restrict__ status, uint32_t step, int64_t out_cap, sidm_event* __restrict__ out,
+    uint32_t* __restrict__ lists)
 {
-    __shared__ int pending;
+    __shared__ int pending, n_mine;
     const int t = threadIdx.x;
+    const int groups = (int)gridDim.x, g = (int)blockIdx.x;
     const unsigned long long total = counters->n_events_total;
     if ((int64_t)total > max_events) {
-        for (int h = t; h < n_halos; h += kRoundThreads) atomicOr(&status[h], SIDM_DEV_EVENT_OVERFLOW);
+        for (int h = g + groups * t; h < n_halos; h += groups * kRoundThreads)
+            atomicOr(&status[h], SIDM_DEV_EVENT_OVERFLOW);
         return;
     }
-    const int64_t n = (int64_t)total;
-    for (int64_t e = t; e < n; e += kRoundThreads) {
+    const int64_t n_all = (int64_t)total;
+    uint32_t* __restrict__ mine_e = lists + (int64_t)g * max_events;
+    if (t == 0) n_mine = 0;
+    __syncthreads();
+    for (int64_t e = t; e < n_all; e += kRoundThreads)
+        if (ev[e].halo % groups == g) mine_e[atomicAdd(&n_mine, 1)] = (uint32_t)e;
+    __syncthreads();
+    const int64_t n = n_mine;
+    for (int64_t q = t; q < n; q += kRoundThreads) {
+        const int64_t e = mine_e[q];
         ev[e].round = 0u;
         owner_free(&owner[ev[e].ia]);
         owner_free(&owner[ev[e].ib]);
     }
     __syncthreads();
     for (uint32_t r = 1; n > 0; ++r) {
-        for (int64_t e = t; e < n; e += kRoundThreads)
+        for (int64_t q = t; q < n; q += kRoundThreads) {
+            const int64_t e = mine_e[q];
             if (ev[e].round == 0u) {
                 atomicMin(&owner[ev[e].ia], ev[e].key);
                 atomicMin(&owner[ev[e].ib], ev[e].key);
             }
+        }
         __syncthreads();
-        for (int64_t e = t; e < n; e += kRoundThreads)
+        for (int64_t q = t; q < n; q += kRoundThreads) {
+            const int64_t e = mine_e[q];
             if (ev[e].round == 0u) {
                 const unsigned long long key = ev[e].key;
                 if (owner_load(&owner[ev[e].ia]) == key && owner_load(&owner[ev[e].ib]) == key)
                     ev[e].round = r;
             }
+        }
         __syncthreads();
         if (t == 0) pending = 0;
-        for (int64_t e = t; e < n; e += kRoundThreads) {
+        for (int64_t q = t; q < n; q += kRoundThreads) {
+            const int64_t e = mine_e[q];
             const uint32_t er = ev[e].round;
             if (er == 0u || er == r) {
                 owner_free(&owner[ev[e].ia]);
@@ -505,7 +528,8 @@ __global__ __launch_bounds__(kRoundThreads) void k_rounds(
         }
         __syncthreads();
         int mine = 0;
-        for (int64_t e = t; e < n; e += kRoundThreads) {
+        for (int64_t q = t; q < n; q += kRoundThreads) {
+            const int64_t e = mine_e[q];
             const EventRec E = ev[e];
             if (E.round == r) {
                 const HaloDev& H = halos[E.halo];
@@ -528,8 +552,9 @@ __global__ __launch_bounds__(kRoundThreads) void k_rounds(
         if (left == 0) break;
     }
     if (out) {
-        const int64_t nout = n < out_cap ? n : out_cap;
-        for (int64_t e = t; e < nout; e += kRoundThreads) {
+        for (int64_t q = t; q < n; q += kRoundThreads) {
+            const int64_t e = mine_e[q];
+            if (e >= out_cap) continue;
             sidm_event o;
             o.a = (uint32_t)(ev[e].key >> 32);
             o.b = (uint32_t)ev[e].key;
@@ -623,9 +648,11 @@ hipError_t launch_scatter(const Plan& P, const sidm_state* s, Scratch& w, uint32
                        w.counters, w.events, w.max_events, (unsigned long long*)w.ev_counts);
     pairs(k_pairs<true>);
     if (after_pairs) (void)hipEventRecord(after_pairs, st);
-    hipLaunchKernelGGL(k_rounds, dim3(1), dim3(kRoundThreads), 0, st, w.halos, P.n_halos,
-                       w.counters, w.events, w.max_events, w.owner, s->vx, s->vy, s->vz, s->m,
-                       (unsigned long long*)w.ev_counts, w.status, step, out_cap, out_events);
+    const int groups = P.n_halos < kRoundGroups ? P.n_halos : kRoundGroups;
+    hipLaunchKernelGGL(k_rounds, dim3((unsigned)groups), dim3(kRoundThreads), 0, st, w.halos,
+                       P.n_halos, w.counters, w.events, w.max_events, w.owner, s->vx, s->vy,
+                       s->vz, s->m, (unsigned long long*)w.ev_counts, w.status, step, out_cap,
+                       out_events, (uint32_t*)w.cands);
     return hipGetLastError();
 }
 
