@@ -363,12 +363,12 @@ __global__ __launch_bounds__(kBucket) void k_pairs(
                 continue;
             }
             for (; jj < je; ++jj) {
-                bool pair = false;
-                if (act && (!same || idi < J.id[jj])) {
-                    const double d2 = dist2_pair(xi, yi, zi, J.x[jj], J.y[jj], J.z[jj]);
-                    const double hs = hi + J.h[jj];
-                    pair = d2 < hs * hs;
-                }
+                // every lane evaluates the test, without a branch per
+                // candidate (a lane past the bucket's end tests lane 0's copy)
+                const double d2 = dist2_pair(xi, yi, zi, J.x[jj], J.y[jj], J.z[jj]);
+                const double hs = hi + J.h[jj];
+                const bool ord = !same || idi < J.id[jj];
+                const bool pair = act & ord & (d2 < hs * hs);
                 const unsigned long long mask = __ballot(pair);
                 if (pair) queue[qn + __popcll(mask & lt)] = (uint16_t)(lane | (jj << 8));
                 qn += __popcll(mask);
