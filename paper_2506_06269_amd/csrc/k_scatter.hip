@@ -208,7 +208,8 @@ __global__ __launch_bounds__(kBucket) void k_pairs(
     const HaloDev* __restrict__ halos, const BucketInfo* __restrict__ buckets,
     const NodeChild* __restrict__ nodes, const double* __restrict__ box,
     const double* __restrict__ hmax, const SubRange* __restrict__ sub,
-    const int* __restrict__ sub_n, const double* __restrict__ cbox, int64_t n_buckets,
+    const int* __restrict__ sub_n, const double* __restrict__ cbox,
+    const double* __restrict__ chmax, int64_t n_buckets,
     const double* __restrict__ sx,
     const double* __restrict__ sy, const double* __restrict__ sz, const double* __restrict__ svx,
     const double* __restrict__ svy, const double* __restrict__ svz, const double* __restrict__ sh,
@@ -356,9 +357,10 @@ __global__ __launch_bounds__(kBucket) void k_pairs(
             for (int jj = 0; jj < R.cnt;) {
             const int g = (R.off + jj) / kChunk;
             const int je = chunked ? min(R.cnt, (g + 1) * kChunk - R.off) : R.cnt;
+            const double rc = hi_l + chmax[kChunks * c + g];   // the chunk's own largest h
             if (chunked &&
                 !__ballot(act && point_box_dist2(xl, yl, zl, cbox + 6 * (kChunks * c + g)) <
-                                     rr * rr * (1.0 + 1e-9))) {
+                                     rc * rc * (1.0 + 1e-9))) {
                 jj = je;
                 continue;
             }
@@ -638,7 +640,7 @@ hipError_t launch_scatter(const Plan& P, const sidm_state* s, Scratch& w, uint32
     const int split = search_split(P.n_buckets, kPairSplitMax);
     auto pairs = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3((unsigned)(P.n_buckets * split)), dim3(kBucket), 0, st, w.halos,
-                           w.buckets, w.nodes, w.box, w.hmax, w.sub, w.sub_n, w.cbox, P.n_buckets, w.sx,
+                           w.buckets, w.nodes, w.box, w.hmax, w.sub, w.sub_n, w.cbox, w.chmax, P.n_buckets, w.sx,
                            w.sy, w.sz, w.svx, w.svy, w.svz, w.sh, w.cref, w.sid, w.perm, step,
                            w.counters, w.cands, w.max_cands, w.events, w.max_events,
                            (unsigned long long*)w.ev_counts, w.status, split);

@@ -415,16 +415,24 @@ __global__ __launch_bounds__(256) void k_bucket_boxes(
     }
 }
 
+// The largest kernel size of every bucket and (when chmax is given) of each of
+// its chunks of kChunk particles (0 for an empty chunk).
 __global__ __launch_bounds__(256) void k_bucket_hmax(
     const BucketInfo* __restrict__ buckets, int64_t nb, const double* __restrict__ sh,
-    double* __restrict__ hmax)
+    double* __restrict__ hmax, double* __restrict__ chmax)
 {
     const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (b >= nb) return;
     const int lane = threadIdx.x & 63;
     const BucketInfo B = buckets[b];
-    const double v = wave_max(sh[B.start + (lane < B.count ? lane : 0)]);
+    const double h = sh[B.start + (lane < B.count ? lane : 0)];
+    const double v = wave_max(h);
     if (lane == 0) hmax[b] = v;
+    if (chmax)
+        for (int g = 0; g < kChunks; ++g) {
+            const double c = wave_max(lane < B.count && lane / kChunk == g ? h : 0.0);
+            if (lane == 0) chmax[kChunks * b + g] = c;
+        }
 }
 
 __global__ __launch_bounds__(256) void k_node_boxes(const NodeTask* __restrict__ tasks,
@@ -522,7 +530,7 @@ hipError_t launch_cell_list(const Plan& P, const sidm_state* s, Scratch& w, hipS
 hipError_t launch_tree_hmax(const Plan& P, Scratch& w, hipStream_t st)
 {
     hipLaunchKernelGGL(k_bucket_hmax, dim3(grid_of(P.n_buckets, 4)), dim3(256), 0, st, w.buckets,
-                       P.n_buckets, w.sh, w.hmax);
+                       P.n_buckets, w.sh, w.hmax, w.chmax);
     for (int l = 1; l < P.n_levels; ++l) {
         const int64_t t0 = P.level_task_off[l - 1], nt = P.level_task_off[l] - t0;
         if (nt > 0)

@@ -124,6 +124,7 @@ struct Scratch {
     SubRange* sub = nullptr;      // kSubMax per bucket
     int* sub_n = nullptr;         // sub-ranges per bucket
     double* cbox = nullptr;       // 6 per chunk, kChunks per bucket (searches only)
+    double* chmax = nullptr;      // largest h per chunk, kChunks per bucket (pair search)
     unsigned long long* skeys = nullptr;   // sorted keys (one of keys[0..1])
     double* hmax = nullptr;       // 1 per node
     // scattering
@@ -251,7 +252,7 @@ inline bool alloc_scratch(Scratch& w, int64_t N, int32_t H, int64_t max_events, 
               dalloc(w.mom, w.nodes_cap) && dalloc(w.mom2, 6 * w.nodes_cap) && dalloc(w.tree_terms, H) && dalloc(w.sid, N) && dalloc(w.perm, N) &&
               dalloc(w.box, 6 * w.nodes_cap) && dalloc(w.hmax, w.nodes_cap) &&
               dalloc(w.sub, kSubMax * w.buckets_cap) && dalloc(w.sub_n, w.buckets_cap) &&
-              dalloc(w.cbox, 6 * kChunks * w.buckets_cap) &&
+              dalloc(w.cbox, 6 * kChunks * w.buckets_cap) && dalloc(w.chmax, kChunks * w.buckets_cap) &&
               dalloc(w.owner, N) && dalloc(w.counters, 1) && dalloc(w.ev_counts, kEvCounts * H) &&
               dalloc(w.status, H) && dalloc(w.sticky, 1) && dalloc(w.fp_dev, 1);
     if (!ok) {
@@ -296,7 +297,7 @@ inline void free_scratch(Scratch& w)
     dfree(w.items_tick); dfree(w.partial_tick);
     w.items_tick_cap = w.partial_tick_rows = 0;
     dfree(w.sh); dfree(w.sm); dfree(w.bin); dfree(w.mom); dfree(w.mom2); dfree(w.tree_terms); dfree(w.sid); dfree(w.perm); dfree(w.box); dfree(w.hmax);
-    dfree(w.sub); dfree(w.sub_n); dfree(w.cbox);
+    dfree(w.sub); dfree(w.sub_n); dfree(w.cbox); dfree(w.chmax);
     dfree(w.owner); dfree(w.events); dfree(w.cands); dfree(w.counters); dfree(w.ev_counts); dfree(w.status);
     dfree(w.sticky); dfree(w.fp_dev);
     dfree(w.sym_items); dfree(w.symacc);
