@@ -146,7 +146,7 @@ def _log_step(S, run_label, step, dl, e0, passes):
     _LOG.flush()
 
 
-def _run(S, torch, halos, s, prec, steps, warmup, timing, progress=False):
+def _run(S, torch, halos, s, prec, steps, warmup, timing, progress=False, graph_replays=0):
     n = s["x"].size
     dev = S.state_to_device(s)
     ctx = S.sidm_create(0, n, len(halos))
@@ -190,6 +190,27 @@ def _run(S, torch, halos, s, prec, steps, warmup, timing, progress=False):
     _run.last = {k: sum(x[k] for x in dl) for k in ("n_pairs", "n_candidates", "n_p_gt1")}
     for k in passes:
         passes[k] /= steps
+    _run.graph_ms = None
+    if graph_replays > 0:
+        # the same step captured once in a HIP graph and replayed (the step
+        # index, and so the draws, are those of the captured call)
+        S.sidm_enable_timing(ctx, False)
+        S.sidm_diagnostics(ctx, halos, dev, diag)
+        torch.cuda.synchronize()
+        stream = torch.cuda.Stream()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(stream):
+            graph.capture_begin()
+            S.sidm_kdk_step(ctx, halos, dev, step, prec, diag=diag)
+            graph.capture_end()
+        graph.replay()
+        torch.cuda.synchronize()
+        g0 = time.perf_counter()
+        for _ in range(graph_replays):
+            graph.replay()
+        torch.cuda.synchronize()
+        _run.graph_ms = (time.perf_counter() - g0) / graph_replays * 1e3
+        del graph
     S.sidm_destroy(ctx)
     return (t1 - t0) / steps, rel_e, passes, d, events
 
@@ -447,7 +468,7 @@ def _bench_c4(a, S, torch, W):
         off += h["n"]
     inter = sum(h["n"] * (h["n"] - 1) for h in hl)
     ms, de, passes, _, events = _run(S, torch, halos, s, S.SIDM_PREC_MIXED, a.steps, a.warmup,
-                                     True)
+                                     True, graph_replays=a.steps)
     out = {"metric": "gravity interactions/s + SIDM particle-updates/s (64-halo batch)",
            "value": inter / ms, "unit": "gravity interactions/s", "n_gpus": 1,
            "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms * 1e3,
@@ -457,7 +478,7 @@ def _bench_c4(a, S, torch, W):
                                                                   "sigma/m {1,10,50}, k {16..128}",
                                                      "n_total": total, "halos": 64},
            "sidm_particle_updates_per_s": total / ms, "dE_over_E": de, "events_last_step": events,
-           "pass_ms": passes, "tiles": _run.tiles}
+           "pass_ms": passes, "tiles": _run.tiles, "graph_replay_ms_per_step": _run.graph_ms}
     print(json.dumps(out), flush=True)
 
 
