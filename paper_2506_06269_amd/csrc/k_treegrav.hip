@@ -11,8 +11,9 @@
 // centre of mass (a bucket's from its particles, a node's from its children
 // by parallel axes).
 //
-// A group is a bucket: one wave of 64 lanes, one member per lane, walks the
-// tree once for all members.  A node is accepted when its box and the group's
+// A group is a bucket: waves of 64 lanes, one member per lane, walk the tree
+// for all members, one wave per part of the walk (the parts share out the
+// subtrees below a frontier level; see kTreeSplit).  A node is accepted when its box and the group's
 // box are disjoint and (G M l^2)^2 <= alpha^2 |a_old|^2 r^8, with l the node
 // box's largest side, |a_old| the smallest previous acceleration of the
 // members and r the distance between the two boxes: the paper's criterion
@@ -25,8 +26,8 @@
 // tested by lanes 0..7 at once, accepted ones appended by a ballot prefix);
 // full lists are summed by all lanes, each for its own member, with the self
 // pair skipped in the group's own bucket, and the list sums are folded into
-// compensated accumulators.  The result is one partial row per particle, finished by the
-// gravity finalize pass (G, host, kicks).
+// compensated accumulators.  The result is one partial row per particle and
+// part, summed in part order by the gravity finalize pass (G, host, kicks).
 //
 // FP64 form: positions and arithmetic in FP64.  Mixed form: the list holds
 // FP64 positions; each pair's separation is taken in FP64 and rounded to FP32,
@@ -40,8 +41,17 @@
 
 namespace sidm {
 
-constexpr int kTreeList = 128;                    // source list entries per group
-constexpr int kTreeNodes = 64;                    // accepted-node list entries per group
+// A walk round pops up to kTreePop pending nodes and tests their children
+// (at most kTreePop * kFanout), so the accepted-node list holds one round's
+// acceptances; the particle list one opened bucket.  These sizes keep a
+// group's LDS at 9.5 KB, 16 groups per compute unit (as many as the
+// registers allow): 128 and 64 entries with eight pops per round took
+// 308.8 against 281.2 ms at N = 2^24.
+constexpr int kTreePop = 4;
+constexpr int kTreeList = 64;                     // source list entries per group
+constexpr int kTreeNodes = kTreePop * kFanout;    // accepted-node list entries per group
+static_assert(kTreeList >= kBucket, "an opened bucket must fit the particle list");
+static_assert(kTreePop <= kFanout, "the stack bound below assumes kTreePop <= kFanout");
 
 // An accepted node: centre of mass, mass and second moments about the centre
 // (xx, yy, zz, xy, xz, yz).
@@ -49,9 +59,9 @@ struct NodeEntry {
     double x, y, z, m;
     double S[6];
 };
-// Popping kFanout nodes per round and pushing at most kFanout^2 children, the
-// stack holds at most (kFanout^2 - kFanout) nodes per level plus one round's
-// pushes: 56 * kMaxLevels + 64 = 624 for ten levels.
+// Popping up to kTreePop <= kFanout nodes per round and pushing at most
+// kFanout children of each, the stack holds at most kFanout^2 - kFanout nodes
+// per level plus one round's pushes (624 for ten levels).
 constexpr int kTreeStack = (kFanout * kFanout - kFanout) * kMaxLevels + kFanout * kFanout;
 
 // ---------------------------------------------------------------- moments
@@ -348,7 +358,8 @@ struct TreeAcc<true> {
 
 
 // ---------------------------------------------------------------- walk
-// One block = one wave = one group.  tick > 0: tick of a cycle of block steps
+// One block = one wave = one part of one group's walk (writing the group's
+// partial row of that part).  tick > 0: tick of a cycle of block steps
 // (groups without an active member are skipped).
 template <bool MIXED>
 __global__ __launch_bounds__(64) void k_tree_walk(
@@ -359,7 +370,7 @@ __global__ __launch_bounds__(64) void k_tree_walk(
     const uint32_t* __restrict__ perm, const double* __restrict__ ax_old,
     const double* __restrict__ ay_old, const double* __restrict__ az_old,
     const int8_t* __restrict__ bin, int tick, int bmax, double4* __restrict__ partial,
-    unsigned long long* __restrict__ terms)
+    unsigned long long* __restrict__ terms, int parts)
 {
     using Acc = TreeAcc<MIXED>;
     using Entry = typename Acc::Entry;
@@ -368,11 +379,17 @@ __global__ __launch_bounds__(64) void k_tree_walk(
     // pending inner nodes as (first child, number of children)
     __shared__ int2 stack[kTreeStack];
 
-    const int64_t g = xcd_chunked<256>(blockIdx.x, gridDim.x);
+    // part s of group g, in the dispatcher's order (runs of groups per XCD
+    // would put the costly centre groups, neighbours on the Morton curve, on
+    // one XCD)
+    const int64_t g = blockIdx.x / parts;
+    const int s = (int)(blockIdx.x % parts);
     const int lane = threadIdx.x;
     const BucketInfo GB = buckets[g];
     const HaloDev& H = halos[GB.halo];
-    if (!(H.tree_alpha > 0.0)) return;
+    if (!(H.tree_alpha > 0.0) || s >= H.grav_split) return;
+    const int nparts = H.grav_split;
+    const int front = nparts > 1 ? tree_front_level(H.level_n, H.n_levels, nparts) : -1;
     const bool live = lane < GB.count;
     const int64_t p = GB.start + (live ? lane : 0);
     const int64_t o = perm[p];
@@ -428,10 +445,11 @@ __global__ __launch_bounds__(64) void k_tree_walk(
         len += cnt;
     };
 
+    // a stack entry: first child and (number of children | their level << 4)
     {
         const NodeChild rc = nodes[root];
         if (rc.nchild > 0) {
-            if (lane == 0) stack[0] = make_int2((int)rc.child0, rc.nchild);
+            if (lane == 0) stack[0] = make_int2((int)rc.child0, rc.nchild | ((H.n_levels - 2) << 4));
             sp = 1;
         } else {
             append_bucket(GB.start, GB.count, true);   // a halo of one bucket
@@ -439,10 +457,10 @@ __global__ __launch_bounds__(64) void k_tree_walk(
         __syncthreads();
     }
 
-    // Each round pops up to kFanout pending nodes; lane 8 s + k tests child k of
+    // Each round pops up to kTreePop pending nodes; lane 8 s + k tests child k of
     // the s-th popped node, so one round of dependent loads serves 64 children.
     while (sp > 0) {
-        const int npop = sp < kFanout ? sp : kFanout;
+        const int npop = sp < kTreePop ? sp : kTreePop;
         const int slot = lane / kFanout, ci = lane % kFanout;
         int2 nd = make_int2(0, 0);
         if (slot < npop) nd = stack[sp - 1 - slot];
@@ -452,14 +470,17 @@ __global__ __launch_bounds__(64) void k_tree_walk(
         int2 push = make_int2(0, 0);
         int64_t bstart = 0;
         int bcnt = 0;
-        if (slot < npop && ci < nd.y) {
-            const int64_t c = (int64_t)nd.x + ci;
+        const int lvl = nd.y >> 4;
+        const int64_t c = (int64_t)nd.x + ci;
+        // a frontier node belongs to one part; those above it count in part 0
+        const bool own = lvl != front || (int)(c - H.level_off[front]) % nparts == s;
+        if (slot < npop && ci < (nd.y & 15) && own) {
             double cb[6];
             for (int q = 0; q < 6; ++q) cb[q] = box[6 * c + q];
             const double4 mm = mom[c];
             const NodeChild cc = nodes[c];
             if (tree_accept(cb, mm.x, gb, H.G, alpha2, a2min)) {
-                if (mm.x != 0.0) {
+                if (mm.x != 0.0 && (lvl <= front || s == 0)) {
                     take = true;
                     e.x = mm.y / mm.x;
                     e.y = mm.z / mm.x;
@@ -469,7 +490,7 @@ __global__ __launch_bounds__(64) void k_tree_walk(
                 }
             } else if (cc.nchild > 0) {
                 open_inner = true;
-                push = make_int2((int)cc.child0, cc.nchild);
+                push = make_int2((int)cc.child0, cc.nchild | ((lvl - 1) << 4));
             } else {
                 open_bucket = true;
                 const BucketInfo cbk = buckets[c];
@@ -500,7 +521,7 @@ __global__ __launch_bounds__(64) void k_tree_walk(
         __syncthreads();
     }
     flush();
-    if (live) partial[H.part_base + (p - H.sbase)] = acc.result();
+    if (live) partial[H.part_base + (int64_t)s * H.n + (p - H.sbase)] = acc.result();
     if (lane == 0) atomicAdd(&terms[GB.halo], total);
 }
 
@@ -520,18 +541,18 @@ hipError_t launch_tree_gravity(bool mixed, const Plan& P, Scratch& w, const sidm
             hipLaunchKernelGGL(k_tree_mom_node, dim3(grid_of(nt, 256)), dim3(256), 0, st,
                                w.node_tasks + t0, nt, w.mom, w.mom2);
     }
+    int parts = 1;
+    for (const auto& H : P.halos)
+        if (H.tree_alpha > 0.0) parts = std::max(parts, (int)H.grav_split);
+    const dim3 grid((unsigned)(P.n_buckets * parts));
     if (mixed)
-        hipLaunchKernelGGL(k_tree_walk<true>, dim3((unsigned)P.n_buckets), dim3(64), 0, st,
-                           w.buckets, w.nodes, w.box, w.mom, w.mom2, w.halos, w.sx, w.sy, w.sz,
-                           w.sm,
-                           w.perm, s->ax, s->ay, s->az, w.bin, tick, bmax, w.partial,
-                           w.tree_terms);
+        hipLaunchKernelGGL(k_tree_walk<true>, grid, dim3(64), 0, st, w.buckets, w.nodes, w.box,
+                           w.mom, w.mom2, w.halos, w.sx, w.sy, w.sz, w.sm, w.perm, s->ax, s->ay,
+                           s->az, w.bin, tick, bmax, w.partial, w.tree_terms, parts);
     else
-        hipLaunchKernelGGL(k_tree_walk<false>, dim3((unsigned)P.n_buckets), dim3(64), 0, st,
-                           w.buckets, w.nodes, w.box, w.mom, w.mom2, w.halos, w.sx, w.sy, w.sz,
-                           w.sm,
-                           w.perm, s->ax, s->ay, s->az, w.bin, tick, bmax, w.partial,
-                           w.tree_terms);
+        hipLaunchKernelGGL(k_tree_walk<false>, grid, dim3(64), 0, st, w.buckets, w.nodes, w.box,
+                           w.mom, w.mom2, w.halos, w.sx, w.sy, w.sz, w.sm, w.perm, s->ax, s->ay,
+                           s->az, w.bin, tick, bmax, w.partial, w.tree_terms, parts);
     return hipGetLastError();
 }
 

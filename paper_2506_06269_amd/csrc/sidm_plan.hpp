@@ -56,6 +56,28 @@ struct NodeChild {
 constexpr int kSubMax = 4;
 // At most this many j-ranges per halo for the one-sided gravity tiles.
 constexpr int64_t kMaxGravSplit = 32;
+// The tree walk of a group is cut into kTreeSplit parts, each with a partial
+// row of its own: the nodes of one level of the halo's tree (its frontier)
+// are dealt out to the parts in turn, and a part descends only into its own
+// frontier nodes (every part tests the nodes above the frontier, and an
+// accepted one counts in part 0 only).  Every node is then accepted or opened
+// for the group exactly as in one walk, while the few groups that open most
+// of the tree (a bucket that straddles the halo's centre, the densest centre
+// groups) are shared out over four waves.  The frontier is the highest level
+// below the root with at least kTreeFrontPer nodes per part; a halo without
+// one walks in one part.
+constexpr int kTreeSplit = 4;
+constexpr int kTreeFrontPer = 32;
+constexpr int tree_front_level(const int64_t* level_n, int n_levels, int parts)
+{
+    for (int l = n_levels - 2; l >= 0; --l)
+        if (level_n[l] >= (int64_t)kTreeFrontPer * parts) return l;
+    return -1;
+}
+inline int32_t tree_parts(const HaloDev& H)
+{
+    return tree_front_level(H.level_n, H.n_levels, kTreeSplit) >= 0 ? kTreeSplit : 1;
+}
 // The searches also skip chunks of kChunk consecutive particles of a bucket
 // (aligned to the bucket start) that no lane's sphere reaches.
 constexpr int kChunk = 16;
@@ -423,18 +445,22 @@ inline void choose_splits(std::vector<HaloDev>& hd, int64_t partial_rows, int64_
                           const GravShape& shape)
 {
     const int64_t kIBlock = (int64_t)shape.ireg * shape.nt, kGravTileJ = shape.nt;
-    int64_t iblocks = 0, ntot = 0;
+    int64_t iblocks = 0, ntot = 0, tree_rows = 0;
     for (auto& H : hd) {
-        if (H.tree_alpha > 0.0) continue;
+        if (H.tree_alpha > 0.0) {
+            tree_rows += H.n * tree_parts(H);
+            continue;
+        }
         iblocks += (H.n + kIBlock - 1) / kIBlock;
         ntot += H.n;
     }
     iblocks = std::max<int64_t>(iblocks, 1);
     // at most kMaxGravSplit j-ranges per halo, and as many as the partial rows
-    // hold (four for calls of 2^16 particles and more; small calls get more
-    // j-ranges to fill the device)
+    // left by the tree halos hold (four or more for calls of 2^16 particles
+    // and more; small calls get more j-ranges to fill the device)
     const int64_t smax = std::min<int64_t>(
-        kMaxGravSplit, std::max<int64_t>(1, partial_rows / std::max<int64_t>(ntot, 1)));
+        kMaxGravSplit,
+        std::max<int64_t>(1, (partial_rows - tree_rows) / std::max<int64_t>(ntot, 1)));
     int64_t best = 1;
     if (slots <= 0) {
         best = std::min<int64_t>(smax, std::max<int64_t>(1, (2048 + iblocks - 1) / iblocks));
@@ -474,8 +500,10 @@ inline void choose_splits(std::vector<HaloDev>& hd, int64_t partial_rows, int64_
     }
     for (auto& H : hd) {
         const int64_t tiles = (H.n + kGravTileJ - 1) / kGravTileJ;
-        H.grav_split = H.tree_alpha > 0.0 ? 1
-                                           : (int32_t)std::max<int64_t>(1, std::min<int64_t>(best, tiles));
+        if (H.tree_alpha > 0.0)
+            H.grav_split = tree_parts(H);
+        else
+            H.grav_split = (int32_t)std::max<int64_t>(1, std::min<int64_t>(best, tiles));
     }
 }
 

@@ -35,6 +35,26 @@ extern "C" long long plan_items(int nh, const long long* n, long long slots, int
     return items;
 }
 extern "C" int search_split(long long nb, int max_split) { return sidm::search_split(nb, max_split); }
+extern "C" long long plan_rows(int nh, const long long* n, const double* alpha,
+                               long long partial_rows, int* split) {
+    std::vector<sidm::HaloDev> hd(nh);
+    for (int h = 0; h < nh; ++h) {
+        std::memset(&hd[h], 0, sizeof(hd[h]));
+        hd[h].n = n[h]; hd[h].tree_alpha = alpha[h];
+        long long m = (n[h] + 63) / 64;   // buckets of 64, then levels of 8 children
+        int l = 0;
+        hd[h].level_n[0] = m;
+        while (m > 1) { m = (m + 7) / 8; hd[h].level_n[++l] = m; }
+        hd[h].n_levels = l + 1;
+    }
+    sidm::GravShape shape;
+    shape.ireg = 4;
+    shape.nt = 256;
+    sidm::choose_splits(hd, partial_rows, 0, shape);
+    long long rows = 0;
+    for (int h = 0; h < nh; ++h) { split[h] = hd[h].grav_split; rows += n[h] * hd[h].grav_split; }
+    return rows;
+}
 extern "C" int plan_split(int nh, const long long* n, long long slots, long long partial_rows,
                           int ireg, int nt) {
     std::vector<sidm::HaloDev> hd(nh);
@@ -239,3 +259,32 @@ def test_search_split(L):
         assert s in (1, 2, 4, 8, 16)
         assert nb * s >= 2048 or s == 16
         assert s == 1 or nb * (s // 2) < 2048
+
+
+@pytest.mark.parametrize("ns,alphas", [
+    ([1 << 20], [5e-4]),
+    ([(1 << 20) - 4096, 4096], [5e-4, 0.0]),
+    ([1 << 19, 1 << 19], [5e-4, 0.0]),
+    ([8192, 8191, 100, 1 << 16], [5e-4, 5e-4, 5e-4, 0.0]),
+    ([1 << 20] + [4096] * 8, [0.0] + [5e-4] * 8),
+])
+def test_tree_parts_fit_the_partial_rows(L, ns, alphas):
+    """A tree halo's walk runs in four parts (a partial row each) when a level
+    below the root holds at least 128 nodes, else in one; the rows of all
+    halos fit the context's partial rows (the tree halos' rows are set aside
+    before the direct halos' j-splits are chosen)."""
+    nh = len(ns)
+    rows_cap = max(4 * sum(ns), 1 << 18)
+    split = (C.c_int * nh)()
+    L.plan_rows.restype = C.c_longlong
+    used = L.plan_rows(nh, (C.c_longlong * nh)(*ns), (C.c_double * nh)(*alphas), rows_cap, split)
+    assert used <= rows_cap
+    for n, a, s in zip(ns, alphas, split):
+        if a > 0:
+            levels = [-(-n // 64)]
+            while levels[-1] > 1:
+                levels.append(-(-levels[-1] // 8))
+            front = [l for l in range(len(levels) - 1) if levels[l] >= 32 * 4]
+            assert s == (4 if front else 1), (n, s)
+        else:
+            assert s >= 1
