@@ -13,10 +13,11 @@
 //
 // A group is a bucket: waves of 64 lanes, one member per lane, walk the tree
 // for all members, one wave per part of the walk (the parts share out the
-// subtrees below a frontier level; see kTreeSplit).  A node is accepted when its box and the group's
-// box are disjoint and (G M l^2)^2 <= alpha^2 |a_old|^2 r^8, with l the node
-// box's largest side, |a_old| the smallest previous acceleration of the
-// members and r the distance between the two boxes: the paper's criterion
+// subtrees below a frontier level; see kTreeSplit).  A node is accepted when
+// its box and the group's box are disjoint and (G M l^2)^2 <= alpha^2
+// |a_old|^2 r^8, with l the node box's largest side, |a_old| the smallest
+// previous acceleration of the members and r the distance between the two
+// boxes: the paper's criterion
 // G M l^2 <= alpha |a_old| r^4, squared (no square root in the decision) and
 // made to hold for every member and every particle of the node.  An accepted
 // node contributes its monopole and quadrupole (the second-order term of the
@@ -44,7 +45,7 @@ namespace sidm {
 // A walk round pops up to kTreePop pending nodes and tests their children
 // (at most kTreePop * kFanout), so the accepted-node list holds one round's
 // acceptances; the particle list one opened bucket.  These sizes keep a
-// group's LDS at 9.5 KB, 16 groups per compute unit (as many as the
+// group's LDS at 9.6 KB, 16 groups per compute unit (as many as the
 // registers allow): 128 and 64 entries with eight pops per round took
 // 308.8 against 281.2 ms at N = 2^24.
 constexpr int kTreePop = 4;
