@@ -4,7 +4,10 @@ tree, through the C ABI.  Both sides build the same tree (Morton order,
 64-particle buckets, fan-out 8) and take the opening decisions in FP64 from
 the same inputs, so the number of source terms must be equal exactly; forces
 and potentials within 1e-12 (FP64) or 1e-5 (mixed) of the oracle's tree,
-normwise against the direct-sum scale sum m r / (r^2 + eps^2)^(3/2)."""
+normwise against the direct-sum scale sum m r / (r^2 + eps^2)^(3/2).  A
+group's walk runs in four parts that share out the subtrees below a frontier
+level; the sizes put that level at the buckets (20 000 particles) and one
+level above them (2^17), and leave the small halos in one part."""
 import numpy as np
 import pytest
 
@@ -41,7 +44,7 @@ def _gravity_terms(S, ctx, halos, dev, prec):
 
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("n,alpha", [(20000, 5e-4), (20000, 2.5e-2), (2, 5e-4), (64, 5e-4),
-                                     (65, 5e-4), (4097, 5e-3)])
+                                     (65, 5e-4), (4097, 5e-3), (1 << 17, 5e-4)])
 def test_tree_forces_match_the_oracle_tree(S, orc, prec, n, alpha):
     s0 = W.nfw_halo(max(n, 2), seed=91)
     s, an = _with_old_accel(orc, s0, 0.01)
