@@ -55,11 +55,40 @@ static_assert(kTreeList >= kBucket, "an opened bucket must fit the particle list
 static_assert(kTreePop <= kFanout, "the stack bound below assumes kTreePop <= kFanout");
 
 // An accepted node: centre of mass, mass and second moments about the centre
-// (xx, yy, zz, xy, xz, yz).
+// (xx, yy, zz, xy, xz, yz).  The mixed sums take the mass and the moments in
+// FP32: they are rounded once when the node is listed (with the trace T of
+// the rounded moments), not per term, which saves 9 of about 56 vector
+// instructions per node term and a third of the entry's bytes.
 struct NodeEntry {
     double x, y, z, m;
     double S[6];
 };
+struct NodeEntryF {
+    double x, y, z;
+    float m, S[6], T;
+};
+template <bool MIXED>
+struct NodeOf {
+    using type = NodeEntry;
+};
+template <>
+struct NodeOf<true> {
+    using type = NodeEntryF;
+};
+
+__device__ inline void set_node(NodeEntry& e, double x, double y, double z, double m,
+                                const double* __restrict__ S)
+{
+    e.x = x; e.y = y; e.z = z; e.m = m;
+    for (int k = 0; k < 6; ++k) e.S[k] = S[k];
+}
+__device__ inline void set_node(NodeEntryF& e, double x, double y, double z, double m,
+                                const double* __restrict__ S)
+{
+    e.x = x; e.y = y; e.z = z; e.m = (float)m;
+    for (int k = 0; k < 6; ++k) e.S[k] = (float)S[k];
+    e.T = e.S[0] + e.S[1] + e.S[2];
+}
 // Popping up to kTreePop <= kFanout nodes per round and pushing at most
 // kFanout children of each, the stack holds at most kFanout^2 - kFanout nodes
 // per level plus one round's pushes (624 for ten levels).
@@ -331,26 +360,26 @@ struct TreeAcc<true> {
         y = p[3] - cp; t = sp + y; cp = (t - sp) - y; sp = t;
     }
     // Accepted nodes (see the FP64 form): separations from FP64, the rest FP32.
-    __device__ inline void sum_nodes(const NodeEntry* L, int len)
+    __device__ inline void sum_nodes(const NodeEntryF* L, int len)
     {
         len = __builtin_amdgcn_readfirstlane(len);
         float p[4] = {0.f, 0.f, 0.f, 0.f};
         for (int jj = 0; jj < len; ++jj) {
-            const NodeEntry& q = L[jj];
+            const NodeEntryF& q = L[jj];
             const float dx = (float)(q.x - xi), dy = (float)(q.y - yi), dz = (float)(q.z - zi);
             const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
             const float rinv = __builtin_amdgcn_rsqf(r2);
-            const float mr = (float)q.m * rinv;
+            const float mr = q.m * rinv;
             const float ri2 = rinv * rinv;
             const float mr3 = mr * ri2;
             const float ri5 = rinv * ri2 * ri2, ri7 = ri5 * ri2;
-            const float S0 = (float)q.S[0], S1 = (float)q.S[1], S2 = (float)q.S[2];
-            const float S3 = (float)q.S[3], S4 = (float)q.S[4], S5 = (float)q.S[5];
+            const float S0 = q.S[0], S1 = q.S[1], S2 = q.S[2];
+            const float S3 = q.S[3], S4 = q.S[4], S5 = q.S[5];
             const float d0 = -dx, d1 = -dy, d2 = -dz;
             const float Sd0 = fmaf(S0, d0, fmaf(S3, d1, S4 * d2));
             const float Sd1 = fmaf(S3, d0, fmaf(S1, d1, S5 * d2));
             const float Sd2 = fmaf(S4, d0, fmaf(S5, d1, S2 * d2));
-            const float T = S0 + S1 + S2;
+            const float T = q.T;
             const float br = 3.f * fmaf(d0, Sd0, fmaf(d1, Sd1, d2 * Sd2)) - r2 * T;
             const float c5 = 2.5f * br * ri7;
             p[0] += fmaf(mr3, dx, (3.f * Sd0 - T * d0) * ri5 - c5 * d0);
@@ -390,7 +419,8 @@ __global__ __launch_bounds__(64) void k_tree_walk(
     using Acc = TreeAcc<MIXED>;
     using Entry = typename Acc::Entry;
     __shared__ Entry list[kTreeList];
-    __shared__ NodeEntry nlist[kTreeNodes];
+    using Node = typename NodeOf<MIXED>::type;
+    __shared__ Node nlist[kTreeNodes];
     // pending inner nodes as (first child, number of children)
     __shared__ int2 stack[kTreeStack];
 
@@ -481,7 +511,7 @@ __global__ __launch_bounds__(64) void k_tree_walk(
         if (slot < npop) nd = stack[sp - 1 - slot];
         sp -= npop;
         bool take = false, open_inner = false, open_bucket = false, self = false;
-        NodeEntry e{};
+        Node e{};
         int2 push = make_int2(0, 0);
         int64_t bstart = 0;
         int bcnt = 0;
@@ -497,11 +527,7 @@ __global__ __launch_bounds__(64) void k_tree_walk(
             if (tree_accept(cb, mm.x, gb, H.G, alpha2, a2min)) {
                 if (mm.x != 0.0 && (lvl <= front || s == 0)) {
                     take = true;
-                    e.x = mm.y / mm.x;
-                    e.y = mm.z / mm.x;
-                    e.z = mm.w / mm.x;
-                    e.m = mm.x;
-                    for (int k = 0; k < 6; ++k) e.S[k] = mom2[6 * c + k];
+                    set_node(e, mm.y / mm.x, mm.z / mm.x, mm.w / mm.x, mm.x, mom2 + 6 * c);
                 }
             } else if (cc.nchild > 0) {
                 open_inner = true;
