@@ -55,17 +55,17 @@ static_assert(kTreeList >= kBucket, "an opened bucket must fit the particle list
 static_assert(kTreePop <= kFanout, "the stack bound below assumes kTreePop <= kFanout");
 
 // An accepted node: centre of mass, mass and second moments about the centre
-// (xx, yy, zz, xy, xz, yz).  The mixed sums take the mass and the moments in
-// FP32: they are rounded once when the node is listed (with the trace T of
-// the rounded moments), not per term, which saves 9 of about 56 vector
-// instructions per node term and a third of the entry's bytes.
+// (xx, yy, zz, xy, xz, yz).  The mixed sums take the mass, three times the
+// moments and their trace in FP32, rounded once when the node is listed
+// rather than per term (a third of the entry's bytes, and about 15 of 53
+// vector instructions per node term).
 struct NodeEntry {
     double x, y, z, m;
     double S[6];
 };
 struct NodeEntryF {
     double x, y, z;
-    float m, S[6], T;
+    float m, S3[6], T;   // S3 = 3 S
 };
 template <bool MIXED>
 struct NodeOf {
@@ -86,8 +86,8 @@ __device__ inline void set_node(NodeEntryF& e, double x, double y, double z, dou
                                 const double* __restrict__ S)
 {
     e.x = x; e.y = y; e.z = z; e.m = (float)m;
-    for (int k = 0; k < 6; ++k) e.S[k] = (float)S[k];
-    e.T = e.S[0] + e.S[1] + e.S[2];
+    for (int k = 0; k < 6; ++k) e.S3[k] = (float)(3.0 * S[k]);
+    e.T = (float)(S[0] + S[1] + S[2]);
 }
 // Popping up to kTreePop <= kFanout nodes per round and pushing at most
 // kFanout children of each, the stack holds at most kFanout^2 - kFanout nodes
@@ -373,19 +373,19 @@ struct TreeAcc<true> {
             const float ri2 = rinv * rinv;
             const float mr3 = mr * ri2;
             const float ri5 = rinv * ri2 * ri2, ri7 = ri5 * ri2;
-            const float S0 = q.S[0], S1 = q.S[1], S2 = q.S[2];
-            const float S3 = q.S[3], S4 = q.S[4], S5 = q.S[5];
+            // with d = -(dx, dy, dz) and U = 3 S d: br = d.U - rho^2 T and
+            // a_Q = (U - T d) rho^-5 - (5/2) br rho^-7 d = U rho^-5 - k d
             const float d0 = -dx, d1 = -dy, d2 = -dz;
-            const float Sd0 = fmaf(S0, d0, fmaf(S3, d1, S4 * d2));
-            const float Sd1 = fmaf(S3, d0, fmaf(S1, d1, S5 * d2));
-            const float Sd2 = fmaf(S4, d0, fmaf(S5, d1, S2 * d2));
-            const float T = q.T;
-            const float br = 3.f * fmaf(d0, Sd0, fmaf(d1, Sd1, d2 * Sd2)) - r2 * T;
+            const float U0 = fmaf(q.S3[0], d0, fmaf(q.S3[3], d1, q.S3[4] * d2));
+            const float U1 = fmaf(q.S3[3], d0, fmaf(q.S3[1], d1, q.S3[5] * d2));
+            const float U2 = fmaf(q.S3[4], d0, fmaf(q.S3[5], d1, q.S3[2] * d2));
+            const float br = fmaf(-r2, q.T, fmaf(d0, U0, fmaf(d1, U1, d2 * U2)));
             const float c5 = 2.5f * br * ri7;
-            p[0] += fmaf(mr3, dx, (3.f * Sd0 - T * d0) * ri5 - c5 * d0);
-            p[1] += fmaf(mr3, dy, (3.f * Sd1 - T * d1) * ri5 - c5 * d1);
-            p[2] += fmaf(mr3, dz, (3.f * Sd2 - T * d2) * ri5 - c5 * d2);
-            p[3] += mr + 0.5f * br * ri5;
+            const float k = fmaf(q.T, ri5, c5);
+            p[0] += fmaf(mr3, dx, fmaf(U0, ri5, -k * d0));
+            p[1] += fmaf(mr3, dy, fmaf(U1, ri5, -k * d1));
+            p[2] += fmaf(mr3, dz, fmaf(U2, ri5, -k * d2));
+            p[3] += fmaf(0.5f * br, ri5, mr);
         }
         float y, t;
         y = p[0] - cx; t = sx + y; cx = (t - sx) - y; sx = t;
